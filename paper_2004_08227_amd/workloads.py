@@ -1,0 +1,158 @@
+"""Seeded synthetic pairwise MRF generators.
+
+This module only draws inputs: it holds none of the solver's arithmetic and is
+the single piece of code that both the HIP path and the CPU oracle are fed
+from.  Every model is a triple (edges, unaries, pairwise) in the layout of the
+energy of Eq. (1) in Sec. 3 of the paper:
+
+* ``edges``    int32 [m, 2], each row (u, v) with u < v (the paper's edge
+  orientation convention, Sec. 3 "Notation"), lexicographic order;
+* ``unaries``  float [n, L], theta_u(s);
+* ``pairwise`` float [m, L, L], theta_uv(s, t) with rows indexed by the label
+  s of the lower node u and columns by the label t of v.
+
+Draw order (numpy ``default_rng`` = PCG64): unaries first, then the graph (for
+random graphs), then the pairwise potentials in edge order.  The workloads
+stand in for the paper's datasets (Sec. 7), which are not available here:
+
+* ``tiny``      K_8, L=4, i.i.d. uniform[0,1) costs (FP64 brute-force size);
+* ``pose``      fully connected 6D-pose-shaped model (Sec. 7 "pose"): label s
+  of node u is a 3D point p_us in the unit cube, node u has a model point
+  q_u, and theta_uv(s,t) = min((| |p_us - p_vt| - |q_u - q_v| |)^2, tau).
+  q_u is planted as p_{u, s*_u} for a random s*_u so that a zero-pairwise
+  labelling exists, as for a real object under a correct pose;
+* ``potts_er``  Erdos-Renyi graph of given density (the sparsification study
+  of Sec. 7), Potts weight w_uv ~ U[0.1, 1] on s != t plus U[0, 0.2) noise;
+* ``uniform``   fully connected, i.i.d. uniform[0,1) costs (the
+  differentiation workload);
+* ``batched_mix`` 256 pose-shaped models with n ~ U{20..300}, L ~ U{8..64}.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class Model:
+    n: int
+    L: int
+    edges: np.ndarray      # int32 [m, 2], u < v
+    unaries: np.ndarray    # float [n, L]
+    pairwise: np.ndarray   # float [m, L, L]
+    name: str = ""
+
+    @property
+    def m(self) -> int:
+        return int(self.edges.shape[0])
+
+    def astype(self, dtype) -> "Model":
+        return Model(self.n, self.L, self.edges,
+                     np.ascontiguousarray(self.unaries, dtype=dtype),
+                     np.ascontiguousarray(self.pairwise, dtype=dtype), self.name)
+
+
+def complete_edges(n: int) -> np.ndarray:
+    """All pairs u < v in lexicographic order, int32 [n(n-1)/2, 2]."""
+    iu, iv = np.triu_indices(n, k=1)
+    return np.ascontiguousarray(np.stack([iu, iv], axis=1).astype(np.int32))
+
+
+def tiny(seed: int = 0, n: int = 8, L: int = 4, dtype=np.float64) -> Model:
+    rng = np.random.default_rng(seed)
+    unaries = rng.random((n, L))
+    edges = complete_edges(n)
+    pairwise = rng.random((edges.shape[0], L, L))
+    return Model(n, L, edges, unaries.astype(dtype), pairwise.astype(dtype), f"tiny_n{n}_L{L}_s{seed}")
+
+
+def uniform(n: int, L: int, seed: int = 0, dtype=np.float32) -> Model:
+    rng = np.random.default_rng(seed)
+    unaries = rng.random((n, L))
+    edges = complete_edges(n)
+    pairwise = rng.random((edges.shape[0], L, L))
+    return Model(n, L, edges, unaries.astype(dtype), pairwise.astype(dtype), f"uniform_n{n}_L{L}_s{seed}")
+
+
+def pose(n: int, L: int, seed: int = 0, tau: float = 0.04, dtype=np.float32,
+         chunk: int = 4096) -> Model:
+    """Fully connected pose-shaped model; pairwise is built in float64 and
+    rounded once to ``dtype``."""
+    rng = np.random.default_rng(seed)
+    unaries = rng.random((n, L))
+    P = rng.random((n, L, 3))
+    star = rng.integers(0, L, size=n)
+    Q = P[np.arange(n), star]                       # planted model points [n, 3]
+    edges = complete_edges(n)
+    m = edges.shape[0]
+    pairwise = np.empty((m, L, L), dtype=dtype)
+    for lo in range(0, m, chunk):
+        hi = min(m, lo + chunk)
+        u = edges[lo:hi, 0]
+        v = edges[lo:hi, 1]
+        dp = np.linalg.norm(P[u][:, :, None, :] - P[v][:, None, :, :], axis=-1)   # [c, L, L]
+        dq = np.linalg.norm(Q[u] - Q[v], axis=-1)[:, None, None]                    # [c, 1, 1]
+        pairwise[lo:hi] = np.minimum((dp - dq) ** 2, tau).astype(dtype)
+    return Model(n, L, edges, unaries.astype(dtype), pairwise, f"pose_n{n}_L{L}_s{seed}")
+
+
+def potts_er(n: int, L: int, density: float, seed: int = 0, dtype=np.float32) -> Model:
+    rng = np.random.default_rng(seed)
+    unaries = rng.random((n, L))
+    allpairs = complete_edges(n)
+    if density >= 1.0:
+        edges = allpairs
+    else:
+        keep = rng.random(allpairs.shape[0]) < density
+        edges = np.ascontiguousarray(allpairs[keep])
+    m = edges.shape[0]
+    w = rng.uniform(0.1, 1.0, size=m)
+    noise = rng.uniform(0.0, 0.2, size=(m, L, L))
+    off = 1.0 - np.eye(L)
+    pairwise = w[:, None, None] * off[None] + noise
+    return Model(n, L, edges, unaries.astype(dtype), pairwise.astype(dtype),
+                 f"potts_er_n{n}_L{L}_p{density}_s{seed}")
+
+
+def batched_mix(count: int = 256, seed: int = 0, n_range=(20, 300), L_range=(8, 64),
+                dtype=np.float32, models: bool = True):
+    """Sizes (and, if ``models``, the models) of the batched pose-shaped mix.
+    Model i is ``pose(n_i, L_i, seed=1_000_003 * seed + i)``."""
+    rng = np.random.default_rng(seed)
+    ns = rng.integers(n_range[0], n_range[1] + 1, size=count)
+    Ls = rng.integers(L_range[0], L_range[1] + 1, size=count)
+    sizes = [(int(a), int(b)) for a, b in zip(ns, Ls)]
+    if not models:
+        return sizes
+    return [pose(n, L, seed=1_000_003 * seed + i, dtype=dtype) for i, (n, L) in enumerate(sizes)]
+
+
+def random_graph_model(n: int, L: int, density: float, seed: int = 0, dtype=np.float64,
+                       lo: float = 0.0, hi: float = 1.0) -> Model:
+    """Small random model on a G(n, p) graph with i.i.d. uniform costs (tests)."""
+    rng = np.random.default_rng(seed)
+    unaries = rng.uniform(lo, hi, size=(n, L))
+    allpairs = complete_edges(n)
+    keep = rng.random(allpairs.shape[0]) < density
+    edges = np.ascontiguousarray(allpairs[keep])
+    pairwise = rng.uniform(lo, hi, size=(edges.shape[0], L, L))
+    return Model(n, L, edges, unaries.astype(dtype), pairwise.astype(dtype), f"rg_n{n}_L{L}_p{density}_s{seed}")
+
+
+def chain(n: int, L: int, seed: int = 0, dtype=np.float64) -> Model:
+    rng = np.random.default_rng(seed)
+    unaries = rng.random((n, L))
+    edges = np.ascontiguousarray(np.stack([np.arange(n - 1), np.arange(1, n)], axis=1).astype(np.int32))
+    pairwise = rng.random((n - 1, L, L))
+    return Model(n, L, edges, unaries.astype(dtype), pairwise.astype(dtype), f"chain_n{n}_L{L}_s{seed}")
+
+
+# The five workloads the measurements and parity tests are quoted on.
+CONFIGS = {
+    "tiny_k8_l4_fp64": dict(kind="tiny", n=8, L=4, iters=200),
+    "pose_k200_l64": dict(kind="pose", n=200, L=64, iters=200),
+    "potts_er_n1000_l16": dict(kind="potts_er", n=1000, L=16, densities=(0.05, 0.25, 0.5, 1.0)),
+    "batched_pose_mix_256": dict(kind="batched_mix", count=256, iters=100),
+    "uniform_k100_l32_adjoint": dict(kind="uniform", n=100, L=32, K=50, every=10),
+}

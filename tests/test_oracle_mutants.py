@@ -1,0 +1,65 @@
+"""Plants plausible mistakes in a copy of the oracle's C source and checks
+that the pin tests catch every one of them.
+
+Each mutant is compiled with gcc into a temporary library and the pin tests
+run against it in a child process (``MPLP_ORACLE_LIB`` points the oracle's
+loader at the mutant).  A mutant that passes all pins means the pins have a
+hole; the test then fails and names the mutant.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "mplp_oracle.c")
+
+# (name, text in the oracle, replacement)
+MUTANTS = [
+    ("mplp half dropped on u", "hu[s] = 0.5 * mn;\n    }", "hu[s] = mn;\n    }"),
+    ("mplp half dropped on v", "hv[t] = 0.5 * mn;\n    }\n}", "hv[t] = mn;\n    }\n}"),
+    ("row min instead of column min", "for (int s = 0; s < L; ++s) mn = fmin(mn, g[(size_t)s * L + t]);\n        hv[t] = 0.5",
+     "for (int s = 0; s < L; ++s) mn = fmin(mn, g[(size_t)t * L + s]);\n        hv[t] = 0.5"),
+    ("v correction drops its base", "hv[t] = hv[t] + mn;", "hv[t] = mn;"),
+    ("u correction drops its base", "hu[s] = hu[s] + mn;", "hu[s] = mn;"),
+    ("u corrected before v", "/* (H), second line", "/* (H), second line */ for (int s = 0; s < L; ++s) { double mn = INFINITY; for (int t = 0; t < L; ++t) mn = fmin(mn, g[(size_t)s * L + t] - hv[t] - hu[s]); hu[s] = hu[s] + mn; } /*"),
+    ("wrong sign in write back", "- hu[s] - hv[t];", "- hu[s] + hv[t];"),
+    ("wrong index in aggregate", "+ Tu_u[s] + Tu_v[t];", "+ Tu_u[s] + Tu_v[s];"),
+    ("transposed table in aggregate", "g[(size_t)s * L + t] = Te[(size_t)s * L + t] + Tu_u[s]",
+     "g[(size_t)s * L + t] = Te[(size_t)t * L + s] + Tu_u[s]"),
+    ("uniform half dropped", "for (int t = 0; t < L; ++t) hv[t] = 0.5 * mn;", "for (int t = 0; t < L; ++t) hv[t] = mn;"),
+    ("dual drops edge terms", "for (size_t i = 0; i < (size_t)L * L; ++i) mn = fmin(mn, T[i]);\n        d += mn;",
+     "for (size_t i = 0; i < (size_t)L * L; ++i) mn = fmin(mn, T[i]);\n        d += 0.0 * mn;"),
+    ("dual uses max", "for (int s = 0; s < L; ++s) mn = fmin(mn, Tu[(size_t)u * L + s]);",
+     "for (int s = 0; s < L; ++s) mn = fmax(mn == INFINITY ? -INFINITY : mn, Tu[(size_t)u * L + s]);"),
+    ("decode transposed table", "cost[x] += row[x];", "cost[x] += Te[(size_t)e * L * L + (size_t)x * L + labels[v]];"),
+    ("decode ties to highest label", "if (cost[x] < cost[best]) best = x;", "if (cost[x] <= cost[best]) best = x;"),
+    ("decode ignores neighbours", "if (edges[2 * e + 1] != u) continue;", "continue;"),
+    ("energy transposed lookup", "(size_t)labels[u] * L + labels[v]];", "(size_t)labels[v] * L + labels[u]];"),
+    ("energy drops unaries", "for (int u = 0; u < n; ++u) en += unaries", "for (int u = 0; u < 0; ++u) en += unaries"),
+    ("circle method wrong partner", "b = ((r - k) % (N - 1)", "b = ((r - k + 1) % (N - 1)"),
+    ("greedy ignores the second node", "if (!busy[u] && !busy[v]) {", "if (!busy[u]) {"),
+    ("reversed input not transposed", "double x = (a < b) ? src[(size_t)s * L + t] : src[(size_t)t * L + s];",
+     "double x = src[(size_t)s * L + t];"),
+    ("duplicates accepted", "if (keys[e] == keys[e - 1]) { free(keys); return ORC_EINVAL; }", ""),
+    ("brute force skips labellings", "while (i < n && ++y[i] == L) y[i++] = 0;", "while (i < n && (y[i] += 2) >= L) y[i++] = 0;"),
+]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_mutant(tmp_path, name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation site not unique/present: {name}"
+    mut = src.replace(old, new)
+    c = tmp_path / "mut.c"
+    c.write_text(mut)
+    so = tmp_path / "libmut.so"
+    subprocess.run(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-o", str(so),
+                    str(c), "-lm"], check=True)
+    env = dict(os.environ, MPLP_ORACLE_LIB=str(so))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        "tests/test_oracle_pins.py", "tests/test_oracle_schedule.py"],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0, f"mutant '{name}' survived every pin:\n{r.stdout[-2000:]}"
