@@ -1,0 +1,187 @@
+/*
+ * mplpxx — MPLP++ dual block-coordinate ascent on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the solver library (libmplpxx.so).  All device work runs in the
+ * library's own HIP kernels.  Paper: Tourani, Shekhovtsov, Rother,
+ * Savchynskyy, "MPLP++: Fast, Parallel Dual Block-Coordinate Ascent for
+ * Dense Graphical Models", ECCV 2018.
+ *
+ * Model (Sec. 3, Eq. (1)): an undirected graph with n nodes and m edges,
+ * one label set {0..L-1} for all nodes, unary costs theta_u(s) and pairwise
+ * costs theta_uv(s, t).  The solver maximizes the dual lower bound of
+ * Eq. (3) over reparametrizations phi (Eq. (2)) by the handshake update (H)
+ * of Sec. 4, applied to every edge once per iteration, matching by matching
+ * (Sec. 6, Alg. 1).
+ *
+ * Conventions shared by every call:
+ *  - Return value: 0 on success, a negative MPLPXX_E* code on failure; the
+ *    text of the last failure on the calling thread is mplpxx_last_error().
+ *  - Handles are not thread-safe; use one handle per thread.
+ *  - "Host pointer" arguments are read or written before the call returns;
+ *    the caller keeps ownership.  "Device pointer" arguments must stay valid
+ *    for as long as the handle uses them (stated per call).
+ *  - Layouts are row-major and dense:
+ *      edges    int32  [m][2]   any order; (u, v) and (v, u) name the same
+ *                               edge; a table given for (v, u) is transposed
+ *                               internally so that rows always belong to the
+ *                               lower node index (Sec. 3 "Notation");
+ *      unaries  T      [n][L]   theta_u(s);
+ *      pairwise T      [m][L][L] theta_uv(s, t), row s = label of edges[e][0];
+ *    with T = float (MPLPXX_F32) or double (MPLPXX_F64).
+ *  - Solver state, in the order of the given edge list:
+ *      U        T      [n][L]   reparametrized unaries theta^phi_u (Eq. 2);
+ *      phi      T      [m][2][L] messages of edge e = (u, v), u < v:
+ *                               phi[e][0] = phi_{v->u} (into the lower
+ *                               node), phi[e][1] = phi_{u->v} (into the
+ *                               upper node); theta^phi_uv(s,t) =
+ *                               theta_uv(s,t) - phi[e][0][s] - phi[e][1][t].
+ *    The state starts at phi = 0, U = theta_u.
+ */
+#ifndef MPLPXX_H
+#define MPLPXX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* scalar types of costs and state */
+#define MPLPXX_F32 0
+#define MPLPXX_F64 1
+
+/* error codes */
+#define MPLPXX_OK 0
+#define MPLPXX_EINVAL (-1)   /* invalid argument or model */
+#define MPLPXX_ENOMEM (-2)   /* host or device allocation failed */
+#define MPLPXX_EDEVICE (-3)  /* a HIP call failed (text in mplpxx_last_error) */
+#define MPLPXX_ETIMEOUT (-4) /* a device-side wait exceeded its bound */
+#define MPLPXX_ESTATE (-5)   /* call not valid in the handle's current state */
+
+/* largest label count the kernels accept */
+#define MPLPXX_MAX_LABELS 128
+
+typedef struct mplpxx_solver mplpxx_solver;
+
+/* ------------------------------------------------------------------------
+ * Core calls.
+ * --------------------------------------------------------------------- */
+
+/* Creates a solver for one model (Sec. 3, Eq. (1)) from HOST pointers; the
+ * library copies everything to device memory.  Builds the edge schedule
+ * (Alg. 1, Sec. 6): the round-robin 1-factorization for a complete graph,
+ * greedy maximal matchings (remaining edges scanned in ascending (u, v)
+ * order) otherwise.  Initial state phi = 0, U = unaries.
+ * Errors: MPLPXX_EINVAL for n < 1, L < 1, L > MPLPXX_MAX_LABELS, m < 0,
+ * m > n(n-1)/2, an index out of [0, n), a self loop, a duplicate unordered
+ * pair, a non-finite cost, a NULL pointer (edges/pairwise may be NULL only
+ * when m == 0), an unknown dtype, or out == NULL; MPLPXX_ENOMEM;
+ * MPLPXX_EDEVICE.  On error *out is set to NULL. */
+int mplpxx_create(int32_t n, int32_t L, int64_t m, const int32_t* edges, const void* unaries,
+                  const void* pairwise, int32_t dtype, mplpxx_solver** out);
+
+/* Same as mplpxx_create, but unaries and pairwise are DEVICE pointers (for
+ * example torch tensor storage) in the same layout; edges stay on the host.
+ * The library copies the costs into its own layout before returning, so the
+ * device buffers may be reused afterwards.  The copy runs on the stream
+ * given (NULL = the default stream). */
+int mplpxx_create_device(int32_t n, int32_t L, int64_t m, const int32_t* edges, const void* unaries_dev,
+                         const void* pairwise_dev, int32_t dtype, void* hip_stream, mplpxx_solver** out);
+
+/* Runs k >= 0 full BCA-iterations (Sec. 5 "BCA-iteration"): every edge gets
+ * one (H) update, matching after matching.  Synchronous unless a stream was
+ * set with mplpxx_set_stream, in which case the work is queued on it and the
+ * value-returning calls below synchronize that stream.  MPLPXX_ETIMEOUT
+ * means a device wait exceeded its bound (the state is then undefined). */
+int mplpxx_iterate(mplpxx_solver* h, int32_t k);
+
+/* Dual lower bound D(phi) of Eq. (3) for the current state, recomputed from
+ * the input costs and the messages (node terms theta_u + sum of incoming
+ * messages, edge terms theta_uv - phi[e][0] - phi[e][1]) with FP64
+ * accumulation, written to the HOST pointer out. */
+int mplpxx_dual_bound(mplpxx_solver* h, double* out);
+
+/* Sequential primal rounding of Eq. (5) on the reparametrized costs: nodes
+ * in ascending index order, each takes the label minimizing its
+ * reparametrized unary plus the reparametrized pairwise terms to its
+ * already-labelled lower neighbours (sums in FP64, ties to the smallest
+ * label).  labels: HOST int32 [n].  energy (HOST, may be NULL): Eq. (1) of
+ * that labelling on the original costs, accumulated in FP64. */
+int mplpxx_decode(mplpxx_solver* h, int32_t* labels, double* energy);
+
+/* Frees the handle and all its device memory; NULL is a no-op.  Waits for
+ * queued work on the handle's stream first. */
+void mplpxx_destroy(mplpxx_solver* h);
+
+/* Static text for an error code. */
+const char* mplpxx_error_string(int code);
+
+/* Text of the last failure on the calling thread ("" if none). */
+const char* mplpxx_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Extensions (streams, schedule, state, traces, tuning).
+ * --------------------------------------------------------------------- */
+
+/* Sets the HIP stream (a hipStream_t, e.g. torch.cuda.current_stream()
+ * .cuda_stream) the handle queues its work on; NULL restores the library's
+ * synchronous default. */
+int mplpxx_set_stream(mplpxx_solver* h, void* hip_stream);
+
+/* Copies the schedule of Alg. 1 to HOST buffers: step_ptr int32 [S+1] and
+ * order int32 [m] (edge indices of the input list, matching by matching,
+ * each matching in ascending (u, v) order).  Pass NULL buffers to query S
+ * alone through n_steps. */
+int mplpxx_get_schedule(mplpxx_solver* h, int32_t* n_steps, int32_t* step_ptr, int32_t* order);
+
+/* Host-only (no device work, usable without a GPU): the schedule that
+ * mplpxx_create would build for this graph (Alg. 1, Sec. 6; see
+ * mplpxx_create).  edges: HOST int32 [m][2].  step_ptr needs m + 1 entries
+ * and order m entries; pass NULL for both to query only n_steps.  Errors:
+ * MPLPXX_EINVAL for the graph errors listed under mplpxx_create. */
+int mplpxx_schedule(int32_t n, int64_t m, const int32_t* edges, int32_t* n_steps, int32_t* step_ptr,
+                    int32_t* order);
+
+/* Copies the state (U [n][L], phi [m][2][L], see above) to / from HOST
+ * buffers of the handle's dtype.  Either pointer may be NULL to skip it. */
+int mplpxx_get_state(mplpxx_solver* h, void* U, void* phi);
+int mplpxx_set_state(mplpxx_solver* h, const void* U, const void* phi);
+
+/* Same as mplpxx_iterate, and writes to the HOST buffer trace[k] the value
+ * sum_u min_s U_u(s) after every iteration, accumulated in FP64.  After an
+ * edge's (H) update its reparametrized pairwise term has minimum zero
+ * (Sec. 4, after (H)), so once every edge has been updated this sum equals
+ * the dual bound of Eq. (3) up to rounding. */
+int mplpxx_iterate_trace(mplpxx_solver* h, int32_t k, double* trace);
+
+/* Tuning options (never change results: every option gives bitwise the same
+ * state, because each entry of a pass is one IEEE add followed by an exact,
+ * order-free minimum). */
+#define MPLPXX_OPT_ENGINE 1      /* 0 auto, 1 one launch per matching, 2 persistent */
+#define MPLPXX_OPT_THREADS 2     /* threads per workgroup: 0 auto, 256, 512, 1024 */
+#define MPLPXX_OPT_GRID 3        /* workgroups of the persistent engine (0 auto) */
+#define MPLPXX_OPT_SPIN_LIMIT 4  /* device wait bound in polls (0 default) */
+int mplpxx_set_option(mplpxx_solver* h, int32_t key, int64_t value);
+
+/* Read-only facts about the handle. */
+#define MPLPXX_INFO_N 1
+#define MPLPXX_INFO_L 2
+#define MPLPXX_INFO_M 3
+#define MPLPXX_INFO_STEPS 4
+#define MPLPXX_INFO_DTYPE 5
+#define MPLPXX_INFO_ENGINE 6     /* engine the next iterate call will use */
+#define MPLPXX_INFO_GRID 7       /* workgroups of the persistent engine */
+#define MPLPXX_INFO_THREADS 8    /* threads per workgroup */
+#define MPLPXX_INFO_ITERATIONS 9 /* iterations run since create / set_state */
+int mplpxx_get_info(mplpxx_solver* h, int32_t key, int64_t* value);
+
+/* Average duration in milliseconds of the device work of the last iterate
+ * call, measured with HIP events on the handle's stream around the launch
+ * (0 if none). */
+int mplpxx_last_iterate_ms(mplpxx_solver* h, double* ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPLPXX_H */

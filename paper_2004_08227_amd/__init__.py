@@ -1,0 +1,234 @@
+"""mplpxx — MPLP++ dual block-coordinate ascent on AMD MI355X (gfx950).
+
+Thin ctypes binding of ``libmplpxx.so`` (C ABI in ``include/mplpxx.h``).  The
+binding only marshals arguments: every step of the solver runs in the
+library's HIP kernels.  PyTorch is used only to hand over device memory and
+streams (``Solver.from_torch``).  There is no CPU fallback: if the library is
+not built, every call raises.
+
+Paper: Tourani et al., "MPLP++: Fast, Parallel Dual Block-Coordinate Ascent
+for Dense Graphical Models", ECCV 2018.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmplpxx.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "mplpxx.h")
+
+F32, F64 = 0, 1
+OK, EINVAL, ENOMEM, EDEVICE, ETIMEOUT, ESTATE = 0, -1, -2, -3, -4, -5
+MAX_LABELS = 128
+OPT_ENGINE, OPT_THREADS, OPT_GRID, OPT_SPIN_LIMIT = 1, 2, 3, 4
+ENGINE_AUTO, ENGINE_STEP, ENGINE_PERSISTENT = 0, 1, 2
+INFO = {"n": 1, "L": 2, "m": 3, "steps": 4, "dtype": 5, "engine": 6, "grid": 7, "threads": 8, "iterations": 9}
+
+_lib = None
+
+
+class MplpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mplpxx error {code}: {msg}")
+        self.code = code
+
+
+def header_symbols():
+    """Names of the functions declared in include/mplpxx.h."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(mplpxx_[a-z_0-9]+)\s*\(", text)))
+
+
+def lib():
+    """Loads libmplpxx.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build() "
+                           "or python paper_2004_08227_amd/build.py")
+    try:
+        # load PyTorch's HIP runtime first: the library then binds to the same
+        # runtime (same soname), so device pointers and streams can be shared
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    sig = {
+        "mplpxx_create": (ctypes.c_int, [i32, i32, i64, vp, vp, vp, i32, pp]),
+        "mplpxx_create_device": (ctypes.c_int, [i32, i32, i64, vp, vp, vp, i32, vp, pp]),
+        "mplpxx_iterate": (ctypes.c_int, [vp, i32]),
+        "mplpxx_iterate_trace": (ctypes.c_int, [vp, i32, vp]),
+        "mplpxx_dual_bound": (ctypes.c_int, [vp, ctypes.POINTER(dbl)]),
+        "mplpxx_decode": (ctypes.c_int, [vp, vp, ctypes.POINTER(dbl)]),
+        "mplpxx_destroy": (None, [vp]),
+        "mplpxx_error_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "mplpxx_last_error": (ctypes.c_char_p, []),
+        "mplpxx_set_stream": (ctypes.c_int, [vp, vp]),
+        "mplpxx_get_schedule": (ctypes.c_int, [vp, vp, vp, vp]),
+        "mplpxx_get_state": (ctypes.c_int, [vp, vp, vp]),
+        "mplpxx_schedule": (ctypes.c_int, [i32, i64, vp, vp, vp, vp]),
+        "mplpxx_set_state": (ctypes.c_int, [vp, vp, vp]),
+        "mplpxx_set_option": (ctypes.c_int, [vp, i32, i64]),
+        "mplpxx_get_info": (ctypes.c_int, [vp, i32, ctypes.POINTER(i64)]),
+        "mplpxx_last_iterate_ms": (ctypes.c_int, [vp, ctypes.POINTER(dbl)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != 0:
+        raise MplpError(rc, lib().mplpxx_last_error().decode())
+
+
+def _ptr(a):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+def schedule(n, edges):
+    """Host-only schedule of Alg. 1 for a graph: (step_ptr [S+1], order [m])."""
+    edges = np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
+    m = edges.shape[0]
+    S = ctypes.c_int32()
+    sp = np.zeros(m + 1, dtype=np.int32)
+    order = np.zeros(max(m, 1), dtype=np.int32)
+    _check(lib().mplpxx_schedule(int(n), int(m), _ptr(edges) if m else None, ctypes.byref(S), _ptr(sp), _ptr(order)))
+    return sp[:S.value + 1].copy(), order[:m].copy()
+
+
+class Solver:
+    """One model: ``Solver(n, L, edges, unaries, pairwise)`` with host numpy
+    arrays (float32 or float64), or ``Solver.from_torch`` with device tensors."""
+
+    def __init__(self, n, L, edges, unaries, pairwise, dtype=None, _handle=None):
+        self._h = None
+        if _handle is not None:
+            self._h = _handle
+        else:
+            if dtype is None:
+                dtype = np.asarray(unaries).dtype
+            dt = np.dtype(dtype)
+            if dt not in (np.float32, np.float64):
+                raise ValueError("dtype must be float32 or float64")
+            edges = np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
+            m = edges.shape[0]
+            un = np.ascontiguousarray(unaries, dtype=dt)
+            pw = np.ascontiguousarray(pairwise, dtype=dt)
+            if un.size != n * L or pw.size != m * L * L:
+                raise ValueError("unaries must hold n*L and pairwise m*L*L values")
+            h = ctypes.c_void_p()
+            _check(lib().mplpxx_create(int(n), int(L), int(m), _ptr(edges) if m else None, _ptr(un),
+                                       _ptr(pw) if m else None, F32 if dt == np.float32 else F64,
+                                       ctypes.byref(h)))
+            self._h = h
+        self.n = self.info("n")
+        self.L = self.info("L")
+        self.m = self.info("m")
+        self.dtype = np.float32 if self.info("dtype") == F32 else np.float64
+
+    @classmethod
+    def from_model(cls, model):
+        return cls(model.n, model.L, model.edges, model.unaries, model.pairwise)
+
+    @classmethod
+    def from_torch(cls, n, L, edges, unaries, pairwise, stream=None):
+        """unaries [n, L] and pairwise [m, L, L]: contiguous float32/float64
+        torch tensors on the GPU; edges: host int32 [m, 2]."""
+        import torch  # noqa: F401  (device memory and streams only)
+        edges = np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
+        m = edges.shape[0]
+        assert unaries.is_cuda and unaries.is_contiguous() and pairwise.is_contiguous()
+        assert unaries.numel() == n * L and pairwise.numel() == m * L * L
+        dt = F32 if str(unaries.dtype) == "torch.float32" else F64
+        h = ctypes.c_void_p()
+        st = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
+        _check(lib().mplpxx_create_device(int(n), int(L), int(m), _ptr(edges) if m else None,
+                                          ctypes.c_void_p(unaries.data_ptr()),
+                                          ctypes.c_void_p(pairwise.data_ptr()) if m else None, dt, st,
+                                          ctypes.byref(h)))
+        return cls(n, L, None, None, None, _handle=h)
+
+    # ------------------------------------------------------------------
+    def close(self):
+        if self._h is not None:
+            lib().mplpxx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # ------------------------------------------------------------------
+    def iterate(self, k=1):
+        _check(lib().mplpxx_iterate(self._h, int(k)))
+
+    def iterate_trace(self, k):
+        tr = np.zeros(max(int(k), 1), dtype=np.float64)
+        _check(lib().mplpxx_iterate_trace(self._h, int(k), _ptr(tr)))
+        return tr[:k]
+
+    def dual_bound(self):
+        d = ctypes.c_double()
+        _check(lib().mplpxx_dual_bound(self._h, ctypes.byref(d)))
+        return d.value
+
+    def decode(self):
+        labels = np.zeros(self.n, dtype=np.int32)
+        e = ctypes.c_double()
+        _check(lib().mplpxx_decode(self._h, _ptr(labels), ctypes.byref(e)))
+        return labels, e.value
+
+    def schedule(self):
+        S = ctypes.c_int32()
+        _check(lib().mplpxx_get_schedule(self._h, ctypes.byref(S), None, None))
+        sp = np.zeros(S.value + 1, dtype=np.int32)
+        order = np.zeros(max(self.m, 1), dtype=np.int32)
+        _check(lib().mplpxx_get_schedule(self._h, None, _ptr(sp), _ptr(order)))
+        return sp, order[:self.m]
+
+    def get_state(self):
+        U = np.zeros((self.n, self.L), dtype=self.dtype)
+        phi = np.zeros((self.m, 2, self.L), dtype=self.dtype)
+        _check(lib().mplpxx_get_state(self._h, _ptr(U), _ptr(phi) if self.m else None))
+        return U, phi
+
+    def set_state(self, U=None, phi=None):
+        U = None if U is None else np.ascontiguousarray(U, dtype=self.dtype).reshape(self.n, self.L)
+        phi = None if phi is None else np.ascontiguousarray(phi, dtype=self.dtype).reshape(self.m, 2, self.L)
+        _check(lib().mplpxx_set_state(self._h, _ptr(U), _ptr(phi)))
+
+    def set_option(self, key, value):
+        _check(lib().mplpxx_set_option(self._h, int(key), int(value)))
+
+    def set_stream(self, stream):
+        """stream: a torch.cuda.Stream (or None for the library default)."""
+        _check(lib().mplpxx_set_stream(self._h, None if stream is None else ctypes.c_void_p(stream.cuda_stream)))
+
+    def info(self, key):
+        v = ctypes.c_int64()
+        _check(lib().mplpxx_get_info(self._h, INFO[key], ctypes.byref(v)))
+        return v.value
+
+    def last_iterate_ms(self):
+        d = ctypes.c_double()
+        _check(lib().mplpxx_last_iterate_ms(self._h, ctypes.byref(d)))
+        return d.value

@@ -1,0 +1,58 @@
+// Internal declarations shared by the host runtime and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mplpxx.h"
+
+namespace mplpxx {
+
+enum { ENGINE_AUTO = 0, ENGINE_STEP = 1, ENGINE_PERSISTENT = 2 };
+
+// One entry per schedule slot (slot i = i-th edge of the schedule queue).
+struct SlotInfo {
+  int e;       // index of the edge in the caller's edge list
+  int u, v;    // its nodes, u < v
+  int pos_u;   // number of edges of u that precede this one in the queue
+  int pos_v;   // same for v
+  int pad0, pad1, pad2;
+};
+
+template <typename T> struct HsArgs {
+  const T* tables;        // [m][L][L] slot order, read-only
+  T* phi;                 // [m][2][L] slot order
+  T* U;                   // [n][L]
+  const SlotInfo* slots;  // [m]
+  const int* deg;         // [n]
+  int* ver;               // [n] per-node update counters (persistent engine)
+  int* err;               // device error word
+  double* trace;          // [iters][n] per-node minima after the node's last update, or null
+  int L, m, n;
+  long long spin_limit;
+};
+
+template <typename T>
+hipError_t launch_handshake(const HsArgs<T>& a, int engine, int LT, int NT, int slot_begin, int count, int grid,
+                            int iters, hipStream_t st);
+template <typename T> int max_blocks_per_cu(int engine, int LT, int NT);
+
+// dual bound, traces, decode (dual.hip)
+template <typename T>
+hipError_t launch_dual(const T* unaries, const T* tables, const T* phi, const int* node_ptr, const int* inc, int n,
+                       int L, int m, double* node_min, double* edge_min, double* out, hipStream_t st);
+template <typename T>
+hipError_t launch_trace_nodes(const T* U, int n, int L, double* row, hipStream_t st);
+template <typename T>
+hipError_t launch_trace_sum(double* trace_nodes, const T* U, const int* deg, int n, int L, int iters, double* out,
+                            hipStream_t st);
+template <typename T>
+hipError_t launch_decode(const T* unaries, const T* tables, const T* phi, const SlotInfo* slots, const int* node_ptr,
+                         const int* inc, int n, int L, int m, int* labels, double* energy, hipStream_t st);
+template <typename T>
+hipError_t launch_check_finite(const T* p, size_t count, int* flag, hipStream_t st);
+template <typename T>
+hipError_t launch_pack_tables(const T* src, T* dst, const int* slot_edge, const int* slot_flip, int m, int L,
+                              hipStream_t st);
+hipError_t launch_fill_int(int* p, int value, size_t count, hipStream_t st);
+
+}  // namespace mplpxx

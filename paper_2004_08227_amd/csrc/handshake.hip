@@ -1,0 +1,403 @@
+// Handshake (H) edge-block update of MPLP++ on gfx950.
+//
+// Paper: Tourani et al., "MPLP++: Fast, Parallel Dual Block-Coordinate Ascent
+// for Dense Graphical Models", ECCV 2018, Sec. 4 (updates (M), (H) and the
+// "message passing" subroutine) and Sec. 6 (parallel processing of the edges
+// of one matching, a barrier between consecutive matchings).
+//
+// State kept per model (all device memory):
+//   tables  [m][L][L]  input pairwise costs, read-only, packed in schedule
+//                      order (slot i holds edge order[i]);
+//   phi     [m][2][L]  messages of the edge in slot i: phi[i][0] into the
+//                      lower node u, phi[i][1] into the upper node v;
+//   U       [n][L]     reparametrized unaries theta^phi_u.
+//
+// One (H) update of edge (u, v) with original table th.  The aggregated cost
+// of Sec. 4 is g(s,t) = th(s,t) + a_u(s) + a_v(t) with a_u = U_u - phi[0] and
+// a_v = U_v - phi[1].  Evaluating (H) on g with the three-minimization form
+// the paper gives right after (H):
+//   p(s) = min_t [th(s,t) + a_v(t)]           MPLP half for u: (a_u + p) / 2
+//   b(s) = (a_u(s) - p(s)) / 2                so that a_u - theta^H_u = b
+//   q(t) = min_s [th(s,t) + b(s)]             theta^H_v = a_v + q
+//   r(s) = min_t [th(s,t) - q(t)]             theta^H_u = a_u + r
+//   phi[1] := q, phi[0] := r, U_v := a_v + q, U_u := a_u + r.
+// Each pass is the paper's message-passing primitive min_t [th(s,t) + x(t)]
+// with the table fixed, so the tables are never written.
+//
+// Work mapping: one workgroup per edge update.  The L x L table (padded to
+// an LT x LT tile, pads = +inf) lives in registers as a grid of
+// RB x 16 thread blocks; thread (rb, cb) holds rows rb*BR .. rb*BR+BR-1 and
+// columns cb*BC .. cb*BC+BC-1.  Row minima reduce across the 16 lanes of a
+// DPP row, column minima across the RB row blocks (lanes 16 and 32 apart,
+// then across waves through LDS).  Every entry of a pass is one IEEE add
+// followed by an exact minimum, so results do not depend on LT, NT, the
+// reduction tree or the engine.
+#include "common.h"
+
+namespace mplpxx {
+
+template <typename T> __device__ __forceinline__ T inf_v();
+template <> __device__ __forceinline__ float inf_v<float>() { return __builtin_inff(); }
+template <> __device__ __forceinline__ double inf_v<double>() { return __builtin_inf(); }
+
+__device__ __forceinline__ float vmin(float a, float b) { return __builtin_fminf(a, b); }
+__device__ __forceinline__ double vmin(double a, double b) { return __builtin_fmin(a, b); }
+
+// minimum over the 16 lanes of a row (lanes 16k .. 16k+15), result in all 16
+template <typename T> __device__ __forceinline__ T row16_min(T x) {
+  x = vmin(x, __shfl_xor(x, 1, 16));
+  x = vmin(x, __shfl_xor(x, 2, 16));
+  x = vmin(x, __shfl_xor(x, 4, 16));
+  x = vmin(x, __shfl_xor(x, 8, 16));
+  return x;
+}
+
+// minimum over lanes l, l^16, l^32, l^48 (the 4 row blocks of one wave)
+template <typename T> __device__ __forceinline__ T col4_min(T x) {
+  x = vmin(x, __shfl_xor(x, 16, 64));
+  x = vmin(x, __shfl_xor(x, 32, 64));
+  return x;
+}
+
+// coherent (device-scope) accesses for data shared between workgroups
+__device__ __forceinline__ int ld_dev(const int* p) {
+  return __hip_atomic_load(const_cast<int*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(int* p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T> __device__ __forceinline__ T ldv_dev(const T* p) {
+  return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T> __device__ __forceinline__ void stv_dev(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// wait until this wave's memory operations have completed
+__device__ __forceinline__ void wait_vmem() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+template <typename T, int LT, int NT> struct TileShape {
+  static constexpr int RB = NT / 16;   // row blocks
+  static constexpr int BR = LT / RB;   // rows per thread
+  static constexpr int BC = LT / 16;   // columns per thread
+  static constexpr int W = NT / 64;    // waves
+  static_assert(BR >= 1 && BC >= 1 && RB * BR == LT, "tile shape");
+};
+
+// Loads the table of one slot into the register tile; pads are +inf.
+template <typename T, int LT, int NT>
+__device__ __forceinline__ void load_tile(const T* __restrict__ tab, int L, T (&x)[TileShape<T, LT, NT>::BR][TileShape<T, LT, NT>::BC]) {
+  using S = TileShape<T, LT, NT>;
+  const int tid = threadIdx.x;
+  const int rb = tid >> 4, cb = tid & 15;
+  if (L == LT && (S::BC % 4) == 0 && sizeof(T) == 4) {
+    // full tile, 16-byte aligned rows: vector loads
+#pragma unroll
+    for (int i = 0; i < S::BR; ++i) {
+      const int s = rb * S::BR + i;
+#pragma unroll
+      for (int j = 0; j < S::BC; j += 4) {
+        const float4 v = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(tab) + s * LT + cb * S::BC + j);
+        x[i][j] = v.x;
+        x[i][j + 1] = v.y;
+        x[i][j + 2] = v.z;
+        x[i][j + 3] = v.w;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < S::BR; ++i) {
+      const int s = rb * S::BR + i;
+#pragma unroll
+      for (int j = 0; j < S::BC; ++j) {
+        const int t = cb * S::BC + j;
+        x[i][j] = (s < L && t < L) ? tab[s * L + t] : inf_v<T>();
+      }
+    }
+  }
+}
+
+template <typename T, int LT, int NT> struct Smem {
+  T au[LT];
+  T av[LT];
+  T red[TileShape<T, LT, NT>::W][LT];
+  T nu[LT];
+  T nv[LT];
+  int abort_flag;
+};
+
+// The three passes on a register tile; a_u / a_v must be in smem.  Writes
+// the new messages and unaries to global memory (coherent stores when
+// `shared_nodes`).  Returns after all writes of this workgroup completed.
+template <typename T, int LT, int NT, bool kCoherent>
+__device__ __forceinline__ void handshake_passes(const T (&x)[TileShape<T, LT, NT>::BR][TileShape<T, LT, NT>::BC],
+                                                 Smem<T, LT, NT>& sm, int L, T* __restrict__ phi_slot,
+                                                 T* __restrict__ Uu, T* __restrict__ Uv, bool keep_new) {
+  using S = TileShape<T, LT, NT>;
+  const int tid = threadIdx.x;
+  const int rb = tid >> 4, cb = tid & 15;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+
+  T av[S::BC];
+#pragma unroll
+  for (int j = 0; j < S::BC; ++j) {
+    const int t = cb * S::BC + j;
+    av[j] = (t < L) ? sm.av[t] : T(0);
+  }
+  // pass 1: p(s) = min_t [th(s,t) + a_v(t)],  b(s) = (a_u(s) - p(s)) / 2
+  T b[S::BR];
+#pragma unroll
+  for (int i = 0; i < S::BR; ++i) {
+    T mn = x[i][0] + av[0];
+#pragma unroll
+    for (int j = 1; j < S::BC; ++j) mn = vmin(mn, x[i][j] + av[j]);
+    mn = row16_min(mn);
+    const int s = rb * S::BR + i;
+    b[i] = (s < L) ? T(0.5) * (sm.au[s] - mn) : T(0);
+  }
+  // pass 2: q(t) = min_s [th(s,t) + b(s)]
+  T q[S::BC];
+#pragma unroll
+  for (int j = 0; j < S::BC; ++j) {
+    T mn = x[0][j] + b[0];
+#pragma unroll
+    for (int i = 1; i < S::BR; ++i) mn = vmin(mn, x[i][j] + b[i]);
+    mn = col4_min(mn);
+    q[j] = mn;
+  }
+  if constexpr (S::W > 1) {
+    if (lane < 16) {
+#pragma unroll
+      for (int j = 0; j < S::BC; ++j) sm.red[wave][cb * S::BC + j] = q[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < S::BC; ++j) {
+      const int t = cb * S::BC + j;
+      T mn = sm.red[0][t];
+#pragma unroll
+      for (int w = 1; w < S::W; ++w) mn = vmin(mn, sm.red[w][t]);
+      q[j] = mn;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < S::BC; ++j) {
+    const int t = cb * S::BC + j;
+    if (t >= L) q[j] = T(0);
+  }
+  // pass 3: r(s) = min_t [th(s,t) - q(t)]
+  T r[S::BR];
+#pragma unroll
+  for (int i = 0; i < S::BR; ++i) {
+    T mn = x[i][0] - q[0];
+#pragma unroll
+    for (int j = 1; j < S::BC; ++j) mn = vmin(mn, x[i][j] - q[j]);
+    r[i] = row16_min(mn);
+  }
+  // push back: phi[1] = q, U_v = a_v + q (threads of row block 0);
+  //            phi[0] = r, U_u = a_u + r (threads of column block 0)
+  if (rb == 0) {
+#pragma unroll
+    for (int j = 0; j < S::BC; ++j) {
+      const int t = cb * S::BC + j;
+      if (t < L) {
+        const T nvv = av[j] + q[j];
+        phi_slot[L + t] = q[j];
+        if (kCoherent) stv_dev(Uv + t, nvv); else Uv[t] = nvv;
+        if (keep_new) sm.nv[t] = nvv;
+      }
+    }
+  }
+  if (cb == 0) {
+#pragma unroll
+    for (int i = 0; i < S::BR; ++i) {
+      const int s = rb * S::BR + i;
+      if (s < L) {
+        const T nuu = sm.au[s] + r[i];
+        phi_slot[s] = r[i];
+        if (kCoherent) stv_dev(Uu + s, nuu); else Uu[s] = nuu;
+        if (keep_new) sm.nu[s] = nuu;
+      }
+    }
+  }
+  if (kCoherent) wait_vmem();
+  __syncthreads();
+}
+
+// a_u = U_u - phi[0], a_v = U_v - phi[1] into smem (wave 0 gathers u, wave 1 v
+// when there are two waves)
+template <typename T, int LT, int NT, bool kCoherent>
+__device__ __forceinline__ void gather(Smem<T, LT, NT>& sm, int L, const T* __restrict__ phi_slot, const T* Uu,
+                                       const T* Uv) {
+  const int tid = threadIdx.x;
+  for (int s = tid; s < 2 * LT; s += NT) {
+    if (s < LT) {
+      if (s < L) sm.au[s] = (kCoherent ? ldv_dev(Uu + s) : Uu[s]) - phi_slot[s];
+    } else {
+      const int t = s - LT;
+      if (t < L) sm.av[t] = (kCoherent ? ldv_dev(Uv + t) : Uv[t]) - phi_slot[L + t];
+    }
+  }
+  __syncthreads();
+}
+
+// min over the L entries of sm.nu / sm.nv in FP64 (wave `w` of the block),
+// written by its lane 0
+template <typename T, int LT, int NT>
+__device__ __forceinline__ void node_min_to(const T* v, int L, double* out) {
+  const int lane = threadIdx.x & 63;
+  double mn = __builtin_inf();
+  for (int s = lane; s < L; s += 64) mn = __builtin_fmin(mn, (double)v[s]);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) mn = __builtin_fmin(mn, __shfl_xor(mn, o, 64));
+  if (lane == 0) *out = mn;
+}
+
+// ---------------------------------------------------------------------------
+// Engine 1: one launch per matching.  Grid = edges of the matching.  Kernel
+// boundaries order the matchings (the paper's barrier between matchings).
+// ---------------------------------------------------------------------------
+template <typename T, int LT, int NT>
+__global__ void __launch_bounds__(NT) k_step(HsArgs<T> a, int slot_begin) {
+  using S = TileShape<T, LT, NT>;
+  __shared__ Smem<T, LT, NT> sm;
+  const int slot = slot_begin + blockIdx.x;
+  const SlotInfo si = a.slots[slot];
+  const int L = a.L;
+  T x[S::BR][S::BC];
+  load_tile<T, LT, NT>(a.tables + (size_t)slot * L * L, L, x);
+  T* phi_slot = a.phi + (size_t)slot * 2 * L;
+  T* Uu = a.U + (size_t)si.u * L;
+  T* Uv = a.U + (size_t)si.v * L;
+  gather<T, LT, NT, false>(sm, L, phi_slot, Uu, Uv);
+  handshake_passes<T, LT, NT, false>(x, sm, L, phi_slot, Uu, Uv, false);
+}
+
+// ---------------------------------------------------------------------------
+// Engine 2: persistent.  Workgroup w owns the slots w, w+G, w+2G, ... (a
+// static map, so an edge's messages never leave one workgroup) and visits
+// them in schedule order for every iteration.  Before updating edge (u, v) it
+// waits until u and v have seen exactly the updates that precede this one in
+// the schedule (per-node version counters); afterwards it publishes the new
+// unaries and bumps both versions.  This is the paper's barrier between
+// matchings reduced to the two nodes an edge depends on.
+// ---------------------------------------------------------------------------
+template <typename T, int LT, int NT>
+__global__ void __launch_bounds__(NT) k_persistent(HsArgs<T> a, int iters) {
+  using S = TileShape<T, LT, NT>;
+  __shared__ Smem<T, LT, NT> sm;
+  const int tid = threadIdx.x;
+  const int L = a.L;
+  const int G = gridDim.x;
+  if (tid == 0) sm.abort_flag = 0;
+  __syncthreads();
+  int slot = blockIdx.x;
+  if (slot >= a.m) return;
+  T x[S::BR][S::BC];
+  load_tile<T, LT, NT>(a.tables + (size_t)slot * L * L, L, x);
+  for (int it = 0; it < iters; ++it) {
+    for (slot = blockIdx.x; slot < a.m; slot += G) {
+      const SlotInfo si = a.slots[slot];
+      // wait for the two nodes (thread 0: u, thread 64 or 1: v)
+      const int waiter_v = (NT >= 128) ? 64 : 1;
+      if (tid == 0 || tid == waiter_v) {
+        const int node = (tid == 0) ? si.u : si.v;
+        const int want = it * a.deg[node] + ((tid == 0) ? si.pos_u : si.pos_v);
+        long long spins = 0;
+        while (ld_dev(a.ver + node) < want) {
+          if (++spins > a.spin_limit || ((spins & 1023) == 0 && ld_dev(a.err) != 0)) {
+            atomicCAS(a.err, 0, MPLPXX_ETIMEOUT);
+            sm.abort_flag = 1;
+            break;
+          }
+        }
+      }
+      __syncthreads();
+      if (sm.abort_flag) return;
+      T* phi_slot = a.phi + (size_t)slot * 2 * L;
+      T* Uu = a.U + (size_t)si.u * L;
+      T* Uv = a.U + (size_t)si.v * L;
+      gather<T, LT, NT, true>(sm, L, phi_slot, Uu, Uv);
+      const bool last_u = a.trace && si.pos_u == a.deg[si.u] - 1;
+      const bool last_v = a.trace && si.pos_v == a.deg[si.v] - 1;
+      handshake_passes<T, LT, NT, true>(x, sm, L, phi_slot, Uu, Uv, last_u || last_v);
+      if (tid == 0) {
+        st_dev(a.ver + si.u, it * a.deg[si.u] + si.pos_u + 1);
+        st_dev(a.ver + si.v, it * a.deg[si.v] + si.pos_v + 1);
+      }
+      // next table of this workgroup (the same slot again in the next
+      // iteration when it owns a single slot)
+      int nxt = slot + G;
+      if (nxt >= a.m) nxt = blockIdx.x;
+      if (nxt != slot && (it + 1 < iters || nxt > slot)) load_tile<T, LT, NT>(a.tables + (size_t)nxt * L * L, L, x);
+      if (last_u && (tid >> 6) == 0) node_min_to<T, LT, NT>(sm.nu, L, a.trace + (size_t)it * a.n + si.u);
+      if (last_v && (tid >> 6) == (S::W > 1 ? 1 : 0)) node_min_to<T, LT, NT>(sm.nv, L, a.trace + (size_t)it * a.n + si.v);
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+template <typename T, int LT, int NT>
+static hipError_t launch_one(const HsArgs<T>& a, int engine, int slot_begin, int count, int grid, int iters,
+                             hipStream_t st) {
+  if (engine == ENGINE_STEP) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_step<T, LT, NT>), dim3(count), dim3(NT), 0, st, a, slot_begin);
+    return hipGetLastError();
+  }
+  void* args[] = {(void*)&a, (void*)&iters};
+  return hipLaunchCooperativeKernel((const void*)k_persistent<T, LT, NT>, dim3(grid), dim3(NT), args, 0, st);
+}
+
+template <typename T>
+hipError_t launch_handshake(const HsArgs<T>& a, int engine, int LT, int NT, int slot_begin, int count, int grid,
+                            int iters, hipStream_t st) {
+#define MPLPXX_CASE(lt, nt) \
+  if (LT == lt && NT == nt) return launch_one<T, lt, nt>(a, engine, slot_begin, count, grid, iters, st);
+  MPLPXX_CASE(16, 256)
+  MPLPXX_CASE(32, 256)
+  MPLPXX_CASE(32, 512)
+  MPLPXX_CASE(64, 256)
+  MPLPXX_CASE(64, 512)
+  MPLPXX_CASE(64, 1024)
+  MPLPXX_CASE(128, 256)
+  MPLPXX_CASE(128, 512)
+  MPLPXX_CASE(128, 1024)
+#undef MPLPXX_CASE
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+int max_blocks_per_cu(int engine, int LT, int NT) {
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+#define MPLPXX_CASE(lt, nt)                                                                           \
+  if (LT == lt && NT == nt)                                                                           \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(                                                 \
+        &nb, engine == ENGINE_STEP ? (const void*)k_step<T, lt, nt> : (const void*)k_persistent<T, lt, nt>, nt, 0);
+  MPLPXX_CASE(16, 256)
+  MPLPXX_CASE(32, 256)
+  MPLPXX_CASE(32, 512)
+  MPLPXX_CASE(64, 256)
+  MPLPXX_CASE(64, 512)
+  MPLPXX_CASE(64, 1024)
+  MPLPXX_CASE(128, 256)
+  MPLPXX_CASE(128, 512)
+  MPLPXX_CASE(128, 1024)
+#undef MPLPXX_CASE
+  return e == hipSuccess ? nb : 0;
+}
+
+template hipError_t launch_handshake<float>(const HsArgs<float>&, int, int, int, int, int, int, int, hipStream_t);
+template hipError_t launch_handshake<double>(const HsArgs<double>&, int, int, int, int, int, int, int, hipStream_t);
+template int max_blocks_per_cu<float>(int, int, int);
+template int max_blocks_per_cu<double>(int, int, int);
+
+}  // namespace mplpxx

@@ -1,0 +1,638 @@
+// Host runtime of the MPLP++ solver library: the C ABI of include/mplpxx.h.
+//
+// create  -> validate, orient edges u < v (Sec. 3 "Notation"), build the
+//            schedule (Alg. 1, Sec. 6), pack the tables in schedule order,
+//            copy everything to device memory, start from phi = 0;
+// iterate -> BCA-iterations (Sec. 5) with the handshake update (H) of Sec. 4
+//            on the device, one of two engines:
+//              step        one kernel per matching (kernel boundaries are the
+//                          paper's barrier between matchings);
+//              persistent  one cooperative kernel per call; a workgroup waits
+//                          only for the two nodes of its next edge;
+// dual    -> Eq. (3) recomputed from costs and messages in FP64;
+// decode  -> Eq. (5) and the energy of Eq. (1).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "schedule.h"
+
+using namespace mplpxx;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                            \
+  do {                                                                                           \
+    hipError_t e_ = (expr);                                                                      \
+    if (e_ != hipSuccess) {                                                                      \
+      if (e_ == hipErrorOutOfMemory) return fail(MPLPXX_ENOMEM, "%s: %s", #expr, hipGetErrorString(e_)); \
+      return fail(MPLPXX_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));                       \
+    }                                                                                            \
+  } while (0)
+
+int next_tile(int L) {
+  int lt = 16;
+  while (lt < L) lt *= 2;
+  return lt;
+}
+
+bool valid_threads(int LT, int NT) {
+  if (NT != 256 && NT != 512 && NT != 1024) return false;
+  return NT <= 16 * LT;
+}
+
+template <typename T> T* dalloc(size_t count, hipError_t* err) {
+  void* p = nullptr;
+  *err = hipMalloc(&p, count * sizeof(T) > 0 ? count * sizeof(T) : 16);
+  return static_cast<T*>(p);
+}
+
+}  // namespace
+
+struct mplpxx_solver {
+  int n = 0, L = 0, m = 0, dtype = 0, S = 0;
+  size_t esz = 4;
+  std::vector<int> step_ptr, order;      // schedule (edge ids of the input list)
+  std::vector<int> slot_of_edge;         // inverse of order
+  std::vector<SlotInfo> slots;
+  std::vector<int> flip;                 // per input edge: 1 if given as (v, u)
+  std::vector<int> deg;
+  // device
+  void* d_tables = nullptr;
+  void* d_phi = nullptr;
+  void* d_U = nullptr;
+  void* d_unaries = nullptr;
+  SlotInfo* d_slots = nullptr;
+  int* d_deg = nullptr;
+  int* d_ver = nullptr;
+  int* d_err = nullptr;
+  int* d_node_ptr = nullptr;
+  int* d_inc = nullptr;
+  double* d_node_min = nullptr;
+  double* d_edge_min = nullptr;
+  double* d_scalar = nullptr;
+  int* d_labels = nullptr;
+  double* d_trace_nodes = nullptr;
+  double* d_trace_out = nullptr;
+  int trace_cap = 0;
+  // execution
+  hipStream_t user_stream = nullptr;
+  hipStream_t own_stream = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  int engine_opt = ENGINE_AUTO;
+  int threads_opt = 0;
+  int grid_opt = 0;
+  long long spin_limit = 1ll << 22;
+  int num_cus = 0;
+  long long iterations = 0;
+  double last_ms = 0.0;
+  bool timed = false;
+
+  hipStream_t stream() const { return user_stream ? user_stream : own_stream; }
+  int LT() const { return next_tile(L); }
+  int NT() const {
+    int nt = threads_opt ? threads_opt : 256;
+    if (!valid_threads(LT(), nt)) nt = 256;
+    return nt;
+  }
+  int engine() const {
+    if (engine_opt == ENGINE_STEP || engine_opt == ENGINE_PERSISTENT) return engine_opt;
+    return ENGINE_PERSISTENT;
+  }
+  int grid() const {
+    int g = grid_opt > 0 ? grid_opt : num_cus;
+    if (g > m) g = m;
+    if (g < 1) g = 1;
+    return g;
+  }
+};
+
+namespace {
+
+void free_all(mplpxx_solver* h) {
+  void* ptrs[] = {h->d_tables, h->d_phi, h->d_U, h->d_unaries, h->d_slots, h->d_deg, h->d_ver, h->d_err,
+                  h->d_node_ptr, h->d_inc, h->d_node_min, h->d_edge_min, h->d_scalar, h->d_labels,
+                  h->d_trace_nodes, h->d_trace_out};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (h->ev0) (void)hipEventDestroy(h->ev0);
+  if (h->ev1) (void)hipEventDestroy(h->ev1);
+  if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
+}
+
+bool finite_host(const void* p, size_t count, int dtype) {
+  if (dtype == MPLPXX_F32) {
+    const float* f = static_cast<const float*>(p);
+    for (size_t i = 0; i < count; ++i)
+      if (!std::isfinite(f[i])) return false;
+  } else {
+    const double* f = static_cast<const double*>(p);
+    for (size_t i = 0; i < count; ++i)
+      if (!std::isfinite(f[i])) return false;
+  }
+  return true;
+}
+
+// Validates the graph and fills orientation, schedule, slot metadata.
+int prepare_graph(mplpxx_solver* h, const int32_t* edges) {
+  const int n = h->n, m = h->m;
+  std::vector<int> eu(m), ev(m);
+  h->flip.assign(m, 0);
+  for (int e = 0; e < m; ++e) {
+    const int a = edges[2 * e], b = edges[2 * e + 1];
+    if (a < 0 || a >= n || b < 0 || b >= n) return fail(MPLPXX_EINVAL, "edge %d: node index out of range", e);
+    if (a == b) return fail(MPLPXX_EINVAL, "edge %d: self loop", e);
+    eu[e] = std::min(a, b);
+    ev[e] = std::max(a, b);
+    h->flip[e] = a > b;
+  }
+  {
+    std::vector<int64_t> keys(m);
+    for (int e = 0; e < m; ++e) keys[e] = (int64_t)eu[e] * n + ev[e];
+    std::sort(keys.begin(), keys.end());
+    for (int e = 1; e < m; ++e)
+      if (keys[e] == keys[e - 1]) return fail(MPLPXX_EINVAL, "duplicate edge (%lld, %lld)", (long long)(keys[e] / n), (long long)(keys[e] % n));
+  }
+  build_schedule(n, eu, ev, h->step_ptr, h->order);
+  h->S = (int)h->step_ptr.size() - 1;
+  if ((int)h->order.size() != m) return fail(MPLPXX_EINVAL, "internal: schedule does not cover the edges");
+  h->slot_of_edge.assign(m, -1);
+  h->slots.resize(m);
+  h->deg.assign(n, 0);
+  for (int i = 0; i < m; ++i) {
+    const int e = h->order[i];
+    h->slot_of_edge[e] = i;
+    SlotInfo si{};
+    si.e = e;
+    si.u = eu[e];
+    si.v = ev[e];
+    si.pos_u = h->deg[si.u]++;
+    si.pos_v = h->deg[si.v]++;
+    h->slots[i] = si;
+  }
+  return MPLPXX_OK;
+}
+
+int create_impl(int32_t n, int32_t L, int64_t m, const int32_t* edges, const void* unaries, const void* pairwise,
+                int32_t dtype, bool device_costs, hipStream_t copy_stream, mplpxx_solver** out) {
+  if (!out) return fail(MPLPXX_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (dtype != MPLPXX_F32 && dtype != MPLPXX_F64) return fail(MPLPXX_EINVAL, "unknown dtype %d", dtype);
+  if (n < 1) return fail(MPLPXX_EINVAL, "n must be >= 1 (got %d)", n);
+  if (L < 1 || L > MPLPXX_MAX_LABELS) return fail(MPLPXX_EINVAL, "L must be in [1, %d] (got %d)", MPLPXX_MAX_LABELS, L);
+  if (m < 0 || m > (int64_t)n * (n - 1) / 2) return fail(MPLPXX_EINVAL, "m must be in [0, n(n-1)/2] (got %lld)", (long long)m);
+  if (m > 0x3fffffff) return fail(MPLPXX_EINVAL, "too many edges");
+  if (!unaries) return fail(MPLPXX_EINVAL, "unaries is NULL");
+  if (m > 0 && (!edges || !pairwise)) return fail(MPLPXX_EINVAL, "edges/pairwise is NULL");
+  const size_t esz = dtype == MPLPXX_F32 ? 4 : 8;
+  const size_t nL = (size_t)n * L, mLL = (size_t)m * L * L;
+  if (!device_costs) {
+    if (!finite_host(unaries, nL, dtype)) return fail(MPLPXX_EINVAL, "non-finite unary cost");
+    if (m > 0 && !finite_host(pairwise, mLL, dtype)) return fail(MPLPXX_EINVAL, "non-finite pairwise cost");
+  }
+  mplpxx_solver* h = new (std::nothrow) mplpxx_solver();
+  if (!h) return fail(MPLPXX_ENOMEM, "host allocation failed");
+  h->n = n;
+  h->L = L;
+  h->m = (int)m;
+  h->dtype = dtype;
+  h->esz = esz;
+  int rc = prepare_graph(h, edges);
+  if (rc != MPLPXX_OK) {
+    delete h;
+    return rc;
+  }
+  auto bail = [&](int code) {
+    free_all(h);
+    delete h;
+    return code;
+  };
+#define TRY(expr)                                  \
+  do {                                             \
+    hipError_t e_ = (expr);                        \
+    if (e_ != hipSuccess) {                        \
+      int c_ = e_ == hipErrorOutOfMemory ? MPLPXX_ENOMEM : MPLPXX_EDEVICE; \
+      fail(c_, "%s: %s", #expr, hipGetErrorString(e_)); \
+      return bail(c_);                             \
+    }                                              \
+  } while (0)
+  int dev = 0;
+  TRY(hipGetDevice(&dev));
+  TRY(hipDeviceGetAttribute(&h->num_cus, hipDeviceAttributeMultiprocessorCount, dev));
+  TRY(hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking));
+  TRY(hipEventCreate(&h->ev0));
+  TRY(hipEventCreate(&h->ev1));
+  hipError_t ae = hipSuccess;
+  h->d_tables = dalloc<char>(mLL * esz, &ae); TRY(ae);
+  h->d_phi = dalloc<char>((size_t)m * 2 * L * esz, &ae); TRY(ae);
+  h->d_U = dalloc<char>(nL * esz, &ae); TRY(ae);
+  h->d_unaries = dalloc<char>(nL * esz, &ae); TRY(ae);
+  h->d_slots = dalloc<SlotInfo>(m, &ae); TRY(ae);
+  h->d_deg = dalloc<int>(n, &ae); TRY(ae);
+  h->d_ver = dalloc<int>(n, &ae); TRY(ae);
+  h->d_err = dalloc<int>(4, &ae); TRY(ae);
+  h->d_node_ptr = dalloc<int>(n + 1, &ae); TRY(ae);
+  h->d_inc = dalloc<int>(2 * (size_t)m, &ae); TRY(ae);
+  h->d_node_min = dalloc<double>(n, &ae); TRY(ae);
+  h->d_edge_min = dalloc<double>(m, &ae); TRY(ae);
+  h->d_scalar = dalloc<double>(4, &ae); TRY(ae);
+  h->d_labels = dalloc<int>(n, &ae); TRY(ae);
+
+  hipStream_t st = h->own_stream;
+  // incidence lists (CSR by node, slots ascending) for dual and decode
+  std::vector<int> node_ptr(n + 1, 0), inc(2 * (size_t)m);
+  for (int i = 0; i < h->m; ++i) {
+    node_ptr[h->slots[i].u + 1]++;
+    node_ptr[h->slots[i].v + 1]++;
+  }
+  for (int u = 0; u < n; ++u) node_ptr[u + 1] += node_ptr[u];
+  {
+    std::vector<int> fillp(node_ptr.begin(), node_ptr.end() - 1);
+    for (int i = 0; i < h->m; ++i) {
+      inc[fillp[h->slots[i].u]++] = 2 * i + 0;
+      inc[fillp[h->slots[i].v]++] = 2 * i + 1;
+    }
+  }
+  TRY(hipMemcpyAsync(h->d_node_ptr, node_ptr.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice, st));
+  if (m) TRY(hipMemcpyAsync(h->d_inc, inc.data(), inc.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  if (m) TRY(hipMemcpyAsync(h->d_slots, h->slots.data(), m * sizeof(SlotInfo), hipMemcpyHostToDevice, st));
+  TRY(hipMemcpyAsync(h->d_deg, h->deg.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
+  TRY(hipMemsetAsync(h->d_phi, 0, (size_t)m * 2 * L * esz, st));
+  TRY(hipMemsetAsync(h->d_err, 0, 4 * sizeof(int), st));
+
+  if (!device_costs) {
+    TRY(hipMemcpyAsync(h->d_unaries, unaries, nL * esz, hipMemcpyHostToDevice, st));
+    if (m) {
+      // pack tables in slot order, transposing edges given as (v, u)
+      std::vector<char> packed(mLL * esz);
+      const size_t tb = (size_t)L * L * esz;
+      const char* src = static_cast<const char*>(pairwise);
+      for (int i = 0; i < h->m; ++i) {
+        const int e = h->order[i];
+        char* dst = packed.data() + (size_t)i * tb;
+        const char* s = src + (size_t)e * tb;
+        if (!h->flip[e]) {
+          std::memcpy(dst, s, tb);
+        } else {
+          for (int r = 0; r < L; ++r)
+            for (int c = 0; c < L; ++c)
+              std::memcpy(dst + ((size_t)r * L + c) * esz, s + ((size_t)c * L + r) * esz, esz);
+        }
+      }
+      TRY(hipMemcpyAsync(h->d_tables, packed.data(), packed.size(), hipMemcpyHostToDevice, st));
+      TRY(hipStreamSynchronize(st));  // `packed` goes out of scope
+    }
+  } else {
+    int* d_flag = nullptr;
+    int* d_se = nullptr;
+    int* d_sf = nullptr;
+    TRY(hipStreamSynchronize(st));
+    hipStream_t cs = copy_stream ? copy_stream : st;
+    if (copy_stream) TRY(hipStreamSynchronize(copy_stream));
+    TRY(hipMalloc(&d_flag, sizeof(int)));
+    TRY(hipMemsetAsync(d_flag, 0, sizeof(int), cs));
+    TRY(hipMemcpyAsync(h->d_unaries, unaries, nL * esz, hipMemcpyDeviceToDevice, cs));
+    if (dtype == MPLPXX_F32) {
+      TRY(launch_check_finite<float>((const float*)unaries, nL, d_flag, cs));
+      if (m) TRY(launch_check_finite<float>((const float*)pairwise, mLL, d_flag, cs));
+    } else {
+      TRY(launch_check_finite<double>((const double*)unaries, nL, d_flag, cs));
+      if (m) TRY(launch_check_finite<double>((const double*)pairwise, mLL, d_flag, cs));
+    }
+    if (m) {
+      std::vector<int> se(m), sf(m);
+      for (int i = 0; i < h->m; ++i) {
+        se[i] = h->order[i];
+        sf[i] = h->flip[h->order[i]];
+      }
+      TRY(hipMalloc(&d_se, m * sizeof(int)));
+      TRY(hipMalloc(&d_sf, m * sizeof(int)));
+      TRY(hipMemcpyAsync(d_se, se.data(), m * sizeof(int), hipMemcpyHostToDevice, cs));
+      TRY(hipMemcpyAsync(d_sf, sf.data(), m * sizeof(int), hipMemcpyHostToDevice, cs));
+      if (dtype == MPLPXX_F32)
+        TRY(launch_pack_tables<float>((const float*)pairwise, (float*)h->d_tables, d_se, d_sf, h->m, L, cs));
+      else
+        TRY(launch_pack_tables<double>((const double*)pairwise, (double*)h->d_tables, d_se, d_sf, h->m, L, cs));
+    }
+    int flag = 0;
+    TRY(hipMemcpyAsync(&flag, d_flag, sizeof(int), hipMemcpyDeviceToHost, cs));
+    TRY(hipStreamSynchronize(cs));
+    (void)hipFree(d_flag);
+    if (d_se) (void)hipFree(d_se);
+    if (d_sf) (void)hipFree(d_sf);
+    if (flag) {
+      fail(MPLPXX_EINVAL, "non-finite cost");
+      return bail(MPLPXX_EINVAL);
+    }
+  }
+  TRY(hipMemcpyAsync(h->d_U, h->d_unaries, nL * esz, hipMemcpyDeviceToDevice, st));
+  TRY(hipStreamSynchronize(st));
+#undef TRY
+  *out = h;
+  return MPLPXX_OK;
+}
+
+int sync_and_check(mplpxx_solver* h) {
+  HIP_TRY(hipStreamSynchronize(h->stream()));
+  int err = 0;
+  HIP_TRY(hipMemcpy(&err, h->d_err, sizeof(int), hipMemcpyDeviceToHost));
+  if (err != 0) {
+    (void)hipMemset(h->d_err, 0, sizeof(int));
+    return fail(err, "device wait exceeded its bound (code %d)", err);
+  }
+  return MPLPXX_OK;
+}
+
+template <typename T> HsArgs<T> hs_args(mplpxx_solver* h, double* trace) {
+  HsArgs<T> a{};
+  a.tables = static_cast<const T*>(h->d_tables);
+  a.phi = static_cast<T*>(h->d_phi);
+  a.U = static_cast<T*>(h->d_U);
+  a.slots = h->d_slots;
+  a.deg = h->d_deg;
+  a.ver = h->d_ver;
+  a.err = h->d_err;
+  a.trace = trace;
+  a.L = h->L;
+  a.m = h->m;
+  a.n = h->n;
+  a.spin_limit = h->spin_limit;
+  return a;
+}
+
+template <typename T> int iterate_t(mplpxx_solver* h, int k, double* trace_host) {
+  hipStream_t st = h->stream();
+  if (trace_host && k > h->trace_cap) {
+    if (h->d_trace_nodes) (void)hipFree(h->d_trace_nodes);
+    if (h->d_trace_out) (void)hipFree(h->d_trace_out);
+    h->d_trace_nodes = nullptr;
+    h->d_trace_out = nullptr;
+    h->trace_cap = 0;
+    HIP_TRY(hipMalloc(&h->d_trace_nodes, (size_t)k * h->n * sizeof(double)));
+    HIP_TRY(hipMalloc(&h->d_trace_out, (size_t)k * sizeof(double)));
+    h->trace_cap = k;
+  }
+  const int engine = h->engine();
+  const int LT = h->LT(), NT = h->NT();
+  HIP_TRY(hipEventRecord(h->ev0, st));
+  if (h->m > 0 && k > 0) {
+    if (engine == ENGINE_STEP) {
+      HsArgs<T> a = hs_args<T>(h, nullptr);
+      for (int it = 0; it < k; ++it) {
+        for (int s = 0; s < h->S; ++s) {
+          const int b = h->step_ptr[s], c = h->step_ptr[s + 1] - b;
+          HIP_TRY(launch_handshake<T>(a, ENGINE_STEP, LT, NT, b, c, 0, 1, st));
+        }
+        if (trace_host)
+          HIP_TRY(launch_trace_nodes<T>(static_cast<const T*>(h->d_U), h->n, h->L, h->d_trace_nodes + (size_t)it * h->n, st));
+      }
+    } else {
+      HsArgs<T> a = hs_args<T>(h, trace_host ? h->d_trace_nodes : nullptr);
+      HIP_TRY(launch_fill_int(h->d_ver, 0, h->n, st));
+      HIP_TRY(launch_handshake<T>(a, ENGINE_PERSISTENT, LT, NT, 0, 0, h->grid(), k, st));
+    }
+  }
+  HIP_TRY(hipEventRecord(h->ev1, st));
+  h->timed = true;
+  if (trace_host && k > 0) {
+    // nodes without edges (all of them when m == 0) read U directly
+    HIP_TRY(launch_trace_sum<T>(h->d_trace_nodes, static_cast<const T*>(h->d_U), h->d_deg, h->n, h->L, k,
+                                h->d_trace_out, st));
+  }
+  h->iterations += k;
+  if (!h->user_stream || trace_host) {
+    int rc = sync_and_check(h);
+    if (rc != MPLPXX_OK) return rc;
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+    h->last_ms = ms;
+    if (trace_host && k > 0)
+      HIP_TRY(hipMemcpy(trace_host, h->d_trace_out, (size_t)k * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  return MPLPXX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mplpxx_create(int32_t n, int32_t L, int64_t m, const int32_t* edges, const void* unaries, const void* pairwise,
+                  int32_t dtype, mplpxx_solver** out) {
+  return create_impl(n, L, m, edges, unaries, pairwise, dtype, false, nullptr, out);
+}
+
+int mplpxx_create_device(int32_t n, int32_t L, int64_t m, const int32_t* edges, const void* unaries_dev,
+                         const void* pairwise_dev, int32_t dtype, void* hip_stream, mplpxx_solver** out) {
+  return create_impl(n, L, m, edges, unaries_dev, pairwise_dev, dtype, true, static_cast<hipStream_t>(hip_stream), out);
+}
+
+int mplpxx_iterate(mplpxx_solver* h, int32_t k) {
+  if (!h) return fail(MPLPXX_EINVAL, "handle is NULL");
+  if (k < 0) return fail(MPLPXX_EINVAL, "k must be >= 0");
+  return h->dtype == MPLPXX_F32 ? iterate_t<float>(h, k, nullptr) : iterate_t<double>(h, k, nullptr);
+}
+
+int mplpxx_iterate_trace(mplpxx_solver* h, int32_t k, double* trace) {
+  if (!h) return fail(MPLPXX_EINVAL, "handle is NULL");
+  if (k < 0) return fail(MPLPXX_EINVAL, "k must be >= 0");
+  if (k > 0 && !trace) return fail(MPLPXX_EINVAL, "trace is NULL");
+  return h->dtype == MPLPXX_F32 ? iterate_t<float>(h, k, trace) : iterate_t<double>(h, k, trace);
+}
+
+int mplpxx_dual_bound(mplpxx_solver* h, double* out) {
+  if (!h || !out) return fail(MPLPXX_EINVAL, "NULL argument");
+  hipStream_t st = h->stream();
+  if (h->dtype == MPLPXX_F32)
+    HIP_TRY(launch_dual<float>((const float*)h->d_unaries, (const float*)h->d_tables, (const float*)h->d_phi,
+                               h->d_node_ptr, h->d_inc, h->n, h->L, h->m, h->d_node_min, h->d_edge_min, h->d_scalar, st));
+  else
+    HIP_TRY(launch_dual<double>((const double*)h->d_unaries, (const double*)h->d_tables, (const double*)h->d_phi,
+                                h->d_node_ptr, h->d_inc, h->n, h->L, h->m, h->d_node_min, h->d_edge_min, h->d_scalar, st));
+  int rc = sync_and_check(h);
+  if (rc != MPLPXX_OK) return rc;
+  HIP_TRY(hipMemcpy(out, h->d_scalar, sizeof(double), hipMemcpyDeviceToHost));
+  return MPLPXX_OK;
+}
+
+int mplpxx_decode(mplpxx_solver* h, int32_t* labels, double* energy) {
+  if (!h || !labels) return fail(MPLPXX_EINVAL, "NULL argument");
+  hipStream_t st = h->stream();
+  if (h->dtype == MPLPXX_F32)
+    HIP_TRY(launch_decode<float>((const float*)h->d_unaries, (const float*)h->d_tables, (const float*)h->d_phi,
+                                 h->d_slots, h->d_node_ptr, h->d_inc, h->n, h->L, h->m, h->d_labels, h->d_scalar + 1, st));
+  else
+    HIP_TRY(launch_decode<double>((const double*)h->d_unaries, (const double*)h->d_tables, (const double*)h->d_phi,
+                                  h->d_slots, h->d_node_ptr, h->d_inc, h->n, h->L, h->m, h->d_labels, h->d_scalar + 1, st));
+  int rc = sync_and_check(h);
+  if (rc != MPLPXX_OK) return rc;
+  HIP_TRY(hipMemcpy(labels, h->d_labels, (size_t)h->n * sizeof(int), hipMemcpyDeviceToHost));
+  if (energy) HIP_TRY(hipMemcpy(energy, h->d_scalar + 1, sizeof(double), hipMemcpyDeviceToHost));
+  return MPLPXX_OK;
+}
+
+void mplpxx_destroy(mplpxx_solver* h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->stream());
+  free_all(h);
+  delete h;
+}
+
+const char* mplpxx_error_string(int code) {
+  switch (code) {
+    case MPLPXX_OK: return "ok";
+    case MPLPXX_EINVAL: return "invalid argument";
+    case MPLPXX_ENOMEM: return "out of memory";
+    case MPLPXX_EDEVICE: return "device error";
+    case MPLPXX_ETIMEOUT: return "device wait timed out";
+    case MPLPXX_ESTATE: return "invalid state";
+    default: return "unknown error";
+  }
+}
+
+const char* mplpxx_last_error(void) { return g_last_error.c_str(); }
+
+int mplpxx_set_stream(mplpxx_solver* h, void* hip_stream) {
+  if (!h) return fail(MPLPXX_EINVAL, "handle is NULL");
+  HIP_TRY(hipStreamSynchronize(h->stream()));
+  h->user_stream = static_cast<hipStream_t>(hip_stream);
+  return MPLPXX_OK;
+}
+
+int mplpxx_get_schedule(mplpxx_solver* h, int32_t* n_steps, int32_t* step_ptr, int32_t* order) {
+  if (!h) return fail(MPLPXX_EINVAL, "handle is NULL");
+  if (n_steps) *n_steps = h->S;
+  if (step_ptr) std::memcpy(step_ptr, h->step_ptr.data(), h->step_ptr.size() * sizeof(int));
+  if (order && h->m) std::memcpy(order, h->order.data(), h->order.size() * sizeof(int));
+  return MPLPXX_OK;
+}
+
+int mplpxx_schedule(int32_t n, int64_t m, const int32_t* edges, int32_t* n_steps, int32_t* step_ptr,
+                    int32_t* order) {
+  if (n < 1) return fail(MPLPXX_EINVAL, "n must be >= 1 (got %d)", n);
+  if (m < 0 || m > (int64_t)n * (n - 1) / 2 || m > 0x3fffffff)
+    return fail(MPLPXX_EINVAL, "m must be in [0, n(n-1)/2] (got %lld)", (long long)m);
+  if (m > 0 && !edges) return fail(MPLPXX_EINVAL, "edges is NULL");
+  mplpxx_solver tmp;
+  tmp.n = n;
+  tmp.m = (int)m;
+  int rc = prepare_graph(&tmp, edges);
+  if (rc != MPLPXX_OK) return rc;
+  if (n_steps) *n_steps = tmp.S;
+  if (step_ptr) std::memcpy(step_ptr, tmp.step_ptr.data(), tmp.step_ptr.size() * sizeof(int));
+  if (order && m) std::memcpy(order, tmp.order.data(), tmp.order.size() * sizeof(int));
+  return MPLPXX_OK;
+}
+
+int mplpxx_get_state(mplpxx_solver* h, void* U, void* phi) {
+  if (!h) return fail(MPLPXX_EINVAL, "handle is NULL");
+  HIP_TRY(hipStreamSynchronize(h->stream()));
+  const size_t esz = h->esz, L = h->L;
+  if (U) HIP_TRY(hipMemcpy(U, h->d_U, (size_t)h->n * L * esz, hipMemcpyDeviceToHost));
+  if (phi && h->m) {
+    std::vector<char> tmp((size_t)h->m * 2 * L * esz);
+    HIP_TRY(hipMemcpy(tmp.data(), h->d_phi, tmp.size(), hipMemcpyDeviceToHost));
+    char* dst = static_cast<char*>(phi);
+    const size_t row = 2 * L * esz;
+    for (int e = 0; e < h->m; ++e) std::memcpy(dst + (size_t)e * row, tmp.data() + (size_t)h->slot_of_edge[e] * row, row);
+  }
+  return MPLPXX_OK;
+}
+
+int mplpxx_set_state(mplpxx_solver* h, const void* U, const void* phi) {
+  if (!h) return fail(MPLPXX_EINVAL, "handle is NULL");
+  HIP_TRY(hipStreamSynchronize(h->stream()));
+  const size_t esz = h->esz, L = h->L;
+  if (U) {
+    if (!finite_host(U, (size_t)h->n * L, h->dtype)) return fail(MPLPXX_EINVAL, "non-finite U");
+    HIP_TRY(hipMemcpy(h->d_U, U, (size_t)h->n * L * esz, hipMemcpyHostToDevice));
+  }
+  if (phi && h->m) {
+    if (!finite_host(phi, (size_t)h->m * 2 * L, h->dtype)) return fail(MPLPXX_EINVAL, "non-finite phi");
+    std::vector<char> tmp((size_t)h->m * 2 * L * esz);
+    const char* src = static_cast<const char*>(phi);
+    const size_t row = 2 * L * esz;
+    for (int e = 0; e < h->m; ++e) std::memcpy(tmp.data() + (size_t)h->slot_of_edge[e] * row, src + (size_t)e * row, row);
+    HIP_TRY(hipMemcpy(h->d_phi, tmp.data(), tmp.size(), hipMemcpyHostToDevice));
+  }
+  h->iterations = 0;
+  return MPLPXX_OK;
+}
+
+int mplpxx_set_option(mplpxx_solver* h, int32_t key, int64_t value) {
+  if (!h) return fail(MPLPXX_EINVAL, "handle is NULL");
+  switch (key) {
+    case MPLPXX_OPT_ENGINE:
+      if (value < 0 || value > 2) return fail(MPLPXX_EINVAL, "engine must be 0, 1 or 2");
+      h->engine_opt = (int)value;
+      return MPLPXX_OK;
+    case MPLPXX_OPT_THREADS:
+      if (value != 0 && !valid_threads(h->LT(), (int)value))
+        return fail(MPLPXX_EINVAL, "threads %lld not valid for L=%d", (long long)value, h->L);
+      h->threads_opt = (int)value;
+      return MPLPXX_OK;
+    case MPLPXX_OPT_GRID: {
+      if (value < 0) return fail(MPLPXX_EINVAL, "grid must be >= 0");
+      const int nb = h->dtype == MPLPXX_F32 ? max_blocks_per_cu<float>(ENGINE_PERSISTENT, h->LT(), h->NT())
+                                            : max_blocks_per_cu<double>(ENGINE_PERSISTENT, h->LT(), h->NT());
+      if (value > (int64_t)nb * h->num_cus) return fail(MPLPXX_EINVAL, "grid %lld exceeds co-resident limit %d", (long long)value, nb * h->num_cus);
+      h->grid_opt = (int)value;
+      return MPLPXX_OK;
+    }
+    case MPLPXX_OPT_SPIN_LIMIT:
+      if (value < 0) return fail(MPLPXX_EINVAL, "spin limit must be >= 0");
+      h->spin_limit = value ? value : (1ll << 22);
+      return MPLPXX_OK;
+    default:
+      return fail(MPLPXX_EINVAL, "unknown option %d", key);
+  }
+}
+
+int mplpxx_get_info(mplpxx_solver* h, int32_t key, int64_t* value) {
+  if (!h || !value) return fail(MPLPXX_EINVAL, "NULL argument");
+  switch (key) {
+    case MPLPXX_INFO_N: *value = h->n; return MPLPXX_OK;
+    case MPLPXX_INFO_L: *value = h->L; return MPLPXX_OK;
+    case MPLPXX_INFO_M: *value = h->m; return MPLPXX_OK;
+    case MPLPXX_INFO_STEPS: *value = h->S; return MPLPXX_OK;
+    case MPLPXX_INFO_DTYPE: *value = h->dtype; return MPLPXX_OK;
+    case MPLPXX_INFO_ENGINE: *value = h->engine(); return MPLPXX_OK;
+    case MPLPXX_INFO_GRID: *value = h->grid(); return MPLPXX_OK;
+    case MPLPXX_INFO_THREADS: *value = h->NT(); return MPLPXX_OK;
+    case MPLPXX_INFO_ITERATIONS: *value = h->iterations; return MPLPXX_OK;
+    default: return fail(MPLPXX_EINVAL, "unknown info key %d", key);
+  }
+}
+
+int mplpxx_last_iterate_ms(mplpxx_solver* h, double* ms) {
+  if (!h || !ms) return fail(MPLPXX_EINVAL, "NULL argument");
+  if (h->user_stream && h->timed) {
+    HIP_TRY(hipEventSynchronize(h->ev1));
+    float f = 0.f;
+    HIP_TRY(hipEventElapsedTime(&f, h->ev0, h->ev1));
+    h->last_ms = f;
+  }
+  *ms = h->last_ms;
+  return MPLPXX_OK;
+}
+
+}  // extern "C"

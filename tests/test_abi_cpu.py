@@ -1,0 +1,131 @@
+"""CPU-side checks of the C-ABI library: it loads without a GPU, exports
+every function the header declares, rejects invalid models before any device
+work, and its host-only schedule equals the oracle's independently computed
+schedule bit for bit."""
+import ctypes
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2004_08227_amd as M
+from paper_2004_08227_amd import workloads as W
+
+
+def test_library_exports_every_header_symbol():
+    lib = M.lib()
+    syms = M.header_symbols()
+    assert len(syms) >= 15
+    for s in syms:
+        assert hasattr(lib, s), s
+
+
+def test_header_constants_match_binding():
+    text = open(M.HEADER).read()
+    defs = dict(re.findall(r"#define (MPLPXX_\w+)\s+\(?(-?\d+)\)?", text))
+    assert int(defs["MPLPXX_F32"]) == M.F32 and int(defs["MPLPXX_F64"]) == M.F64
+    assert int(defs["MPLPXX_EINVAL"]) == M.EINVAL and int(defs["MPLPXX_ETIMEOUT"]) == M.ETIMEOUT
+    assert int(defs["MPLPXX_ENOMEM"]) == M.ENOMEM and int(defs["MPLPXX_EDEVICE"]) == M.EDEVICE
+    assert int(defs["MPLPXX_MAX_LABELS"]) == M.MAX_LABELS
+    assert int(defs["MPLPXX_OPT_ENGINE"]) == M.OPT_ENGINE and int(defs["MPLPXX_OPT_SPIN_LIMIT"]) == M.OPT_SPIN_LIMIT
+    for k, v in M.INFO.items():
+        name = {"n": "N", "L": "L", "m": "M"}.get(k, k.upper())
+        assert int(defs[f"MPLPXX_INFO_{name}"]) == v
+
+
+def test_error_strings():
+    lib = M.lib()
+    for code in (M.OK, M.EINVAL, M.ENOMEM, M.EDEVICE, M.ETIMEOUT, M.ESTATE):
+        assert lib.mplpxx_error_string(code)
+    assert lib.mplpxx_error_string(12345) == b"unknown error"
+
+
+def _create(n, L, edges, un, pw, dtype=M.F32):
+    h = ctypes.c_void_p()
+    e = None if edges is None else ctypes.c_void_p(edges.ctypes.data)
+    u = None if un is None else ctypes.c_void_p(un.ctypes.data)
+    p = None if pw is None else ctypes.c_void_p(pw.ctypes.data)
+    m = 0 if edges is None else edges.shape[0]
+    rc = M.lib().mplpxx_create(n, L, m, e, u, p, dtype, ctypes.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("case", ["n0", "L0", "Lbig", "self", "range", "neg", "dup", "nan_u", "inf_p", "dtype",
+                                  "null_u", "too_many"])
+def test_invalid_models_rejected_without_device_work(case):
+    n, L = 5, 3
+    model = W.uniform(n, L, seed=0)
+    edges, un, pw, dt = model.edges.copy(), model.unaries.copy(), model.pairwise.copy(), M.F32
+    if case == "n0":
+        n = 0
+    elif case == "L0":
+        L = 0
+    elif case == "Lbig":
+        L = M.MAX_LABELS + 1
+    elif case == "self":
+        edges[2] = [3, 3]
+    elif case == "range":
+        edges[2] = [3, 5]
+    elif case == "neg":
+        edges[0] = [-1, 2]
+    elif case == "dup":
+        edges[4] = edges[1][::-1]
+    elif case == "nan_u":
+        un[1, 1] = np.nan
+    elif case == "inf_p":
+        pw[3, 0, 2] = np.inf
+    elif case == "dtype":
+        dt = 7
+    elif case == "null_u":
+        un = None
+    elif case == "too_many":
+        n = 4                     # 10 edges > 4*3/2
+    rc, h = _create(n, L, edges, un, pw, dt)
+    assert rc == M.EINVAL and not h.value
+    assert M.lib().mplpxx_last_error()
+
+
+def test_null_out_and_null_handle():
+    lib = M.lib()
+    model = W.uniform(3, 2, seed=0)
+    assert lib.mplpxx_create(3, 2, 3, ctypes.c_void_p(model.edges.ctypes.data), ctypes.c_void_p(model.unaries.ctypes.data),
+                             ctypes.c_void_p(model.pairwise.ctypes.data), M.F32, None) == M.EINVAL
+    assert lib.mplpxx_iterate(None, 1) == M.EINVAL
+    d = ctypes.c_double()
+    assert lib.mplpxx_dual_bound(None, ctypes.byref(d)) == M.EINVAL
+    lib.mplpxx_destroy(None)
+
+
+@pytest.mark.parametrize("kind,args", [("complete", (2,)), ("complete", (3,)), ("complete", (8,)), ("complete", (57,)),
+                                       ("complete", (200,)), ("er", (100, 0.05, 1)), ("er", (60, 0.5, 2)),
+                                       ("er", (1000, 0.01, 3)), ("chain", (12,))])
+def test_host_schedule_equals_oracle_schedule(kind, args):
+    if kind == "complete":
+        n = args[0]
+        edges = W.complete_edges(n)
+        # scramble the input order and orientation: the schedule must not care
+        rng = np.random.default_rng(n)
+        perm = rng.permutation(edges.shape[0])
+        edges = edges[perm]
+        flip = rng.random(edges.shape[0]) < 0.5
+        edges[flip] = edges[flip][:, ::-1]
+    elif kind == "er":
+        n, p, seed = args
+        edges = W.potts_er(n, 2, p, seed=seed).edges
+    else:
+        n = args[0]
+        edges = W.chain(n, 2).edges
+    sp, order = M.schedule(n, edges)
+    canon = np.sort(edges, axis=1).astype(np.int32)
+    sp_o, ord_o = oracle.schedule(n, canon)
+    assert np.array_equal(sp, sp_o) and np.array_equal(order, ord_o)
+
+
+def test_host_schedule_rejects_bad_graphs():
+    with pytest.raises(M.MplpError):
+        M.schedule(3, np.array([[0, 1], [1, 0]], np.int32))
+    with pytest.raises(M.MplpError):
+        M.schedule(3, np.array([[0, 3]], np.int32))
+    sp, order = M.schedule(4, np.zeros((0, 2), np.int32))
+    assert list(sp) == [0] and order.size == 0

@@ -1,0 +1,212 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+FP64 runs must agree with the oracle to rounding (1e-12 relative); FP32 runs
+must reproduce the oracle's dual bound to 1e-5 relative after the same
+schedule and iteration count.  Integer results (schedules) must match
+exactly.  Each case prints its name before it touches the GPU.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2004_08227_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+M = pytest.importorskip("paper_2004_08227_amd")
+
+
+def _announce(*a):
+    print("CASE", *a, flush=True)
+
+
+def _rel(a, b):
+    return abs(a - b) / max(1.0, abs(b))
+
+
+ENGINES = [M.ENGINE_STEP, M.ENGINE_PERSISTENT]
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_tiny_fp64_matches_oracle_and_bruteforce(engine):
+    _announce("tiny fp64", engine)
+    model = W.tiny(0)
+    st, ref = oracle.run_model(model, 200)
+    e_map, _ = oracle.bruteforce(model)
+    with M.Solver.from_model(model) as s:
+        s.set_option(M.OPT_ENGINE, engine)
+        tr = s.iterate_trace(200)
+        d = s.dual_bound()
+        U, phi = s.get_state()
+        labels, energy = s.decode()
+    assert np.max(np.abs(tr - ref)) <= 1e-12 * abs(ref[-1])
+    assert _rel(d, st.dual()) <= 1e-12
+    assert np.max(np.abs(U - st.Tu)) <= 1e-12 * np.abs(st.Tu).max()
+    # reparametrized pairwise of the GPU state against the oracle's Te
+    Te = st.pairwise - phi[:, 0, :, None] - phi[:, 1, None, :]
+    assert np.max(np.abs(Te - st.Te)) <= 1e-12 * max(1.0, np.abs(st.Te).max())
+    assert d <= e_map + 1e-12
+    assert energy >= e_map - 1e-12
+    assert abs(energy - oracle.State(model).energy(labels)) <= 1e-12 * abs(energy)
+    assert list(labels) == list(st.decode())
+
+
+def test_schedule_matches_oracle_exactly():
+    for model in [W.tiny(0), W.pose(33, 8, seed=2), W.random_graph_model(40, 3, 0.2, seed=1),
+                  W.chain(9, 3), W.potts_er(60, 4, 0.3, seed=3)]:
+        _announce("schedule", model.name)
+        sp_o, ord_o = oracle.schedule(model.n, oracle.canonicalize(model.n, model.L, model.edges, model.unaries,
+                                                                    model.pairwise)[0])
+        with M.Solver.from_model(model) as s:
+            sp, order = s.schedule()
+        assert np.array_equal(sp, sp_o) and np.array_equal(order, ord_o)
+
+
+FP32_CASES = [
+    ("pose", lambda: W.pose(40, 64, seed=3), 20),
+    ("pose_ragged13", lambda: W.pose(31, 13, seed=4), 30),
+    ("pose_L100", lambda: W.pose(18, 100, seed=5), 10),
+    ("uniform_L32", lambda: W.uniform(30, 32, seed=6), 20),
+    ("potts_er", lambda: W.potts_er(80, 16, 0.3, seed=7), 20),
+    ("uniform_L1", lambda: W.uniform(10, 1, seed=8), 3),
+    ("uniform_L128", lambda: W.uniform(9, 128, seed=9), 5),
+    ("uniform_L65", lambda: W.uniform(12, 65, seed=10), 5),
+]
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+@pytest.mark.parametrize("name,make,iters", FP32_CASES, ids=[c[0] for c in FP32_CASES])
+def test_fp32_dual_matches_oracle(name, make, iters, engine):
+    _announce("fp32", name, engine)
+    model = make()
+    st, ref = oracle.run_model(model, iters)
+    with M.Solver.from_model(model) as s:
+        s.set_option(M.OPT_ENGINE, engine)
+        tr = s.iterate_trace(iters)
+        d = s.dual_bound()
+        U, _ = s.get_state()
+    assert _rel(d, ref[-1]) <= 1e-5, (d, ref[-1])
+    assert np.max(np.abs(tr - ref) / np.maximum(1.0, np.abs(ref))) <= 1e-5
+    assert np.max(np.abs(U - st.Tu)) <= 1e-4 * max(1.0, np.abs(st.Tu).max())
+
+
+def test_engines_and_tunings_are_bitwise_identical():
+    model = W.pose(50, 64, seed=11)
+    states = []
+    for engine, threads, grid in [(M.ENGINE_STEP, 256, 0), (M.ENGINE_STEP, 1024, 0),
+                                  (M.ENGINE_PERSISTENT, 256, 0), (M.ENGINE_PERSISTENT, 512, 7),
+                                  (M.ENGINE_PERSISTENT, 1024, 64)]:
+        _announce("tuning", engine, threads, grid)
+        with M.Solver.from_model(model) as s:
+            s.set_option(M.OPT_ENGINE, engine)
+            s.set_option(M.OPT_THREADS, threads)
+            s.set_option(M.OPT_GRID, grid)
+            s.iterate(6)
+            states.append(s.get_state())
+    for U, phi in states[1:]:
+        assert np.array_equal(U, states[0][0]) and np.array_equal(phi, states[0][1])
+
+
+def test_checkpoint_resume_is_bitwise():
+    model = W.pose(30, 32, seed=12)
+    _announce("resume")
+    with M.Solver.from_model(model) as a:
+        a.iterate(10)
+        Ua, pa = a.get_state()
+    with M.Solver.from_model(model) as b:
+        b.iterate(5)
+        U5, p5 = b.get_state()
+    with M.Solver.from_model(model) as c:
+        c.set_state(U5, p5)
+        c.iterate(5)
+        Uc, pc = c.get_state()
+    assert np.array_equal(Ua, Uc) and np.array_equal(pa, pc)
+
+
+def test_reversed_edges_and_device_create():
+    import torch
+    model = W.pose(20, 16, seed=13)
+    flip = W.Model(model.n, model.L, model.edges[:, ::-1].copy(), model.unaries,
+                   np.transpose(model.pairwise, (0, 2, 1)).copy())
+    _announce("reversed+device")
+    with M.Solver.from_model(model) as a:
+        a.iterate(4)
+        Ua, pa = a.get_state()
+    with M.Solver.from_model(flip) as b:
+        b.iterate(4)
+        Ub, pb = b.get_state()
+    with M.Solver.from_torch(flip.n, flip.L, flip.edges, torch.from_numpy(flip.unaries).cuda(),
+                             torch.from_numpy(flip.pairwise).cuda()) as c:
+        c.iterate(4)
+        Uc, pc = c.get_state()
+    assert np.array_equal(Ua, Ub) and np.array_equal(pa, pb)
+    assert np.array_equal(Ua, Uc) and np.array_equal(pa, pc)
+
+
+def test_degenerate_models():
+    _announce("degenerate")
+    # single node, no edges
+    m1 = W.Model(1, 3, np.zeros((0, 2), np.int32), np.array([[0.5, 0.25, 2.0]], np.float32), np.zeros((0, 3, 3), np.float32))
+    with M.Solver.from_model(m1) as s:
+        tr = s.iterate_trace(3)
+        assert np.allclose(tr, 0.25) and s.dual_bound() == 0.25
+        labels, e = s.decode()
+        assert list(labels) == [1] and e == 0.25
+    # isolated nodes among edges, greedy schedule
+    m2 = W.random_graph_model(15, 5, 0.15, seed=3, dtype=np.float64)
+    st, ref = oracle.run_model(m2, 10)
+    with M.Solver.from_model(m2) as s:
+        tr = s.iterate_trace(10)
+        assert np.max(np.abs(tr - ref)) <= 1e-12 * max(1, abs(ref[-1]))
+        assert _rel(s.dual_bound(), st.dual()) <= 1e-12
+    # single edge: one update reaches the MAP energy
+    m3 = W.uniform(2, 7, seed=4, dtype=np.float64)
+    e_map, _ = oracle.bruteforce(m3)
+    with M.Solver.from_model(m3) as s:
+        s.iterate(1)
+        assert abs(s.dual_bound() - e_map) <= 1e-12
+
+
+def test_iterate_zero_and_timeout_error_path():
+    _announce("timeout")
+    model = W.pose(40, 16, seed=14)
+    with M.Solver.from_model(model) as s:
+        s.iterate(0)
+        assert s.dual_bound() == pytest.approx(oracle.State(model).dual(), rel=1e-6)
+        s.set_option(M.OPT_ENGINE, M.ENGINE_PERSISTENT)
+        s.set_option(M.OPT_SPIN_LIMIT, 1)    # every wait gives up at once
+        with pytest.raises(M.MplpError) as ei:
+            s.iterate(3)
+        assert ei.value.code == M.ETIMEOUT
+        # the handle recovers after the state is reset
+        s.set_option(M.OPT_SPIN_LIMIT, 0)
+        U0 = model.unaries.copy()
+        s.set_state(U0, np.zeros((model.m, 2, model.L), np.float32))
+        s.iterate(2)
+        st, ref = oracle.run_model(model, 2)
+        assert _rel(s.dual_bound(), ref[-1]) <= 1e-5
+
+
+def test_decode_is_valid_rounding_of_gpu_state():
+    _announce("decode")
+    model = W.pose(30, 20, seed=15)
+    with M.Solver.from_model(model) as s:
+        s.iterate(10)
+        labels, energy = s.decode()
+        U, phi = s.get_state()
+    # energy reported = Eq. (1) of the labels (test-side arithmetic)
+    un = model.unaries.astype(np.float64)
+    pw = model.pairwise.astype(np.float64)
+    e = un[np.arange(model.n), labels].sum() + pw[np.arange(model.m), labels[model.edges[:, 0]], labels[model.edges[:, 1]]].sum()
+    assert abs(e - energy) <= 1e-9 * abs(e)
+    # every label satisfies Eq. (5) on the GPU's reparametrized costs (FP64)
+    ph = phi.astype(np.float64)
+    Tu = un.copy()
+    np.add.at(Tu, model.edges[:, 0], ph[:, 0])
+    np.add.at(Tu, model.edges[:, 1], ph[:, 1])
+    for u in range(model.n):
+        c = Tu[u].copy()
+        for e_id in np.flatnonzero(model.edges[:, 1] == u):
+            v = model.edges[e_id, 0]
+            c += pw[e_id, labels[v], :] - ph[e_id, 0, labels[v]] - ph[e_id, 1, :]
+        assert c[labels[u]] <= c.min() + 1e-9 * max(1.0, np.abs(c).max())
