@@ -161,6 +161,7 @@ int mplpxx_iterate_trace(mplpxx_solver* h, int32_t k, double* trace);
 #define MPLPXX_OPT_THREADS 2     /* threads per workgroup: 0 auto, 256, 512, 1024 */
 #define MPLPXX_OPT_GRID 3        /* workgroups of the persistent engine (0 auto) */
 #define MPLPXX_OPT_SPIN_LIMIT 4  /* device wait bound in polls (0 default) */
+#define MPLPXX_OPT_PROFILE 5     /* 1: record per-slot timestamps (persistent FP32 engine) */
 int mplpxx_set_option(mplpxx_solver* h, int32_t key, int64_t value);
 
 /* Read-only facts about the handle. */
@@ -173,7 +174,15 @@ int mplpxx_set_option(mplpxx_solver* h, int32_t key, int64_t value);
 #define MPLPXX_INFO_GRID 7       /* workgroups of the persistent engine */
 #define MPLPXX_INFO_THREADS 8    /* threads per workgroup */
 #define MPLPXX_INFO_ITERATIONS 9 /* iterations run since create / set_state */
+#define MPLPXX_INFO_WALLCLOCK_KHZ 10 /* device wall-clock rate of the timestamps */
 int mplpxx_get_info(mplpxx_solver* h, int32_t key, int64_t* value);
+
+/* Per-slot timestamps of the last iteration of the last iterate call of the
+ * persistent FP32 engine with MPLPXX_OPT_PROFILE set: HOST int64 [m][4] in
+ * schedule (slot) order = (start of the wait for the lower node, its data
+ * seen, upper node's data seen, results stored), in device wall-clock ticks
+ * (MPLPXX_INFO_WALLCLOCK_KHZ).  MPLPXX_ESTATE if nothing was recorded. */
+int mplpxx_get_step_profile(mplpxx_solver* h, int64_t* stamps);
 
 /* Average duration in milliseconds of the device work of the last iterate
  * call, measured with HIP events on the handle's stream around the launch

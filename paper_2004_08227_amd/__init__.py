@@ -24,9 +24,10 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "mplpxx.h")
 F32, F64 = 0, 1
 OK, EINVAL, ENOMEM, EDEVICE, ETIMEOUT, ESTATE = 0, -1, -2, -3, -4, -5
 MAX_LABELS = 128
-OPT_ENGINE, OPT_THREADS, OPT_GRID, OPT_SPIN_LIMIT = 1, 2, 3, 4
+OPT_ENGINE, OPT_THREADS, OPT_GRID, OPT_SPIN_LIMIT, OPT_PROFILE = 1, 2, 3, 4, 5
 ENGINE_AUTO, ENGINE_STEP, ENGINE_PERSISTENT = 0, 1, 2
-INFO = {"n": 1, "L": 2, "m": 3, "steps": 4, "dtype": 5, "engine": 6, "grid": 7, "threads": 8, "iterations": 9}
+INFO = {"n": 1, "L": 2, "m": 3, "steps": 4, "dtype": 5, "engine": 6, "grid": 7, "threads": 8, "iterations": 9,
+        "wallclock_khz": 10}
 
 _lib = None
 
@@ -78,6 +79,7 @@ def lib():
         "mplpxx_set_option": (ctypes.c_int, [vp, i32, i64]),
         "mplpxx_get_info": (ctypes.c_int, [vp, i32, ctypes.POINTER(i64)]),
         "mplpxx_last_iterate_ms": (ctypes.c_int, [vp, ctypes.POINTER(dbl)]),
+        "mplpxx_get_step_profile": (ctypes.c_int, [vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -227,6 +229,12 @@ class Solver:
         v = ctypes.c_int64()
         _check(lib().mplpxx_get_info(self._h, INFO[key], ctypes.byref(v)))
         return v.value
+
+    def step_profile(self):
+        """[m, 4] int64 timestamps (slot order) of the last iteration."""
+        st = np.zeros((max(self.m, 1), 4), dtype=np.int64)
+        _check(lib().mplpxx_get_step_profile(self._h, _ptr(st)))
+        return st[:self.m]
 
     def last_iterate_ms(self):
         d = ctypes.c_double()

@@ -9,6 +9,13 @@ namespace mplpxx {
 
 enum { ENGINE_AUTO = 0, ENGINE_STEP = 1, ENGINE_PERSISTENT = 2 };
 
+// timestamps per slot: 4 in normal builds; a diagnostics build
+// (-DMPLPXX_FINE_STAMPS=1) records 4 more points inside the edge update
+#ifndef MPLPXX_FINE_STAMPS
+#define MPLPXX_FINE_STAMPS 0
+#endif
+constexpr int kStampStride = MPLPXX_FINE_STAMPS ? 8 : 4;
+
 // One entry per schedule slot (slot i = i-th edge of the schedule queue).
 struct SlotInfo {
   int e;       // index of the edge in the caller's edge list
@@ -27,6 +34,7 @@ template <typename T> struct HsArgs {
   int* ver;               // [n] per-node update counters (persistent engine)
   int* err;               // device error word
   double* trace;          // [iters][n] per-node minima after the node's last update, or null
+  long long* stamps;      // [m][4] wall-clock stamps of the last iteration, or null
   int L, m, n;
   long long spin_limit;
 };
@@ -35,6 +43,11 @@ template <typename T>
 hipError_t launch_handshake(const HsArgs<T>& a, int engine, int LT, int NT, int slot_begin, int count, int grid,
                             int iters, hipStream_t st);
 template <typename T> int max_blocks_per_cu(int engine, int LT, int NT);
+// FP32 persistent engine with tagged mailboxes
+hipError_t launch_persistent_mb(const HsArgs<float>& a, unsigned long long* mb, int LT, int NT, int grid, int iters,
+                                int phi_in_lds, size_t dyn_lds, hipStream_t st);
+hipError_t launch_mb_init(const float* U, unsigned long long* mb, size_t count, hipStream_t st);
+hipError_t launch_mb_fini(float* U, const unsigned long long* mb, int n, int L, double* trace_row, hipStream_t st);
 
 // dual bound, traces, decode (dual.hip)
 template <typename T>

@@ -43,17 +43,51 @@ template <> __device__ __forceinline__ double inf_v<double>() { return __builtin
 __device__ __forceinline__ float vmin(float a, float b) { return __builtin_fminf(a, b); }
 __device__ __forceinline__ double vmin(double a, double b) { return __builtin_fmin(a, b); }
 
+// Cross-lane minima without LDS traffic.  DPP row operations stay inside a
+// 16-lane row: quad_perm [1,0,3,2] and [2,3,0,1] combine lanes of a quad,
+// row_half_mirror joins the two quads of each half row, row_mirror the two
+// halves.  gfx950's v_permlane16_swap / v_permlane32_swap exchange rows
+// (lanes 16 and 32 apart).  Min is exact and order-free, so every lane ends
+// with the same bits whatever the exchange pattern.
+template <int CTRL> __device__ __forceinline__ float dpp_f(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL> __device__ __forceinline__ double dpp_f(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(v & 0xffffffff), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // minimum over the 16 lanes of a row (lanes 16k .. 16k+15), result in all 16
 template <typename T> __device__ __forceinline__ T row16_min(T x) {
-  x = vmin(x, __shfl_xor(x, 1, 16));
-  x = vmin(x, __shfl_xor(x, 2, 16));
-  x = vmin(x, __shfl_xor(x, 4, 16));
-  x = vmin(x, __shfl_xor(x, 8, 16));
+  x = vmin(x, dpp_f<0xB1>(x));   // quad_perm [1,0,3,2]
+  x = vmin(x, dpp_f<0x4E>(x));   // quad_perm [2,3,0,1]
+  x = vmin(x, dpp_f<0x141>(x));  // row_half_mirror
+  x = vmin(x, dpp_f<0x140>(x));  // row_mirror
   return x;
 }
 
+// the same for N independent values at once (interleaved for ILP)
+template <int N, typename T> __device__ __forceinline__ void row16_min_n(T (&x)[N]) {
+#pragma unroll
+  for (int k = 0; k < N; ++k) x[k] = vmin(x[k], dpp_f<0xB1>(x[k]));
+#pragma unroll
+  for (int k = 0; k < N; ++k) x[k] = vmin(x[k], dpp_f<0x4E>(x[k]));
+#pragma unroll
+  for (int k = 0; k < N; ++k) x[k] = vmin(x[k], dpp_f<0x141>(x[k]));
+#pragma unroll
+  for (int k = 0; k < N; ++k) x[k] = vmin(x[k], dpp_f<0x140>(x[k]));
+}
+
 // minimum over lanes l, l^16, l^32, l^48 (the 4 row blocks of one wave)
-template <typename T> __device__ __forceinline__ T col4_min(T x) {
+__device__ __forceinline__ float col4_min(float x) {
+  auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  x = vmin(__uint_as_float(a[0]), __uint_as_float(a[1]));
+  auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  return vmin(__uint_as_float(b[0]), __uint_as_float(b[1]));
+}
+__device__ __forceinline__ double col4_min(double x) {
   x = vmin(x, __shfl_xor(x, 16, 64));
   x = vmin(x, __shfl_xor(x, 32, 64));
   return x;
@@ -342,6 +376,291 @@ __global__ void __launch_bounds__(NT) k_persistent(HsArgs<T> a, int iters) {
 }
 
 // ---------------------------------------------------------------------------
+// Engine 2, FP32: persistent with tagged mailboxes.
+//
+// The reparametrized unaries travel between workgroups through a mailbox
+// array MB[n][L] of 64-bit words: low half = the FP32 bits of U_u(s), high
+// half = the number of updates node u has seen in this launch.  A consumer
+// polls the words it needs until every one carries the version it expects,
+// so the data is its own ready flag: no separate flag store, no wait for
+// store completion on the producer side.  Each word is written and read with
+// one 64-bit device-scope atomic access, so a value and its version can
+// never be seen torn.
+//
+// Two extra "sync" waves (threads NT .. NT+127) do all polling and gathering:
+// they issue no other loads, so a poll never queues behind a table prefetch
+// in the in-order memory counter of the compute waves.  The messages of the
+// slots a workgroup owns stay in LDS for the whole launch when they fit.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long mb_pack(float v, unsigned ver) {
+  return ((unsigned long long)ver << 32) | (unsigned long long)__float_as_uint(v);
+}
+__device__ __forceinline__ unsigned long long mb_load(const unsigned long long* p) {
+  return __hip_atomic_load(const_cast<unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void mb_store(unsigned long long* p, unsigned long long w) {
+  __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int LT, int NT> struct SmemMB {
+  float uu[2][LT];   // raw U_u delivered by the sync wave (double buffered by slot parity)
+  float uv[2][LT];
+  float red[TileShape<float, LT, NT>::W][LT];
+  int abort_flag;
+};
+
+// the sync wave: poll MB[node] until all L words carry `want`, deliver values
+template <int LT>
+__device__ __forceinline__ bool sync_gather(const unsigned long long* __restrict__ mb_row, int L, unsigned want,
+                                            float* dst, long long spin_limit, const int* err) {
+  const int lane = threadIdx.x & 63;
+  constexpr int PER = (LT + 63) / 64;
+  bool have[PER];
+  float val[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) have[k] = (lane + 64 * k) >= L;
+  long long spins = 0;
+  for (;;) {
+    bool all = true;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      if (!have[k]) {
+        const unsigned long long w = mb_load(mb_row + lane + 64 * k);
+        if ((unsigned)(w >> 32) == want) {
+          have[k] = true;
+          val[k] = __uint_as_float((unsigned)w);
+        } else {
+          all = false;
+        }
+      }
+    }
+    if (__all(all)) break;
+    if (++spins > spin_limit || ((spins & 255) == 0 && ld_dev(err) != 0)) return false;
+  }
+#pragma unroll
+  for (int k = 0; k < PER; ++k)
+    if (lane + 64 * k < L) dst[lane + 64 * k] = val[k];
+  return true;
+}
+
+template <int LT, int NT, bool PHI_LDS, bool FULL>
+__global__ void __launch_bounds__(NT + 128) k_persistent_mb(HsArgs<float> a, unsigned long long* __restrict__ mb,
+                                                            int iters) {
+  // FULL: L == LT, every tile entry is real and no index needs a bound check
+  constexpr bool phi_in_lds = PHI_LDS;
+  using S = TileShape<float, LT, NT>;
+  __shared__ SmemMB<LT, NT> sm;
+  extern __shared__ float phi_lds[];
+  const int tid = threadIdx.x;
+  const int L = FULL ? LT : a.L;
+  const int G = gridDim.x;
+  const int wave = tid >> 6;
+  const bool is_compute = tid < NT;
+  const bool is_sync_u = wave == NT / 64;
+  const bool is_sync_v = wave == NT / 64 + 1;
+  if (blockIdx.x >= a.m) return;
+  if (tid == 0) sm.abort_flag = 0;
+  // messages of the owned slots into LDS
+  if (phi_in_lds) {
+    for (int slot = blockIdx.x, j = 0; slot < a.m; slot += G, ++j)
+      for (int k = tid; k < 2 * L; k += NT + 128) phi_lds[j * 2 * L + k] = a.phi[(size_t)slot * 2 * L + k];
+  }
+  __syncthreads();
+
+  float x[S::BR][S::BC];
+  float y[S::BR][S::BC];
+  if (is_compute) load_tile<float, LT, NT>(a.tables + (size_t)blockIdx.x * L * L, L, x);
+  int parity = 0;
+  for (int it = 0; it < iters; ++it) {
+    int j = 0;
+    for (int slot = blockIdx.x; slot < a.m; slot += G, ++j, parity ^= 1) {
+      const SlotInfo si = a.slots[slot];
+      const unsigned want_u = (unsigned)(it * a.deg[si.u] + si.pos_u);
+      const unsigned want_v = (unsigned)(it * a.deg[si.v] + si.pos_v);
+      int nxt = slot + G;
+      if (nxt >= a.m) nxt = blockIdx.x;
+      const bool pref = nxt != slot && (it + 1 < iters || nxt > slot);
+      if (is_compute) {
+        // table of the next owned slot, off the dependency chain
+        if (pref) load_tile<float, LT, NT>(a.tables + (size_t)nxt * L * L, L, y);
+#if MPLPXX_FINE_STAMPS
+        if (a.stamps && it == iters - 1 && tid == 0) a.stamps[(size_t)slot * kStampStride + 4] = wall_clock64();
+#endif
+      } else {
+        const bool last_iter = it == iters - 1;
+        if (a.stamps && last_iter && (tid & 63) == 0 && is_sync_u) a.stamps[(size_t)slot * kStampStride + 0] = wall_clock64();
+        const int node = is_sync_u ? si.u : si.v;
+        const unsigned want = is_sync_u ? want_u : want_v;
+        float* dst = is_sync_u ? sm.uu[parity] : sm.uv[parity];
+        if (!sync_gather<LT>(mb + (size_t)node * L, L, want, dst, a.spin_limit, a.err)) {
+          if ((tid & 63) == 0) {
+            atomicCAS(a.err, 0, MPLPXX_ETIMEOUT);
+            sm.abort_flag = 1;
+          }
+        }
+        if (a.stamps && last_iter && (tid & 63) == 0) a.stamps[(size_t)slot * kStampStride + (is_sync_u ? 1 : 2)] = wall_clock64();
+      }
+      __syncthreads();
+      if (sm.abort_flag) return;
+      if (is_compute) {
+#if MPLPXX_FINE_STAMPS
+        if (a.stamps && it == iters - 1 && tid == 0) a.stamps[(size_t)slot * kStampStride + 5] = wall_clock64();
+#endif
+        const float* phi_s = phi_in_lds ? phi_lds + j * 2 * L : a.phi + (size_t)slot * 2 * L;
+        using SS = S;
+        const int rb = tid >> 4, cb = tid & 15;
+        const int lane = tid & 63;
+        // unconditional LDS reads at clamped indices, then a select: keeps
+        // the reads in one batch instead of one branch and wait per entry
+        float av[SS::BC], au[SS::BR];
+#pragma unroll
+        for (int jj = 0; jj < SS::BC; ++jj) {
+          const int t = cb * SS::BC + jj;
+          const int tc = (FULL || t < L) ? t : L - 1;
+          const float v = sm.uv[parity][tc] - phi_s[L + tc];
+          av[jj] = (FULL || t < L) ? v : 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < SS::BR; ++i) {
+          const int s = rb * SS::BR + i;
+          const int sc = (FULL || s < L) ? s : L - 1;
+          const float v = sm.uu[parity][sc] - phi_s[sc];
+          au[i] = (FULL || s < L) ? v : 0.f;
+        }
+        // pass 1
+        float b[SS::BR];
+        {
+          float pm[SS::BR];
+#pragma unroll
+          for (int i = 0; i < SS::BR; ++i) {
+            float mn = x[i][0] + av[0];
+#pragma unroll
+            for (int jj = 1; jj < SS::BC; ++jj) mn = vmin(mn, x[i][jj] + av[jj]);
+            pm[i] = mn;
+          }
+          row16_min_n<SS::BR>(pm);
+#pragma unroll
+          for (int i = 0; i < SS::BR; ++i) {
+            const int s = rb * SS::BR + i;
+            b[i] = (FULL || s < L) ? 0.5f * (au[i] - pm[i]) : 0.f;
+          }
+        }
+        // pass 2
+        float q[SS::BC];
+#pragma unroll
+        for (int jj = 0; jj < SS::BC; ++jj) {
+          float mn = x[0][jj] + b[0];
+#pragma unroll
+          for (int i = 1; i < SS::BR; ++i) mn = vmin(mn, x[i][jj] + b[i]);
+          q[jj] = col4_min(mn);
+        }
+        if (lane < 16) {
+#pragma unroll
+          for (int jj = 0; jj < SS::BC; ++jj) sm.red[wave][cb * SS::BC + jj] = q[jj];
+        }
+#if MPLPXX_FINE_STAMPS
+        if (a.stamps && it == iters - 1 && tid == 0) a.stamps[(size_t)slot * kStampStride + 6] = wall_clock64();
+#endif
+        __syncthreads();  // matched by the sync waves' barrier below
+#if MPLPXX_FINE_STAMPS
+        if (a.stamps && it == iters - 1 && tid == 0) a.stamps[(size_t)slot * kStampStride + 7] = wall_clock64();
+#endif
+#pragma unroll
+        for (int jj = 0; jj < SS::BC; ++jj) {
+          const int t = cb * SS::BC + jj;
+          float mn = sm.red[0][t];
+#pragma unroll
+          for (int w = 1; w < SS::W; ++w) mn = vmin(mn, sm.red[w][t]);
+          q[jj] = (FULL || t < L) ? mn : 0.f;
+        }
+        // pass 3
+        float r[SS::BR];
+#pragma unroll
+        for (int i = 0; i < SS::BR; ++i) {
+          float mn = x[i][0] - q[0];
+#pragma unroll
+          for (int jj = 1; jj < SS::BC; ++jj) mn = vmin(mn, x[i][jj] - q[jj]);
+          r[i] = mn;
+        }
+        row16_min_n<SS::BR>(r);
+        float* phi_w = phi_in_lds ? phi_lds + j * 2 * L : a.phi + (size_t)slot * 2 * L;
+        if (rb == 0) {
+#pragma unroll
+          for (int jj = 0; jj < SS::BC; ++jj) {
+            const int t = cb * SS::BC + jj;
+            if (FULL || t < L) {
+              mb_store(mb + (size_t)si.v * L + t, mb_pack(av[jj] + q[jj], want_v + 1));
+              phi_w[L + t] = q[jj];
+            }
+          }
+        }
+        if (cb == 0) {
+#pragma unroll
+          for (int i = 0; i < SS::BR; ++i) {
+            const int s = rb * SS::BR + i;
+            if (FULL || s < L) {
+              mb_store(mb + (size_t)si.u * L + s, mb_pack(au[i] + r[i], want_u + 1));
+              phi_w[s] = r[i];
+            }
+          }
+        }
+        if (a.stamps && it == iters - 1 && tid == 0) a.stamps[(size_t)slot * kStampStride + 3] = wall_clock64();
+        if (pref) {
+#pragma unroll
+          for (int i = 0; i < SS::BR; ++i)
+#pragma unroll
+            for (int jj = 0; jj < SS::BC; ++jj) x[i][jj] = y[i][jj];
+        }
+      } else {
+        // the sync waves take part in the compute waves' mid-slot barrier
+        __syncthreads();
+        // per-iteration trace: the first update of a node in iteration it
+        // sees the node's value at the end of iteration it-1
+        if (a.trace && it > 0) {
+          const bool first = is_sync_u ? (si.pos_u == 0) : (si.pos_v == 0);
+          if (first) {
+            const float* src = is_sync_u ? sm.uu[parity] : sm.uv[parity];
+            const int lane = tid & 63;
+            double mn = __builtin_inf();
+            for (int s2 = lane; s2 < L; s2 += 64) mn = __builtin_fmin(mn, (double)src[s2]);
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) mn = __builtin_fmin(mn, __shfl_xor(mn, o, 64));
+            if (lane == 0) a.trace[(size_t)(it - 1) * a.n + (is_sync_u ? si.u : si.v)] = mn;
+          }
+        }
+      }
+    }
+  }
+  // messages back to global memory
+  __syncthreads();
+  if (phi_in_lds) {
+    for (int slot = blockIdx.x, j = 0; slot < a.m; slot += G, ++j)
+      for (int k = tid; k < 2 * L; k += NT + 128) a.phi[(size_t)slot * 2 * L + k] = phi_lds[j * 2 * L + k];
+  }
+}
+
+// mailbox <- (U, version 0)
+__global__ void k_mb_init(const float* __restrict__ U, unsigned long long* __restrict__ mb, size_t count) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+    mb[i] = ((unsigned long long)__float_as_uint(U[i]));
+}
+
+// U <- mailbox values; trace row of the last iteration from the final values
+__global__ void k_mb_fini(float* __restrict__ U, const unsigned long long* __restrict__ mb, int n, int L,
+                          double* __restrict__ trace_row) {
+  const int u = blockIdx.x;
+  double mn = __builtin_inf();
+  for (int s = threadIdx.x; s < L; s += 64) {
+    const float v = __uint_as_float((unsigned)mb[(size_t)u * L + s]);
+    U[(size_t)u * L + s] = v;
+    mn = __builtin_fmin(mn, (double)v);
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) mn = __builtin_fmin(mn, __shfl_xor(mn, o, 64));
+  if (trace_row && threadIdx.x == 0) trace_row[u] = mn;
+}
+
+// ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
 template <typename T, int LT, int NT>
@@ -354,6 +673,44 @@ static hipError_t launch_one(const HsArgs<T>& a, int engine, int slot_begin, int
   }
   void* args[] = {(void*)&a, (void*)&iters};
   return hipLaunchCooperativeKernel((const void*)k_persistent<T, LT, NT>, dim3(grid), dim3(NT), args, 0, st);
+}
+
+template <int LT, int NT>
+static hipError_t launch_mb_one(const HsArgs<float>& a, unsigned long long* mb, int grid, int iters, int phi_in_lds,
+                                size_t dyn_lds, hipStream_t st) {
+  void* args[] = {(void*)&a, (void*)&mb, (void*)&iters};
+  const bool full = a.L == LT;
+  const void* f = phi_in_lds ? (full ? (const void*)k_persistent_mb<LT, NT, true, true> : (const void*)k_persistent_mb<LT, NT, true, false>)
+                             : (full ? (const void*)k_persistent_mb<LT, NT, false, true> : (const void*)k_persistent_mb<LT, NT, false, false>);
+  return hipLaunchCooperativeKernel(f, dim3(grid), dim3(NT + 128), args, dyn_lds, st);
+}
+
+hipError_t launch_persistent_mb(const HsArgs<float>& a, unsigned long long* mb, int LT, int NT, int grid, int iters,
+                                int phi_in_lds, size_t dyn_lds, hipStream_t st) {
+#define MPLPXX_CASE(lt, nt) \
+  if (LT == lt && NT == nt) return launch_mb_one<lt, nt>(a, mb, grid, iters, phi_in_lds, dyn_lds, st);
+  MPLPXX_CASE(16, 256)
+  MPLPXX_CASE(32, 256)
+  MPLPXX_CASE(32, 512)
+  MPLPXX_CASE(64, 256)
+  MPLPXX_CASE(64, 512)
+  MPLPXX_CASE(128, 256)
+  MPLPXX_CASE(128, 512)
+#undef MPLPXX_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_mb_init(const float* U, unsigned long long* mb, size_t count, hipStream_t st) {
+  size_t blocks = (count + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mb_init, dim3((unsigned)blocks), dim3(256), 0, st, U, mb, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_mb_fini(float* U, const unsigned long long* mb, int n, int L, double* trace_row, hipStream_t st) {
+  hipLaunchKernelGGL(k_mb_fini, dim3(n), dim3(64), 0, st, U, mb, n, L, trace_row);
+  return hipGetLastError();
 }
 
 template <typename T>

@@ -95,6 +95,10 @@ struct mplpxx_solver {
   double* d_trace_nodes = nullptr;
   double* d_trace_out = nullptr;
   int trace_cap = 0;
+  unsigned long long* d_mb = nullptr;    // FP32 mailboxes of the persistent engine
+  long long* d_stamps = nullptr;         // per-slot timestamps (profiling option)
+  bool profile = false;
+  int wallclock_khz = 0;
   // execution
   hipStream_t user_stream = nullptr;
   hipStream_t own_stream = nullptr;
@@ -113,6 +117,8 @@ struct mplpxx_solver {
   int NT() const {
     int nt = threads_opt ? threads_opt : 256;
     if (!valid_threads(LT(), nt)) nt = 256;
+    // the FP32 persistent engine adds two sync waves: at most 512 + 128 threads
+    if (dtype == MPLPXX_F32 && engine() == ENGINE_PERSISTENT && nt > 512) nt = 512;
     return nt;
   }
   int engine() const {
@@ -132,7 +138,7 @@ namespace {
 void free_all(mplpxx_solver* h) {
   void* ptrs[] = {h->d_tables, h->d_phi, h->d_U, h->d_unaries, h->d_slots, h->d_deg, h->d_ver, h->d_err,
                   h->d_node_ptr, h->d_inc, h->d_node_min, h->d_edge_min, h->d_scalar, h->d_labels,
-                  h->d_trace_nodes, h->d_trace_out};
+                  h->d_trace_nodes, h->d_trace_out, h->d_mb, h->d_stamps};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h->ev0) (void)hipEventDestroy(h->ev0);
@@ -239,6 +245,7 @@ int create_impl(int32_t n, int32_t L, int64_t m, const int32_t* edges, const voi
   int dev = 0;
   TRY(hipGetDevice(&dev));
   TRY(hipDeviceGetAttribute(&h->num_cus, hipDeviceAttributeMultiprocessorCount, dev));
+  TRY(hipDeviceGetAttribute(&h->wallclock_khz, hipDeviceAttributeWallClockRate, dev));
   TRY(hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking));
   TRY(hipEventCreate(&h->ev0));
   TRY(hipEventCreate(&h->ev1));
@@ -257,6 +264,10 @@ int create_impl(int32_t n, int32_t L, int64_t m, const int32_t* edges, const voi
   h->d_edge_min = dalloc<double>(m, &ae); TRY(ae);
   h->d_scalar = dalloc<double>(4, &ae); TRY(ae);
   h->d_labels = dalloc<int>(n, &ae); TRY(ae);
+  if (dtype == MPLPXX_F32) {
+    h->d_mb = dalloc<unsigned long long>(nL, &ae);
+    TRY(ae);
+  }
 
   hipStream_t st = h->own_stream;
   // incidence lists (CSR by node, slots ascending) for dual and decode
@@ -373,6 +384,7 @@ template <typename T> HsArgs<T> hs_args(mplpxx_solver* h, double* trace) {
   a.ver = h->d_ver;
   a.err = h->d_err;
   a.trace = trace;
+  a.stamps = h->profile ? h->d_stamps : nullptr;
   a.L = h->L;
   a.m = h->m;
   a.n = h->n;
@@ -380,8 +392,15 @@ template <typename T> HsArgs<T> hs_args(mplpxx_solver* h, double* trace) {
   return a;
 }
 
+// messages of a workgroup's slots kept in LDS up to this size
+constexpr size_t kPhiLdsBudget = 96 * 1024;
+
 template <typename T> int iterate_t(mplpxx_solver* h, int k, double* trace_host) {
   hipStream_t st = h->stream();
+  if (h->profile && !h->d_stamps && h->m > 0) {
+    HIP_TRY(hipMalloc(&h->d_stamps, (size_t)h->m * kStampStride * sizeof(long long)));
+    HIP_TRY(hipMemsetAsync(h->d_stamps, 0, (size_t)h->m * kStampStride * sizeof(long long), st));
+  }
   if (trace_host && k > h->trace_cap) {
     if (h->d_trace_nodes) (void)hipFree(h->d_trace_nodes);
     if (h->d_trace_out) (void)hipFree(h->d_trace_out);
@@ -406,6 +425,17 @@ template <typename T> int iterate_t(mplpxx_solver* h, int k, double* trace_host)
         if (trace_host)
           HIP_TRY(launch_trace_nodes<T>(static_cast<const T*>(h->d_U), h->n, h->L, h->d_trace_nodes + (size_t)it * h->n, st));
       }
+    } else if (sizeof(T) == 4) {
+      // FP32: tagged mailboxes; messages stay in LDS when they fit
+      HsArgs<float> a = hs_args<float>(h, trace_host ? h->d_trace_nodes : nullptr);
+      const int G = h->grid();
+      const size_t owned = ((size_t)h->m + G - 1) / G;
+      const size_t phi_bytes = owned * 2 * h->L * sizeof(float);
+      const int in_lds = phi_bytes <= kPhiLdsBudget ? 1 : 0;
+      HIP_TRY(launch_mb_init(static_cast<const float*>(h->d_U), h->d_mb, (size_t)h->n * h->L, st));
+      HIP_TRY(launch_persistent_mb(a, h->d_mb, LT, NT, G, k, in_lds, in_lds ? phi_bytes : 0, st));
+      HIP_TRY(launch_mb_fini(static_cast<float*>(h->d_U), h->d_mb, h->n, h->L,
+                             trace_host ? h->d_trace_nodes + (size_t)(k - 1) * h->n : nullptr, st));
     } else {
       HsArgs<T> a = hs_args<T>(h, trace_host ? h->d_trace_nodes : nullptr);
       HIP_TRY(launch_fill_int(h->d_ver, 0, h->n, st));
@@ -602,6 +632,9 @@ int mplpxx_set_option(mplpxx_solver* h, int32_t key, int64_t value) {
       if (value < 0) return fail(MPLPXX_EINVAL, "spin limit must be >= 0");
       h->spin_limit = value ? value : (1ll << 22);
       return MPLPXX_OK;
+    case MPLPXX_OPT_PROFILE:
+      h->profile = value != 0;
+      return MPLPXX_OK;
     default:
       return fail(MPLPXX_EINVAL, "unknown option %d", key);
   }
@@ -619,8 +652,17 @@ int mplpxx_get_info(mplpxx_solver* h, int32_t key, int64_t* value) {
     case MPLPXX_INFO_GRID: *value = h->grid(); return MPLPXX_OK;
     case MPLPXX_INFO_THREADS: *value = h->NT(); return MPLPXX_OK;
     case MPLPXX_INFO_ITERATIONS: *value = h->iterations; return MPLPXX_OK;
+    case MPLPXX_INFO_WALLCLOCK_KHZ: *value = h->wallclock_khz; return MPLPXX_OK;
     default: return fail(MPLPXX_EINVAL, "unknown info key %d", key);
   }
+}
+
+int mplpxx_get_step_profile(mplpxx_solver* h, int64_t* stamps) {
+  if (!h || !stamps) return fail(MPLPXX_EINVAL, "NULL argument");
+  if (!h->d_stamps) return fail(MPLPXX_ESTATE, "no profile recorded (set MPLPXX_OPT_PROFILE and iterate first)");
+  HIP_TRY(hipStreamSynchronize(h->stream()));
+  HIP_TRY(hipMemcpy(stamps, h->d_stamps, (size_t)h->m * kStampStride * sizeof(long long), hipMemcpyDeviceToHost));
+  return MPLPXX_OK;
 }
 
 int mplpxx_last_iterate_ms(mplpxx_solver* h, double* ms) {

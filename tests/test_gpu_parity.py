@@ -210,3 +210,16 @@ def test_decode_is_valid_rounding_of_gpu_state():
             v = model.edges[e_id, 0]
             c += pw[e_id, labels[v], :] - ph[e_id, 0, labels[v]] - ph[e_id, 1, :]
         assert c[labels[u]] <= c.min() + 1e-9 * max(1.0, np.abs(c).max())
+
+
+def test_step_profile_timestamps_are_ordered():
+    _announce("profile")
+    model = W.pose(40, 32, seed=16)
+    with M.Solver.from_model(model) as s:
+        s.set_option(M.OPT_ENGINE, M.ENGINE_PERSISTENT)
+        s.set_option(M.OPT_PROFILE, 1)
+        s.iterate(3)
+        st = s.step_profile()
+        assert s.info("wallclock_khz") > 0
+    assert st.shape == (model.m, 4) and np.all(st > 0)
+    assert np.all(st[:, 1] >= st[:, 0]) and np.all(st[:, 3] >= np.maximum(st[:, 1], st[:, 2]))
