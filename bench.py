@@ -129,7 +129,8 @@ def main():
         "dual_bound": d_final,
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_persistent<float,64,256>" if s.info("engine") == 2 else "k_step<float,64,256>",
+                     "kernel": (f"k_persistent_mb<{L},{s.info('threads')},...>" if s.info("engine") == 2
+                                else f"k_step<float,{L},{s.info('threads')}>"),
                      "bytes_per_update": B, "updates_per_launch": m * K if s.info("engine") == 2 else m // s.info("steps")},
     }
     if not args.no_cpu:

@@ -443,197 +443,251 @@ __device__ __forceinline__ bool sync_gather(const unsigned long long* __restrict
   return true;
 }
 
+// One model as the mailbox engine sees it.
+struct MbView {
+  const float* tables;          // [m][L][L] slot order
+  float* phi;                   // [m][2][L] slot order
+  unsigned long long* mb;       // [n][L] mailboxes
+  const SlotInfo* slots;        // [m]
+  const int* deg;               // [n]
+  double* trace;                // [iters][n] or null
+  long long* stamps;            // [m][kStampStride] or null
+  int L, m, n;
+};
+
+// Messages of one slot for this thread's rows (into u) and columns (into v).
 template <int LT, int NT, bool PHI_LDS, bool FULL>
-__global__ void __launch_bounds__(NT + 128) k_persistent_mb(HsArgs<float> a, unsigned long long* __restrict__ mb,
-                                                            int iters) {
-  // FULL: L == LT, every tile entry is real and no index needs a bound check
-  constexpr bool phi_in_lds = PHI_LDS;
+__device__ __forceinline__ void load_phi(const float* src, int L, float (&pu)[TileShape<float, LT, NT>::BR],
+                                         float (&pv)[TileShape<float, LT, NT>::BC]) {
   using S = TileShape<float, LT, NT>;
-  __shared__ SmemMB<LT, NT> sm;
-  extern __shared__ float phi_lds[];
+  const int rb = threadIdx.x >> 4, cb = threadIdx.x & 15;
+#pragma unroll
+  for (int i = 0; i < S::BR; ++i) {
+    const int s = rb * S::BR + i;
+    pu[i] = src[(FULL || s < L) ? s : L - 1];
+  }
+#pragma unroll
+  for (int jj = 0; jj < S::BC; ++jj) {
+    const int t = cb * S::BC + jj;
+    pv[jj] = src[L + ((FULL || t < L) ? t : L - 1)];
+  }
+}
+
+// Runs `iters` iterations over the slots first, first+stride, ... of one
+// model.  Compute threads [0, NT) hold the table of the current slot in
+// registers and prefetch the next one together with its messages; threads
+// [NT, NT+128) are the two sync waves.  Returns false if a wait timed out
+// (the error word is set); every thread of the block returns the same value.
+template <int LT, int NT, bool PHI_LDS, bool FULL>
+__device__ __forceinline__ bool mb_run(const MbView& v, int first, int stride, int iters, SmemMB<LT, NT>& sm,
+                                       float* phi_lds, long long spin_limit, int* err) {
+  using S = TileShape<float, LT, NT>;
   const int tid = threadIdx.x;
-  const int L = FULL ? LT : a.L;
-  const int G = gridDim.x;
+  const int L = FULL ? LT : v.L;
   const int wave = tid >> 6;
   const bool is_compute = tid < NT;
   const bool is_sync_u = wave == NT / 64;
-  const bool is_sync_v = wave == NT / 64 + 1;
-  if (blockIdx.x >= a.m) return;
-  if (tid == 0) sm.abort_flag = 0;
-  // messages of the owned slots into LDS
-  if (phi_in_lds) {
-    for (int slot = blockIdx.x, j = 0; slot < a.m; slot += G, ++j)
-      for (int k = tid; k < 2 * L; k += NT + 128) phi_lds[j * 2 * L + k] = a.phi[(size_t)slot * 2 * L + k];
+  const int rb = tid >> 4, cb = tid & 15, lane = tid & 63;
+  if (first >= v.m) return true;
+  auto phi_of = [&](int slot, int j) -> float* {
+    return PHI_LDS ? phi_lds + (size_t)j * 2 * L : v.phi + (size_t)slot * 2 * L;
+  };
+  float x[S::BR][S::BC], y[S::BR][S::BC];
+  float pu[S::BR], pv[S::BC], npu[S::BR], npv[S::BC];
+  if (is_compute) {
+    load_tile<float, LT, NT>(v.tables + (size_t)first * L * L, L, x);
+    load_phi<LT, NT, PHI_LDS, FULL>(phi_of(first, 0), L, pu, pv);
   }
-  __syncthreads();
-
-  float x[S::BR][S::BC];
-  float y[S::BR][S::BC];
-  if (is_compute) load_tile<float, LT, NT>(a.tables + (size_t)blockIdx.x * L * L, L, x);
   int parity = 0;
   for (int it = 0; it < iters; ++it) {
     int j = 0;
-    for (int slot = blockIdx.x; slot < a.m; slot += G, ++j, parity ^= 1) {
-      const SlotInfo si = a.slots[slot];
-      const unsigned want_u = (unsigned)(it * a.deg[si.u] + si.pos_u);
-      const unsigned want_v = (unsigned)(it * a.deg[si.v] + si.pos_v);
-      int nxt = slot + G;
-      if (nxt >= a.m) nxt = blockIdx.x;
+    for (int slot = first; slot < v.m; slot += stride, ++j, parity ^= 1) {
+      const SlotInfo si = v.slots[slot];
+      const unsigned want_u = (unsigned)(it * v.deg[si.u] + si.pos_u);
+      const unsigned want_v = (unsigned)(it * v.deg[si.v] + si.pos_v);
+      int nxt = slot + stride, jn = j + 1;
+      if (nxt >= v.m) { nxt = first; jn = 0; }
       const bool pref = nxt != slot && (it + 1 < iters || nxt > slot);
+      const bool last_iter = it == iters - 1;
       if (is_compute) {
-        // table of the next owned slot, off the dependency chain
-        if (pref) load_tile<float, LT, NT>(a.tables + (size_t)nxt * L * L, L, y);
+        // table and messages of the next owned slot, off the dependency chain
+        if (pref) {
+          load_tile<float, LT, NT>(v.tables + (size_t)nxt * L * L, L, y);
+          load_phi<LT, NT, PHI_LDS, FULL>(phi_of(nxt, jn), L, npu, npv);
+        }
 #if MPLPXX_FINE_STAMPS
-        if (a.stamps && it == iters - 1 && tid == 0) a.stamps[(size_t)slot * kStampStride + 4] = wall_clock64();
+        if (v.stamps && last_iter && tid == 0) v.stamps[(size_t)slot * kStampStride + 4] = wall_clock64();
 #endif
       } else {
-        const bool last_iter = it == iters - 1;
-        if (a.stamps && last_iter && (tid & 63) == 0 && is_sync_u) a.stamps[(size_t)slot * kStampStride + 0] = wall_clock64();
+        if (v.stamps && last_iter && lane == 0 && is_sync_u) v.stamps[(size_t)slot * kStampStride + 0] = wall_clock64();
         const int node = is_sync_u ? si.u : si.v;
         const unsigned want = is_sync_u ? want_u : want_v;
         float* dst = is_sync_u ? sm.uu[parity] : sm.uv[parity];
-        if (!sync_gather<LT>(mb + (size_t)node * L, L, want, dst, a.spin_limit, a.err)) {
-          if ((tid & 63) == 0) {
-            atomicCAS(a.err, 0, MPLPXX_ETIMEOUT);
+        if (!sync_gather<LT>(v.mb + (size_t)node * L, L, want, dst, spin_limit, err)) {
+          if (lane == 0) {
+            atomicCAS(err, 0, MPLPXX_ETIMEOUT);
             sm.abort_flag = 1;
           }
         }
-        if (a.stamps && last_iter && (tid & 63) == 0) a.stamps[(size_t)slot * kStampStride + (is_sync_u ? 1 : 2)] = wall_clock64();
+        if (v.stamps && last_iter && lane == 0) v.stamps[(size_t)slot * kStampStride + (is_sync_u ? 1 : 2)] = wall_clock64();
       }
       __syncthreads();
-      if (sm.abort_flag) return;
+      if (sm.abort_flag) return false;
       if (is_compute) {
 #if MPLPXX_FINE_STAMPS
-        if (a.stamps && it == iters - 1 && tid == 0) a.stamps[(size_t)slot * kStampStride + 5] = wall_clock64();
+        if (v.stamps && last_iter && tid == 0) v.stamps[(size_t)slot * kStampStride + 5] = wall_clock64();
 #endif
-        const float* phi_s = phi_in_lds ? phi_lds + j * 2 * L : a.phi + (size_t)slot * 2 * L;
-        using SS = S;
-        const int rb = tid >> 4, cb = tid & 15;
-        const int lane = tid & 63;
-        // unconditional LDS reads at clamped indices, then a select: keeps
-        // the reads in one batch instead of one branch and wait per entry
-        float av[SS::BC], au[SS::BR];
+        // a = U - phi; unconditional LDS reads at clamped indices, then a
+        // select, so the reads issue as one batch
+        float av[S::BC], au[S::BR];
 #pragma unroll
-        for (int jj = 0; jj < SS::BC; ++jj) {
-          const int t = cb * SS::BC + jj;
+        for (int jj = 0; jj < S::BC; ++jj) {
+          const int t = cb * S::BC + jj;
           const int tc = (FULL || t < L) ? t : L - 1;
-          const float v = sm.uv[parity][tc] - phi_s[L + tc];
-          av[jj] = (FULL || t < L) ? v : 0.f;
+          av[jj] = (FULL || t < L) ? sm.uv[parity][tc] - pv[jj] : 0.f;
         }
 #pragma unroll
-        for (int i = 0; i < SS::BR; ++i) {
-          const int s = rb * SS::BR + i;
+        for (int i = 0; i < S::BR; ++i) {
+          const int s = rb * S::BR + i;
           const int sc = (FULL || s < L) ? s : L - 1;
-          const float v = sm.uu[parity][sc] - phi_s[sc];
-          au[i] = (FULL || s < L) ? v : 0.f;
+          au[i] = (FULL || s < L) ? sm.uu[parity][sc] - pu[i] : 0.f;
         }
-        // pass 1
-        float b[SS::BR];
+        // pass 1: p(s) = min_t [th(s,t) + a_v(t)], b = (a_u - p) / 2
+        float b[S::BR];
         {
-          float pm[SS::BR];
+          float pm[S::BR];
 #pragma unroll
-          for (int i = 0; i < SS::BR; ++i) {
+          for (int i = 0; i < S::BR; ++i) {
             float mn = x[i][0] + av[0];
 #pragma unroll
-            for (int jj = 1; jj < SS::BC; ++jj) mn = vmin(mn, x[i][jj] + av[jj]);
+            for (int jj = 1; jj < S::BC; ++jj) mn = vmin(mn, x[i][jj] + av[jj]);
             pm[i] = mn;
           }
-          row16_min_n<SS::BR>(pm);
+          row16_min_n<S::BR>(pm);
 #pragma unroll
-          for (int i = 0; i < SS::BR; ++i) {
-            const int s = rb * SS::BR + i;
+          for (int i = 0; i < S::BR; ++i) {
+            const int s = rb * S::BR + i;
             b[i] = (FULL || s < L) ? 0.5f * (au[i] - pm[i]) : 0.f;
           }
         }
-        // pass 2
-        float q[SS::BC];
+        // pass 2: q(t) = min_s [th(s,t) + b(s)]
+        float q[S::BC];
 #pragma unroll
-        for (int jj = 0; jj < SS::BC; ++jj) {
+        for (int jj = 0; jj < S::BC; ++jj) {
           float mn = x[0][jj] + b[0];
 #pragma unroll
-          for (int i = 1; i < SS::BR; ++i) mn = vmin(mn, x[i][jj] + b[i]);
+          for (int i = 1; i < S::BR; ++i) mn = vmin(mn, x[i][jj] + b[i]);
           q[jj] = col4_min(mn);
         }
         if (lane < 16) {
 #pragma unroll
-          for (int jj = 0; jj < SS::BC; ++jj) sm.red[wave][cb * SS::BC + jj] = q[jj];
+          for (int jj = 0; jj < S::BC; ++jj) sm.red[wave][cb * S::BC + jj] = q[jj];
         }
 #if MPLPXX_FINE_STAMPS
-        if (a.stamps && it == iters - 1 && tid == 0) a.stamps[(size_t)slot * kStampStride + 6] = wall_clock64();
+        if (v.stamps && last_iter && tid == 0) v.stamps[(size_t)slot * kStampStride + 6] = wall_clock64();
 #endif
         __syncthreads();  // matched by the sync waves' barrier below
 #if MPLPXX_FINE_STAMPS
-        if (a.stamps && it == iters - 1 && tid == 0) a.stamps[(size_t)slot * kStampStride + 7] = wall_clock64();
+        if (v.stamps && last_iter && tid == 0) v.stamps[(size_t)slot * kStampStride + 7] = wall_clock64();
 #endif
 #pragma unroll
-        for (int jj = 0; jj < SS::BC; ++jj) {
-          const int t = cb * SS::BC + jj;
+        for (int jj = 0; jj < S::BC; ++jj) {
+          const int t = cb * S::BC + jj;
           float mn = sm.red[0][t];
 #pragma unroll
-          for (int w = 1; w < SS::W; ++w) mn = vmin(mn, sm.red[w][t]);
+          for (int w = 1; w < S::W; ++w) mn = vmin(mn, sm.red[w][t]);
           q[jj] = (FULL || t < L) ? mn : 0.f;
         }
-        // pass 3
-        float r[SS::BR];
+        // pass 3: r(s) = min_t [th(s,t) - q(t)]
+        float r[S::BR];
 #pragma unroll
-        for (int i = 0; i < SS::BR; ++i) {
+        for (int i = 0; i < S::BR; ++i) {
           float mn = x[i][0] - q[0];
 #pragma unroll
-          for (int jj = 1; jj < SS::BC; ++jj) mn = vmin(mn, x[i][jj] - q[jj]);
+          for (int jj = 1; jj < S::BC; ++jj) mn = vmin(mn, x[i][jj] - q[jj]);
           r[i] = mn;
         }
-        row16_min_n<SS::BR>(r);
-        float* phi_w = phi_in_lds ? phi_lds + j * 2 * L : a.phi + (size_t)slot * 2 * L;
+        row16_min_n<S::BR>(r);
+        // push back: new unaries through the mailboxes, messages to memory
+        float* phi_w = phi_of(slot, j);
         if (rb == 0) {
 #pragma unroll
-          for (int jj = 0; jj < SS::BC; ++jj) {
-            const int t = cb * SS::BC + jj;
+          for (int jj = 0; jj < S::BC; ++jj) {
+            const int t = cb * S::BC + jj;
             if (FULL || t < L) {
-              mb_store(mb + (size_t)si.v * L + t, mb_pack(av[jj] + q[jj], want_v + 1));
+              mb_store(v.mb + (size_t)si.v * L + t, mb_pack(av[jj] + q[jj], want_v + 1));
               phi_w[L + t] = q[jj];
             }
           }
         }
         if (cb == 0) {
 #pragma unroll
-          for (int i = 0; i < SS::BR; ++i) {
-            const int s = rb * SS::BR + i;
+          for (int i = 0; i < S::BR; ++i) {
+            const int s = rb * S::BR + i;
             if (FULL || s < L) {
-              mb_store(mb + (size_t)si.u * L + s, mb_pack(au[i] + r[i], want_u + 1));
+              mb_store(v.mb + (size_t)si.u * L + s, mb_pack(au[i] + r[i], want_u + 1));
               phi_w[s] = r[i];
             }
           }
         }
-        if (a.stamps && it == iters - 1 && tid == 0) a.stamps[(size_t)slot * kStampStride + 3] = wall_clock64();
+        if (v.stamps && last_iter && tid == 0) v.stamps[(size_t)slot * kStampStride + 3] = wall_clock64();
         if (pref) {
 #pragma unroll
-          for (int i = 0; i < SS::BR; ++i)
+          for (int i = 0; i < S::BR; ++i) {
+            pu[i] = npu[i];
 #pragma unroll
-            for (int jj = 0; jj < SS::BC; ++jj) x[i][jj] = y[i][jj];
+            for (int jj = 0; jj < S::BC; ++jj) x[i][jj] = y[i][jj];
+          }
+#pragma unroll
+          for (int jj = 0; jj < S::BC; ++jj) pv[jj] = npv[jj];
+        } else {
+          // the same slot comes next: its messages are the ones just made
+#pragma unroll
+          for (int i = 0; i < S::BR; ++i) pu[i] = r[i];
+#pragma unroll
+          for (int jj = 0; jj < S::BC; ++jj) pv[jj] = q[jj];
         }
       } else {
         // the sync waves take part in the compute waves' mid-slot barrier
         __syncthreads();
         // per-iteration trace: the first update of a node in iteration it
         // sees the node's value at the end of iteration it-1
-        if (a.trace && it > 0) {
-          const bool first = is_sync_u ? (si.pos_u == 0) : (si.pos_v == 0);
-          if (first) {
+        if (v.trace && it > 0) {
+          const bool first_upd = is_sync_u ? (si.pos_u == 0) : (si.pos_v == 0);
+          if (first_upd) {
             const float* src = is_sync_u ? sm.uu[parity] : sm.uv[parity];
-            const int lane = tid & 63;
             double mn = __builtin_inf();
             for (int s2 = lane; s2 < L; s2 += 64) mn = __builtin_fmin(mn, (double)src[s2]);
 #pragma unroll
             for (int o = 32; o >= 1; o >>= 1) mn = __builtin_fmin(mn, __shfl_xor(mn, o, 64));
-            if (lane == 0) a.trace[(size_t)(it - 1) * a.n + (is_sync_u ? si.u : si.v)] = mn;
+            if (lane == 0) v.trace[(size_t)(it - 1) * v.n + (is_sync_u ? si.u : si.v)] = mn;
           }
         }
       }
     }
   }
-  // messages back to global memory
+  return true;
+}
+
+template <int LT, int NT, bool PHI_LDS, bool FULL>
+__global__ void __launch_bounds__(NT + 128) k_persistent_mb(HsArgs<float> a, unsigned long long* __restrict__ mb,
+                                                            int iters) {
+  __shared__ SmemMB<LT, NT> sm;
+  extern __shared__ float phi_lds[];
+  const int tid = threadIdx.x;
+  const int L = FULL ? LT : a.L;
+  const int G = gridDim.x;
+  if (blockIdx.x >= a.m) return;
+  if (tid == 0) sm.abort_flag = 0;
+  if (PHI_LDS) {
+    for (int slot = blockIdx.x, j = 0; slot < a.m; slot += G, ++j)
+      for (int k = tid; k < 2 * L; k += NT + 128) phi_lds[j * 2 * L + k] = a.phi[(size_t)slot * 2 * L + k];
+  }
   __syncthreads();
-  if (phi_in_lds) {
+  MbView v{a.tables, a.phi, mb, a.slots, a.deg, a.trace, a.stamps, L, a.m, a.n};
+  if (!mb_run<LT, NT, PHI_LDS, FULL>(v, blockIdx.x, G, iters, sm, phi_lds, a.spin_limit, a.err)) return;
+  __syncthreads();
+  if (PHI_LDS) {
     for (int slot = blockIdx.x, j = 0; slot < a.m; slot += G, ++j)
       for (int k = tid; k < 2 * L; k += NT + 128) a.phi[(size_t)slot * 2 * L + k] = phi_lds[j * 2 * L + k];
   }
