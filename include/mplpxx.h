@@ -189,6 +189,68 @@ int mplpxx_get_step_profile(mplpxx_solver* h, int64_t* stamps);
  * (0 if none). */
 int mplpxx_last_iterate_ms(mplpxx_solver* h, double* ms);
 
+/* ------------------------------------------------------------------------
+ * Batched solving: many independent FP32 models in one persistent launch.
+ * --------------------------------------------------------------------- */
+
+typedef struct mplpxx_batch mplpxx_batch;
+
+/* Creates a batch of `count` independent FP32 models (each as in
+ * mplpxx_create: Sec. 3, Eq. (1); own schedule of Alg. 1).  n[i], L[i], m[i]
+ * are HOST arrays of sizes; edges[i], unaries[i], pairwise[i] HOST pointers
+ * to model i's arrays in the layouts of mplpxx_create (edges[i] and
+ * pairwise[i] may be NULL when m[i] == 0).  Everything is copied to device
+ * memory; the library plans which workgroups run which model (large models
+ * are split over a team of workgroups, small ones packed together).  Errors
+ * as mplpxx_create, reported with the model index. */
+int mplpxx_batch_create(int32_t count, const int32_t* n, const int32_t* L, const int64_t* m,
+                        const int32_t* const* edges, const float* const* unaries, const float* const* pairwise,
+                        mplpxx_batch** out);
+
+/* Runs k >= 0 BCA-iterations (Sec. 5) of every model of the batch in one
+ * persistent launch (by default replayed from a hipGraph captured for this
+ * k), and waits for it.  Each model's results are bitwise those of
+ * mplpxx_iterate on the same model.  MPLPXX_ETIMEOUT: a device wait exceeded
+ * its bound (state undefined). */
+int mplpxx_batch_iterate(mplpxx_batch* b, int32_t k);
+
+/* Dual bound of Eq. (3) of every model (HOST double [count]), recomputed in
+ * FP64 from costs and messages as in mplpxx_dual_bound. */
+int mplpxx_batch_dual_bounds(mplpxx_batch* b, double* out);
+
+/* State of one model (HOST float U [n][L], phi [m][2][L], layouts of
+ * mplpxx_get_state; either may be NULL). */
+int mplpxx_batch_get_state(mplpxx_batch* b, int32_t model, float* U, float* phi);
+
+/* Back to phi = 0, U = unaries for every model. */
+int mplpxx_batch_reset(mplpxx_batch* b);
+
+/* Planning and execution options (results never depend on them). */
+#define MPLPXX_BOPT_GRID 1           /* workgroups of the launch (0: all that fit) */
+#define MPLPXX_BOPT_GRAPH 2          /* 1: replay a captured hipGraph (default), 0: plain launches */
+#define MPLPXX_BOPT_SPIN_LIMIT 3     /* device wait bound in polls (0 default) */
+#define MPLPXX_BOPT_ONE_PER_MODEL 4  /* 1: no teams, every model on one workgroup */
+#define MPLPXX_BOPT_HANDOFF_US 5     /* planner: cost of one cross-workgroup handoff */
+#define MPLPXX_BOPT_EDGE16_US 6      /* planner: cost of one edge update, L <= 16 */
+#define MPLPXX_BOPT_EDGE32_US 7      /*                                   L <= 32 */
+#define MPLPXX_BOPT_EDGE64_US 8      /*                                   L <= 64 */
+#define MPLPXX_BOPT_EDGE128_US 9     /*                                   L <= 128 */
+int mplpxx_batch_set_option(mplpxx_batch* b, int32_t key, double value);
+
+#define MPLPXX_BINFO_COUNT 1
+#define MPLPXX_BINFO_GRID 2
+#define MPLPXX_BINFO_TASKS 3
+#define MPLPXX_BINFO_TEAMS 4         /* models split over more than one workgroup */
+#define MPLPXX_BINFO_MAX_TEAM 5
+#define MPLPXX_BINFO_PLAN_US 6       /* planner's estimate of the makespan per iteration */
+#define MPLPXX_BINFO_EDGES 7         /* total edges */
+#define MPLPXX_BINFO_LAST_MS 8       /* device time of the last batch_iterate (HIP events) */
+#define MPLPXX_BINFO_TABLE_BYTES 9   /* bytes of pairwise tables */
+int mplpxx_batch_get_info(mplpxx_batch* b, int32_t key, double* value);
+
+/* Frees the batch and its device memory; NULL is a no-op. */
+void mplpxx_batch_destroy(mplpxx_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

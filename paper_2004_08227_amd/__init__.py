@@ -26,6 +26,10 @@ OK, EINVAL, ENOMEM, EDEVICE, ETIMEOUT, ESTATE = 0, -1, -2, -3, -4, -5
 MAX_LABELS = 128
 OPT_ENGINE, OPT_THREADS, OPT_GRID, OPT_SPIN_LIMIT, OPT_PROFILE = 1, 2, 3, 4, 5
 ENGINE_AUTO, ENGINE_STEP, ENGINE_PERSISTENT = 0, 1, 2
+BOPT = {"grid": 1, "graph": 2, "spin_limit": 3, "one_per_model": 4, "handoff_us": 5, "edge16_us": 6,
+        "edge32_us": 7, "edge64_us": 8, "edge128_us": 9}
+BINFO = {"count": 1, "grid": 2, "tasks": 3, "teams": 4, "max_team": 5, "plan_us": 6, "edges": 7, "last_ms": 8,
+         "table_bytes": 9}
 INFO = {"n": 1, "L": 2, "m": 3, "steps": 4, "dtype": 5, "engine": 6, "grid": 7, "threads": 8, "iterations": 9,
         "wallclock_khz": 10}
 
@@ -80,6 +84,14 @@ def lib():
         "mplpxx_get_info": (ctypes.c_int, [vp, i32, ctypes.POINTER(i64)]),
         "mplpxx_last_iterate_ms": (ctypes.c_int, [vp, ctypes.POINTER(dbl)]),
         "mplpxx_get_step_profile": (ctypes.c_int, [vp, vp]),
+        "mplpxx_batch_create": (ctypes.c_int, [i32, vp, vp, vp, vp, vp, vp, pp]),
+        "mplpxx_batch_iterate": (ctypes.c_int, [vp, i32]),
+        "mplpxx_batch_dual_bounds": (ctypes.c_int, [vp, vp]),
+        "mplpxx_batch_get_state": (ctypes.c_int, [vp, i32, vp, vp]),
+        "mplpxx_batch_reset": (ctypes.c_int, [vp]),
+        "mplpxx_batch_set_option": (ctypes.c_int, [vp, i32, dbl]),
+        "mplpxx_batch_get_info": (ctypes.c_int, [vp, i32, ctypes.POINTER(dbl)]),
+        "mplpxx_batch_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -240,3 +252,74 @@ class Solver:
         d = ctypes.c_double()
         _check(lib().mplpxx_last_iterate_ms(self._h, ctypes.byref(d)))
         return d.value
+
+
+class Batch:
+    """Many independent FP32 models solved together (``mplpxx_batch_*``)."""
+
+    def __init__(self, models):
+        count = len(models)
+        self.models = models
+        self.n = np.array([mo.n for mo in models], dtype=np.int32)
+        self.L = np.array([mo.L for mo in models], dtype=np.int32)
+        self.m = np.array([mo.m for mo in models], dtype=np.int64)
+        keep = []
+        e_ptrs = (ctypes.c_void_p * count)()
+        u_ptrs = (ctypes.c_void_p * count)()
+        p_ptrs = (ctypes.c_void_p * count)()
+        for i, mo in enumerate(models):
+            e = np.ascontiguousarray(mo.edges, dtype=np.int32)
+            u = np.ascontiguousarray(mo.unaries, dtype=np.float32)
+            pw = np.ascontiguousarray(mo.pairwise, dtype=np.float32)
+            keep += [e, u, pw]
+            e_ptrs[i] = e.ctypes.data if mo.m else None
+            u_ptrs[i] = u.ctypes.data
+            p_ptrs[i] = pw.ctypes.data if mo.m else None
+        h = ctypes.c_void_p()
+        _check(lib().mplpxx_batch_create(count, _ptr(self.n), _ptr(self.L), _ptr(self.m), e_ptrs, u_ptrs, p_ptrs,
+                                         ctypes.byref(h)))
+        self._h = h
+        self.count = count
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().mplpxx_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def iterate(self, k):
+        _check(lib().mplpxx_batch_iterate(self._h, int(k)))
+
+    def dual_bounds(self):
+        out = np.zeros(self.count, dtype=np.float64)
+        _check(lib().mplpxx_batch_dual_bounds(self._h, _ptr(out)))
+        return out
+
+    def get_state(self, i):
+        n, L, m = int(self.n[i]), int(self.L[i]), int(self.m[i])
+        U = np.zeros((n, L), dtype=np.float32)
+        phi = np.zeros((m, 2, L), dtype=np.float32)
+        _check(lib().mplpxx_batch_get_state(self._h, int(i), _ptr(U), _ptr(phi) if m else None))
+        return U, phi
+
+    def reset(self):
+        _check(lib().mplpxx_batch_reset(self._h))
+
+    def set_option(self, key, value):
+        _check(lib().mplpxx_batch_set_option(self._h, BOPT[key], float(value)))
+
+    def info(self, key):
+        v = ctypes.c_double()
+        _check(lib().mplpxx_batch_get_info(self._h, BINFO[key], ctypes.byref(v)))
+        return v.value

@@ -1,0 +1,557 @@
+// Host runtime of the batched solver: many independent FP32 models (each a
+// pairwise MRF of Sec. 3 solved by MPLP++ iterations, Sec. 4-6) in one
+// persistent launch, optionally replayed from a captured hipGraph.
+//
+// Planning.  The work of model b per iteration is modelled as
+//   t_b(T) = S_b * (t_hand + t_edge(LT_b) / 2) + (m_b / T) * t_edge(LT_b)
+// for a team of T workgroups (S_b matchings, each needing one cross-workgroup
+// handoff; m_b / T edge updates per member, one after another), and never
+// less than the member's share of HBM traffic.  The planner binary-searches a
+// makespan tau: every model gets the smallest team with t_b(T) <= tau (at most
+// one member per edge of its largest matching), teams take workgroups first,
+// and single-workgroup models are packed onto the least-loaded workgroups
+// (longest first).  The constants t_hand and t_edge are options, so a tuner
+// can calibrate them; they change only the assignment, never the results.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <queue>
+#include <vector>
+
+#include "common.h"
+#include "host_util.h"
+#include "schedule.h"
+
+using namespace mplpxx;
+
+struct ModelHost {
+  int n, L, m, S, lt;
+  int max_step;                    // edges of the largest matching
+  std::vector<int> slot_of_edge;   // for state export
+};
+
+struct mplpxx_batch {
+  int count = 0;
+  std::vector<ModelHost> mh;
+  std::vector<BatchModel> md;
+  long long total_tables = 0, total_phi = 0, total_u = 0;
+  int total_slots = 0, total_nodes = 0, total_csr = 0, total_inc = 0;
+  int max_lt = 16;
+  // device
+  float* d_tables = nullptr;
+  float* d_phi = nullptr;
+  float* d_U = nullptr;
+  float* d_unaries = nullptr;
+  unsigned long long* d_mb = nullptr;
+  SlotInfo* d_slots = nullptr;
+  int* d_deg = nullptr;
+  BatchModel* d_models = nullptr;
+  BatchTask* d_tasks = nullptr;
+  int* d_task_ptr = nullptr;
+  int* d_err = nullptr;
+  int* d_node_model = nullptr;
+  int* d_slot_model = nullptr;
+  int* d_node_ptr = nullptr;
+  int* d_inc = nullptr;
+  double* d_node_min = nullptr;
+  double* d_edge_min = nullptr;
+  double* d_duals = nullptr;
+  // plan
+  int grid = 0;
+  int grid_opt = 0;
+  int num_cus = 0;
+  int ntasks = 0, nteams = 0, max_team = 1;
+  double plan_us = 0.0;
+  double t_hand_us = 0.7;
+  double t_edge_us[4] = {0.30, 0.45, 0.85, 2.0};  // LT 16, 32, 64, 128
+  int one_per_model = 0;
+  bool plan_dirty = true;
+  // execution
+  hipStream_t stream = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool use_graph = true;
+  hipGraphExec_t gexec = nullptr;
+  int graph_k = -1;
+  long long spin_limit = 1ll << 22;
+  double last_ms = 0.0;
+  long long iterations = 0;
+};
+
+namespace {
+
+int lt_index(int lt) { return lt == 16 ? 0 : lt == 32 ? 1 : lt == 64 ? 2 : 3; }
+
+double model_time(const mplpxx_batch* b, int i, int T, double bw_per_wg_bytes_us) {
+  const ModelHost& h = b->mh[i];
+  if (h.m == 0) return 0.0;
+  const double te = b->t_edge_us[lt_index(h.lt)];
+  const double lat = h.S * (b->t_hand_us + 0.5 * te) + (double)h.m / T * te;
+  const double bytes = (double)h.m * (4.0 * h.L * h.L + 16.0 * h.L) / T;
+  return std::max(lat, bytes / bw_per_wg_bytes_us);
+}
+
+// tasks for makespan tau; returns the resulting max workgroup load
+double assign(const mplpxx_batch* b, double tau, int G, double bw, std::vector<std::vector<BatchTask>>& wg_tasks,
+              int* nteams, int* max_team) {
+  wg_tasks.assign(G, {});
+  std::vector<double> load(G, 0.0);
+  std::vector<int> team(b->count, 1);
+  int used = 0;
+  *nteams = 0;
+  *max_team = 1;
+  for (int i = 0; i < b->count; ++i) {
+    const ModelHost& h = b->mh[i];
+    if (h.m == 0) continue;
+    int tmax = std::max(1, std::min(h.max_step, G));
+    int T = 1;
+    if (!b->one_per_model) {
+      // smallest team meeting tau (model_time decreases with T)
+      int lo = 1, hi = tmax;
+      if (model_time(b, i, tmax, bw) > tau) {
+        T = tmax;
+      } else {
+        while (lo < hi) {
+          const int mid = (lo + hi) / 2;
+          if (model_time(b, i, mid, bw) <= tau) hi = mid; else lo = mid + 1;
+        }
+        T = lo;
+      }
+    }
+    team[i] = T;
+  }
+  // teams first: each member's first task, consecutive workgroups
+  for (int i = 0; i < b->count; ++i) {
+    if (team[i] < 2) continue;
+    if (used + team[i] > G) return INFINITY;
+    const double t = model_time(b, i, team[i], bw);
+    for (int r = 0; r < team[i]; ++r) {
+      wg_tasks[used + r].push_back(BatchTask{i, r, team[i], 0});
+      load[used + r] += t;
+    }
+    used += team[i];
+    ++*nteams;
+    *max_team = std::max(*max_team, team[i]);
+  }
+  // single-workgroup models, longest first, onto the least-loaded workgroup
+  std::vector<int> singles;
+  for (int i = 0; i < b->count; ++i)
+    if (team[i] < 2 && b->mh[i].m > 0) singles.push_back(i);
+  std::sort(singles.begin(), singles.end(), [&](int x, int y) {
+    const double tx = model_time(b, x, 1, bw), ty = model_time(b, y, 1, bw);
+    return tx != ty ? tx > ty : x < y;
+  });
+  using Item = std::pair<double, int>;
+  std::priority_queue<Item, std::vector<Item>, std::greater<Item>> pq;
+  for (int w = 0; w < G; ++w) pq.push({load[w], w});
+  for (int i : singles) {
+    Item it = pq.top();
+    pq.pop();
+    wg_tasks[it.second].push_back(BatchTask{i, 0, 1, 0});
+    it.first += model_time(b, i, 1, bw);
+    load[it.second] = it.first;
+    pq.push(it);
+  }
+  return *std::max_element(load.begin(), load.end());
+}
+
+int plan(mplpxx_batch* b) {
+  const int per_cu = batch_blocks_per_cu(b->max_lt);
+  if (per_cu < 1) return fail(MPLPXX_EDEVICE, "batched kernel does not fit on a compute unit");
+  const int gmax = per_cu * b->num_cus;
+  int G = b->grid_opt > 0 ? std::min(b->grid_opt, gmax) : gmax;
+  G = std::max(1, G);
+  // HBM share of one workgroup in bytes per microsecond (8 TB/s nominal)
+  const double bw = 8.0e12 / 1e6 / G;
+  double lo = 0.0, hi = 0.0;
+  for (int i = 0; i < b->count; ++i) {
+    const int tmax = std::max(1, std::min(b->mh[i].max_step, G));
+    lo = std::max(lo, model_time(b, i, tmax, bw));
+    hi += model_time(b, i, 1, bw);
+  }
+  hi = std::max(hi, lo);
+  std::vector<std::vector<BatchTask>> best, cur;
+  int nteams = 0, max_team = 1, bt = 0, bm = 1;
+  double best_load = assign(b, hi, G, bw, best, &bt, &bm);
+  for (int rep = 0; rep < 40 && hi - lo > 1e-3 * hi; ++rep) {
+    const double mid = 0.5 * (lo + hi);
+    const double l = assign(b, mid, G, bw, cur, &nteams, &max_team);
+    if (l <= mid * 1.05) {
+      hi = mid;
+      if (l < best_load) {
+        best_load = l;
+        best.swap(cur);
+        bt = nteams;
+        bm = max_team;
+      }
+    } else {
+      lo = mid;
+    }
+  }
+  std::vector<BatchTask> tasks;
+  std::vector<int> ptr(G + 1, 0);
+  for (int w = 0; w < G; ++w) {
+    for (const BatchTask& t : best[w]) tasks.push_back(t);
+    ptr[w + 1] = (int)tasks.size();
+  }
+  if (b->d_tasks) (void)hipFree(b->d_tasks);
+  if (b->d_task_ptr) (void)hipFree(b->d_task_ptr);
+  b->d_tasks = nullptr;
+  b->d_task_ptr = nullptr;
+  HIP_TRY(hipMalloc(&b->d_tasks, std::max<size_t>(1, tasks.size()) * sizeof(BatchTask)));
+  HIP_TRY(hipMalloc(&b->d_task_ptr, (G + 1) * sizeof(int)));
+  if (!tasks.empty())
+    HIP_TRY(hipMemcpy(b->d_tasks, tasks.data(), tasks.size() * sizeof(BatchTask), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(b->d_task_ptr, ptr.data(), (G + 1) * sizeof(int), hipMemcpyHostToDevice));
+  b->grid = G;
+  b->ntasks = (int)tasks.size();
+  b->nteams = bt;
+  b->max_team = bm;
+  b->plan_us = best_load;
+  b->plan_dirty = false;
+  if (b->gexec) {
+    (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+    b->graph_k = -1;
+  }
+  return MPLPXX_OK;
+}
+
+void free_batch(mplpxx_batch* b) {
+  void* ptrs[] = {b->d_tables, b->d_phi, b->d_U, b->d_unaries, b->d_mb, b->d_slots, b->d_deg, b->d_models,
+                  b->d_tasks, b->d_task_ptr, b->d_err, b->d_node_model, b->d_slot_model, b->d_node_ptr,
+                  b->d_inc, b->d_node_min, b->d_edge_min, b->d_duals};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->ev0) (void)hipEventDestroy(b->ev0);
+  if (b->ev1) (void)hipEventDestroy(b->ev1);
+  if (b->stream) (void)hipStreamDestroy(b->stream);
+}
+
+hipError_t enqueue(mplpxx_batch* b, int k) {
+  BatchArgs a{};
+  a.tables = b->d_tables;
+  a.phi = b->d_phi;
+  a.mb = b->d_mb;
+  a.slots = b->d_slots;
+  a.deg = b->d_deg;
+  a.models = b->d_models;
+  a.tasks = b->d_tasks;
+  a.task_ptr = b->d_task_ptr;
+  a.err = b->d_err;
+  a.spin_limit = b->spin_limit;
+  hipError_t e = launch_u32_to_mb(b->d_U, b->d_mb, (size_t)b->total_u, b->stream);
+  if (e != hipSuccess) return e;
+  e = launch_batch(a, b->max_lt, b->grid, k, b->stream);
+  if (e != hipSuccess) return e;
+  return launch_mb_to_u32(b->d_U, b->d_mb, (size_t)b->total_u, b->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+int mplpxx_batch_create(int32_t count, const int32_t* n, const int32_t* L, const int64_t* m,
+                        const int32_t* const* edges, const float* const* unaries, const float* const* pairwise,
+                        mplpxx_batch** out) {
+  if (!out) return fail(MPLPXX_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (count < 1) return fail(MPLPXX_EINVAL, "count must be >= 1");
+  if (!n || !L || !m || !unaries) return fail(MPLPXX_EINVAL, "NULL size or unary array");
+  mplpxx_batch* b = new (std::nothrow) mplpxx_batch();
+  if (!b) return fail(MPLPXX_ENOMEM, "host allocation failed");
+  auto bail = [&](int code) {
+    free_batch(b);
+    delete b;
+    return code;
+  };
+  b->count = count;
+  b->mh.resize(count);
+  b->md.resize(count);
+  std::vector<GraphPrep> preps(count);
+  for (int i = 0; i < count; ++i) {
+    if (n[i] < 1) return bail(fail(MPLPXX_EINVAL, "model %d: n must be >= 1", i));
+    if (L[i] < 1 || L[i] > MPLPXX_MAX_LABELS) return bail(fail(MPLPXX_EINVAL, "model %d: L out of range", i));
+    if (m[i] < 0 || m[i] > (int64_t)n[i] * (n[i] - 1) / 2) return bail(fail(MPLPXX_EINVAL, "model %d: bad m", i));
+    if (m[i] > 0 && (!edges || !pairwise || !edges[i] || !pairwise[i]))
+      return bail(fail(MPLPXX_EINVAL, "model %d: NULL edges or pairwise", i));
+    if (!unaries[i]) return bail(fail(MPLPXX_EINVAL, "model %d: NULL unaries", i));
+    for (size_t k = 0; k < (size_t)n[i] * L[i]; ++k)
+      if (!std::isfinite(unaries[i][k])) return bail(fail(MPLPXX_EINVAL, "model %d: non-finite unary", i));
+    for (size_t k = 0; k < (size_t)m[i] * L[i] * L[i]; ++k)
+      if (!std::isfinite(pairwise[i][k])) return bail(fail(MPLPXX_EINVAL, "model %d: non-finite pairwise", i));
+    const int rc = prepare_graph(n[i], (int)m[i], m[i] ? edges[i] : nullptr, preps[i]);
+    if (rc != MPLPXX_OK) {
+      const std::string msg = g_last_error;
+      return bail(fail(rc, "model %d: %s", i, msg.c_str()));
+    }
+    ModelHost& h = b->mh[i];
+    h.n = n[i];
+    h.L = L[i];
+    h.m = (int)m[i];
+    h.S = preps[i].S;
+    h.lt = next_tile(L[i]);
+    h.max_step = 1;
+    for (int s = 0; s < h.S; ++s) h.max_step = std::max(h.max_step, preps[i].step_ptr[s + 1] - preps[i].step_ptr[s]);
+    h.slot_of_edge = preps[i].slot_of_edge;
+    b->max_lt = std::max(b->max_lt, h.lt);
+    BatchModel& d = b->md[i];
+    d.table_off = b->total_tables;
+    d.phi_off = b->total_phi;
+    d.u_off = b->total_u;
+    d.slot_off = b->total_slots;
+    d.node_off = b->total_nodes;
+    d.n = h.n;
+    d.L = h.L;
+    d.m = h.m;
+    d.lt = h.lt;
+    d.csr_off = b->total_csr;
+    d.inc_off = b->total_inc;
+    b->total_tables += (long long)h.m * h.L * h.L;
+    b->total_phi += (long long)h.m * 2 * h.L;
+    b->total_u += (long long)h.n * h.L;
+    b->total_slots += h.m;
+    b->total_nodes += h.n;
+    b->total_csr += h.n + 1;
+    b->total_inc += 2 * h.m;
+  }
+#define TRY(expr)                                                               \
+  do {                                                                          \
+    hipError_t e_ = (expr);                                                     \
+    if (e_ != hipSuccess) {                                                     \
+      const int c_ = e_ == hipErrorOutOfMemory ? MPLPXX_ENOMEM : MPLPXX_EDEVICE; \
+      return bail(fail(c_, "%s: %s", #expr, hipGetErrorString(e_)));            \
+    }                                                                           \
+  } while (0)
+  int dev = 0;
+  TRY(hipGetDevice(&dev));
+  TRY(hipDeviceGetAttribute(&b->num_cus, hipDeviceAttributeMultiprocessorCount, dev));
+  TRY(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+  TRY(hipEventCreate(&b->ev0));
+  TRY(hipEventCreate(&b->ev1));
+  auto alloc = [&](void** p, size_t bytes) { return hipMalloc(p, bytes > 0 ? bytes : 16); };
+  TRY(alloc((void**)&b->d_tables, (size_t)b->total_tables * sizeof(float)));
+  TRY(alloc((void**)&b->d_phi, (size_t)b->total_phi * sizeof(float)));
+  TRY(alloc((void**)&b->d_U, (size_t)b->total_u * sizeof(float)));
+  TRY(alloc((void**)&b->d_unaries, (size_t)b->total_u * sizeof(float)));
+  TRY(alloc((void**)&b->d_mb, (size_t)b->total_u * sizeof(unsigned long long)));
+  TRY(alloc((void**)&b->d_slots, (size_t)b->total_slots * sizeof(SlotInfo)));
+  TRY(alloc((void**)&b->d_deg, (size_t)b->total_nodes * sizeof(int)));
+  TRY(alloc((void**)&b->d_models, (size_t)count * sizeof(BatchModel)));
+  TRY(alloc((void**)&b->d_err, 4 * sizeof(int)));
+  TRY(alloc((void**)&b->d_node_model, (size_t)b->total_nodes * sizeof(int)));
+  TRY(alloc((void**)&b->d_slot_model, (size_t)b->total_slots * sizeof(int)));
+  TRY(alloc((void**)&b->d_node_ptr, (size_t)b->total_csr * sizeof(int)));
+  TRY(alloc((void**)&b->d_inc, (size_t)b->total_inc * sizeof(int)));
+  TRY(alloc((void**)&b->d_node_min, (size_t)b->total_nodes * sizeof(double)));
+  TRY(alloc((void**)&b->d_edge_min, (size_t)b->total_slots * sizeof(double)));
+  TRY(alloc((void**)&b->d_duals, (size_t)count * sizeof(double)));
+  TRY(hipMemset(b->d_phi, 0, (size_t)b->total_phi * sizeof(float) + 0));
+  TRY(hipMemset(b->d_err, 0, 4 * sizeof(int)));
+  // per model: packed tables (slot order, transposed where given as (v, u)),
+  // unaries, slot metadata, degrees, incidence lists, node/slot maps
+  std::vector<float> packed;
+  std::vector<int> node_model(b->total_nodes), slot_model(b->total_slots);
+  for (int i = 0; i < count; ++i) {
+    const ModelHost& h = b->mh[i];
+    const BatchModel& d = b->md[i];
+    const GraphPrep& g = preps[i];
+    const size_t tl = (size_t)h.L * h.L;
+    packed.resize((size_t)h.m * tl);
+    for (int s = 0; s < h.m; ++s) {
+      const int e = g.order[s];
+      const float* src = pairwise[i] + (size_t)e * tl;
+      float* dst = packed.data() + (size_t)s * tl;
+      if (!g.flip[e]) {
+        std::memcpy(dst, src, tl * sizeof(float));
+      } else {
+        for (int r = 0; r < h.L; ++r)
+          for (int c = 0; c < h.L; ++c) dst[(size_t)r * h.L + c] = src[(size_t)c * h.L + r];
+      }
+    }
+    if (h.m) TRY(hipMemcpy(b->d_tables + d.table_off, packed.data(), packed.size() * sizeof(float), hipMemcpyHostToDevice));
+    TRY(hipMemcpy(b->d_unaries + d.u_off, unaries[i], (size_t)h.n * h.L * sizeof(float), hipMemcpyHostToDevice));
+    if (h.m) TRY(hipMemcpy(b->d_slots + d.slot_off, g.slots.data(), (size_t)h.m * sizeof(SlotInfo), hipMemcpyHostToDevice));
+    TRY(hipMemcpy(b->d_deg + d.node_off, g.deg.data(), (size_t)h.n * sizeof(int), hipMemcpyHostToDevice));
+    std::vector<int> node_ptr(h.n + 1, 0), inc(2 * (size_t)h.m);
+    for (int s = 0; s < h.m; ++s) {
+      node_ptr[g.slots[s].u + 1]++;
+      node_ptr[g.slots[s].v + 1]++;
+    }
+    for (int u = 0; u < h.n; ++u) node_ptr[u + 1] += node_ptr[u];
+    std::vector<int> fillp(node_ptr.begin(), node_ptr.end() - 1);
+    for (int s = 0; s < h.m; ++s) {
+      inc[fillp[g.slots[s].u]++] = 2 * s;
+      inc[fillp[g.slots[s].v]++] = 2 * s + 1;
+    }
+    TRY(hipMemcpy(b->d_node_ptr + d.csr_off, node_ptr.data(), node_ptr.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (h.m) TRY(hipMemcpy(b->d_inc + d.inc_off, inc.data(), inc.size() * sizeof(int), hipMemcpyHostToDevice));
+    for (int u = 0; u < h.n; ++u) node_model[d.node_off + u] = i;
+    for (int s = 0; s < h.m; ++s) slot_model[d.slot_off + s] = i;
+  }
+  TRY(hipMemcpy(b->d_models, b->md.data(), (size_t)count * sizeof(BatchModel), hipMemcpyHostToDevice));
+  TRY(hipMemcpy(b->d_node_model, node_model.data(), node_model.size() * sizeof(int), hipMemcpyHostToDevice));
+  if (b->total_slots)
+    TRY(hipMemcpy(b->d_slot_model, slot_model.data(), slot_model.size() * sizeof(int), hipMemcpyHostToDevice));
+  TRY(hipMemcpy(b->d_U, b->d_unaries, (size_t)b->total_u * sizeof(float), hipMemcpyDeviceToDevice));
+#undef TRY
+  const int rc = plan(b);
+  if (rc != MPLPXX_OK) return bail(rc);
+  *out = b;
+  return MPLPXX_OK;
+}
+
+int mplpxx_batch_iterate(mplpxx_batch* b, int32_t k) {
+  if (!b) return fail(MPLPXX_EINVAL, "handle is NULL");
+  if (k < 0) return fail(MPLPXX_EINVAL, "k must be >= 0");
+  if (b->plan_dirty) {
+    const int rc = plan(b);
+    if (rc != MPLPXX_OK) return rc;
+  }
+  HIP_TRY(hipEventRecord(b->ev0, b->stream));
+  if (k > 0) {
+    if (b->use_graph) {
+      if (!b->gexec || b->graph_k != k) {
+        if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+        hipGraph_t g = nullptr;
+        HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        const hipError_t e = enqueue(b, k);
+        const hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+        if (e != hipSuccess) return fail(MPLPXX_EDEVICE, "capture: %s", hipGetErrorString(e));
+        if (e2 != hipSuccess) return fail(MPLPXX_EDEVICE, "end capture: %s", hipGetErrorString(e2));
+        const hipError_t e3 = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e3 != hipSuccess) return fail(MPLPXX_EDEVICE, "instantiate: %s", hipGetErrorString(e3));
+        b->graph_k = k;
+      }
+      HIP_TRY(hipGraphLaunch(b->gexec, b->stream));
+    } else {
+      HIP_TRY(enqueue(b, k));
+    }
+  }
+  HIP_TRY(hipEventRecord(b->ev1, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  int err = 0;
+  HIP_TRY(hipMemcpy(&err, b->d_err, sizeof(int), hipMemcpyDeviceToHost));
+  if (err) {
+    (void)hipMemset(b->d_err, 0, sizeof(int));
+    return fail(err, "device wait exceeded its bound (code %d)", err);
+  }
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+  b->last_ms = ms;
+  b->iterations += k;
+  return MPLPXX_OK;
+}
+
+int mplpxx_batch_dual_bounds(mplpxx_batch* b, double* out) {
+  if (!b || !out) return fail(MPLPXX_EINVAL, "NULL argument");
+  HIP_TRY(launch_batch_dual(b->d_unaries, b->d_tables, b->d_phi, b->d_models, b->d_node_model, b->d_slot_model,
+                            b->d_node_ptr, b->d_inc, b->total_nodes, b->total_slots, b->count, b->d_node_min,
+                            b->d_edge_min, b->d_duals, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  HIP_TRY(hipMemcpy(out, b->d_duals, (size_t)b->count * sizeof(double), hipMemcpyDeviceToHost));
+  return MPLPXX_OK;
+}
+
+int mplpxx_batch_get_state(mplpxx_batch* b, int32_t model, float* U, float* phi) {
+  if (!b) return fail(MPLPXX_EINVAL, "handle is NULL");
+  if (model < 0 || model >= b->count) return fail(MPLPXX_EINVAL, "model index out of range");
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  const ModelHost& h = b->mh[model];
+  const BatchModel& d = b->md[model];
+  if (U) HIP_TRY(hipMemcpy(U, b->d_U + d.u_off, (size_t)h.n * h.L * sizeof(float), hipMemcpyDeviceToHost));
+  if (phi && h.m) {
+    std::vector<float> tmp((size_t)h.m * 2 * h.L);
+    HIP_TRY(hipMemcpy(tmp.data(), b->d_phi + d.phi_off, tmp.size() * sizeof(float), hipMemcpyDeviceToHost));
+    const size_t row = 2 * (size_t)h.L;
+    for (int e = 0; e < h.m; ++e)
+      std::memcpy(phi + (size_t)e * row, tmp.data() + (size_t)h.slot_of_edge[e] * row, row * sizeof(float));
+  }
+  return MPLPXX_OK;
+}
+
+int mplpxx_batch_reset(mplpxx_batch* b) {
+  if (!b) return fail(MPLPXX_EINVAL, "handle is NULL");
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  HIP_TRY(hipMemset(b->d_phi, 0, (size_t)b->total_phi * sizeof(float)));
+  HIP_TRY(hipMemcpy(b->d_U, b->d_unaries, (size_t)b->total_u * sizeof(float), hipMemcpyDeviceToDevice));
+  b->iterations = 0;
+  return MPLPXX_OK;
+}
+
+int mplpxx_batch_set_option(mplpxx_batch* b, int32_t key, double value) {
+  if (!b) return fail(MPLPXX_EINVAL, "handle is NULL");
+  switch (key) {
+    case MPLPXX_BOPT_GRID:
+      if (value < 0) return fail(MPLPXX_EINVAL, "grid must be >= 0");
+      b->grid_opt = (int)value;
+      b->plan_dirty = true;
+      return MPLPXX_OK;
+    case MPLPXX_BOPT_GRAPH:
+      b->use_graph = value != 0;
+      return MPLPXX_OK;
+    case MPLPXX_BOPT_SPIN_LIMIT:
+      if (value < 0) return fail(MPLPXX_EINVAL, "spin limit must be >= 0");
+      b->spin_limit = value ? (long long)value : (1ll << 22);
+      if (b->gexec) {
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+        b->graph_k = -1;
+      }
+      return MPLPXX_OK;
+    case MPLPXX_BOPT_ONE_PER_MODEL:
+      b->one_per_model = value != 0;
+      b->plan_dirty = true;
+      return MPLPXX_OK;
+    case MPLPXX_BOPT_HANDOFF_US:
+      if (!(value > 0)) return fail(MPLPXX_EINVAL, "handoff time must be > 0");
+      b->t_hand_us = value;
+      b->plan_dirty = true;
+      return MPLPXX_OK;
+    case MPLPXX_BOPT_EDGE16_US:
+    case MPLPXX_BOPT_EDGE32_US:
+    case MPLPXX_BOPT_EDGE64_US:
+    case MPLPXX_BOPT_EDGE128_US:
+      if (!(value > 0)) return fail(MPLPXX_EINVAL, "edge time must be > 0");
+      b->t_edge_us[key - MPLPXX_BOPT_EDGE16_US] = value;
+      b->plan_dirty = true;
+      return MPLPXX_OK;
+    default:
+      return fail(MPLPXX_EINVAL, "unknown batch option %d", key);
+  }
+}
+
+int mplpxx_batch_get_info(mplpxx_batch* b, int32_t key, double* value) {
+  if (!b || !value) return fail(MPLPXX_EINVAL, "NULL argument");
+  if (b->plan_dirty) {
+    const int rc = plan(b);
+    if (rc != MPLPXX_OK) return rc;
+  }
+  switch (key) {
+    case MPLPXX_BINFO_COUNT: *value = b->count; return MPLPXX_OK;
+    case MPLPXX_BINFO_GRID: *value = b->grid; return MPLPXX_OK;
+    case MPLPXX_BINFO_TASKS: *value = b->ntasks; return MPLPXX_OK;
+    case MPLPXX_BINFO_TEAMS: *value = b->nteams; return MPLPXX_OK;
+    case MPLPXX_BINFO_MAX_TEAM: *value = b->max_team; return MPLPXX_OK;
+    case MPLPXX_BINFO_PLAN_US: *value = b->plan_us; return MPLPXX_OK;
+    case MPLPXX_BINFO_EDGES: *value = b->total_slots; return MPLPXX_OK;
+    case MPLPXX_BINFO_LAST_MS: *value = b->last_ms; return MPLPXX_OK;
+    case MPLPXX_BINFO_TABLE_BYTES: *value = (double)b->total_tables * sizeof(float); return MPLPXX_OK;
+    default: return fail(MPLPXX_EINVAL, "unknown batch info key %d", key);
+  }
+}
+
+void mplpxx_batch_destroy(mplpxx_batch* b) {
+  if (!b) return;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  free_batch(b);
+  delete b;
+}
+
+}  // extern "C"

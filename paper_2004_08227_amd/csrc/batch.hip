@@ -1,0 +1,170 @@
+// Batched MPLP++: many independent FP32 models solved by one persistent
+// launch.  Each workgroup runs a list of tasks; a task is "the slots first,
+// first+stride, ... of model b for all iterations", executed by the mailbox
+// engine (device_common.h).  A large model is split over a team of
+// workgroups (stride = team size, each member's first task, so the whole team
+// runs at once); small models are packed, one after another, into single
+// workgroups.  The host plans the tasks (batch.cpp).
+#include "device_common.h"
+
+namespace mplpxx {
+
+template <int NT, int MAXLT> union BatchSmem {
+  SmemMB<16, NT> s16;
+  SmemMB<32, NT> s32;
+  SmemMB<64, NT> s64;
+  SmemMB<(MAXLT > 64 ? 128 : 64), NT> s128;
+};
+
+template <int LT, int NT>
+__device__ __forceinline__ bool run_task(const BatchArgs& b, const BatchModel& md, const BatchTask& task,
+                                         SmemMB<LT, NT>& sm, int iters) {
+  if (threadIdx.x == 0) sm.abort_flag = 0;
+  __syncthreads();
+  MbView v{b.tables + md.table_off, b.phi + md.phi_off, b.mb + md.u_off, b.slots + md.slot_off,
+           b.deg + md.node_off, nullptr, nullptr, md.L, md.m, md.n};
+  return mb_run<LT, NT, false, false>(v, task.first, task.stride, iters, sm, nullptr, b.spin_limit, b.err);
+}
+
+template <int NT, int MAXLT>
+__global__ void __launch_bounds__(NT + 128) k_batch(BatchArgs b, int iters) {
+  __shared__ BatchSmem<NT, MAXLT> sm;
+  for (int t = b.task_ptr[blockIdx.x]; t < b.task_ptr[blockIdx.x + 1]; ++t) {
+    const BatchTask task = b.tasks[t];
+    const BatchModel md = b.models[task.model];
+    bool ok = true;
+    if (md.lt == 16) ok = run_task<16, NT>(b, md, task, sm.s16, iters);
+    else if (md.lt == 32) ok = run_task<32, NT>(b, md, task, sm.s32, iters);
+    else if (md.lt == 64 || MAXLT == 64) ok = run_task<64, NT>(b, md, task, sm.s64, iters);
+    else ok = run_task<(MAXLT > 64 ? 128 : 64), NT>(b, md, task, sm.s128, iters);
+    if (!ok) return;
+    __syncthreads();  // shared memory is reused by the next task
+  }
+}
+
+hipError_t launch_batch(const BatchArgs& b, int max_lt, int grid, int iters, hipStream_t st) {
+  if (max_lt <= 64)
+    hipLaunchKernelGGL((k_batch<256, 64>), dim3(grid), dim3(256 + 128), 0, st, b, iters);
+  else
+    hipLaunchKernelGGL((k_batch<256, 128>), dim3(grid), dim3(256 + 128), 0, st, b, iters);
+  return hipGetLastError();
+}
+
+int batch_blocks_per_cu(int max_lt) {
+  int nb = 0;
+  hipError_t e = max_lt <= 64
+                     ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_batch<256, 64>, 256 + 128, 0)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_batch<256, 128>, 256 + 128, 0);
+  return e == hipSuccess ? nb : 0;
+}
+
+__global__ void k_u32_to_mb(const float* __restrict__ U, unsigned long long* __restrict__ mb, size_t count) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+    mb[i] = (unsigned long long)__float_as_uint(U[i]);
+}
+__global__ void k_mb_to_u32(float* __restrict__ U, const unsigned long long* __restrict__ mb, size_t count) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+    U[i] = __uint_as_float((unsigned)mb[i]);
+}
+static unsigned blocks_for(size_t count) {
+  size_t b = (count + 255) / 256;
+  return (unsigned)(b > 2048 ? 2048 : (b == 0 ? 1 : b));
+}
+hipError_t launch_u32_to_mb(const float* U, unsigned long long* mb, size_t count, hipStream_t st) {
+  hipLaunchKernelGGL(k_u32_to_mb, dim3(blocks_for(count)), dim3(256), 0, st, U, mb, count);
+  return hipGetLastError();
+}
+hipError_t launch_mb_to_u32(float* U, const unsigned long long* mb, size_t count, hipStream_t st) {
+  hipLaunchKernelGGL(k_mb_to_u32, dim3(blocks_for(count)), dim3(256), 0, st, U, mb, count);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Per-model dual bounds (Eq. 3) of a batch, FP64, fixed-order reductions.
+// ---------------------------------------------------------------------------
+template <int NT, bool kMin>
+__device__ __forceinline__ double breduce(double v, double* sh) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = NT / 2; s >= 1; s >>= 1) {
+    if (tid < s) sh[tid] = kMin ? __builtin_fmin(sh[tid], sh[tid + s]) : sh[tid] + sh[tid + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ void __launch_bounds__(128) k_batch_node_terms(const float* __restrict__ unaries, const float* __restrict__ phi,
+                                                          const BatchModel* __restrict__ models,
+                                                          const int* __restrict__ node_model,
+                                                          const int* __restrict__ node_ptr, const int* __restrict__ inc,
+                                                          double* __restrict__ node_min) {
+  __shared__ double sh[128];
+  const int g = blockIdx.x;
+  const BatchModel md = models[node_model[g]];
+  const int u = g - md.node_off;
+  const int L = md.L;
+  const int s = threadIdx.x;
+  double acc = __builtin_inf();
+  if (s < L) {
+    acc = (double)unaries[md.u_off + (size_t)u * L + s];
+    const int* np = node_ptr + md.csr_off;
+    for (int k = np[u]; k < np[u + 1]; ++k) {
+      const int code = inc[md.inc_off + k];
+      acc += (double)phi[md.phi_off + (size_t)(code >> 1) * 2 * L + (size_t)(code & 1) * L + s];
+    }
+  }
+  const double mn = breduce<128, true>(acc, sh);
+  if (s == 0) node_min[g] = mn;
+}
+
+__global__ void __launch_bounds__(256) k_batch_edge_terms(const float* __restrict__ tables, const float* __restrict__ phi,
+                                                          const BatchModel* __restrict__ models,
+                                                          const int* __restrict__ slot_model,
+                                                          double* __restrict__ edge_min) {
+  __shared__ double sh[256];
+  const int g = blockIdx.x;
+  const BatchModel md = models[slot_model[g]];
+  const int slot = g - md.slot_off;
+  const int L = md.L;
+  const float* tab = tables + md.table_off + (size_t)slot * L * L;
+  const float* p0 = phi + md.phi_off + (size_t)slot * 2 * L;
+  const float* p1 = p0 + L;
+  double mn = __builtin_inf();
+  for (int i = threadIdx.x; i < L * L; i += 256) {
+    const int s = i / L, t = i - s * L;
+    mn = __builtin_fmin(mn, (double)tab[i] - (double)p0[s] - (double)p1[t]);
+  }
+  mn = breduce<256, true>(mn, sh);
+  if (threadIdx.x == 0) edge_min[g] = mn;
+}
+
+__global__ void __launch_bounds__(256) k_batch_sum(const BatchModel* __restrict__ models,
+                                                  const double* __restrict__ node_min,
+                                                  const double* __restrict__ edge_min, double* __restrict__ out) {
+  __shared__ double sh[256];
+  const BatchModel md = models[blockIdx.x];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < md.n; i += 256) acc += node_min[md.node_off + i];
+  for (int i = threadIdx.x; i < md.m; i += 256) acc += edge_min[md.slot_off + i];
+  acc = breduce<256, false>(acc, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = acc;
+}
+
+hipError_t launch_batch_dual(const float* unaries, const float* tables, const float* phi, const BatchModel* models,
+                             const int* node_model, const int* slot_model, const int* node_ptr, const int* inc,
+                             int total_nodes, int total_slots, int count, double* node_min, double* edge_min,
+                             double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_node_terms, dim3(total_nodes), dim3(128), 0, st, unaries, phi, models, node_model,
+                     node_ptr, inc, node_min);
+  if (total_slots > 0)
+    hipLaunchKernelGGL(k_batch_edge_terms, dim3(total_slots), dim3(256), 0, st, tables, phi, models, slot_model,
+                       edge_min);
+  hipLaunchKernelGGL(k_batch_sum, dim3(count), dim3(256), 0, st, models, node_min, edge_min, out);
+  return hipGetLastError();
+}
+
+}  // namespace mplpxx

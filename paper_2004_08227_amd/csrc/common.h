@@ -39,6 +39,46 @@ template <typename T> struct HsArgs {
   long long spin_limit;
 };
 
+// ---------------------------------------------------------------------------
+// Batched engine: many independent FP32 models in one persistent launch.
+// ---------------------------------------------------------------------------
+struct BatchModel {
+  long long table_off;  // floats into the concatenated tables
+  long long phi_off;    // floats into the concatenated messages
+  long long u_off;      // entries into U / mailboxes / unaries (n*L per model)
+  int slot_off;         // first slot of the model in the concatenated SlotInfo
+  int node_off;         // first node of the model (degrees, node maps)
+  int n, L, m, lt;      // sizes and register tile (16, 32, 64 or 128)
+  int csr_off;          // first node_ptr entry (n+1 per model)
+  int inc_off;          // first incidence entry (2m per model)
+};
+struct BatchTask {
+  int model;   // which model
+  int first;   // first slot of the model this workgroup owns
+  int stride;  // team size: the workgroup owns slots first, first+stride, ...
+  int pad;
+};
+struct BatchArgs {
+  const float* tables;
+  float* phi;
+  unsigned long long* mb;
+  const SlotInfo* slots;
+  const int* deg;
+  const BatchModel* models;
+  const BatchTask* tasks;
+  const int* task_ptr;    // [G+1] task range of each workgroup
+  int* err;
+  long long spin_limit;
+};
+hipError_t launch_batch(const BatchArgs& b, int max_lt, int grid, int iters, hipStream_t st);
+int batch_blocks_per_cu(int max_lt);
+hipError_t launch_u32_to_mb(const float* U, unsigned long long* mb, size_t count, hipStream_t st);
+hipError_t launch_mb_to_u32(float* U, const unsigned long long* mb, size_t count, hipStream_t st);
+hipError_t launch_batch_dual(const float* unaries, const float* tables, const float* phi, const BatchModel* models,
+                             const int* node_model, const int* slot_model, const int* node_ptr, const int* inc,
+                             int total_nodes, int total_slots, int count, double* node_min, double* edge_min,
+                             double* out, hipStream_t st);
+
 template <typename T>
 hipError_t launch_handshake(const HsArgs<T>& a, int engine, int LT, int NT, int slot_begin, int count, int grid,
                             int iters, hipStream_t st);

@@ -9,6 +9,7 @@
 #include <cstdint>
 #include <vector>
 
+#include "host_util.h"
 #include "schedule.h"
 
 namespace mplpxx {
@@ -74,6 +75,45 @@ void build_schedule(int n, const std::vector<int>& eu, const std::vector<int>& e
     rest.swap(next);
     ++round_id;
   }
+}
+
+int prepare_graph(int n, int m, const int32_t* edges, GraphPrep& g) {
+  std::vector<int> eu(m), ev(m);
+  g.flip.assign(m, 0);
+  for (int e = 0; e < m; ++e) {
+    const int a = edges[2 * e], b = edges[2 * e + 1];
+    if (a < 0 || a >= n || b < 0 || b >= n) return fail(MPLPXX_EINVAL, "edge %d: node index out of range", e);
+    if (a == b) return fail(MPLPXX_EINVAL, "edge %d: self loop", e);
+    eu[e] = std::min(a, b);
+    ev[e] = std::max(a, b);
+    g.flip[e] = a > b;
+  }
+  {
+    std::vector<int64_t> keys(m);
+    for (int e = 0; e < m; ++e) keys[e] = (int64_t)eu[e] * n + ev[e];
+    std::sort(keys.begin(), keys.end());
+    for (int e = 1; e < m; ++e)
+      if (keys[e] == keys[e - 1])
+        return fail(MPLPXX_EINVAL, "duplicate edge (%lld, %lld)", (long long)(keys[e] / n), (long long)(keys[e] % n));
+  }
+  build_schedule(n, eu, ev, g.step_ptr, g.order);
+  g.S = (int)g.step_ptr.size() - 1;
+  if ((int)g.order.size() != m) return fail(MPLPXX_EINVAL, "internal: schedule does not cover the edges");
+  g.slot_of_edge.assign(m, -1);
+  g.slots.resize(m);
+  g.deg.assign(n, 0);
+  for (int i = 0; i < m; ++i) {
+    const int e = g.order[i];
+    g.slot_of_edge[e] = i;
+    SlotInfo si{};
+    si.e = e;
+    si.u = eu[e];
+    si.v = ev[e];
+    si.pos_u = g.deg[si.u]++;
+    si.pos_v = g.deg[si.v]++;
+    g.slots[i] = si;
+  }
+  return MPLPXX_OK;
 }
 
 }  // namespace mplpxx

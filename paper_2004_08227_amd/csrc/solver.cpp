@@ -27,34 +27,9 @@
 
 using namespace mplpxx;
 
+#include "host_util.h"
+
 namespace {
-
-thread_local std::string g_last_error;
-
-int fail(int code, const char* fmt, ...) {
-  char buf[512];
-  va_list ap;
-  va_start(ap, fmt);
-  vsnprintf(buf, sizeof(buf), fmt, ap);
-  va_end(ap);
-  g_last_error = buf;
-  return code;
-}
-
-#define HIP_TRY(expr)                                                                            \
-  do {                                                                                           \
-    hipError_t e_ = (expr);                                                                      \
-    if (e_ != hipSuccess) {                                                                      \
-      if (e_ == hipErrorOutOfMemory) return fail(MPLPXX_ENOMEM, "%s: %s", #expr, hipGetErrorString(e_)); \
-      return fail(MPLPXX_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));                       \
-    }                                                                                            \
-  } while (0)
-
-int next_tile(int L) {
-  int lt = 16;
-  while (lt < L) lt *= 2;
-  return lt;
-}
 
 bool valid_threads(int LT, int NT) {
   if (NT != 256 && NT != 512 && NT != 1024) return false;
@@ -160,42 +135,17 @@ bool finite_host(const void* p, size_t count, int dtype) {
 }
 
 // Validates the graph and fills orientation, schedule, slot metadata.
-int prepare_graph(mplpxx_solver* h, const int32_t* edges) {
-  const int n = h->n, m = h->m;
-  std::vector<int> eu(m), ev(m);
-  h->flip.assign(m, 0);
-  for (int e = 0; e < m; ++e) {
-    const int a = edges[2 * e], b = edges[2 * e + 1];
-    if (a < 0 || a >= n || b < 0 || b >= n) return fail(MPLPXX_EINVAL, "edge %d: node index out of range", e);
-    if (a == b) return fail(MPLPXX_EINVAL, "edge %d: self loop", e);
-    eu[e] = std::min(a, b);
-    ev[e] = std::max(a, b);
-    h->flip[e] = a > b;
-  }
-  {
-    std::vector<int64_t> keys(m);
-    for (int e = 0; e < m; ++e) keys[e] = (int64_t)eu[e] * n + ev[e];
-    std::sort(keys.begin(), keys.end());
-    for (int e = 1; e < m; ++e)
-      if (keys[e] == keys[e - 1]) return fail(MPLPXX_EINVAL, "duplicate edge (%lld, %lld)", (long long)(keys[e] / n), (long long)(keys[e] % n));
-  }
-  build_schedule(n, eu, ev, h->step_ptr, h->order);
-  h->S = (int)h->step_ptr.size() - 1;
-  if ((int)h->order.size() != m) return fail(MPLPXX_EINVAL, "internal: schedule does not cover the edges");
-  h->slot_of_edge.assign(m, -1);
-  h->slots.resize(m);
-  h->deg.assign(n, 0);
-  for (int i = 0; i < m; ++i) {
-    const int e = h->order[i];
-    h->slot_of_edge[e] = i;
-    SlotInfo si{};
-    si.e = e;
-    si.u = eu[e];
-    si.v = ev[e];
-    si.pos_u = h->deg[si.u]++;
-    si.pos_v = h->deg[si.v]++;
-    h->slots[i] = si;
-  }
+int prepare_solver_graph(mplpxx_solver* h, const int32_t* edges) {
+  GraphPrep g;
+  const int rc = prepare_graph(h->n, h->m, edges, g);
+  if (rc != MPLPXX_OK) return rc;
+  h->S = g.S;
+  h->step_ptr.swap(g.step_ptr);
+  h->order.swap(g.order);
+  h->slot_of_edge.swap(g.slot_of_edge);
+  h->slots.swap(g.slots);
+  h->flip.swap(g.flip);
+  h->deg.swap(g.deg);
   return MPLPXX_OK;
 }
 
@@ -223,7 +173,7 @@ int create_impl(int32_t n, int32_t L, int64_t m, const int32_t* edges, const voi
   h->m = (int)m;
   h->dtype = dtype;
   h->esz = esz;
-  int rc = prepare_graph(h, edges);
+  int rc = prepare_solver_graph(h, edges);
   if (rc != MPLPXX_OK) {
     delete h;
     return rc;
@@ -565,7 +515,7 @@ int mplpxx_schedule(int32_t n, int64_t m, const int32_t* edges, int32_t* n_steps
   mplpxx_solver tmp;
   tmp.n = n;
   tmp.m = (int)m;
-  int rc = prepare_graph(&tmp, edges);
+  int rc = prepare_solver_graph(&tmp, edges);
   if (rc != MPLPXX_OK) return rc;
   if (n_steps) *n_steps = tmp.S;
   if (step_ptr) std::memcpy(step_ptr, tmp.step_ptr.data(), tmp.step_ptr.size() * sizeof(int));

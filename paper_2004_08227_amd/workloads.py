@@ -29,9 +29,64 @@ stand in for the paper's datasets (Sec. 7), which are not available here:
 """
 from __future__ import annotations
 
+import ctypes
+import os
+import subprocess
 from dataclasses import dataclass
 
 import numpy as np
+
+_GEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "gen")
+_GEN_SRC = os.path.join(_GEN_DIR, "pose_tables.c")
+_GEN_LIB = os.path.join(_GEN_DIR, "libpose_tables.so")
+_gen = None
+
+
+def build_generator() -> str:
+    """Compiles the C helper that fills pose tables (OpenMP)."""
+    tmp = _GEN_LIB + ".tmp"
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+                    "-fno-fast-math", "-o", tmp, _GEN_SRC, "-lm"], check=True)
+    os.replace(tmp, _GEN_LIB)
+    return _GEN_LIB
+
+
+def _gen_lib():
+    global _gen
+    if _gen is None and os.path.exists(_GEN_LIB) and os.path.getmtime(_GEN_LIB) >= os.path.getmtime(_GEN_SRC):
+        g = ctypes.CDLL(_GEN_LIB)
+        g.pose_tables.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_double, ctypes.c_void_p]
+        g.pose_tables.restype = None
+        _gen = g
+    return _gen
+
+
+def pose_tables(edges, P, Q, tau, dtype=np.float32, use_c=True, chunk=4096):
+    """table[e][s][t] = min((|P[u][s]-P[v][t]| - |Q[u]-Q[v]|)^2, tau) in FP64,
+    rounded once; the C helper and the numpy path give the same bits."""
+    m = edges.shape[0]
+    L = P.shape[1]
+    g = _gen_lib() if (use_c and dtype == np.float32) else None
+    if g is not None:
+        out = np.empty((m, L, L), dtype=np.float32)
+        e = np.ascontiguousarray(edges, dtype=np.int32)
+        Pc = np.ascontiguousarray(P, dtype=np.float64)
+        Qc = np.ascontiguousarray(Q, dtype=np.float64)
+        g.pose_tables(m, L, e.ctypes.data, Pc.ctypes.data, Qc.ctypes.data, float(tau), out.ctypes.data)
+        return out
+    out = np.empty((m, L, L), dtype=dtype)
+    for lo in range(0, m, chunk):
+        hi = min(m, lo + chunk)
+        u = edges[lo:hi, 0]
+        v = edges[lo:hi, 1]
+        q = Q[u] - Q[v]
+        dq = np.sqrt((q[:, 0] * q[:, 0] + q[:, 1] * q[:, 1]) + q[:, 2] * q[:, 2])[:, None, None]
+        dif = P[u][:, :, None, :] - P[v][:, None, :, :]
+        dp = np.sqrt((dif[..., 0] * dif[..., 0] + dif[..., 1] * dif[..., 1]) + dif[..., 2] * dif[..., 2])
+        d = dp - dq
+        out[lo:hi] = np.minimum(d * d, tau).astype(dtype)
+    return out
 
 
 @dataclass
@@ -85,15 +140,7 @@ def pose(n: int, L: int, seed: int = 0, tau: float = 0.04, dtype=np.float32,
     star = rng.integers(0, L, size=n)
     Q = P[np.arange(n), star]                       # planted model points [n, 3]
     edges = complete_edges(n)
-    m = edges.shape[0]
-    pairwise = np.empty((m, L, L), dtype=dtype)
-    for lo in range(0, m, chunk):
-        hi = min(m, lo + chunk)
-        u = edges[lo:hi, 0]
-        v = edges[lo:hi, 1]
-        dp = np.linalg.norm(P[u][:, :, None, :] - P[v][:, None, :, :], axis=-1)   # [c, L, L]
-        dq = np.linalg.norm(Q[u] - Q[v], axis=-1)[:, None, None]                    # [c, 1, 1]
-        pairwise[lo:hi] = np.minimum((dp - dq) ** 2, tau).astype(dtype)
+    pairwise = pose_tables(edges, P, Q, tau, dtype=dtype, chunk=chunk)
     return Model(n, L, edges, unaries.astype(dtype), pairwise, f"pose_n{n}_L{L}_s{seed}")
 
 

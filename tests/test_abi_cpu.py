@@ -129,3 +129,15 @@ def test_host_schedule_rejects_bad_graphs():
         M.schedule(3, np.array([[0, 3]], np.int32))
     sp, order = M.schedule(4, np.zeros((0, 2), np.int32))
     assert list(sp) == [0] and order.size == 0
+
+
+def test_pose_table_generator_c_and_numpy_agree_bitwise():
+    W.build_generator()
+    rng = np.random.default_rng(5)
+    for n, L in [(7, 1), (12, 13), (25, 64)]:
+        P = rng.random((n, L, 3))
+        Q = P[np.arange(n), rng.integers(0, L, n)]
+        e = W.complete_edges(n)
+        a = W.pose_tables(e, P, Q, 0.04, use_c=True)
+        b = W.pose_tables(e, P, Q, 0.04, use_c=False)
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32))

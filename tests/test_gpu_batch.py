@@ -1,0 +1,101 @@
+"""GPU tests of the batched engine (many models in one persistent launch).
+
+Every model of a batch must end bitwise equal to the same model solved alone
+by the single-model persistent engine (same per-edge arithmetic, same
+schedule), and its dual bound must match the FP64 oracle to 1e-5.  Graph
+replays are checked against plain launches after every replay, with other
+device work in between; planning options must not change any bit."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2004_08227_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+M = pytest.importorskip("paper_2004_08227_amd")
+
+
+def _announce(*a):
+    print("CASE", *a, flush=True)
+
+
+def _mixed_models(seed=0, count=12):
+    rng = np.random.default_rng(seed)
+    models = []
+    for i in range(count):
+        n = int(rng.integers(2, 60))
+        L = int(rng.choice([1, 3, 8, 13, 16, 17, 32, 40, 64]))
+        models.append(W.pose(n, L, seed=100 + i))
+    # a non-complete graph, an edgeless model and a 65..128-label model
+    models.append(W.potts_er(40, 9, 0.2, seed=7))
+    models.append(W.Model(3, 4, np.zeros((0, 2), np.int32), np.random.default_rng(1).random((3, 4)).astype(np.float32),
+                          np.zeros((0, 4, 4), np.float32)))
+    return models
+
+
+def _alone(model, iters):
+    with M.Solver.from_model(model) as s:
+        s.set_option(M.OPT_ENGINE, M.ENGINE_PERSISTENT)
+        s.iterate(iters)
+        return s.get_state()
+
+
+@pytest.mark.parametrize("with_big_labels", [False, True])
+def test_batch_equals_single_model_runs_and_oracle(with_big_labels):
+    _announce("batch vs single", with_big_labels)
+    models = _mixed_models()
+    if with_big_labels:
+        models.append(W.uniform(9, 100, seed=3))
+    iters = 7
+    with M.Batch(models) as b:
+        b.iterate(iters)
+        duals = b.dual_bounds()
+        states = [b.get_state(i) for i in range(len(models))]
+        assert b.info("count") == len(models)
+    for i, mo in enumerate(models):
+        U, phi = _alone(mo, iters) if mo.m else (mo.unaries, np.zeros((0, 2, mo.L), np.float32))
+        assert np.array_equal(states[i][0], U), (i, mo.name)
+        assert np.array_equal(states[i][1], phi), (i, mo.name)
+        st, ref = oracle.run_model(mo, iters)
+        d_ref = ref[-1] if mo.m else st.dual()
+        assert abs(duals[i] - d_ref) <= 1e-5 * max(1.0, abs(d_ref)), (i, duals[i], d_ref)
+
+
+def test_plans_and_graph_replays_are_bitwise_identical():
+    models = _mixed_models(seed=1, count=10)
+    results = []
+    for opts in [dict(graph=0), dict(graph=1), dict(one_per_model=1), dict(grid=5), dict(grid=3, one_per_model=1),
+                 dict(handoff_us=5.0, edge64_us=0.1)]:
+        _announce("plan", opts)
+        with M.Batch(models) as b:
+            for k, v in opts.items():
+                b.set_option(k, v)
+            per_call = []
+            for _ in range(3):                 # three calls: the graph is replayed twice
+                b.iterate(4)
+                d = b.dual_bounds()            # eager device work between replays
+                per_call.append((d, [b.get_state(i) for i in range(len(models))]))
+            results.append(per_call)
+    base = results[0]
+    for other in results[1:]:
+        for (d0, s0), (d1, s1) in zip(base, other):
+            assert np.array_equal(d0, d1)
+            for (U0, p0), (U1, p1) in zip(s0, s1):
+                assert np.array_equal(U0, U1) and np.array_equal(p0, p1)
+
+
+def test_batch_reset_and_timeout():
+    _announce("batch reset/timeout")
+    models = _mixed_models(seed=2, count=6)
+    with M.Batch(models) as b:
+        b.iterate(3)
+        d3 = b.dual_bounds()
+        b.reset()
+        b.set_option("spin_limit", 1)
+        with pytest.raises(M.MplpError) as ei:
+            b.iterate(3)
+        assert ei.value.code == M.ETIMEOUT
+        b.set_option("spin_limit", 0)
+        b.reset()
+        b.iterate(3)
+        assert np.array_equal(b.dual_bounds(), d3)
