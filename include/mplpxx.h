@@ -190,6 +190,30 @@ int mplpxx_get_step_profile(mplpxx_solver* h, int64_t* stamps);
 int mplpxx_last_iterate_ms(mplpxx_solver* h, double* ms);
 
 /* ------------------------------------------------------------------------
+ * Differentiation: adjoint of K unrolled iterations.
+ * --------------------------------------------------------------------- */
+
+/* Resets the state to phi = 0, U = unaries, runs K >= 1 iterations with the
+ * handle's engine, keeping a checkpoint of (U, phi) every `every` >= 1
+ * iterations, and writes to the HOST pointer `loss` (may be NULL)
+ *   D_K = sum_u min_s U_u(s)  (FP64 sum).
+ * After the last sweep every edge's reparametrized pairwise term has minimum
+ * zero (Sec. 4, after (H)), so D_K is the dual bound of Eq. (3) up to
+ * rounding. */
+int mplpxx_adjoint_forward(mplpxx_solver* h, int32_t K, int32_t every, double* loss);
+
+/* Gradient of D_K with respect to the input costs, by reverse sweeps over
+ * the recorded minimizers (recomputing each segment from its checkpoint):
+ * DEVICE buffers grad_unaries [n][L] and grad_pairwise [m][L][L] in the
+ * handle's dtype and in the caller's layout (edge order and orientation of
+ * mplpxx_create).  D_K is piecewise linear in the costs; the gradient is the
+ * one of the linear piece selected by the recorded minimizers (lowest label
+ * on ties).  Either pointer may be NULL.  MPLPXX_ESTATE if no
+ * mplpxx_adjoint_forward preceded it or the state was changed since.  The
+ * handle's state is left at the end of the forward. */
+int mplpxx_adjoint_backward(mplpxx_solver* h, void* grad_unaries, void* grad_pairwise);
+
+/* ------------------------------------------------------------------------
  * Batched solving: many independent FP32 models in one persistent launch.
  * --------------------------------------------------------------------- */
 

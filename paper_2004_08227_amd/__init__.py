@@ -84,6 +84,8 @@ def lib():
         "mplpxx_get_info": (ctypes.c_int, [vp, i32, ctypes.POINTER(i64)]),
         "mplpxx_last_iterate_ms": (ctypes.c_int, [vp, ctypes.POINTER(dbl)]),
         "mplpxx_get_step_profile": (ctypes.c_int, [vp, vp]),
+        "mplpxx_adjoint_forward": (ctypes.c_int, [vp, i32, i32, ctypes.POINTER(dbl)]),
+        "mplpxx_adjoint_backward": (ctypes.c_int, [vp, vp, vp]),
         "mplpxx_batch_create": (ctypes.c_int, [i32, vp, vp, vp, vp, vp, vp, pp]),
         "mplpxx_batch_iterate": (ctypes.c_int, [vp, i32]),
         "mplpxx_batch_dual_bounds": (ctypes.c_int, [vp, vp]),
@@ -241,6 +243,29 @@ class Solver:
         v = ctypes.c_int64()
         _check(lib().mplpxx_get_info(self._h, INFO[key], ctypes.byref(v)))
         return v.value
+
+    def adjoint_forward(self, K, every=10):
+        """K iterations from phi = 0 with checkpoints every `every`; returns
+        D_K = sum_u min_s U_u(s)."""
+        d = ctypes.c_double()
+        _check(lib().mplpxx_adjoint_forward(self._h, int(K), int(every), ctypes.byref(d)))
+        return d.value
+
+    def adjoint_backward_device(self, grad_unaries, grad_pairwise):
+        """Writes dD_K/dunaries and dD_K/dpairwise into contiguous torch
+        tensors on the GPU (the handle's dtype, the caller's layouts)."""
+        _check(lib().mplpxx_adjoint_backward(self._h, ctypes.c_void_p(grad_unaries.data_ptr()),
+                                             ctypes.c_void_p(grad_pairwise.data_ptr()) if self.m else None))
+
+    def adjoint_backward(self):
+        """Host copies (numpy) of the gradients of the last adjoint_forward."""
+        import torch
+        dt = torch.float32 if self.dtype == np.float32 else torch.float64
+        gu = torch.empty((self.n, self.L), dtype=dt, device="cuda")
+        gp = torch.empty((max(self.m, 1), self.L, self.L), dtype=dt, device="cuda")
+        self.adjoint_backward_device(gu, gp)
+        torch.cuda.synchronize()
+        return gu.cpu().numpy(), gp[:self.m].cpu().numpy()
 
     def step_profile(self):
         """[m, 4] int64 timestamps (slot order) of the last iteration."""

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmplpxx.so")
 
-SOURCES = ["solver.cpp", "batch.cpp", "schedule.cpp", "handshake.hip", "dual.hip", "batch.hip"]
+SOURCES = ["solver.cpp", "batch.cpp", "schedule.cpp", "handshake.hip", "dual.hip", "batch.hip", "adjoint.hip"]
 ARCH = os.environ.get("MPLPXX_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -53,6 +53,7 @@ struct mplpxx_batch {
   BatchTask* d_tasks = nullptr;
   int* d_task_ptr = nullptr;
   int* d_err = nullptr;
+  int* d_ticket = nullptr;
   int* d_node_model = nullptr;
   int* d_slot_model = nullptr;
   int* d_node_ptr = nullptr;
@@ -95,8 +96,8 @@ double model_time(const mplpxx_batch* b, int i, int T, double bw_per_wg_bytes_us
 }
 
 // tasks for makespan tau; returns the resulting max workgroup load
-double assign(const mplpxx_batch* b, double tau, int G, double bw, std::vector<std::vector<BatchTask>>& wg_tasks,
-              int* nteams, int* max_team) {
+double assign(const mplpxx_batch* b, double tau, int G, int team_cap, double bw,
+              std::vector<std::vector<BatchTask>>& wg_tasks, int* nteams, int* max_team) {
   wg_tasks.assign(G, {});
   std::vector<double> load(G, 0.0);
   std::vector<int> team(b->count, 1);
@@ -106,7 +107,7 @@ double assign(const mplpxx_batch* b, double tau, int G, double bw, std::vector<s
   for (int i = 0; i < b->count; ++i) {
     const ModelHost& h = b->mh[i];
     if (h.m == 0) continue;
-    int tmax = std::max(1, std::min(h.max_step, G));
+    int tmax = std::max(1, std::min(h.max_step, team_cap));
     int T = 1;
     if (!b->one_per_model) {
       // smallest team meeting tau (model_time decreases with T)
@@ -126,7 +127,7 @@ double assign(const mplpxx_batch* b, double tau, int G, double bw, std::vector<s
   // teams first: each member's first task, consecutive workgroups
   for (int i = 0; i < b->count; ++i) {
     if (team[i] < 2) continue;
-    if (used + team[i] > G) return INFINITY;
+    if (used + team[i] > team_cap) return INFINITY;
     const double t = model_time(b, i, team[i], bw);
     for (int r = 0; r < team[i]; ++r) {
       wg_tasks[used + r].push_back(BatchTask{i, r, team[i], 0});
@@ -166,19 +167,22 @@ int plan(mplpxx_batch* b) {
   G = std::max(1, G);
   // HBM share of one workgroup in bytes per microsecond (8 TB/s nominal)
   const double bw = 8.0e12 / 1e6 / G;
+  // teams wait on each other, so they only use the first num_cus logical
+  // workgroups: one per compute unit always fits
+  const int team_cap = std::min(G, b->num_cus);
   double lo = 0.0, hi = 0.0;
   for (int i = 0; i < b->count; ++i) {
-    const int tmax = std::max(1, std::min(b->mh[i].max_step, G));
+    const int tmax = std::max(1, std::min(b->mh[i].max_step, team_cap));
     lo = std::max(lo, model_time(b, i, tmax, bw));
     hi += model_time(b, i, 1, bw);
   }
   hi = std::max(hi, lo);
   std::vector<std::vector<BatchTask>> best, cur;
   int nteams = 0, max_team = 1, bt = 0, bm = 1;
-  double best_load = assign(b, hi, G, bw, best, &bt, &bm);
+  double best_load = assign(b, hi, G, team_cap, bw, best, &bt, &bm);
   for (int rep = 0; rep < 40 && hi - lo > 1e-3 * hi; ++rep) {
     const double mid = 0.5 * (lo + hi);
-    const double l = assign(b, mid, G, bw, cur, &nteams, &max_team);
+    const double l = assign(b, mid, G, team_cap, bw, cur, &nteams, &max_team);
     if (l <= mid * 1.05) {
       hi = mid;
       if (l < best_load) {
@@ -203,9 +207,12 @@ int plan(mplpxx_batch* b) {
   b->d_task_ptr = nullptr;
   HIP_TRY(hipMalloc(&b->d_tasks, std::max<size_t>(1, tasks.size()) * sizeof(BatchTask)));
   HIP_TRY(hipMalloc(&b->d_task_ptr, (G + 1) * sizeof(int)));
+  // every copy and fill goes through the batch's own (non-blocking) stream, so
+  // that it is ordered before the kernels that read it
   if (!tasks.empty())
-    HIP_TRY(hipMemcpy(b->d_tasks, tasks.data(), tasks.size() * sizeof(BatchTask), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(b->d_task_ptr, ptr.data(), (G + 1) * sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpyAsync(b->d_tasks, tasks.data(), tasks.size() * sizeof(BatchTask), hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(hipMemcpyAsync(b->d_task_ptr, ptr.data(), (G + 1) * sizeof(int), hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
   b->grid = G;
   b->ntasks = (int)tasks.size();
   b->nteams = bt;
@@ -222,7 +229,7 @@ int plan(mplpxx_batch* b) {
 
 void free_batch(mplpxx_batch* b) {
   void* ptrs[] = {b->d_tables, b->d_phi, b->d_U, b->d_unaries, b->d_mb, b->d_slots, b->d_deg, b->d_models,
-                  b->d_tasks, b->d_task_ptr, b->d_err, b->d_node_model, b->d_slot_model, b->d_node_ptr,
+                  b->d_tasks, b->d_task_ptr, b->d_err, b->d_ticket, b->d_node_model, b->d_slot_model, b->d_node_ptr,
                   b->d_inc, b->d_node_min, b->d_edge_min, b->d_duals};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -242,9 +249,12 @@ hipError_t enqueue(mplpxx_batch* b, int k) {
   a.models = b->d_models;
   a.tasks = b->d_tasks;
   a.task_ptr = b->d_task_ptr;
+  a.ticket = b->d_ticket;
   a.err = b->d_err;
   a.spin_limit = b->spin_limit;
-  hipError_t e = launch_u32_to_mb(b->d_U, b->d_mb, (size_t)b->total_u, b->stream);
+  hipError_t e = launch_fill_int(b->d_ticket, 0, 1, b->stream);
+  if (e != hipSuccess) return e;
+  e = launch_u32_to_mb(b->d_U, b->d_mb, (size_t)b->total_u, b->stream);
   if (e != hipSuccess) return e;
   e = launch_batch(a, b->max_lt, b->grid, k, b->stream);
   if (e != hipSuccess) return e;
@@ -342,7 +352,8 @@ int mplpxx_batch_create(int32_t count, const int32_t* n, const int32_t* L, const
   TRY(alloc((void**)&b->d_slots, (size_t)b->total_slots * sizeof(SlotInfo)));
   TRY(alloc((void**)&b->d_deg, (size_t)b->total_nodes * sizeof(int)));
   TRY(alloc((void**)&b->d_models, (size_t)count * sizeof(BatchModel)));
-  TRY(alloc((void**)&b->d_err, 4 * sizeof(int)));
+  TRY(alloc((void**)&b->d_err, 8 * sizeof(int)));
+  TRY(alloc((void**)&b->d_ticket, sizeof(int)));
   TRY(alloc((void**)&b->d_node_model, (size_t)b->total_nodes * sizeof(int)));
   TRY(alloc((void**)&b->d_slot_model, (size_t)b->total_slots * sizeof(int)));
   TRY(alloc((void**)&b->d_node_ptr, (size_t)b->total_csr * sizeof(int)));
@@ -350,8 +361,9 @@ int mplpxx_batch_create(int32_t count, const int32_t* n, const int32_t* L, const
   TRY(alloc((void**)&b->d_node_min, (size_t)b->total_nodes * sizeof(double)));
   TRY(alloc((void**)&b->d_edge_min, (size_t)b->total_slots * sizeof(double)));
   TRY(alloc((void**)&b->d_duals, (size_t)count * sizeof(double)));
-  TRY(hipMemset(b->d_phi, 0, (size_t)b->total_phi * sizeof(float) + 0));
-  TRY(hipMemset(b->d_err, 0, 4 * sizeof(int)));
+  hipStream_t cs = b->stream;
+  TRY(hipMemsetAsync(b->d_phi, 0, (size_t)b->total_phi * sizeof(float), cs));
+  TRY(hipMemsetAsync(b->d_err, 0, 8 * sizeof(int), cs));
   // per model: packed tables (slot order, transposed where given as (v, u)),
   // unaries, slot metadata, degrees, incidence lists, node/slot maps
   std::vector<float> packed;
@@ -373,10 +385,13 @@ int mplpxx_batch_create(int32_t count, const int32_t* n, const int32_t* L, const
           for (int c = 0; c < h.L; ++c) dst[(size_t)r * h.L + c] = src[(size_t)c * h.L + r];
       }
     }
-    if (h.m) TRY(hipMemcpy(b->d_tables + d.table_off, packed.data(), packed.size() * sizeof(float), hipMemcpyHostToDevice));
-    TRY(hipMemcpy(b->d_unaries + d.u_off, unaries[i], (size_t)h.n * h.L * sizeof(float), hipMemcpyHostToDevice));
-    if (h.m) TRY(hipMemcpy(b->d_slots + d.slot_off, g.slots.data(), (size_t)h.m * sizeof(SlotInfo), hipMemcpyHostToDevice));
-    TRY(hipMemcpy(b->d_deg + d.node_off, g.deg.data(), (size_t)h.n * sizeof(int), hipMemcpyHostToDevice));
+    if (h.m) {
+      TRY(hipMemcpyAsync(b->d_tables + d.table_off, packed.data(), packed.size() * sizeof(float), hipMemcpyHostToDevice, cs));
+      TRY(hipStreamSynchronize(cs));  // `packed` is reused for the next model
+    }
+    TRY(hipMemcpyAsync(b->d_unaries + d.u_off, unaries[i], (size_t)h.n * h.L * sizeof(float), hipMemcpyHostToDevice, cs));
+    if (h.m) TRY(hipMemcpyAsync(b->d_slots + d.slot_off, g.slots.data(), (size_t)h.m * sizeof(SlotInfo), hipMemcpyHostToDevice, cs));
+    TRY(hipMemcpyAsync(b->d_deg + d.node_off, g.deg.data(), (size_t)h.n * sizeof(int), hipMemcpyHostToDevice, cs));
     std::vector<int> node_ptr(h.n + 1, 0), inc(2 * (size_t)h.m);
     for (int s = 0; s < h.m; ++s) {
       node_ptr[g.slots[s].u + 1]++;
@@ -388,16 +403,18 @@ int mplpxx_batch_create(int32_t count, const int32_t* n, const int32_t* L, const
       inc[fillp[g.slots[s].u]++] = 2 * s;
       inc[fillp[g.slots[s].v]++] = 2 * s + 1;
     }
-    TRY(hipMemcpy(b->d_node_ptr + d.csr_off, node_ptr.data(), node_ptr.size() * sizeof(int), hipMemcpyHostToDevice));
-    if (h.m) TRY(hipMemcpy(b->d_inc + d.inc_off, inc.data(), inc.size() * sizeof(int), hipMemcpyHostToDevice));
+    TRY(hipMemcpyAsync(b->d_node_ptr + d.csr_off, node_ptr.data(), node_ptr.size() * sizeof(int), hipMemcpyHostToDevice, cs));
+    if (h.m) TRY(hipMemcpyAsync(b->d_inc + d.inc_off, inc.data(), inc.size() * sizeof(int), hipMemcpyHostToDevice, cs));
+    TRY(hipStreamSynchronize(cs));  // host vectors of this model go out of scope
     for (int u = 0; u < h.n; ++u) node_model[d.node_off + u] = i;
     for (int s = 0; s < h.m; ++s) slot_model[d.slot_off + s] = i;
   }
-  TRY(hipMemcpy(b->d_models, b->md.data(), (size_t)count * sizeof(BatchModel), hipMemcpyHostToDevice));
-  TRY(hipMemcpy(b->d_node_model, node_model.data(), node_model.size() * sizeof(int), hipMemcpyHostToDevice));
+  TRY(hipMemcpyAsync(b->d_models, b->md.data(), (size_t)count * sizeof(BatchModel), hipMemcpyHostToDevice, cs));
+  TRY(hipMemcpyAsync(b->d_node_model, node_model.data(), node_model.size() * sizeof(int), hipMemcpyHostToDevice, cs));
   if (b->total_slots)
-    TRY(hipMemcpy(b->d_slot_model, slot_model.data(), slot_model.size() * sizeof(int), hipMemcpyHostToDevice));
-  TRY(hipMemcpy(b->d_U, b->d_unaries, (size_t)b->total_u * sizeof(float), hipMemcpyDeviceToDevice));
+    TRY(hipMemcpyAsync(b->d_slot_model, slot_model.data(), slot_model.size() * sizeof(int), hipMemcpyHostToDevice, cs));
+  TRY(hipMemcpyAsync(b->d_U, b->d_unaries, (size_t)b->total_u * sizeof(float), hipMemcpyDeviceToDevice, cs));
+  TRY(hipStreamSynchronize(cs));
 #undef TRY
   const int rc = plan(b);
   if (rc != MPLPXX_OK) return bail(rc);
@@ -436,11 +453,13 @@ int mplpxx_batch_iterate(mplpxx_batch* b, int32_t k) {
   }
   HIP_TRY(hipEventRecord(b->ev1, b->stream));
   HIP_TRY(hipStreamSynchronize(b->stream));
-  int err = 0;
-  HIP_TRY(hipMemcpy(&err, b->d_err, sizeof(int), hipMemcpyDeviceToHost));
-  if (err) {
-    (void)hipMemset(b->d_err, 0, sizeof(int));
-    return fail(err, "device wait exceeded its bound (code %d)", err);
+  int err[8] = {0};
+  HIP_TRY(hipMemcpy(err, b->d_err, 8 * sizeof(int), hipMemcpyDeviceToHost));
+  if (err[0]) {
+    (void)hipMemsetAsync(b->d_err, 0, 8 * sizeof(int), b->stream);
+    (void)hipStreamSynchronize(b->stream);
+    return fail(err[0], "device wait exceeded its bound (workgroup %d, slot %d, node %d, expected version %d, seen %d)",
+                err[1], err[2], err[3], err[4], err[5]);
   }
   float ms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, b->ev0, b->ev1));
@@ -479,8 +498,9 @@ int mplpxx_batch_get_state(mplpxx_batch* b, int32_t model, float* U, float* phi)
 int mplpxx_batch_reset(mplpxx_batch* b) {
   if (!b) return fail(MPLPXX_EINVAL, "handle is NULL");
   HIP_TRY(hipStreamSynchronize(b->stream));
-  HIP_TRY(hipMemset(b->d_phi, 0, (size_t)b->total_phi * sizeof(float)));
-  HIP_TRY(hipMemcpy(b->d_U, b->d_unaries, (size_t)b->total_u * sizeof(float), hipMemcpyDeviceToDevice));
+  HIP_TRY(hipMemsetAsync(b->d_phi, 0, (size_t)b->total_phi * sizeof(float), b->stream));
+  HIP_TRY(hipMemcpyAsync(b->d_U, b->d_unaries, (size_t)b->total_u * sizeof(float), hipMemcpyDeviceToDevice, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
   b->iterations = 0;
   return MPLPXX_OK;
 }

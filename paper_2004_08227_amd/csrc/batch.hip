@@ -26,10 +26,20 @@ __device__ __forceinline__ bool run_task(const BatchArgs& b, const BatchModel& m
   return mb_run<LT, NT, false, false>(v, task.first, task.stride, iters, sm, nullptr, b.spin_limit, b.err);
 }
 
+// at least three waves per SIMD, i.e. two 6-wave workgroups per compute
+// unit: one computes while the other waits for
+// its tables or its neighbours
 template <int NT, int MAXLT>
-__global__ void __launch_bounds__(NT + 128) k_batch(BatchArgs b, int iters) {
+__global__ void __launch_bounds__(NT + 128, 3) k_batch(BatchArgs b, int iters) {
   __shared__ BatchSmem<NT, MAXLT> sm;
-  for (int t = b.task_ptr[blockIdx.x]; t < b.task_ptr[blockIdx.x + 1]; ++t) {
+  __shared__ int s_wg;
+  // logical workgroup = order of arrival: workgroups that hold a ticket have
+  // started, so the first tickets (where the planner puts every team) run
+  // together whatever order the hardware dispatches in
+  if (threadIdx.x == 0) s_wg = atomicAdd(b.ticket, 1);
+  __syncthreads();
+  const int wg = s_wg;
+  for (int t = b.task_ptr[wg]; t < b.task_ptr[wg + 1]; ++t) {
     const BatchTask task = b.tasks[t];
     const BatchModel md = b.models[task.model];
     bool ok = true;

@@ -22,7 +22,9 @@ struct SlotInfo {
   int u, v;    // its nodes, u < v
   int pos_u;   // number of edges of u that precede this one in the queue
   int pos_v;   // same for v
-  int pad0, pad1, pad2;
+  int deg_u;   // degree of u (updates of u per iteration)
+  int deg_v;   // degree of v
+  int pad;
 };
 
 template <typename T> struct HsArgs {
@@ -66,7 +68,8 @@ struct BatchArgs {
   const int* deg;
   const BatchModel* models;
   const BatchTask* tasks;
-  const int* task_ptr;    // [G+1] task range of each workgroup
+  const int* task_ptr;    // [G+1] task range of each logical workgroup
+  int* ticket;            // start-order counter (zeroed before each launch)
   int* err;
   long long spin_limit;
 };
@@ -78,6 +81,16 @@ hipError_t launch_batch_dual(const float* unaries, const float* tables, const fl
                              const int* node_model, const int* slot_model, const int* node_ptr, const int* inc,
                              int total_nodes, int total_slots, int count, double* node_min, double* edge_min,
                              double* out, hipStream_t st);
+
+// adjoint (adjoint.hip)
+template <typename T>
+hipError_t launch_step_record(const T* tables, T* phi, T* U, const SlotInfo* slots, int L, int slot_begin, int count,
+                              unsigned char* rec, hipStream_t st);
+template <typename T>
+hipError_t launch_adj_step(const SlotInfo* slots, int L, int slot_begin, int count, const unsigned char* rec, T* Ub,
+                           T* pb, T* thb, hipStream_t st);
+template <typename T>
+hipError_t launch_adj_seed(const T* U, int n, int L, T* Ub, double* node_min, hipStream_t st);
 
 template <typename T>
 hipError_t launch_handshake(const HsArgs<T>& a, int engine, int LT, int NT, int slot_begin, int count, int grid,

@@ -161,9 +161,22 @@ template <int LT, int NT> struct SmemMB {
 };
 
 // the sync wave: poll MB[node] until all L words carry `want`, deliver values
+// On a timed-out wait: err[0] = MPLPXX_ETIMEOUT and, for the first waiter
+// that gives up, err[1..5] = (workgroup, slot, node, expected version,
+// version seen).
+__device__ __forceinline__ void report_timeout(int* err, int slot, int node, unsigned want, unsigned seen) {
+  if (atomicCAS(err, 0, MPLPXX_ETIMEOUT) == 0) {
+    err[1] = blockIdx.x;
+    err[2] = slot;
+    err[3] = node;
+    err[4] = (int)want;
+    err[5] = (int)seen;
+  }
+}
+
 template <int LT>
 __device__ __forceinline__ bool sync_gather(const unsigned long long* __restrict__ mb_row, int L, unsigned want,
-                                            float* dst, long long spin_limit, const int* err) {
+                                            float* dst, long long spin_limit, const int* err, unsigned* seen_out) {
   const int lane = threadIdx.x & 63;
   constexpr int PER = (LT + 63) / 64;
   bool have[PER];
@@ -186,7 +199,16 @@ __device__ __forceinline__ bool sync_gather(const unsigned long long* __restrict
       }
     }
     if (__all(all)) break;
-    if (++spins > spin_limit || ((spins & 255) == 0 && ld_dev(err) != 0)) return false;
+    if (++spins > spin_limit || ((spins & 255) == 0 && ld_dev(err) != 0)) {
+      unsigned seen = want;
+#pragma unroll
+      for (int k = 0; k < PER; ++k)
+        if (!have[k]) seen = (unsigned)(mb_load(mb_row + lane + 64 * k) >> 32);
+      // smallest version still missing in the wave
+      for (int o = 32; o >= 1; o >>= 1) seen = min(seen, (unsigned)__shfl_xor((int)seen, o, 64));
+      *seen_out = seen;
+      return false;
+    }
   }
 #pragma unroll
   for (int k = 0; k < PER; ++k)
@@ -249,22 +271,32 @@ __device__ __forceinline__ bool mb_run(const MbView& v, int first, int stride, i
     load_tile<float, LT, NT>(v.tables + (size_t)first * L * L, L, x);
     load_phi<LT, NT, PHI_LDS, FULL>(phi_of(first, 0), L, pu, pv);
   }
+  SlotInfo si = v.slots[first];
+  // slots owned: 1 -> the next slot is this one (its messages are the r, q
+  // just computed); 2 -> the next slot is the previous one, whose messages
+  // this workgroup wrote during the last slot: they are read after this
+  // slot's first barrier; >= 3 -> the next slot's messages were written two
+  // or more slots ago, behind two barriers, and are prefetched with its table
+  const int owned = (v.m - first + stride - 1) / stride;
   int parity = 0;
   for (int it = 0; it < iters; ++it) {
     int j = 0;
     for (int slot = first; slot < v.m; slot += stride, ++j, parity ^= 1) {
-      const SlotInfo si = v.slots[slot];
-      const unsigned want_u = (unsigned)(it * v.deg[si.u] + si.pos_u);
-      const unsigned want_v = (unsigned)(it * v.deg[si.v] + si.pos_v);
+      const unsigned want_u = (unsigned)(it * si.deg_u + si.pos_u);
+      const unsigned want_v = (unsigned)(it * si.deg_v + si.pos_v);
       int nxt = slot + stride, jn = j + 1;
       if (nxt >= v.m) { nxt = first; jn = 0; }
       const bool pref = nxt != slot && (it + 1 < iters || nxt > slot);
       const bool last_iter = it == iters - 1;
+      // metadata of the next owned slot, off the dependency chain
+      const SlotInfo si_next = v.slots[nxt];
       if (is_compute) {
-        // table and messages of the next owned slot, off the dependency chain
+        // table of the next owned slot (its messages follow after the barrier,
+        // once this workgroup's earlier writes to them are ordered)
         if (pref) {
           load_tile<float, LT, NT>(v.tables + (size_t)nxt * L * L, L, y);
-          load_phi<LT, NT, PHI_LDS, FULL>(phi_of(nxt, jn), L, npu, npv);
+          // (the very first slot's successor has not been written in this launch)
+          if (owned >= 3 || (it == 0 && j == 0)) load_phi<LT, NT, PHI_LDS, FULL>(phi_of(nxt, jn), L, npu, npv);
         }
 #if MPLPXX_FINE_STAMPS
         if (v.stamps && last_iter && tid == 0) v.stamps[(size_t)slot * kStampStride + 4] = wall_clock64();
@@ -274,9 +306,11 @@ __device__ __forceinline__ bool mb_run(const MbView& v, int first, int stride, i
         const int node = is_sync_u ? si.u : si.v;
         const unsigned want = is_sync_u ? want_u : want_v;
         float* dst = is_sync_u ? sm.uu[parity] : sm.uv[parity];
-        if (!sync_gather<LT>(v.mb + (size_t)node * L, L, want, dst, spin_limit, err)) {
+        unsigned seen = 0;
+        if (!sync_gather<LT>(v.mb + (size_t)node * L, L, want, dst, spin_limit, err, &seen)) {
           if (lane == 0) {
-            atomicCAS(err, 0, MPLPXX_ETIMEOUT);
+            // a wait may also end because another workgroup reported first
+            if (ld_dev(err) == 0 || seen != want) report_timeout(err, slot, node, want, seen);
             sm.abort_flag = 1;
           }
         }
@@ -284,6 +318,8 @@ __device__ __forceinline__ bool mb_run(const MbView& v, int first, int stride, i
       }
       __syncthreads();
       if (sm.abort_flag) return false;
+      if (is_compute && pref && owned == 2 && !(it == 0 && j == 0))
+        load_phi<LT, NT, PHI_LDS, FULL>(phi_of(nxt, jn), L, npu, npv);
       if (is_compute) {
 #if MPLPXX_FINE_STAMPS
         if (v.stamps && last_iter && tid == 0) v.stamps[(size_t)slot * kStampStride + 5] = wall_clock64();
@@ -415,6 +451,7 @@ __device__ __forceinline__ bool mb_run(const MbView& v, int first, int stride, i
           }
         }
       }
+      si = si_next;
     }
   }
   return true;

@@ -113,6 +113,10 @@ int prepare_graph(int n, int m, const int32_t* edges, GraphPrep& g) {
     si.pos_v = g.deg[si.v]++;
     g.slots[i] = si;
   }
+  for (int i = 0; i < m; ++i) {
+    g.slots[i].deg_u = g.deg[g.slots[i].u];
+    g.slots[i].deg_v = g.deg[g.slots[i].v];
+  }
   return MPLPXX_OK;
 }
 

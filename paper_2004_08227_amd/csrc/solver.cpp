@@ -74,6 +74,18 @@ struct mplpxx_solver {
   long long* d_stamps = nullptr;         // per-slot timestamps (profiling option)
   bool profile = false;
   int wallclock_khz = 0;
+  // adjoint of K unrolled iterations
+  int adj_K = 0, adj_every = 0, adj_nck = 0;
+  bool adj_ready = false;
+  long long adj_iter_mark = -1;           // `iterations` right after the forward
+  void* d_ck_U = nullptr;                 // [nck + 1][n][L] (last = final state)
+  void* d_ck_phi = nullptr;               // [nck + 1][m][2][L]
+  unsigned char* d_rec = nullptr;         // [every][m][3][L]
+  void* d_Ub = nullptr;                   // [n][L]
+  void* d_pb = nullptr;                   // [m][2][L]
+  void* d_thb = nullptr;                  // [m][L][L]
+  int* d_slot_of_edge = nullptr;          // [m]
+  int* d_edge_flip = nullptr;             // [m]
   // execution
   hipStream_t user_stream = nullptr;
   hipStream_t own_stream = nullptr;
@@ -113,7 +125,8 @@ namespace {
 void free_all(mplpxx_solver* h) {
   void* ptrs[] = {h->d_tables, h->d_phi, h->d_U, h->d_unaries, h->d_slots, h->d_deg, h->d_ver, h->d_err,
                   h->d_node_ptr, h->d_inc, h->d_node_min, h->d_edge_min, h->d_scalar, h->d_labels,
-                  h->d_trace_nodes, h->d_trace_out, h->d_mb, h->d_stamps};
+                  h->d_trace_nodes, h->d_trace_out, h->d_mb, h->d_stamps, h->d_ck_U, h->d_ck_phi,
+                  h->d_rec, h->d_Ub, h->d_pb, h->d_thb, h->d_slot_of_edge, h->d_edge_flip};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h->ev0) (void)hipEventDestroy(h->ev0);
@@ -207,7 +220,7 @@ int create_impl(int32_t n, int32_t L, int64_t m, const int32_t* edges, const voi
   h->d_slots = dalloc<SlotInfo>(m, &ae); TRY(ae);
   h->d_deg = dalloc<int>(n, &ae); TRY(ae);
   h->d_ver = dalloc<int>(n, &ae); TRY(ae);
-  h->d_err = dalloc<int>(4, &ae); TRY(ae);
+  h->d_err = dalloc<int>(8, &ae); TRY(ae);
   h->d_node_ptr = dalloc<int>(n + 1, &ae); TRY(ae);
   h->d_inc = dalloc<int>(2 * (size_t)m, &ae); TRY(ae);
   h->d_node_min = dalloc<double>(n, &ae); TRY(ae);
@@ -239,7 +252,7 @@ int create_impl(int32_t n, int32_t L, int64_t m, const int32_t* edges, const voi
   if (m) TRY(hipMemcpyAsync(h->d_slots, h->slots.data(), m * sizeof(SlotInfo), hipMemcpyHostToDevice, st));
   TRY(hipMemcpyAsync(h->d_deg, h->deg.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
   TRY(hipMemsetAsync(h->d_phi, 0, (size_t)m * 2 * L * esz, st));
-  TRY(hipMemsetAsync(h->d_err, 0, 4 * sizeof(int), st));
+  TRY(hipMemsetAsync(h->d_err, 0, 8 * sizeof(int), st));
 
   if (!device_costs) {
     TRY(hipMemcpyAsync(h->d_unaries, unaries, nL * esz, hipMemcpyHostToDevice, st));
@@ -315,11 +328,13 @@ int create_impl(int32_t n, int32_t L, int64_t m, const int32_t* edges, const voi
 
 int sync_and_check(mplpxx_solver* h) {
   HIP_TRY(hipStreamSynchronize(h->stream()));
-  int err = 0;
-  HIP_TRY(hipMemcpy(&err, h->d_err, sizeof(int), hipMemcpyDeviceToHost));
-  if (err != 0) {
-    (void)hipMemset(h->d_err, 0, sizeof(int));
-    return fail(err, "device wait exceeded its bound (code %d)", err);
+  int err[8] = {0};
+  HIP_TRY(hipMemcpy(err, h->d_err, 8 * sizeof(int), hipMemcpyDeviceToHost));
+  if (err[0] != 0) {
+    (void)hipMemsetAsync(h->d_err, 0, 8 * sizeof(int), h->stream());
+    (void)hipStreamSynchronize(h->stream());
+    return fail(err[0], "device wait exceeded its bound (workgroup %d, slot %d, node %d, expected version %d, seen %d)",
+                err[1], err[2], err[3], err[4], err[5]);
   }
   return MPLPXX_OK;
 }
@@ -414,6 +429,103 @@ template <typename T> int iterate_t(mplpxx_solver* h, int k, double* trace_host)
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Adjoint of K unrolled iterations (checkpoint every `every` iterations).
+// ---------------------------------------------------------------------------
+namespace {
+
+template <typename T> int adjoint_forward_t(mplpxx_solver* h, int K, int every, double* loss) {
+  hipStream_t st = h->stream();
+  const size_t nL = (size_t)h->n * h->L, mp = (size_t)h->m * 2 * h->L, esz = sizeof(T);
+  const int nck = (K + every - 1) / every;
+  // (re)allocate checkpoint and record storage
+  for (void** p : {&h->d_ck_U, &h->d_ck_phi, (void**)&h->d_rec})
+    if (*p) { (void)hipFree(*p); *p = nullptr; }
+  HIP_TRY(hipMalloc(&h->d_ck_U, (nck + 1) * nL * esz));
+  HIP_TRY(hipMalloc(&h->d_ck_phi, std::max<size_t>(1, (nck + 1) * mp * esz)));
+  HIP_TRY(hipMalloc(&h->d_rec, std::max<size_t>(1, (size_t)every * h->m * 3 * h->L)));
+  if (!h->d_Ub) HIP_TRY(hipMalloc(&h->d_Ub, nL * esz));
+  if (!h->d_pb) HIP_TRY(hipMalloc(&h->d_pb, std::max<size_t>(1, mp * esz)));
+  if (!h->d_thb) HIP_TRY(hipMalloc(&h->d_thb, std::max<size_t>(1, (size_t)h->m * h->L * h->L * esz)));
+  if (!h->d_slot_of_edge && h->m) {
+    HIP_TRY(hipMalloc(&h->d_slot_of_edge, h->m * sizeof(int)));
+    HIP_TRY(hipMalloc(&h->d_edge_flip, h->m * sizeof(int)));
+    HIP_TRY(hipMemcpyAsync(h->d_slot_of_edge, h->slot_of_edge.data(), h->m * sizeof(int), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(h->d_edge_flip, h->flip.data(), h->m * sizeof(int), hipMemcpyHostToDevice, st));
+  }
+  // start from phi = 0, U = theta_u
+  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(hipMemsetAsync(h->d_phi, 0, mp * esz, st));
+  HIP_TRY(hipMemcpyAsync(h->d_U, h->d_unaries, nL * esz, hipMemcpyDeviceToDevice, st));
+  h->iterations = 0;
+  for (int c = 0; c < nck; ++c) {
+    HIP_TRY(hipMemcpyAsync((char*)h->d_ck_U + c * nL * esz, h->d_U, nL * esz, hipMemcpyDeviceToDevice, st));
+    if (h->m) HIP_TRY(hipMemcpyAsync((char*)h->d_ck_phi + c * mp * esz, h->d_phi, mp * esz, hipMemcpyDeviceToDevice, st));
+    const int seg = std::min(every, K - c * every);
+    const int rc = iterate_t<T>(h, seg, nullptr);
+    if (rc != MPLPXX_OK) return rc;
+  }
+  HIP_TRY(hipMemcpyAsync((char*)h->d_ck_U + nck * nL * esz, h->d_U, nL * esz, hipMemcpyDeviceToDevice, st));
+  if (h->m) HIP_TRY(hipMemcpyAsync((char*)h->d_ck_phi + nck * mp * esz, h->d_phi, mp * esz, hipMemcpyDeviceToDevice, st));
+  // loss = sum_u min_s U_u in FP64 (node minima, then a fixed-order sum)
+  HIP_TRY(launch_adj_seed<T>(static_cast<const T*>(h->d_U), h->n, h->L, static_cast<T*>(h->d_Ub), h->d_node_min, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  h->adj_K = K;
+  h->adj_every = every;
+  h->adj_nck = nck;
+  h->adj_ready = true;
+  h->adj_iter_mark = h->iterations;
+  if (loss) {
+    // fixed-order FP64 sum of the node minima
+    std::vector<double> mins(h->n);
+    HIP_TRY(hipMemcpy(mins.data(), h->d_node_min, h->n * sizeof(double), hipMemcpyDeviceToHost));
+    double acc = 0.0;
+    for (double v : mins) acc += v;
+    *loss = acc;
+  }
+  return MPLPXX_OK;
+}
+
+template <typename T> int adjoint_backward_t(mplpxx_solver* h, void* grad_u, void* grad_pw) {
+  hipStream_t st = h->stream();
+  const size_t nL = (size_t)h->n * h->L, mp = (size_t)h->m * 2 * h->L, esz = sizeof(T);
+  const int K = h->adj_K, every = h->adj_every, nck = h->adj_nck;
+  const size_t rec_it = (size_t)h->m * 3 * h->L;
+  // seed from the final state
+  HIP_TRY(launch_adj_seed<T>(static_cast<const T*>((const void*)((char*)h->d_ck_U + nck * nL * esz)), h->n, h->L,
+                             static_cast<T*>(h->d_Ub), h->d_node_min, st));
+  if (h->m) {
+    HIP_TRY(hipMemsetAsync(h->d_pb, 0, mp * esz, st));
+    HIP_TRY(hipMemsetAsync(h->d_thb, 0, (size_t)h->m * h->L * h->L * esz, st));
+  }
+  for (int c = nck - 1; c >= 0 && h->m > 0; --c) {
+    const int seg = std::min(every, K - c * every);
+    HIP_TRY(hipMemcpyAsync(h->d_U, (char*)h->d_ck_U + c * nL * esz, nL * esz, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(h->d_phi, (char*)h->d_ck_phi + c * mp * esz, mp * esz, hipMemcpyDeviceToDevice, st));
+    for (int i = 0; i < seg; ++i)
+      for (int s = 0; s < h->S; ++s)
+        HIP_TRY(launch_step_record<T>(static_cast<const T*>(h->d_tables), static_cast<T*>(h->d_phi),
+                                      static_cast<T*>(h->d_U), h->d_slots, h->L, h->step_ptr[s],
+                                      h->step_ptr[s + 1] - h->step_ptr[s], h->d_rec + i * rec_it, st));
+    for (int i = seg - 1; i >= 0; --i)
+      for (int s = h->S - 1; s >= 0; --s)
+        HIP_TRY(launch_adj_step<T>(h->d_slots, h->L, h->step_ptr[s], h->step_ptr[s + 1] - h->step_ptr[s],
+                                   h->d_rec + i * rec_it, static_cast<T*>(h->d_Ub), static_cast<T*>(h->d_pb),
+                                   static_cast<T*>(h->d_thb), st));
+  }
+  // outputs in the caller's layout; the handle's state back to the forward's end
+  if (grad_u) HIP_TRY(hipMemcpyAsync(grad_u, h->d_Ub, nL * esz, hipMemcpyDeviceToDevice, st));
+  if (grad_pw && h->m)
+    HIP_TRY(launch_pack_tables<T>(static_cast<const T*>(h->d_thb), static_cast<T*>(grad_pw), h->d_slot_of_edge,
+                                  h->d_edge_flip, h->m, h->L, st));
+  HIP_TRY(hipMemcpyAsync(h->d_U, (char*)h->d_ck_U + nck * nL * esz, nL * esz, hipMemcpyDeviceToDevice, st));
+  if (h->m) HIP_TRY(hipMemcpyAsync(h->d_phi, (char*)h->d_ck_phi + nck * mp * esz, mp * esz, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return MPLPXX_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int mplpxx_create(int32_t n, int32_t L, int64_t m, const int32_t* edges, const void* unaries, const void* pairwise,
@@ -437,6 +549,21 @@ int mplpxx_iterate_trace(mplpxx_solver* h, int32_t k, double* trace) {
   if (k < 0) return fail(MPLPXX_EINVAL, "k must be >= 0");
   if (k > 0 && !trace) return fail(MPLPXX_EINVAL, "trace is NULL");
   return h->dtype == MPLPXX_F32 ? iterate_t<float>(h, k, trace) : iterate_t<double>(h, k, trace);
+}
+
+int mplpxx_adjoint_forward(mplpxx_solver* h, int32_t K, int32_t every, double* loss) {
+  if (!h) return fail(MPLPXX_EINVAL, "handle is NULL");
+  if (K < 1 || every < 1) return fail(MPLPXX_EINVAL, "K and every must be >= 1");
+  h->adj_ready = false;
+  return h->dtype == MPLPXX_F32 ? adjoint_forward_t<float>(h, K, every, loss) : adjoint_forward_t<double>(h, K, every, loss);
+}
+
+int mplpxx_adjoint_backward(mplpxx_solver* h, void* grad_unaries, void* grad_pairwise) {
+  if (!h) return fail(MPLPXX_EINVAL, "handle is NULL");
+  if (!h->adj_ready || h->iterations != h->adj_iter_mark)
+    return fail(MPLPXX_ESTATE, "no adjoint forward to differentiate (call mplpxx_adjoint_forward first)");
+  return h->dtype == MPLPXX_F32 ? adjoint_backward_t<float>(h, grad_unaries, grad_pairwise)
+                                : adjoint_backward_t<double>(h, grad_unaries, grad_pairwise);
 }
 
 int mplpxx_dual_bound(mplpxx_solver* h, double* out) {
@@ -544,7 +671,8 @@ int mplpxx_set_state(mplpxx_solver* h, const void* U, const void* phi) {
   const size_t esz = h->esz, L = h->L;
   if (U) {
     if (!finite_host(U, (size_t)h->n * L, h->dtype)) return fail(MPLPXX_EINVAL, "non-finite U");
-    HIP_TRY(hipMemcpy(h->d_U, U, (size_t)h->n * L * esz, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpyAsync(h->d_U, U, (size_t)h->n * L * esz, hipMemcpyHostToDevice, h->stream()));
+    HIP_TRY(hipStreamSynchronize(h->stream()));
   }
   if (phi && h->m) {
     if (!finite_host(phi, (size_t)h->m * 2 * L, h->dtype)) return fail(MPLPXX_EINVAL, "non-finite phi");
@@ -552,9 +680,11 @@ int mplpxx_set_state(mplpxx_solver* h, const void* U, const void* phi) {
     const char* src = static_cast<const char*>(phi);
     const size_t row = 2 * L * esz;
     for (int e = 0; e < h->m; ++e) std::memcpy(tmp.data() + (size_t)h->slot_of_edge[e] * row, src + (size_t)e * row, row);
-    HIP_TRY(hipMemcpy(h->d_phi, tmp.data(), tmp.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpyAsync(h->d_phi, tmp.data(), tmp.size(), hipMemcpyHostToDevice, h->stream()));
+    HIP_TRY(hipStreamSynchronize(h->stream()));
   }
   h->iterations = 0;
+  h->adj_ready = false;
   return MPLPXX_OK;
 }
 

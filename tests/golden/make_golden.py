@@ -1,0 +1,141 @@
+"""Writes the stored expected values used by the full-size GPU parity tests.
+
+Everything here is computed by the FP64 CPU oracle (``oracle/``) on inputs
+from the seeded generators (``paper_2004_08227_amd/workloads.py``); nothing
+comes from the HIP path.  Run from the repository root:
+
+    python tests/golden/make_golden.py [all|pose|potts|batch|adjoint]
+
+Outputs (JSON, one file per workload):
+  pose_k200_l64.json        dual trace of 200 iterations, final node minima
+  potts_er_n1000_l16.json   dual traces (30 iterations) at 5/25/50/100 % density
+  batched_mix_samples.json  100-iteration traces of 8 models of the 256-model mix
+  adjoint_uniform_k100_l32.json  central differences of D_50 along seeded
+                            directions and coordinates, two step sizes
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_2004_08227_amd import workloads as W  # noqa: E402
+
+THREADS = min(8, os.cpu_count() or 1)
+
+
+def dump(name, obj):
+    obj["_source"] = ("FP64 CPU oracle (oracle/mplp_oracle.c) on seeded inputs from workloads.py; "
+                      "written by tests/golden/make_golden.py")
+    with open(os.path.join(HERE, name), "w") as f:
+        json.dump(obj, f, indent=1)
+    print("wrote", name, flush=True)
+
+
+def make_pose():
+    model = W.pose(200, 64, seed=0)
+    st = oracle.State(model)
+    t = time.time()
+    tr = st.run(200, trace=True, nthreads=THREADS)
+    dump("pose_k200_l64.json", {"workload": "pose n=200 L=64 seed=0", "iters": 200, "trace": tr.tolist(),
+                                "node_min": st.Tu.min(axis=1).tolist(), "seconds": time.time() - t})
+
+
+def make_potts():
+    out = {"workload": "potts_er n=1000 L=16 seed=0", "iters": 30, "traces": {}}
+    for p in (0.05, 0.25, 0.5, 1.0):
+        model = W.potts_er(1000, 16, p, seed=0)
+        st = oracle.State(model)
+        out["traces"][str(p)] = {"m": model.m, "steps": st.n_steps,
+                                 "trace": st.run(30, trace=True, nthreads=THREADS).tolist()}
+        print("potts", p, flush=True)
+    dump("potts_er_n1000_l16.json", out)
+
+
+def batch_samples():
+    sizes = W.batched_mix(256, seed=0, models=False)
+    cost = [n * (n - 1) // 2 * L * L for n, L in sizes]
+    order = np.argsort(cost)
+    rng = np.random.default_rng(123)
+    picks = [int(order[0]), int(order[1]), int(order[-1]), int(order[-2])]
+    rest = [i for i in range(256) if i not in picks]
+    picks += [int(i) for i in rng.choice(rest, size=4, replace=False)]
+    return sizes, picks
+
+
+def make_batch():
+    sizes, picks = batch_samples()
+    out = {"workload": "batched_mix count=256 seed=0", "iters": 100, "models": {}}
+    for i in picks:
+        n, L = sizes[i]
+        model = W.pose(n, L, seed=1_000_003 * 0 + i)
+        st = oracle.State(model)
+        tr = st.run(100, trace=True, nthreads=THREADS)
+        out["models"][str(i)] = {"n": n, "L": L, "trace": tr.tolist()}
+        print("batch model", i, n, L, flush=True)
+    dump("batched_mix_samples.json", out)
+
+
+def adjoint_directions(model, count, seed):
+    rng = np.random.default_rng(seed)
+    return [(rng.standard_normal(model.unaries.shape), rng.standard_normal(model.pairwise.shape))
+            for _ in range(count)]
+
+
+def adjoint_coords(model, count, seed):
+    rng = np.random.default_rng(seed)
+    nu = model.unaries.size
+    tot = nu + model.pairwise.size
+    return [int(c) for c in rng.choice(tot, size=count, replace=False)]
+
+
+def make_adjoint():
+    K, every = 50, 10
+    model = W.uniform(100, 32, seed=0)
+    base = model.astype(np.float64)
+
+    def D(du, dp):
+        mo = W.Model(base.n, base.L, base.edges, base.unaries + du, base.pairwise + dp)
+        return oracle.dual_after(mo, K, nthreads=THREADS)
+
+    out = {"workload": "uniform n=100 L=32 seed=0 (FP32 inputs promoted to FP64)", "K": K, "every": every,
+           "D": D(0.0, 0.0), "directions": [], "coords": []}
+    for h in (1e-6, 1e-7):
+        fds = []
+        for du, dp in adjoint_directions(base, 8, 7):
+            fds.append((D(h * du, h * dp) - D(-h * du, -h * dp)) / (2 * h))
+        out["directions"].append({"h": h, "seed": 7, "count": 8, "fd": fds})
+        print("directions h", h, flush=True)
+    nu = base.unaries.size
+    for h in (1e-6, 1e-7):
+        fds = []
+        for c in adjoint_coords(base, 16, 11):
+            du = np.zeros_like(base.unaries)
+            dp = np.zeros_like(base.pairwise)
+            if c < nu:
+                du.flat[c] = 1.0
+            else:
+                dp.flat[c - nu] = 1.0
+            fds.append((D(h * du, h * dp) - D(-h * du, -h * dp)) / (2 * h))
+        out["coords"].append({"h": h, "seed": 11, "count": 16, "fd": fds})
+        print("coords h", h, flush=True)
+    dump("adjoint_uniform_k100_l32.json", out)
+
+
+if __name__ == "__main__":
+    what = sys.argv[1] if len(sys.argv) > 1 else "all"
+    W.build_generator()
+    if what in ("all", "pose"):
+        make_pose()
+    if what in ("all", "potts"):
+        make_potts()
+    if what in ("all", "batch"):
+        make_batch()
+    if what in ("all", "adjoint"):
+        make_adjoint()

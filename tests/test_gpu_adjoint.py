@@ -1,0 +1,146 @@
+"""GPU tests of the adjoint of K unrolled MPLP++ iterations.
+
+D_K is piecewise linear in the costs, so inside a linear piece a central
+finite difference of the FP64 oracle is exact up to rounding.  The FP64
+adjoint must match such differences coordinate by coordinate; the FP32
+adjoint on the differentiation workload (n=100, L=32, K=50, checkpoints every
+10) must match stored FP64 differences along seeded directions and
+coordinates to 1e-4.  Checkpoint spacing must not change a bit."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2004_08227_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+M = pytest.importorskip("paper_2004_08227_amd")
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _announce(*a):
+    print("CASE", *a, flush=True)
+
+
+def _grad(model, K, every):
+    with M.Solver.from_model(model) as s:
+        loss = s.adjoint_forward(K, every)
+        gu, gp = s.adjoint_backward()
+    return loss, gu, gp
+
+
+def _fd(model, K, du, dp, h):
+    base = model.astype(np.float64)
+    plus = W.Model(base.n, base.L, base.edges, base.unaries + h * du, base.pairwise + h * dp)
+    minus = W.Model(base.n, base.L, base.edges, base.unaries - h * du, base.pairwise - h * dp)
+    return (oracle.dual_after(plus, K) - oracle.dual_after(minus, K)) / (2 * h)
+
+
+def test_fp64_adjoint_matches_finite_differences_per_coordinate():
+    _announce("fp64 adjoint all coordinates")
+    model = W.uniform(9, 4, seed=21, dtype=np.float64)
+    K, every = 6, 2
+    loss, gu, gp = _grad(model, K, every)
+    st, tr = oracle.run_model(model, K)
+    assert abs(loss - st.dual()) <= 1e-12 * max(1, abs(loss))
+    h = 1e-7
+    bad = 0
+    total = 0
+    for arr, g in ((model.unaries, gu), (model.pairwise, gp)):
+        for idx in np.ndindex(arr.shape):
+            du = np.zeros(model.unaries.shape)
+            dp = np.zeros(model.pairwise.shape)
+            (du if arr is model.unaries else dp)[idx] = 1.0
+            fd = _fd(model, K, du, dp, h)
+            total += 1
+            if abs(g[idx] - fd) > 1e-6 * max(1.0, abs(fd)):
+                bad += 1
+    # a step may cross a kink of the piecewise-linear D_K for a few coordinates
+    assert bad <= max(1, total // 200), (bad, total)
+
+
+def test_checkpoint_spacing_and_repeats_are_bitwise_identical():
+    for dtype in (np.float64, np.float32):
+        model = W.uniform(14, 6, seed=22, dtype=dtype)
+        _announce("checkpoints", dtype.__name__)
+        ref = None
+        for every in (1, 3, 7, 10):
+            loss, gu, gp = _grad(model, 7, every)
+            if ref is None:
+                ref = (loss, gu, gp)
+            else:
+                assert loss == ref[0] and np.array_equal(gu, ref[1]) and np.array_equal(gp, ref[2])
+
+
+def test_fp32_adjoint_matches_stored_finite_differences_full_size():
+    path = os.path.join(GOLD, "adjoint_uniform_k100_l32.json")
+    if not os.path.exists(path):
+        pytest.skip("golden file missing")
+    g = json.load(open(path))
+    _announce("fp32 adjoint n=100 L=32 K=50")
+    model = W.uniform(100, 32, seed=0)
+    loss, gu, gp = _grad(model, g["K"], g["every"])
+    assert abs(loss - g["D"]) <= 1e-5 * abs(g["D"])
+    base = model.astype(np.float64)
+    rng = np.random.default_rng(g["directions"][0]["seed"])
+    dirs = [(rng.standard_normal(base.unaries.shape), rng.standard_normal(base.pairwise.shape))
+            for _ in range(g["directions"][0]["count"])]
+    for k, (du, dp) in enumerate(dirs):
+        proj = float((gu.astype(np.float64) * du).sum() + (gp.astype(np.float64) * dp).sum())
+        fds = [d["fd"][k] for d in g["directions"]]
+        ok = [abs(proj - fd) <= 1e-4 * max(1.0, abs(fd)) for fd in fds]
+        assert any(ok), (k, proj, fds)
+    rng = np.random.default_rng(g["coords"][0]["seed"])
+    nu = base.unaries.size
+    coords = rng.choice(nu + base.pairwise.size, size=g["coords"][0]["count"], replace=False)
+    flat = np.concatenate([gu.ravel(), gp.ravel()]).astype(np.float64)
+    for k, c in enumerate(coords):
+        fds = [d["fd"][k] for d in g["coords"]]
+        assert any(abs(flat[c] - fd) <= 1e-4 * max(1.0, abs(fd)) for fd in fds), (k, c, flat[c], fds)
+
+
+def test_orientation_and_degenerate_models():
+    _announce("adjoint orientation/degenerate")
+    model = W.uniform(7, 3, seed=23, dtype=np.float64)
+    flip = W.Model(model.n, model.L, model.edges[:, ::-1].copy(), model.unaries,
+                   np.transpose(model.pairwise, (0, 2, 1)).copy())
+    la, gua, gpa = _grad(model, 4, 2)
+    lb, gub, gpb = _grad(flip, 4, 2)
+    assert la == lb and np.array_equal(gua, gub)
+    assert np.array_equal(gpa, np.transpose(gpb, (0, 2, 1)))
+    # no edges: D = sum_u min theta_u, gradient = one-hot at the smallest minimizer
+    un = np.array([[0.5, 0.25, 0.25], [1.0, 2.0, 0.0]], np.float64)
+    m0 = W.Model(2, 3, np.zeros((0, 2), np.int32), un, np.zeros((0, 3, 3)))
+    loss, gu, gp = _grad(m0, 3, 2)
+    assert loss == 0.25 and np.array_equal(gu, [[0, 1, 0], [0, 0, 1]])
+
+
+def test_backward_requires_a_forward():
+    _announce("adjoint state")
+    model = W.uniform(6, 3, seed=24)
+    with M.Solver.from_model(model) as s:
+        with pytest.raises(M.MplpError) as ei:
+            s.adjoint_backward()
+        assert ei.value.code == M.ESTATE
+        s.adjoint_forward(3, 1)
+        s.iterate(1)
+        with pytest.raises(M.MplpError) as ei:
+            s.adjoint_backward()
+        assert ei.value.code == M.ESTATE
+
+
+def test_autograd_function():
+    import torch
+    from paper_2004_08227_amd.autograd import mplp_dual
+    _announce("autograd")
+    model = W.uniform(12, 5, seed=25)
+    un = torch.tensor(model.unaries, device="cuda", requires_grad=True)
+    pw = torch.tensor(model.pairwise, device="cuda", requires_grad=True)
+    loss = mplp_dual(un, pw, model.edges, K=6, every=3)
+    (2.0 * loss).backward()
+    l2, gu, gp = _grad(model, 6, 3)
+    assert float(loss) == np.float32(l2)
+    assert np.array_equal(un.grad.cpu().numpy(), 2.0 * gu)
+    assert np.array_equal(pw.grad.cpu().numpy(), 2.0 * gp)

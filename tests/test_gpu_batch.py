@@ -99,3 +99,48 @@ def test_batch_reset_and_timeout():
         b.reset()
         b.iterate(3)
         assert np.array_equal(b.dual_bounds(), d3)
+
+
+@pytest.mark.parametrize("n,L", [(23, 8), (24, 16), (32, 13), (33, 64), (90, 20)])
+def test_single_and_batched_match_oracle_where_workgroups_own_one_or_two_slots(n, L):
+    """n = 23..33 gives 253..528 edges: with one workgroup per compute unit
+    some workgroups own one slot and some two (the message prefetch must see
+    the messages the same workgroup wrote one slot earlier)."""
+    _announce("ownership", n, L)
+    model = W.pose(n, L, seed=n * 131 + L)
+    iters = 6
+    st, ref = oracle.run_model(model, iters)
+    U1, p1 = _alone(model, iters)
+    with M.Solver.from_model(model) as s:
+        s.set_option(M.OPT_ENGINE, M.ENGINE_PERSISTENT)
+        s.iterate(iters)
+        d1 = s.dual_bound()
+    with M.Batch([model, W.pose(20, 8, seed=1)]) as b:
+        b.iterate(iters)
+        d2 = b.dual_bounds()[0]
+        U2, p2 = b.get_state(0)
+    assert abs(d1 - ref[-1]) <= 1e-5 * max(1.0, abs(ref[-1])), (d1, ref[-1])
+    assert np.array_equal(U1, U2) and np.array_equal(p1, p2)
+    assert d1 == d2
+
+
+def test_batched_mix_samples_match_stored_oracle_traces():
+    """The 256-model pose mix (n in 20..300, L in 8..64), 100 iterations in one
+    launch; 8 sampled models (two smallest, two largest, four random) against
+    the oracle's stored duals."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batched_mix_samples.json")
+    if not os.path.exists(path):
+        pytest.skip("golden file missing")
+    g = json.load(open(path))
+    _announce("batched mix 256 x 100 iterations")
+    models = W.batched_mix(256, seed=0)
+    with M.Batch(models) as b:
+        b.iterate(g["iters"])
+        duals = b.dual_bounds()
+    del models
+    for key, rec in g["models"].items():
+        i = int(key)
+        ref = rec["trace"][-1]
+        assert abs(duals[i] - ref) <= 1e-5 * max(1.0, abs(ref)), (i, rec["n"], rec["L"], duals[i], ref)

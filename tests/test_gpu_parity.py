@@ -223,3 +223,23 @@ def test_step_profile_timestamps_are_ordered():
         assert s.info("wallclock_khz") > 0
     assert st.shape == (model.m, 4) and np.all(st > 0)
     assert np.all(st[:, 1] >= st[:, 0]) and np.all(st[:, 3] >= np.maximum(st[:, 1], st[:, 2]))
+
+
+def test_pose_k200_l64_full_size_200_iterations_matches_stored_oracle():
+    """The measured workload in the measured launch configuration (default
+    engine, grid and tile): FP32 dual trace and certified dual within 1e-5 of
+    the FP64 oracle after the same schedule and 200 iterations."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "pose_k200_l64.json")
+    g = json.load(open(path))
+    _announce("pose K200 L64 200 iterations")
+    model = W.pose(200, 64, seed=0)
+    with M.Solver.from_model(model) as s:
+        tr = s.iterate_trace(g["iters"])
+        d = s.dual_bound()
+        U, _ = s.get_state()
+    ref = np.array(g["trace"])
+    assert np.max(np.abs(tr - ref) / np.abs(ref)) <= 1e-5
+    assert abs(d - ref[-1]) <= 1e-5 * abs(ref[-1])
+    assert np.max(np.abs(U.min(axis=1) - np.array(g["node_min"]))) <= 1e-4
