@@ -61,6 +61,11 @@ extern "C" {
 /* largest label count the kernels accept */
 #define MPLPXX_MAX_LABELS 128
 
+/* largest cost magnitude an FP32 handle accepts (costs, and states passed to
+ * mplpxx_set_state); the FP32 kernels pad tables with 2^126 and need every
+ * real value far below it */
+#define MPLPXX_F32_MAX_COST 1e18
+
 typedef struct mplpxx_solver mplpxx_solver;
 
 /* ------------------------------------------------------------------------
@@ -74,7 +79,8 @@ typedef struct mplpxx_solver mplpxx_solver;
  * order) otherwise.  Initial state phi = 0, U = unaries.
  * Errors: MPLPXX_EINVAL for n < 1, L < 1, L > MPLPXX_MAX_LABELS, m < 0,
  * m > n(n-1)/2, an index out of [0, n), a self loop, a duplicate unordered
- * pair, a non-finite cost, a NULL pointer (edges/pairwise may be NULL only
+ * pair, a non-finite cost (FP32: |cost| > MPLPXX_F32_MAX_COST), a NULL
+ * pointer (edges/pairwise may be NULL only
  * when m == 0), an unknown dtype, or out == NULL; MPLPXX_ENOMEM;
  * MPLPXX_EDEVICE.  On error *out is set to NULL. */
 int mplpxx_create(int32_t n, int32_t L, int64_t m, const int32_t* edges, const void* unaries,
@@ -143,21 +149,36 @@ int mplpxx_schedule(int32_t n, int64_t m, const int32_t* edges, int32_t* n_steps
                     int32_t* order);
 
 /* Copies the state (U [n][L], phi [m][2][L], see above) to / from HOST
- * buffers of the handle's dtype.  Either pointer may be NULL to skip it. */
-int mplpxx_get_state(mplpxx_solver* h, void* U, void* phi);
-int mplpxx_set_state(mplpxx_solver* h, const void* U, const void* phi);
+ * buffers of the handle's dtype.  Any pointer may be NULL to skip it.
+ *
+ * FP32 handles keep each reparametrized unary as an unevaluated sum
+ * U + U_comp: U in FP32 and U_comp a small correction rounded to bf16 that
+ * carries the rounding error of the running sum theta_u + (messages into u)
+ * (Sec. 4, (H)), updated with error-free additions, so the sum does not
+ * drift with the number of updates.  U_comp: HOST float [n][L].  get_state
+ * writes zeros for FP64 handles; set_state takes it only together with U
+ * (NULL: zero correction), rounds it to bf16, and rejects it for FP64
+ * handles (MPLPXX_EINVAL).  Passing back what get_state returned resumes a
+ * run bit for bit. */
+int mplpxx_get_state(mplpxx_solver* h, void* U, void* phi, float* U_comp);
+int mplpxx_set_state(mplpxx_solver* h, const void* U, const void* phi, const float* U_comp);
 
-/* Same as mplpxx_iterate, and writes to the HOST buffer trace[k] the value
- * sum_u min_s U_u(s) after every iteration, accumulated in FP64.  After an
- * edge's (H) update its reparametrized pairwise term has minimum zero
- * (Sec. 4, after (H)), so once every edge has been updated this sum equals
- * the dual bound of Eq. (3) up to rounding. */
+/* Same as mplpxx_iterate, and writes to the HOST buffer trace[k] the dual
+ * bound of Eq. (3) after every iteration, accumulated in FP64: the node
+ * terms sum_u min_s U_u(s) plus, for FP32 handles, the edge terms
+ * min_{s,t} [theta_e(s,t) - phi_e[0](s) - phi_e[1](t)] of the state after
+ * that iteration, computed exactly from the FP32 values.  (After an edge's
+ * (H) update its edge term is zero in exact arithmetic, Sec. 4 after (H);
+ * in FP32 it is a rounding-level number, and summed over many edges it is
+ * not negligible.)  In FP64 the edge terms are left out. */
 int mplpxx_iterate_trace(mplpxx_solver* h, int32_t k, double* trace);
 
 /* Tuning options (never change results: every option gives bitwise the same
  * state, because each entry of a pass is one IEEE add followed by an exact,
  * order-free minimum). */
-#define MPLPXX_OPT_ENGINE 1      /* 0 auto, 1 one launch per matching, 2 persistent */
+#define MPLPXX_OPT_ENGINE 1      /* 0 auto, 1 one launch per matching, 2 persistent
+                                    (FP32 handles with a node of degree >= 65536
+                                    always run one launch per matching) */
 #define MPLPXX_OPT_THREADS 2     /* threads per workgroup: 0 auto, 256, 512, 1024 */
 #define MPLPXX_OPT_GRID 3        /* workgroups of the persistent engine (0 auto) */
 #define MPLPXX_OPT_SPIN_LIMIT 4  /* device wait bound in polls (0 default) */
@@ -195,11 +216,11 @@ int mplpxx_last_iterate_ms(mplpxx_solver* h, double* ms);
 
 /* Resets the state to phi = 0, U = unaries, runs K >= 1 iterations with the
  * handle's engine, keeping a checkpoint of (U, phi) every `every` >= 1
- * iterations, and writes to the HOST pointer `loss` (may be NULL)
- *   D_K = sum_u min_s U_u(s)  (FP64 sum).
- * After the last sweep every edge's reparametrized pairwise term has minimum
- * zero (Sec. 4, after (H)), so D_K is the dual bound of Eq. (3) up to
- * rounding. */
+ * iterations, and writes to the HOST pointer `loss` (may be NULL) the dual
+ * bound D_K of Eq. (3) of the final state (as mplpxx_dual_bound).  After the
+ * last sweep every edge's reparametrized pairwise term has minimum zero
+ * (Sec. 4, after (H)), so in exact arithmetic D_K = sum_u min_s U_u(s); the
+ * gradient below is that of this sum. */
 int mplpxx_adjoint_forward(mplpxx_solver* h, int32_t K, int32_t every, double* loss);
 
 /* Gradient of D_K with respect to the input costs, by reverse sweeps over
@@ -226,7 +247,8 @@ typedef struct mplpxx_batch mplpxx_batch;
  * pairwise[i] may be NULL when m[i] == 0).  Everything is copied to device
  * memory; the library plans which workgroups run which model (large models
  * are split over a team of workgroups, small ones packed together).  Errors
- * as mplpxx_create, reported with the model index. */
+ * as mplpxx_create, reported with the model index; also MPLPXX_EINVAL for a
+ * node of degree >= 65536 (the mailboxes carry 16-bit update counts). */
 int mplpxx_batch_create(int32_t count, const int32_t* n, const int32_t* L, const int64_t* m,
                         const int32_t* const* edges, const float* const* unaries, const float* const* pairwise,
                         mplpxx_batch** out);
@@ -242,9 +264,9 @@ int mplpxx_batch_iterate(mplpxx_batch* b, int32_t k);
  * FP64 from costs and messages as in mplpxx_dual_bound. */
 int mplpxx_batch_dual_bounds(mplpxx_batch* b, double* out);
 
-/* State of one model (HOST float U [n][L], phi [m][2][L], layouts of
- * mplpxx_get_state; either may be NULL). */
-int mplpxx_batch_get_state(mplpxx_batch* b, int32_t model, float* U, float* phi);
+/* State of one model (HOST float U [n][L], phi [m][2][L], U_comp [n][L],
+ * layouts of mplpxx_get_state; any may be NULL). */
+int mplpxx_batch_get_state(mplpxx_batch* b, int32_t model, float* U, float* phi, float* U_comp);
 
 /* Back to phi = 0, U = unaries for every model. */
 int mplpxx_batch_reset(mplpxx_batch* b);

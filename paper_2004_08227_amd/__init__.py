@@ -77,9 +77,9 @@ def lib():
         "mplpxx_last_error": (ctypes.c_char_p, []),
         "mplpxx_set_stream": (ctypes.c_int, [vp, vp]),
         "mplpxx_get_schedule": (ctypes.c_int, [vp, vp, vp, vp]),
-        "mplpxx_get_state": (ctypes.c_int, [vp, vp, vp]),
+        "mplpxx_get_state": (ctypes.c_int, [vp, vp, vp, vp]),
         "mplpxx_schedule": (ctypes.c_int, [i32, i64, vp, vp, vp, vp]),
-        "mplpxx_set_state": (ctypes.c_int, [vp, vp, vp]),
+        "mplpxx_set_state": (ctypes.c_int, [vp, vp, vp, vp]),
         "mplpxx_set_option": (ctypes.c_int, [vp, i32, i64]),
         "mplpxx_get_info": (ctypes.c_int, [vp, i32, ctypes.POINTER(i64)]),
         "mplpxx_last_iterate_ms": (ctypes.c_int, [vp, ctypes.POINTER(dbl)]),
@@ -89,7 +89,7 @@ def lib():
         "mplpxx_batch_create": (ctypes.c_int, [i32, vp, vp, vp, vp, vp, vp, pp]),
         "mplpxx_batch_iterate": (ctypes.c_int, [vp, i32]),
         "mplpxx_batch_dual_bounds": (ctypes.c_int, [vp, vp]),
-        "mplpxx_batch_get_state": (ctypes.c_int, [vp, i32, vp, vp]),
+        "mplpxx_batch_get_state": (ctypes.c_int, [vp, i32, vp, vp, vp]),
         "mplpxx_batch_reset": (ctypes.c_int, [vp]),
         "mplpxx_batch_set_option": (ctypes.c_int, [vp, i32, dbl]),
         "mplpxx_batch_get_info": (ctypes.c_int, [vp, i32, ctypes.POINTER(dbl)]),
@@ -221,16 +221,20 @@ class Solver:
         _check(lib().mplpxx_get_schedule(self._h, None, _ptr(sp), _ptr(order)))
         return sp, order[:self.m]
 
-    def get_state(self):
+    def get_state(self, comp=False):
+        """(U, phi), or (U, phi, U_comp) with comp=True: FP32 unaries are
+        U + U_comp (a bf16 correction; zeros for FP64)."""
         U = np.zeros((self.n, self.L), dtype=self.dtype)
         phi = np.zeros((self.m, 2, self.L), dtype=self.dtype)
-        _check(lib().mplpxx_get_state(self._h, _ptr(U), _ptr(phi) if self.m else None))
-        return U, phi
+        c = np.zeros((self.n, self.L), dtype=np.float32) if comp else None
+        _check(lib().mplpxx_get_state(self._h, _ptr(U), _ptr(phi) if self.m else None, _ptr(c)))
+        return (U, phi, c) if comp else (U, phi)
 
-    def set_state(self, U=None, phi=None):
+    def set_state(self, U=None, phi=None, comp=None):
         U = None if U is None else np.ascontiguousarray(U, dtype=self.dtype).reshape(self.n, self.L)
         phi = None if phi is None else np.ascontiguousarray(phi, dtype=self.dtype).reshape(self.m, 2, self.L)
-        _check(lib().mplpxx_set_state(self._h, _ptr(U), _ptr(phi)))
+        comp = None if comp is None else np.ascontiguousarray(comp, dtype=np.float32).reshape(self.n, self.L)
+        _check(lib().mplpxx_set_state(self._h, _ptr(U), _ptr(phi), _ptr(comp)))
 
     def set_option(self, key, value):
         _check(lib().mplpxx_set_option(self._h, int(key), int(value)))
@@ -331,12 +335,13 @@ class Batch:
         _check(lib().mplpxx_batch_dual_bounds(self._h, _ptr(out)))
         return out
 
-    def get_state(self, i):
+    def get_state(self, i, comp=False):
         n, L, m = int(self.n[i]), int(self.L[i]), int(self.m[i])
         U = np.zeros((n, L), dtype=np.float32)
         phi = np.zeros((m, 2, L), dtype=np.float32)
-        _check(lib().mplpxx_batch_get_state(self._h, int(i), _ptr(U), _ptr(phi) if m else None))
-        return U, phi
+        c = np.zeros((n, L), dtype=np.float32) if comp else None
+        _check(lib().mplpxx_batch_get_state(self._h, int(i), _ptr(U), _ptr(phi) if m else None, _ptr(c)))
+        return (U, phi, c) if comp else (U, phi)
 
     def reset(self):
         _check(lib().mplpxx_batch_reset(self._h))

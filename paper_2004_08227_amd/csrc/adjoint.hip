@@ -6,7 +6,9 @@
 // changes and the dual bound of Eq. (3) reduces to the node terms.
 //
 // Forward of one update (three-minimization form of (H)), with the argmin
-// records the reverse needs (lowest index on ties):
+// records the reverse needs (lowest index on ties); in FP32 the unaries are
+// updated with the same compensated sum as in the other engines, which
+// changes no derivative:
 //   p(s) = min_t [th(s,t) + a_v(t)]   t1(s) = argmin
 //   b(s) = (a_u(s) - p(s)) / 2
 //   q(t) = min_s [th(s,t) + b(s)]     s2(t) = argmin
@@ -24,7 +26,9 @@
 // Every scatter is done by one thread per target in ascending index order, so
 // the result is deterministic.  One workgroup per edge, one launch per
 // matching: the edges of a matching are independent in reverse as forward.
-#include "common.h"
+#include <type_traits>
+
+#include "device_common.h"
 
 namespace mplpxx {
 
@@ -39,9 +43,14 @@ constexpr int kAdjNT = 256;
 // (each entry one IEEE add, exact minimum).
 template <typename T>
 __global__ void __launch_bounds__(kAdjNT) k_step_record(const T* __restrict__ tables, T* __restrict__ phi,
-                                                        T* __restrict__ U, const SlotInfo* __restrict__ slots, int L,
-                                                        int slot_begin, unsigned char* __restrict__ rec) {
+                                                        T* __restrict__ U, T* __restrict__ Ulo,
+                                                        const SlotInfo* __restrict__ slots, int L, int slot_begin,
+                                                        unsigned char* __restrict__ rec) {
+  constexpr bool kComp = std::is_same<T, float>::value;
   __shared__ T au[MPLPXX_MAX_LABELS], av[MPLPXX_MAX_LABELS], b[MPLPXX_MAX_LABELS], q[MPLPXX_MAX_LABELS];
+  __shared__ T hu[MPLPXX_MAX_LABELS], lu[MPLPXX_MAX_LABELS], ou[MPLPXX_MAX_LABELS];
+  __shared__ T hv[MPLPXX_MAX_LABELS], lv[MPLPXX_MAX_LABELS], ov[MPLPXX_MAX_LABELS];
+  __shared__ T cuv[2];
   const int slot = slot_begin + blockIdx.x;
   const SlotInfo si = slots[slot];
   const T* th = tables + (size_t)slot * L * L;
@@ -50,9 +59,37 @@ __global__ void __launch_bounds__(kAdjNT) k_step_record(const T* __restrict__ ta
   T* Uv = U + (size_t)si.v * L;
   unsigned char* rc = rec + (size_t)slot * 3 * L;
   const int tid = threadIdx.x;
-  for (int i = tid; i < L; i += kAdjNT) {
-    au[i] = Uu[i] - ph[i];
-    av[i] = Uv[i] - ph[L + i];
+  T delta = T(0);
+  if constexpr (!kComp) {
+    for (int i = tid; i < L; i += kAdjNT) {
+      au[i] = Uu[i] - ph[i];
+      av[i] = Uv[i] - ph[L + i];
+    }
+  } else {
+    // centred passes, as in the other FP32 engines (device_common.h)
+    for (int i = tid; i < L; i += kAdjNT) {
+      hu[i] = Uu[i];
+      lu[i] = Ulo[(size_t)si.u * L + i];
+      ou[i] = ph[i];
+      hv[i] = Uv[i];
+      lv[i] = Ulo[(size_t)si.v * L + i];
+      ov[i] = ph[L + i];
+    }
+    __syncthreads();
+    const int wave = tid >> 6, lane = tid & 63;
+    if (wave < 2) {
+      const T* h = wave == 0 ? hu : hv;
+      T c = inf_of<T>();
+      for (int i = lane; i < L; i += 64) c = vmin(c, h[i]);
+      c = col4_min(row16_min(c));
+      if (lane == 0) cuv[wave] = c;
+    }
+    __syncthreads();
+    for (int i = tid; i < L; i += kAdjNT) {
+      au[i] = ((hu[i] - cuv[0]) + lu[i]) - ou[i];
+      av[i] = ((hv[i] - cuv[1]) + lv[i]) - ov[i];
+    }
+    delta = T(0.5) * (cuv[0] - cuv[1]);
   }
   __syncthreads();
   for (int s = tid; s < L; s += kAdjNT) {  // pass 1
@@ -85,12 +122,16 @@ __global__ void __launch_bounds__(kAdjNT) k_step_record(const T* __restrict__ ta
       if (x < mn) { mn = x; arg = t; }
     }
     rc[2 * L + s] = (unsigned char)arg;
-    ph[s] = mn;
-    Uu[s] = au[s] + mn;
+    const T rs = mn - delta;
+    ph[s] = rs;
+    if constexpr (kComp) comp_update(hu[s], lu[s], ou[s], rs, Uu[s], Ulo[(size_t)si.u * L + s]);
+    else Uu[s] = au[s] + mn;
   }
   for (int t = tid; t < L; t += kAdjNT) {
-    ph[L + t] = q[t];
-    Uv[t] = av[t] + q[t];
+    const T qs = q[t] + delta;
+    ph[L + t] = qs;
+    if constexpr (kComp) comp_update(hv[t], lv[t], ov[t], qs, Uv[t], Ulo[(size_t)si.v * L + t]);
+    else Uv[t] = av[t] + q[t];
   }
 }
 
@@ -164,33 +205,35 @@ __global__ void __launch_bounds__(kAdjNT) k_adj_step(const SlotInfo* __restrict_
 }
 
 // Seed for D_K = sum_u min_s U_u: one-hot at the smallest minimizing label;
-// loss partial per node in FP64.
+// loss partial per node in FP64 (FP32: U + Ulo, exact in FP64).
 template <typename T>
-__global__ void __launch_bounds__(64) k_adj_seed(const T* __restrict__ U, int L, T* __restrict__ Ub,
-                                                 double* __restrict__ node_min) {
+__global__ void __launch_bounds__(64) k_adj_seed(const T* __restrict__ U, const T* __restrict__ Ulo, int L,
+                                                 T* __restrict__ Ub, double* __restrict__ node_min) {
   const int u = blockIdx.x;
   const int lane = threadIdx.x;
-  T best = inf_of<T>();
+  double best = __builtin_inf();
   int arg = 0x7fffffff;
   for (int s = lane; s < L; s += 64) {
-    const T x = U[(size_t)u * L + s];
+    const size_t i = (size_t)u * L + s;
+    const double x = (double)U[i] + (Ulo ? (double)Ulo[i] : 0.0);
     if (x < best) { best = x; arg = s; }
   }
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) {
-    const T ob = __shfl_xor(best, o, 64);
+    const double ob = __shfl_xor(best, o, 64);
     const int oa = __shfl_xor(arg, o, 64);
     if (ob < best || (ob == best && oa < arg)) { best = ob; arg = oa; }
   }
   for (int s = lane; s < L; s += 64) Ub[(size_t)u * L + s] = (s == arg) ? T(1) : T(0);
-  if (lane == 0) node_min[u] = (double)best;
+  if (lane == 0) node_min[u] = best;
 }
 
 template <typename T>
-hipError_t launch_step_record(const T* tables, T* phi, T* U, const SlotInfo* slots, int L, int slot_begin, int count,
-                              unsigned char* rec, hipStream_t st) {
+hipError_t launch_step_record(const T* tables, T* phi, T* U, T* Ulo, const SlotInfo* slots, int L, int slot_begin,
+                              int count, unsigned char* rec, hipStream_t st) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_step_record<T>, dim3(count), dim3(kAdjNT), 0, st, tables, phi, U, slots, L, slot_begin, rec);
+  hipLaunchKernelGGL(k_step_record<T>, dim3(count), dim3(kAdjNT), 0, st, tables, phi, U, Ulo, slots, L, slot_begin,
+                     rec);
   return hipGetLastError();
 }
 
@@ -203,17 +246,17 @@ hipError_t launch_adj_step(const SlotInfo* slots, int L, int slot_begin, int cou
 }
 
 template <typename T>
-hipError_t launch_adj_seed(const T* U, int n, int L, T* Ub, double* node_min, hipStream_t st) {
-  hipLaunchKernelGGL(k_adj_seed<T>, dim3(n), dim3(64), 0, st, U, L, Ub, node_min);
+hipError_t launch_adj_seed(const T* U, const T* Ulo, int n, int L, T* Ub, double* node_min, hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_seed<T>, dim3(n), dim3(64), 0, st, U, Ulo, L, Ub, node_min);
   return hipGetLastError();
 }
 
 #define MPLPXX_INST(T)                                                                                        \
-  template hipError_t launch_step_record<T>(const T*, T*, T*, const SlotInfo*, int, int, int, unsigned char*, \
-                                            hipStream_t);                                                     \
+  template hipError_t launch_step_record<T>(const T*, T*, T*, T*, const SlotInfo*, int, int, int,            \
+                                            unsigned char*, hipStream_t);                                     \
   template hipError_t launch_adj_step<T>(const SlotInfo*, int, int, int, const unsigned char*, T*, T*, T*,    \
                                          hipStream_t);                                                        \
-  template hipError_t launch_adj_seed<T>(const T*, int, int, T*, double*, hipStream_t);
+  template hipError_t launch_adj_seed<T>(const T*, const T*, int, int, T*, double*, hipStream_t);
 MPLPXX_INST(float)
 MPLPXX_INST(double)
 #undef MPLPXX_INST

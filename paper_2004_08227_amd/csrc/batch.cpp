@@ -45,6 +45,7 @@ struct mplpxx_batch {
   float* d_tables = nullptr;
   float* d_phi = nullptr;
   float* d_U = nullptr;
+  float* d_Ulo = nullptr;  // bf16 corrections of U (compensated FP32 unaries)
   float* d_unaries = nullptr;
   unsigned long long* d_mb = nullptr;
   SlotInfo* d_slots = nullptr;
@@ -228,7 +229,7 @@ int plan(mplpxx_batch* b) {
 }
 
 void free_batch(mplpxx_batch* b) {
-  void* ptrs[] = {b->d_tables, b->d_phi, b->d_U, b->d_unaries, b->d_mb, b->d_slots, b->d_deg, b->d_models,
+  void* ptrs[] = {b->d_tables, b->d_phi, b->d_U, b->d_Ulo, b->d_unaries, b->d_mb, b->d_slots, b->d_deg, b->d_models,
                   b->d_tasks, b->d_task_ptr, b->d_err, b->d_ticket, b->d_node_model, b->d_slot_model, b->d_node_ptr,
                   b->d_inc, b->d_node_min, b->d_edge_min, b->d_duals};
   for (void* p : ptrs)
@@ -254,11 +255,11 @@ hipError_t enqueue(mplpxx_batch* b, int k) {
   a.spin_limit = b->spin_limit;
   hipError_t e = launch_fill_int(b->d_ticket, 0, 1, b->stream);
   if (e != hipSuccess) return e;
-  e = launch_u32_to_mb(b->d_U, b->d_mb, (size_t)b->total_u, b->stream);
+  e = launch_u_to_mb(b->d_U, b->d_Ulo, b->d_mb, (size_t)b->total_u, b->stream);
   if (e != hipSuccess) return e;
   e = launch_batch(a, b->max_lt, b->grid, k, b->stream);
   if (e != hipSuccess) return e;
-  return launch_mb_to_u32(b->d_U, b->d_mb, (size_t)b->total_u, b->stream);
+  return launch_mb_to_u(b->d_U, b->d_Ulo, b->d_mb, (size_t)b->total_u, b->stream);
 }
 
 }  // namespace
@@ -291,9 +292,11 @@ int mplpxx_batch_create(int32_t count, const int32_t* n, const int32_t* L, const
       return bail(fail(MPLPXX_EINVAL, "model %d: NULL edges or pairwise", i));
     if (!unaries[i]) return bail(fail(MPLPXX_EINVAL, "model %d: NULL unaries", i));
     for (size_t k = 0; k < (size_t)n[i] * L[i]; ++k)
-      if (!std::isfinite(unaries[i][k])) return bail(fail(MPLPXX_EINVAL, "model %d: non-finite unary", i));
+      if (!(std::fabs(unaries[i][k]) <= (float)MPLPXX_F32_MAX_COST))
+        return bail(fail(MPLPXX_EINVAL, "model %d: non-finite or too large unary", i));
     for (size_t k = 0; k < (size_t)m[i] * L[i] * L[i]; ++k)
-      if (!std::isfinite(pairwise[i][k])) return bail(fail(MPLPXX_EINVAL, "model %d: non-finite pairwise", i));
+      if (!(std::fabs(pairwise[i][k]) <= (float)MPLPXX_F32_MAX_COST))
+        return bail(fail(MPLPXX_EINVAL, "model %d: non-finite or too large pairwise", i));
     const int rc = prepare_graph(n[i], (int)m[i], m[i] ? edges[i] : nullptr, preps[i]);
     if (rc != MPLPXX_OK) {
       const std::string msg = g_last_error;
@@ -307,6 +310,8 @@ int mplpxx_batch_create(int32_t count, const int32_t* n, const int32_t* L, const
     h.lt = next_tile(L[i]);
     h.max_step = 1;
     for (int s = 0; s < h.S; ++s) h.max_step = std::max(h.max_step, preps[i].step_ptr[s + 1] - preps[i].step_ptr[s]);
+    for (int d : preps[i].deg)
+      if (d >= 65536) return bail(fail(MPLPXX_EINVAL, "model %d: a node has degree >= 65536", i));
     h.slot_of_edge = preps[i].slot_of_edge;
     b->max_lt = std::max(b->max_lt, h.lt);
     BatchModel& d = b->md[i];
@@ -347,6 +352,7 @@ int mplpxx_batch_create(int32_t count, const int32_t* n, const int32_t* L, const
   TRY(alloc((void**)&b->d_tables, (size_t)b->total_tables * sizeof(float)));
   TRY(alloc((void**)&b->d_phi, (size_t)b->total_phi * sizeof(float)));
   TRY(alloc((void**)&b->d_U, (size_t)b->total_u * sizeof(float)));
+  TRY(alloc((void**)&b->d_Ulo, (size_t)b->total_u * sizeof(float)));
   TRY(alloc((void**)&b->d_unaries, (size_t)b->total_u * sizeof(float)));
   TRY(alloc((void**)&b->d_mb, (size_t)b->total_u * sizeof(unsigned long long)));
   TRY(alloc((void**)&b->d_slots, (size_t)b->total_slots * sizeof(SlotInfo)));
@@ -414,6 +420,7 @@ int mplpxx_batch_create(int32_t count, const int32_t* n, const int32_t* L, const
   if (b->total_slots)
     TRY(hipMemcpyAsync(b->d_slot_model, slot_model.data(), slot_model.size() * sizeof(int), hipMemcpyHostToDevice, cs));
   TRY(hipMemcpyAsync(b->d_U, b->d_unaries, (size_t)b->total_u * sizeof(float), hipMemcpyDeviceToDevice, cs));
+  TRY(hipMemsetAsync(b->d_Ulo, 0, (size_t)b->total_u * sizeof(float), cs));
   TRY(hipStreamSynchronize(cs));
 #undef TRY
   const int rc = plan(b);
@@ -478,13 +485,15 @@ int mplpxx_batch_dual_bounds(mplpxx_batch* b, double* out) {
   return MPLPXX_OK;
 }
 
-int mplpxx_batch_get_state(mplpxx_batch* b, int32_t model, float* U, float* phi) {
+int mplpxx_batch_get_state(mplpxx_batch* b, int32_t model, float* U, float* phi, float* U_comp) {
   if (!b) return fail(MPLPXX_EINVAL, "handle is NULL");
   if (model < 0 || model >= b->count) return fail(MPLPXX_EINVAL, "model index out of range");
   HIP_TRY(hipStreamSynchronize(b->stream));
   const ModelHost& h = b->mh[model];
   const BatchModel& d = b->md[model];
   if (U) HIP_TRY(hipMemcpy(U, b->d_U + d.u_off, (size_t)h.n * h.L * sizeof(float), hipMemcpyDeviceToHost));
+  if (U_comp)
+    HIP_TRY(hipMemcpy(U_comp, b->d_Ulo + d.u_off, (size_t)h.n * h.L * sizeof(float), hipMemcpyDeviceToHost));
   if (phi && h.m) {
     std::vector<float> tmp((size_t)h.m * 2 * h.L);
     HIP_TRY(hipMemcpy(tmp.data(), b->d_phi + d.phi_off, tmp.size() * sizeof(float), hipMemcpyDeviceToHost));
@@ -500,6 +509,7 @@ int mplpxx_batch_reset(mplpxx_batch* b) {
   HIP_TRY(hipStreamSynchronize(b->stream));
   HIP_TRY(hipMemsetAsync(b->d_phi, 0, (size_t)b->total_phi * sizeof(float), b->stream));
   HIP_TRY(hipMemcpyAsync(b->d_U, b->d_unaries, (size_t)b->total_u * sizeof(float), hipMemcpyDeviceToDevice, b->stream));
+  HIP_TRY(hipMemsetAsync(b->d_Ulo, 0, (size_t)b->total_u * sizeof(float), b->stream));
   HIP_TRY(hipStreamSynchronize(b->stream));
   b->iterations = 0;
   return MPLPXX_OK;

@@ -22,15 +22,14 @@ __device__ __forceinline__ bool run_task(const BatchArgs& b, const BatchModel& m
   if (threadIdx.x == 0) sm.abort_flag = 0;
   __syncthreads();
   MbView v{b.tables + md.table_off, b.phi + md.phi_off, b.mb + md.u_off, b.slots + md.slot_off,
-           b.deg + md.node_off, nullptr, nullptr, md.L, md.m, md.n};
-  return mb_run<LT, NT, false, false>(v, task.first, task.stride, iters, sm, nullptr, b.spin_limit, b.err);
+           b.deg + md.node_off, nullptr, nullptr, nullptr, md.L, md.m, md.n};
+  return mb_run<LT, NT, false, false, false>(v, task.first, task.stride, iters, sm, nullptr, b.spin_limit, b.err);
 }
 
-// at least three waves per SIMD, i.e. two 6-wave workgroups per compute
-// unit: one computes while the other waits for
-// its tables or its neighbours
+// at least two waves per SIMD: one 6-wave workgroup per compute unit, with
+// registers for every tile size without spills
 template <int NT, int MAXLT>
-__global__ void __launch_bounds__(NT + 128, 3) k_batch(BatchArgs b, int iters) {
+__global__ void __launch_bounds__(NT + 128, 2) k_batch(BatchArgs b, int iters) {
   __shared__ BatchSmem<NT, MAXLT> sm;
   __shared__ int s_wg;
   // logical workgroup = order of arrival: workgroups that hold a ticket have
@@ -68,24 +67,30 @@ int batch_blocks_per_cu(int max_lt) {
   return e == hipSuccess ? nb : 0;
 }
 
-__global__ void k_u32_to_mb(const float* __restrict__ U, unsigned long long* __restrict__ mb, size_t count) {
+// mailbox <- (U, Ulo, version 0) and back
+__global__ void k_u_to_mb(const float* __restrict__ U, const float* __restrict__ Ulo,
+                          unsigned long long* __restrict__ mb, size_t count) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
-    mb[i] = (unsigned long long)__float_as_uint(U[i]);
+    mb[i] = mb_pack(U[i], Ulo[i], 0u);
 }
-__global__ void k_mb_to_u32(float* __restrict__ U, const unsigned long long* __restrict__ mb, size_t count) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
-    U[i] = __uint_as_float((unsigned)mb[i]);
+__global__ void k_mb_to_u(float* __restrict__ U, float* __restrict__ Ulo, const unsigned long long* __restrict__ mb,
+                          size_t count) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
+    const unsigned long long w = mb[i];
+    U[i] = mb_hi(w);
+    Ulo[i] = mb_lo(w);
+  }
 }
 static unsigned blocks_for(size_t count) {
   size_t b = (count + 255) / 256;
   return (unsigned)(b > 2048 ? 2048 : (b == 0 ? 1 : b));
 }
-hipError_t launch_u32_to_mb(const float* U, unsigned long long* mb, size_t count, hipStream_t st) {
-  hipLaunchKernelGGL(k_u32_to_mb, dim3(blocks_for(count)), dim3(256), 0, st, U, mb, count);
+hipError_t launch_u_to_mb(const float* U, const float* Ulo, unsigned long long* mb, size_t count, hipStream_t st) {
+  hipLaunchKernelGGL(k_u_to_mb, dim3(blocks_for(count)), dim3(256), 0, st, U, Ulo, mb, count);
   return hipGetLastError();
 }
-hipError_t launch_mb_to_u32(float* U, const unsigned long long* mb, size_t count, hipStream_t st) {
-  hipLaunchKernelGGL(k_mb_to_u32, dim3(blocks_for(count)), dim3(256), 0, st, U, mb, count);
+hipError_t launch_mb_to_u(float* U, float* Ulo, const unsigned long long* mb, size_t count, hipStream_t st) {
+  hipLaunchKernelGGL(k_mb_to_u, dim3(blocks_for(count)), dim3(256), 0, st, U, Ulo, mb, count);
   return hipGetLastError();
 }
 

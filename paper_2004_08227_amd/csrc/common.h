@@ -31,11 +31,13 @@ template <typename T> struct HsArgs {
   const T* tables;        // [m][L][L] slot order, read-only
   T* phi;                 // [m][2][L] slot order
   T* U;                   // [n][L]
+  T* Ulo;                 // [n][L] FP32 only: bf16 correction of U (U = U + Ulo), else null
   const SlotInfo* slots;  // [m]
   const int* deg;         // [n]
   int* ver;               // [n] per-node update counters (persistent engine)
   int* err;               // device error word
   double* trace;          // [iters][n] per-node minima after the node's last update, or null
+  float* trace_e;         // [iters][m][W] FP32 mailbox engine: per-wave minima of the edge terms, or null
   long long* stamps;      // [m][4] wall-clock stamps of the last iteration, or null
   int L, m, n;
   long long spin_limit;
@@ -75,8 +77,8 @@ struct BatchArgs {
 };
 hipError_t launch_batch(const BatchArgs& b, int max_lt, int grid, int iters, hipStream_t st);
 int batch_blocks_per_cu(int max_lt);
-hipError_t launch_u32_to_mb(const float* U, unsigned long long* mb, size_t count, hipStream_t st);
-hipError_t launch_mb_to_u32(float* U, const unsigned long long* mb, size_t count, hipStream_t st);
+hipError_t launch_u_to_mb(const float* U, const float* Ulo, unsigned long long* mb, size_t count, hipStream_t st);
+hipError_t launch_mb_to_u(float* U, float* Ulo, const unsigned long long* mb, size_t count, hipStream_t st);
 hipError_t launch_batch_dual(const float* unaries, const float* tables, const float* phi, const BatchModel* models,
                              const int* node_model, const int* slot_model, const int* node_ptr, const int* inc,
                              int total_nodes, int total_slots, int count, double* node_min, double* edge_min,
@@ -84,13 +86,13 @@ hipError_t launch_batch_dual(const float* unaries, const float* tables, const fl
 
 // adjoint (adjoint.hip)
 template <typename T>
-hipError_t launch_step_record(const T* tables, T* phi, T* U, const SlotInfo* slots, int L, int slot_begin, int count,
-                              unsigned char* rec, hipStream_t st);
+hipError_t launch_step_record(const T* tables, T* phi, T* U, T* Ulo, const SlotInfo* slots, int L, int slot_begin,
+                              int count, unsigned char* rec, hipStream_t st);
 template <typename T>
 hipError_t launch_adj_step(const SlotInfo* slots, int L, int slot_begin, int count, const unsigned char* rec, T* Ub,
                            T* pb, T* thb, hipStream_t st);
 template <typename T>
-hipError_t launch_adj_seed(const T* U, int n, int L, T* Ub, double* node_min, hipStream_t st);
+hipError_t launch_adj_seed(const T* U, const T* Ulo, int n, int L, T* Ub, double* node_min, hipStream_t st);
 
 template <typename T>
 hipError_t launch_handshake(const HsArgs<T>& a, int engine, int LT, int NT, int slot_begin, int count, int grid,
@@ -99,17 +101,21 @@ template <typename T> int max_blocks_per_cu(int engine, int LT, int NT);
 // FP32 persistent engine with tagged mailboxes
 hipError_t launch_persistent_mb(const HsArgs<float>& a, unsigned long long* mb, int LT, int NT, int grid, int iters,
                                 int phi_in_lds, size_t dyn_lds, hipStream_t st);
-hipError_t launch_mb_init(const float* U, unsigned long long* mb, size_t count, hipStream_t st);
-hipError_t launch_mb_fini(float* U, const unsigned long long* mb, int n, int L, double* trace_row, hipStream_t st);
+hipError_t launch_mb_init(const float* U, const float* Ulo, unsigned long long* mb, size_t count, hipStream_t st);
+hipError_t launch_mb_fini(float* U, float* Ulo, const unsigned long long* mb, int n, int L, double* trace_row,
+                          hipStream_t st);
 
 // dual bound, traces, decode (dual.hip)
 template <typename T>
 hipError_t launch_dual(const T* unaries, const T* tables, const T* phi, const int* node_ptr, const int* inc, int n,
                        int L, int m, double* node_min, double* edge_min, double* out, hipStream_t st);
 template <typename T>
-hipError_t launch_trace_nodes(const T* U, int n, int L, double* row, hipStream_t st);
+hipError_t launch_trace_nodes(const T* U, const T* Ulo, int n, int L, double* row, hipStream_t st);
 template <typename T>
-hipError_t launch_trace_sum(double* trace_nodes, const T* U, const int* deg, int n, int L, int iters, double* out,
+hipError_t launch_trace_edges(const T* tables, const T* phi, int m, int L, float* out, hipStream_t st);
+template <typename T>
+hipError_t launch_trace_sum(double* trace_nodes, const float* trace_e, int m, int W, const T* U, const int* deg, int n,
+                            int L, int iters, double* out,
                             hipStream_t st);
 template <typename T>
 hipError_t launch_decode(const T* unaries, const T* tables, const T* phi, const SlotInfo* slots, const int* node_ptr,

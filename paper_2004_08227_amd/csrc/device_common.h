@@ -65,6 +65,51 @@ __device__ __forceinline__ double col4_min(double x) {
   return x;
 }
 
+// ---------------------------------------------------------------------------
+// Compensated FP32 unaries.  U_u = theta_u + (sum of the messages into u) is
+// a running sum: every update of an incident edge replaces one message,
+// U_u := (U_u - phi_old) + phi_new (Sec. 4, (H)).  Rounding the new value to
+// FP32 each time would let the error grow with the number of updates a node
+// has seen.  In FP32 the state therefore keeps U = hi + lo, hi in FP32 and lo
+// a correction rounded to bf16 (8 significant bits), and updates it with
+// error-free sums (Knuth's TwoSum):
+//   d  = hi - phi_old        (the a_u of the three passes, unchanged)
+//   s  = d + phi_new
+//   c  = (err(d) + err(s)) + lo
+//   hi' = s + c,  lo' = bf16(err(hi'))
+// so the error left per update is the bf16 rounding of lo', at most 2^-9 of
+// an ulp of hi.  Every engine uses this one function, so they agree bitwise.
+//
+// Centred passes.  The messages (about 0.07 on the pose workload) come out
+// of b = (a_u - p)/2, a difference of two O(|U|) numbers (about 2), so FP32
+// a_u and a_v would cost each message a few 1e-7 of absolute error, and the
+// block-coordinate ascent amplifies that over the iterations.  The FP32
+// engines therefore take per node the reference c_u = min_s hi_u(s) (exact)
+// and run the passes on a'_u = ((hi_u - c_u) + lo_u) - phi[0], which is
+// small exactly where the minima are taken.  (H) is invariant under such
+// shifts: with delta = (c_u - c_v)/2 the messages are r = r' - delta and
+// q = q' + delta, where r', q' are the passes' results on a'.
+// ---------------------------------------------------------------------------
+// exact error of s = fl(a + b): a + b = s + two_sum_err(a, b, s)
+__device__ __forceinline__ float two_sum_err(float a, float b, float s) {
+  const float bb = s - a;
+  return (a - (s - bb)) + (b - bb);
+}
+// nearest bf16 value (ties to even); finite inputs
+__device__ __forceinline__ float bf16_round(float x) {
+  const unsigned u = __float_as_uint(x);
+  return __uint_as_float((u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u);
+}
+__device__ __forceinline__ void comp_update(float hi, float lo, float phi_old, float phi_new, float& nhi, float& nlo) {
+  const float d = hi - phi_old;
+  const float e1 = two_sum_err(hi, -phi_old, d);
+  const float s = d + phi_new;
+  const float e2 = two_sum_err(d, phi_new, s);
+  const float c = (e1 + e2) + lo;
+  nhi = s + c;
+  nlo = bf16_round(two_sum_err(s, c, nhi));
+}
+
 // coherent (device-scope) accesses for data shared between workgroups
 __device__ __forceinline__ int ld_dev(const int* p) {
   return __hip_atomic_load(const_cast<int*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -93,9 +138,10 @@ template <typename T, int LT, int NT> struct TileShape {
   static_assert(BR >= 1 && BC >= 1 && RB * BR == LT, "tile shape");
 };
 
-// Loads the table of one slot into the register tile; pads are +inf.
+// Loads the table of one slot into the register tile; pads take `pad`.
 template <typename T, int LT, int NT>
-__device__ __forceinline__ void load_tile(const T* __restrict__ tab, int L, T (&x)[TileShape<T, LT, NT>::BR][TileShape<T, LT, NT>::BC]) {
+__device__ __forceinline__ void load_tile(const T* __restrict__ tab, int L, T (&x)[TileShape<T, LT, NT>::BR][TileShape<T, LT, NT>::BC],
+                                          T pad = inf_v<T>()) {
   using S = TileShape<T, LT, NT>;
   const int tid = threadIdx.x;
   const int rb = tid >> 4, cb = tid & 15;
@@ -120,7 +166,7 @@ __device__ __forceinline__ void load_tile(const T* __restrict__ tab, int L, T (&
 #pragma unroll
       for (int j = 0; j < S::BC; ++j) {
         const int t = cb * S::BC + j;
-        x[i][j] = (s < L && t < L) ? tab[s * L + t] : inf_v<T>();
+        x[i][j] = (s < L && t < L) ? tab[s * L + t] : pad;
       }
     }
   }
@@ -130,8 +176,12 @@ __device__ __forceinline__ void load_tile(const T* __restrict__ tab, int L, T (&
 // Engine 2, FP32: persistent with tagged mailboxes.
 //
 // The reparametrized unaries travel between workgroups through a mailbox
-// array MB[n][L] of 64-bit words: low half = the FP32 bits of U_u(s), high
-// half = the number of updates node u has seen in this launch.  A consumer
+// array MB[n][L] of 64-bit words: bits 0..31 = hi of U_u(s) (FP32), bits
+// 32..47 = its bf16 correction lo, bits 48..63 = the number of updates node u
+// has seen in this launch, modulo 2^16.  A waiter for version w can only see
+// versions w - deg(u) + 1 .. w (it made version w - deg(u) + 1 itself one
+// iteration earlier, and nobody makes w + 1 before it), so 16 bits identify
+// the version when every degree is below 2^16.  A consumer
 // polls the words it needs until every one carries the version it expects,
 // so the data is its own ready flag: no separate flag store, no wait for
 // store completion on the producer side.  Each word is written and read with
@@ -143,9 +193,13 @@ __device__ __forceinline__ void load_tile(const T* __restrict__ tab, int L, T (&
 // in the in-order memory counter of the compute waves.  The messages of the
 // slots a workgroup owns stay in LDS for the whole launch when they fit.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ unsigned long long mb_pack(float v, unsigned ver) {
-  return ((unsigned long long)ver << 32) | (unsigned long long)__float_as_uint(v);
+__device__ __forceinline__ unsigned long long mb_pack(float hi, float lo, unsigned ver) {
+  const unsigned top = (ver << 16) | (__float_as_uint(lo) >> 16);
+  return ((unsigned long long)top << 32) | (unsigned long long)__float_as_uint(hi);
 }
+__device__ __forceinline__ unsigned mb_ver(unsigned long long w) { return (unsigned)(w >> 48); }
+__device__ __forceinline__ float mb_hi(unsigned long long w) { return __uint_as_float((unsigned)w); }
+__device__ __forceinline__ float mb_lo(unsigned long long w) { return __uint_as_float((unsigned)(w >> 32) << 16); }
 __device__ __forceinline__ unsigned long long mb_load(const unsigned long long* p) {
   return __hip_atomic_load(const_cast<unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -154,8 +208,13 @@ __device__ __forceinline__ void mb_store(unsigned long long* p, unsigned long lo
 }
 
 template <int LT, int NT> struct SmemMB {
-  float uu[2][LT];   // raw U_u delivered by the sync wave (double buffered by slot parity)
+  float uu[2][LT];   // centred (hi - c) + lo of U_u from the sync wave (double buffered by slot parity)
   float uv[2][LT];
+  float uh[2][LT];   // hi of U_u
+  float vh[2][LT];
+  float ul[2][LT];   // lo of U_u
+  float vl[2][LT];
+  float cc[2][2];    // references c_u, c_v
   float red[TileShape<float, LT, NT>::W][LT];
   int abort_flag;
 };
@@ -174,13 +233,17 @@ __device__ __forceinline__ void report_timeout(int* err, int slot, int node, uns
   }
 }
 
+// On success delivers hi, lo, the centred values (hi - c) + lo and the
+// reference c = min_s hi(s) of the node.
 template <int LT>
 __device__ __forceinline__ bool sync_gather(const unsigned long long* __restrict__ mb_row, int L, unsigned want,
-                                            float* dst, long long spin_limit, const int* err, unsigned* seen_out) {
+                                            float* dst_un, float* dst_hi, float* dst_lo, float* dst_c,
+                                            long long spin_limit, const int* err, unsigned* seen_out) {
   const int lane = threadIdx.x & 63;
   constexpr int PER = (LT + 63) / 64;
+  want &= 0xFFFFu;
   bool have[PER];
-  float val[PER];
+  unsigned long long val[PER];
 #pragma unroll
   for (int k = 0; k < PER; ++k) have[k] = (lane + 64 * k) >= L;
   long long spins = 0;
@@ -190,9 +253,9 @@ __device__ __forceinline__ bool sync_gather(const unsigned long long* __restrict
     for (int k = 0; k < PER; ++k) {
       if (!have[k]) {
         const unsigned long long w = mb_load(mb_row + lane + 64 * k);
-        if ((unsigned)(w >> 32) == want) {
+        if (mb_ver(w) == want) {
           have[k] = true;
-          val[k] = __uint_as_float((unsigned)w);
+          val[k] = w;
         } else {
           all = false;
         }
@@ -203,16 +266,27 @@ __device__ __forceinline__ bool sync_gather(const unsigned long long* __restrict
       unsigned seen = want;
 #pragma unroll
       for (int k = 0; k < PER; ++k)
-        if (!have[k]) seen = (unsigned)(mb_load(mb_row + lane + 64 * k) >> 32);
+        if (!have[k]) seen = mb_ver(mb_load(mb_row + lane + 64 * k));
       // smallest version still missing in the wave
       for (int o = 32; o >= 1; o >>= 1) seen = min(seen, (unsigned)__shfl_xor((int)seen, o, 64));
       *seen_out = seen;
       return false;
     }
   }
+  float c = __builtin_inff();
 #pragma unroll
   for (int k = 0; k < PER; ++k)
-    if (lane + 64 * k < L) dst[lane + 64 * k] = val[k];
+    if (lane + 64 * k < L) c = vmin(c, mb_hi(val[k]));
+  c = col4_min(row16_min(c));
+#pragma unroll
+  for (int k = 0; k < PER; ++k)
+    if (lane + 64 * k < L) {
+      const float hi = mb_hi(val[k]), lo = mb_lo(val[k]);
+      dst_hi[lane + 64 * k] = hi;
+      dst_lo[lane + 64 * k] = lo;
+      dst_un[lane + 64 * k] = (hi - c) + lo;
+    }
+  if (lane == 0) *dst_c = c;
   return true;
 }
 
@@ -224,6 +298,7 @@ struct MbView {
   const SlotInfo* slots;        // [m]
   const int* deg;               // [n]
   double* trace;                // [iters][n] or null
+  float* trace_e;               // [iters][m][W] per-wave minima of the edge terms, or null
   long long* stamps;            // [m][kStampStride] or null
   int L, m, n;
 };
@@ -246,12 +321,28 @@ __device__ __forceinline__ void load_phi(const float* src, int L, float (&pu)[Ti
   }
 }
 
+// Table pad of the mailbox engine.  With pads = BIG = 2^126 and every real
+// value below 2^100 in magnitude, the three passes need no masks: a padded
+// column never wins a row minimum (BIG + a_v rounds to BIG); a padded row
+// gets p = BIG, b = -BIG/2 exactly, so it never wins a column minimum of a
+// real column (BIG - BIG/2 = BIG/2) and makes q = BIG/2 in every padded
+// column, which in turn never wins pass 3 (BIG - BIG/2).  All values stay
+// finite and every real minimum is the one over the real entries, so the
+// results are bitwise those of the unpadded tile.
+constexpr float kPadBig = 0x1p126f;
+
 // Runs `iters` iterations over the slots first, first+stride, ... of one
 // model.  Compute threads [0, NT) hold the table of the current slot in
 // registers and prefetch the next one together with its messages; threads
 // [NT, NT+128) are the two sync waves.  Returns false if a wait timed out
 // (the error word is set); every thread of the block returns the same value.
-template <int LT, int NT, bool PHI_LDS, bool FULL>
+//
+// Each new unary value (with its message) is finished by one compute lane:
+// row s = rb*BR + i by lane cb = i of row block rb, which holds r and the old
+// message for that row; the columns are shared out over the other lanes of
+// each wave, LT/W per wave, and each column lane keeps the old message of its
+// column in a register of its own.
+template <int LT, int NT, bool PHI_LDS, bool FULL, bool TRACE>
 __device__ __forceinline__ bool mb_run(const MbView& v, int first, int stride, int iters, SmemMB<LT, NT>& sm,
                                        float* phi_lds, long long spin_limit, int* err) {
   using S = TileShape<float, LT, NT>;
@@ -265,18 +356,32 @@ __device__ __forceinline__ bool mb_run(const MbView& v, int first, int stride, i
   auto phi_of = [&](int slot, int j) -> float* {
     return PHI_LDS ? phi_lds + (size_t)j * 2 * L : v.phi + (size_t)slot * 2 * L;
   };
+  // output lane of this thread (compute threads only)
+  constexpr int VPW = LT / S::W;
+  static_assert(VPW <= 4 * (16 - S::BR), "column outputs per wave");
+  const bool out_u = cb < S::BR;
+  const int out_s = rb * S::BR + cb;
+  const int lw = (rb & 3) * (16 - S::BR) + (cb - S::BR);
+  const int out_t = wave * VPW + lw;
+  const bool out_v = is_compute && !out_u && lw < VPW && (FULL || out_t < L);
+  const bool out_uk = is_compute && out_u && (FULL || out_s < L);
+  const int out_i = out_u ? out_s : out_t;     // label of the output
+  const int out_ic = out_i < L ? out_i : L - 1;  // in range for every lane
   float x[S::BR][S::BC], y[S::BR][S::BC];
   float pu[S::BR], pv[S::BC], npu[S::BR], npv[S::BC];
+  float pvo = 0.f, npvo = 0.f;  // old message of this lane's output column
   if (is_compute) {
-    load_tile<float, LT, NT>(v.tables + (size_t)first * L * L, L, x);
+    load_tile<float, LT, NT>(v.tables + (size_t)first * L * L, L, x, kPadBig);
     load_phi<LT, NT, PHI_LDS, FULL>(phi_of(first, 0), L, pu, pv);
+    if (out_v) pvo = phi_of(first, 0)[L + out_t];
   }
   SlotInfo si = v.slots[first];
   // slots owned: 1 -> the next slot is this one (its messages are the r, q
   // just computed); 2 -> the next slot is the previous one, whose messages
   // this workgroup wrote during the last slot: they are read after this
   // slot's first barrier; >= 3 -> the next slot's messages were written two
-  // or more slots ago, behind two barriers, and are prefetched with its table
+  // or more slots ago, behind two barriers, and are prefetched with its table.
+  // A column lane reads back only what it wrote itself, in program order.
   const int owned = (v.m - first + stride - 1) / stride;
   int parity = 0;
   for (int it = 0; it < iters; ++it) {
@@ -294,9 +399,10 @@ __device__ __forceinline__ bool mb_run(const MbView& v, int first, int stride, i
         // table of the next owned slot (its messages follow after the barrier,
         // once this workgroup's earlier writes to them are ordered)
         if (pref) {
-          load_tile<float, LT, NT>(v.tables + (size_t)nxt * L * L, L, y);
+          load_tile<float, LT, NT>(v.tables + (size_t)nxt * L * L, L, y, kPadBig);
           // (the very first slot's successor has not been written in this launch)
           if (owned >= 3 || (it == 0 && j == 0)) load_phi<LT, NT, PHI_LDS, FULL>(phi_of(nxt, jn), L, npu, npv);
+          if (out_v) npvo = phi_of(nxt, jn)[L + out_t];
         }
 #if MPLPXX_FINE_STAMPS
         if (v.stamps && last_iter && tid == 0) v.stamps[(size_t)slot * kStampStride + 4] = wall_clock64();
@@ -306,11 +412,14 @@ __device__ __forceinline__ bool mb_run(const MbView& v, int first, int stride, i
         const int node = is_sync_u ? si.u : si.v;
         const unsigned want = is_sync_u ? want_u : want_v;
         float* dst = is_sync_u ? sm.uu[parity] : sm.uv[parity];
+        float* dst_hi = is_sync_u ? sm.uh[parity] : sm.vh[parity];
+        float* dst_lo = is_sync_u ? sm.ul[parity] : sm.vl[parity];
         unsigned seen = 0;
-        if (!sync_gather<LT>(v.mb + (size_t)node * L, L, want, dst, spin_limit, err, &seen)) {
+        if (!sync_gather<LT>(v.mb + (size_t)node * L, L, want, dst, dst_hi, dst_lo, &sm.cc[parity][is_sync_u ? 0 : 1],
+                             spin_limit, err, &seen)) {
           if (lane == 0) {
             // a wait may also end because another workgroup reported first
-            if (ld_dev(err) == 0 || seen != want) report_timeout(err, slot, node, want, seen);
+            if (ld_dev(err) == 0 || seen != (want & 0xFFFFu)) report_timeout(err, slot, node, want & 0xFFFFu, seen);
             sm.abort_flag = 1;
           }
         }
@@ -324,20 +433,29 @@ __device__ __forceinline__ bool mb_run(const MbView& v, int first, int stride, i
 #if MPLPXX_FINE_STAMPS
         if (v.stamps && last_iter && tid == 0) v.stamps[(size_t)slot * kStampStride + 5] = wall_clock64();
 #endif
-        // a = U - phi; unconditional LDS reads at clamped indices, then a
-        // select, so the reads issue as one batch
+        // a' = centred U - phi (padded labels read label L-1: any finite value works)
         float av[S::BC], au[S::BR];
 #pragma unroll
         for (int jj = 0; jj < S::BC; ++jj) {
           const int t = cb * S::BC + jj;
-          const int tc = (FULL || t < L) ? t : L - 1;
-          av[jj] = (FULL || t < L) ? sm.uv[parity][tc] - pv[jj] : 0.f;
+          av[jj] = sm.uv[parity][(FULL || t < L) ? t : L - 1] - pv[jj];
         }
 #pragma unroll
         for (int i = 0; i < S::BR; ++i) {
           const int s = rb * S::BR + i;
-          const int sc = (FULL || s < L) ? s : L - 1;
-          au[i] = (FULL || s < L) ? sm.uu[parity][sc] - pu[i] : 0.f;
+          au[i] = sm.uu[parity][(FULL || s < L) ? s : L - 1] - pu[i];
+        }
+        // the old value (hi, lo) and message of this lane's output; the shift
+        // between the centred passes and the messages
+        const float ohi = out_u ? sm.uh[parity][out_ic] : sm.vh[parity][out_ic];
+        const float olo = out_u ? sm.ul[parity][out_ic] : sm.vl[parity][out_ic];
+        const float delta = 0.5f * (sm.cc[parity][0] - sm.cc[parity][1]);
+        float ophi = pvo;
+        if (out_u) {
+          ophi = pu[0];
+#pragma unroll
+          for (int i = 1; i < S::BR; ++i)
+            if (cb == i) ophi = pu[i];
         }
         // pass 1: p(s) = min_t [th(s,t) + a_v(t)], b = (a_u - p) / 2
         float b[S::BR];
@@ -352,10 +470,7 @@ __device__ __forceinline__ bool mb_run(const MbView& v, int first, int stride, i
           }
           row16_min_n<S::BR>(pm);
 #pragma unroll
-          for (int i = 0; i < S::BR; ++i) {
-            const int s = rb * S::BR + i;
-            b[i] = (FULL || s < L) ? 0.5f * (au[i] - pm[i]) : 0.f;
-          }
+          for (int i = 0; i < S::BR; ++i) b[i] = 0.5f * (au[i] - pm[i]);
         }
         // pass 2: q(t) = min_s [th(s,t) + b(s)]
         float q[S::BC];
@@ -383,7 +498,15 @@ __device__ __forceinline__ bool mb_run(const MbView& v, int first, int stride, i
           float mn = sm.red[0][t];
 #pragma unroll
           for (int w = 1; w < S::W; ++w) mn = vmin(mn, sm.red[w][t]);
-          q[jj] = (FULL || t < L) ? mn : 0.f;
+          q[jj] = mn;
+        }
+        // the output column's message q' + delta, q' reduced the same way
+        float omsg;
+        {
+          float mn = sm.red[0][out_ic];
+#pragma unroll
+          for (int w = 1; w < S::W; ++w) mn = vmin(mn, sm.red[w][out_ic]);
+          omsg = mn + delta;
         }
         // pass 3: r(s) = min_t [th(s,t) - q(t)]
         float r[S::BR];
@@ -395,27 +518,45 @@ __device__ __forceinline__ bool mb_run(const MbView& v, int first, int stride, i
           r[i] = mn;
         }
         row16_min_n<S::BR>(r);
-        // push back: new unaries through the mailboxes, messages to memory
-        float* phi_w = phi_of(slot, j);
-        if (rb == 0) {
-#pragma unroll
-          for (int jj = 0; jj < S::BC; ++jj) {
-            const int t = cb * S::BC + jj;
-            if (FULL || t < L) {
-              mb_store(v.mb + (size_t)si.v * L + t, mb_pack(av[jj] + q[jj], want_v + 1));
-              phi_w[L + t] = q[jj];
-            }
-          }
-        }
-        if (cb == 0) {
+        if (TRACE) {
+          // edge term of Eq. (3) after this update from the stored messages
+          // rs = r' - delta, qs = q' + delta: min over real rows of
+          // (fl(th - qs) - rs) + err(th - qs), exact up to one rounding of a
+          // number near zero; padded rows are skipped, padded columns stay
+          // near BIG/2
+          float em = __builtin_inff();
 #pragma unroll
           for (int i = 0; i < S::BR; ++i) {
             const int s = rb * S::BR + i;
+            const float rs = r[i] - delta;
             if (FULL || s < L) {
-              mb_store(v.mb + (size_t)si.u * L + s, mb_pack(au[i] + r[i], want_u + 1));
-              phi_w[s] = r[i];
+#pragma unroll
+              for (int jj = 0; jj < S::BC; ++jj) {
+                const float qs = q[jj] + delta;
+                const float d = x[i][jj] - qs;
+                em = vmin(em, (d - rs) + two_sum_err(x[i][jj], -qs, d));
+              }
             }
           }
+          em = col4_min(row16_min(em));
+          if (lane == 0) v.trace_e[((size_t)it * v.m + slot) * S::W + wave] = em;
+        }
+        if (out_u) {
+          float rr = r[0];
+#pragma unroll
+          for (int i = 1; i < S::BR; ++i)
+            if (cb == i) rr = r[i];
+          omsg = rr - delta;
+        }
+        // push back: the new unary through the mailbox, the message to memory
+        float* phi_w = phi_of(slot, j);
+        if (out_uk || out_v) {
+          float nhi, nlo;
+          comp_update(ohi, olo, ophi, omsg, nhi, nlo);
+          const int node = out_u ? si.u : si.v;
+          const unsigned ver = (out_u ? want_u : want_v) + 1;
+          mb_store(v.mb + (size_t)node * L + out_i, mb_pack(nhi, nlo, ver));
+          phi_w[(out_u ? 0 : L) + out_i] = omsg;
         }
         if (v.stamps && last_iter && tid == 0) v.stamps[(size_t)slot * kStampStride + 3] = wall_clock64();
         if (pref) {
@@ -427,24 +568,27 @@ __device__ __forceinline__ bool mb_run(const MbView& v, int first, int stride, i
           }
 #pragma unroll
           for (int jj = 0; jj < S::BC; ++jj) pv[jj] = npv[jj];
+          pvo = npvo;
         } else {
           // the same slot comes next: its messages are the ones just made
 #pragma unroll
-          for (int i = 0; i < S::BR; ++i) pu[i] = r[i];
+          for (int i = 0; i < S::BR; ++i) pu[i] = r[i] - delta;
 #pragma unroll
-          for (int jj = 0; jj < S::BC; ++jj) pv[jj] = q[jj];
+          for (int jj = 0; jj < S::BC; ++jj) pv[jj] = q[jj] + delta;
+          pvo = omsg;
         }
       } else {
         // the sync waves take part in the compute waves' mid-slot barrier
         __syncthreads();
         // per-iteration trace: the first update of a node in iteration it
         // sees the node's value at the end of iteration it-1
-        if (v.trace && it > 0) {
+        if (TRACE && it > 0) {
           const bool first_upd = is_sync_u ? (si.pos_u == 0) : (si.pos_v == 0);
           if (first_upd) {
-            const float* src = is_sync_u ? sm.uu[parity] : sm.uv[parity];
+            const float* src = is_sync_u ? sm.uh[parity] : sm.vh[parity];
+            const float* src_lo = is_sync_u ? sm.ul[parity] : sm.vl[parity];
             double mn = __builtin_inf();
-            for (int s2 = lane; s2 < L; s2 += 64) mn = __builtin_fmin(mn, (double)src[s2]);
+            for (int s2 = lane; s2 < L; s2 += 64) mn = __builtin_fmin(mn, (double)src[s2] + (double)src_lo[s2]);
 #pragma unroll
             for (int o = 32; o >= 1; o >>= 1) mn = __builtin_fmin(mn, __shfl_xor(mn, o, 64));
             if (lane == 0) v.trace[(size_t)(it - 1) * v.n + (is_sync_u ? si.u : si.v)] = mn;

@@ -91,25 +91,59 @@ hipError_t launch_dual(const T* unaries, const T* tables, const T* phi, const in
 // Traces: sum_u min_s U_u(s) in FP64 per iteration.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(64) k_trace_nodes(const T* __restrict__ U, int L, double* __restrict__ row) {
+__global__ void __launch_bounds__(64) k_trace_nodes(const T* __restrict__ U, const T* __restrict__ Ulo, int L,
+                                                    double* __restrict__ row) {
   const int u = blockIdx.x;
   double mn = __builtin_inf();
-  for (int s = threadIdx.x; s < L; s += 64) mn = dmin(mn, (double)U[(size_t)u * L + s]);
+  for (int s = threadIdx.x; s < L; s += 64) {
+    const size_t i = (size_t)u * L + s;
+    mn = dmin(mn, (double)U[i] + (Ulo ? (double)Ulo[i] : 0.0));
+  }
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) mn = dmin(mn, __shfl_xor(mn, o, 64));
   if (threadIdx.x == 0) row[u] = mn;
 }
 
 template <typename T>
-hipError_t launch_trace_nodes(const T* U, int n, int L, double* row, hipStream_t st) {
-  hipLaunchKernelGGL(k_trace_nodes<T>, dim3(n), dim3(64), 0, st, U, L, row);
+hipError_t launch_trace_nodes(const T* U, const T* Ulo, int n, int L, double* row, hipStream_t st) {
+  hipLaunchKernelGGL(k_trace_nodes<T>, dim3(n), dim3(64), 0, st, U, Ulo, L, row);
   return hipGetLastError();
 }
 
-// one workgroup per iteration; nodes without edges keep their input unary
+// Edge terms of Eq. (3) for the trace of one iteration: out[slot] =
+// min_{s,t} [theta(s,t) - phi[0](s) - phi[1](t)] in FP64, stored as FP32 (the
+// FP32 engines' terms are rounding-level numbers, far inside FP32 range).
 template <typename T>
-__global__ void __launch_bounds__(256) k_trace_sum(const double* __restrict__ trace_nodes, const T* __restrict__ U,
-                                                   const int* __restrict__ deg, int n, int L,
+__global__ void __launch_bounds__(256) k_trace_edges(const T* __restrict__ tables, const T* __restrict__ phi, int L,
+                                                     float* __restrict__ out) {
+  __shared__ double sh[256];
+  const int slot = blockIdx.x;
+  const T* tab = tables + (size_t)slot * L * L;
+  const T* p0 = phi + (size_t)slot * 2 * L;
+  const T* p1 = p0 + L;
+  double mn = __builtin_inf();
+  for (int i = threadIdx.x; i < L * L; i += 256) {
+    const int s = i / L, t = i - s * L;
+    mn = dmin(mn, ((double)tab[i] - (double)p0[s]) - (double)p1[t]);
+  }
+  mn = block_reduce<256, true>(mn, sh);
+  if (threadIdx.x == 0) out[slot] = (float)mn;
+}
+
+template <typename T>
+hipError_t launch_trace_edges(const T* tables, const T* phi, int m, int L, float* out, hipStream_t st) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_trace_edges<T>, dim3(m), dim3(256), 0, st, tables, phi, L, out);
+  return hipGetLastError();
+}
+
+// One workgroup per iteration: sum of the node minima (nodes without edges
+// keep their input unary) plus, when trace_e is given, the edge terms (the
+// minimum over the W partial minima of each slot), in a fixed order.
+template <typename T>
+__global__ void __launch_bounds__(256) k_trace_sum(const double* __restrict__ trace_nodes,
+                                                   const float* __restrict__ trace_e, int m, int W,
+                                                   const T* __restrict__ U, const int* __restrict__ deg, int n, int L,
                                                    double* __restrict__ out) {
   __shared__ double sh[256];
   const int it = blockIdx.x;
@@ -124,15 +158,23 @@ __global__ void __launch_bounds__(256) k_trace_sum(const double* __restrict__ tr
     }
     acc += v;
   }
+  if (trace_e) {
+    for (int e = threadIdx.x; e < m; e += 256) {
+      const float* w = trace_e + ((size_t)it * m + e) * W;
+      float v = w[0];
+      for (int k = 1; k < W; ++k) v = __builtin_fminf(v, w[k]);
+      acc += (double)v;
+    }
+  }
   acc = block_reduce<256, false>(acc, sh);
   if (threadIdx.x == 0) out[it] = acc;
 }
 
 template <typename T>
-hipError_t launch_trace_sum(double* trace_nodes, const T* U, const int* deg, int n, int L, int iters, double* out,
-                            hipStream_t st) {
+hipError_t launch_trace_sum(double* trace_nodes, const float* trace_e, int m, int W, const T* U, const int* deg, int n,
+                            int L, int iters, double* out, hipStream_t st) {
   if (iters <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_trace_sum<T>, dim3(iters), dim3(256), 0, st, trace_nodes, U, deg, n, L, out);
+  hipLaunchKernelGGL(k_trace_sum<T>, dim3(iters), dim3(256), 0, st, trace_nodes, trace_e, m, W, U, deg, n, L, out);
   return hipGetLastError();
 }
 
@@ -223,7 +265,7 @@ template <typename T>
 __global__ void k_check_finite(const T* __restrict__ p, size_t count, int* __restrict__ flag) {
   bool bad = false;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
-    bad |= !__builtin_isfinite(p[i]);
+    bad |= sizeof(T) == 4 ? !(__builtin_fabs((double)p[i]) <= MPLPXX_F32_MAX_COST) : !__builtin_isfinite(p[i]);
   if (bad) atomicOr(flag, 1);
 }
 
@@ -274,8 +316,10 @@ hipError_t launch_fill_int(int* p, int value, size_t count, hipStream_t st) {
 #define MPLPXX_INST(T)                                                                                              \
   template hipError_t launch_dual<T>(const T*, const T*, const T*, const int*, const int*, int, int, int, double*,  \
                                      double*, double*, hipStream_t);                                              \
-  template hipError_t launch_trace_nodes<T>(const T*, int, int, double*, hipStream_t);                             \
-  template hipError_t launch_trace_sum<T>(double*, const T*, const int*, int, int, int, double*, hipStream_t);     \
+  template hipError_t launch_trace_nodes<T>(const T*, const T*, int, int, double*, hipStream_t);                             \
+  template hipError_t launch_trace_edges<T>(const T*, const T*, int, int, float*, hipStream_t);               \
+  template hipError_t launch_trace_sum<T>(double*, const float*, int, int, const T*, const int*, int, int, int,   \
+                                          double*, hipStream_t);     \
   template hipError_t launch_decode<T>(const T*, const T*, const T*, const SlotInfo*, const int*, const int*, int, \
                                        int, int, int*, double*, hipStream_t);                                      \
   template hipError_t launch_check_finite<T>(const T*, size_t, int*, hipStream_t);                                 \

@@ -32,6 +32,8 @@
 // then across waves through LDS).  Every entry of a pass is one IEEE add
 // followed by an exact minimum, so results do not depend on LT, NT, the
 // reduction tree or the engine.
+#include <type_traits>
+
 #include "device_common.h"
 
 namespace mplpxx {
@@ -41,8 +43,14 @@ template <typename T, int LT, int NT> struct Smem {
   T red[TileShape<T, LT, NT>::W][LT];
   T nu[LT];
   T nv[LT];
+  // FP32: old hi, lo and message of each label (compensated update), and
+  // the references of the centred passes (see device_common.h)
+  T hu[LT], lu[LT], ou[LT];
+  T hv[LT], lv[LT], ov[LT];
+  T cu, cv;
   int abort_flag;
 };
+template <typename T> constexpr bool kComp = std::is_same<T, float>::value;
 
 // The three passes on a register tile; a_u / a_v must be in smem.  Writes
 // the new messages and unaries to global memory (coherent stores when
@@ -50,7 +58,8 @@ template <typename T, int LT, int NT> struct Smem {
 template <typename T, int LT, int NT, bool kCoherent>
 __device__ __forceinline__ void handshake_passes(const T (&x)[TileShape<T, LT, NT>::BR][TileShape<T, LT, NT>::BC],
                                                  Smem<T, LT, NT>& sm, int L, T* __restrict__ phi_slot,
-                                                 T* __restrict__ Uu, T* __restrict__ Uv, bool keep_new) {
+                                                 T* __restrict__ Uu, T* __restrict__ Uv, T* __restrict__ Lu,
+                                                 T* __restrict__ Lv, bool keep_new) {
   using S = TileShape<T, LT, NT>;
   const int tid = threadIdx.x;
   const int rb = tid >> 4, cb = tid & 15;
@@ -115,15 +124,23 @@ __device__ __forceinline__ void handshake_passes(const T (&x)[TileShape<T, LT, N
   }
   // push back: phi[1] = q, U_v = a_v + q (threads of row block 0);
   //            phi[0] = r, U_u = a_u + r (threads of column block 0)
+  // (FP32: centred passes shifted back by delta, compensated U + Ulo, see
+  // device_common.h; FP64: plain, one rounding)
+  T delta = T(0);
+  if constexpr (kComp<T>) delta = T(0.5) * (sm.cu - sm.cv);
   if (rb == 0) {
 #pragma unroll
     for (int j = 0; j < S::BC; ++j) {
       const int t = cb * S::BC + j;
       if (t < L) {
-        const T nvv = av[j] + q[j];
-        phi_slot[L + t] = q[j];
+        T nvv, nvl = T(0);
+        const T qs = q[j] + delta;
+        if constexpr (kComp<T>) comp_update(sm.hv[t], sm.lv[t], sm.ov[t], qs, nvv, nvl);
+        else nvv = av[j] + q[j];
+        phi_slot[L + t] = qs;
         if (kCoherent) stv_dev(Uv + t, nvv); else Uv[t] = nvv;
-        if (keep_new) sm.nv[t] = nvv;
+        if constexpr (kComp<T>) { if (kCoherent) stv_dev(Lv + t, nvl); else Lv[t] = nvl; }
+        if (keep_new) sm.nv[t] = nvv + nvl;
       }
     }
   }
@@ -132,10 +149,14 @@ __device__ __forceinline__ void handshake_passes(const T (&x)[TileShape<T, LT, N
     for (int i = 0; i < S::BR; ++i) {
       const int s = rb * S::BR + i;
       if (s < L) {
-        const T nuu = sm.au[s] + r[i];
-        phi_slot[s] = r[i];
+        T nuu, nul = T(0);
+        const T rs = r[i] - delta;
+        if constexpr (kComp<T>) comp_update(sm.hu[s], sm.lu[s], sm.ou[s], rs, nuu, nul);
+        else nuu = sm.au[s] + r[i];
+        phi_slot[s] = rs;
         if (kCoherent) stv_dev(Uu + s, nuu); else Uu[s] = nuu;
-        if (keep_new) sm.nu[s] = nuu;
+        if constexpr (kComp<T>) { if (kCoherent) stv_dev(Lu + s, nul); else Lu[s] = nul; }
+        if (keep_new) sm.nu[s] = nuu + nul;
       }
     }
   }
@@ -143,18 +164,56 @@ __device__ __forceinline__ void handshake_passes(const T (&x)[TileShape<T, LT, N
   __syncthreads();
 }
 
-// a_u = U_u - phi[0], a_v = U_v - phi[1] into smem (wave 0 gathers u, wave 1 v
-// when there are two waves)
+// a_u = U_u - phi[0], a_v = U_v - phi[1] into smem (FP32: the centred
+// ((hi - c) + lo) - phi with c = min_s hi(s) per node, see device_common.h)
 template <typename T, int LT, int NT, bool kCoherent>
 __device__ __forceinline__ void gather(Smem<T, LT, NT>& sm, int L, const T* __restrict__ phi_slot, const T* Uu,
-                                       const T* Uv) {
+                                       const T* Uv, const T* Lu, const T* Lv) {
   const int tid = threadIdx.x;
-  for (int s = tid; s < 2 * LT; s += NT) {
-    if (s < LT) {
-      if (s < L) sm.au[s] = (kCoherent ? ldv_dev(Uu + s) : Uu[s]) - phi_slot[s];
-    } else {
-      const int t = s - LT;
-      if (t < L) sm.av[t] = (kCoherent ? ldv_dev(Uv + t) : Uv[t]) - phi_slot[L + t];
+  if constexpr (!kComp<T>) {
+    for (int s = tid; s < 2 * LT; s += NT) {
+      if (s < LT) {
+        if (s < L) sm.au[s] = (kCoherent ? ldv_dev(Uu + s) : Uu[s]) - phi_slot[s];
+      } else {
+        const int t = s - LT;
+        if (t < L) sm.av[t] = (kCoherent ? ldv_dev(Uv + t) : Uv[t]) - phi_slot[L + t];
+      }
+    }
+  } else {
+    for (int s = tid; s < 2 * LT; s += NT) {
+      if (s < LT) {
+        if (s < L) {
+          sm.hu[s] = kCoherent ? ldv_dev(Uu + s) : Uu[s];
+          sm.lu[s] = kCoherent ? ldv_dev(Lu + s) : Lu[s];
+          sm.ou[s] = phi_slot[s];
+        }
+      } else {
+        const int t = s - LT;
+        if (t < L) {
+          sm.hv[t] = kCoherent ? ldv_dev(Uv + t) : Uv[t];
+          sm.lv[t] = kCoherent ? ldv_dev(Lv + t) : Lv[t];
+          sm.ov[t] = phi_slot[L + t];
+        }
+      }
+    }
+    __syncthreads();
+    // wave 0: c_u, wave 1: c_v (min is exact, any order)
+    const int wave = tid >> 6, lane = tid & 63;
+    if (wave < 2) {
+      const T* h = wave == 0 ? sm.hu : sm.hv;
+      T c = inf_v<T>();
+      for (int s = lane; s < L; s += 64) c = vmin(c, h[s]);
+      c = col4_min(row16_min(c));
+      if (lane == 0) (wave == 0 ? sm.cu : sm.cv) = c;
+    }
+    __syncthreads();
+    for (int s = tid; s < 2 * LT; s += NT) {
+      if (s < LT) {
+        if (s < L) sm.au[s] = ((sm.hu[s] - sm.cu) + sm.lu[s]) - sm.ou[s];
+      } else {
+        const int t = s - LT;
+        if (t < L) sm.av[t] = ((sm.hv[t] - sm.cv) + sm.lv[t]) - sm.ov[t];
+      }
     }
   }
   __syncthreads();
@@ -188,8 +247,10 @@ __global__ void __launch_bounds__(NT) k_step(HsArgs<T> a, int slot_begin) {
   T* phi_slot = a.phi + (size_t)slot * 2 * L;
   T* Uu = a.U + (size_t)si.u * L;
   T* Uv = a.U + (size_t)si.v * L;
-  gather<T, LT, NT, false>(sm, L, phi_slot, Uu, Uv);
-  handshake_passes<T, LT, NT, false>(x, sm, L, phi_slot, Uu, Uv, false);
+  T* Lu = a.Ulo ? a.Ulo + (size_t)si.u * L : nullptr;
+  T* Lv = a.Ulo ? a.Ulo + (size_t)si.v * L : nullptr;
+  gather<T, LT, NT, false>(sm, L, phi_slot, Uu, Uv, Lu, Lv);
+  handshake_passes<T, LT, NT, false>(x, sm, L, phi_slot, Uu, Uv, Lu, Lv, false);
 }
 
 // ---------------------------------------------------------------------------
@@ -236,10 +297,12 @@ __global__ void __launch_bounds__(NT) k_persistent(HsArgs<T> a, int iters) {
       T* phi_slot = a.phi + (size_t)slot * 2 * L;
       T* Uu = a.U + (size_t)si.u * L;
       T* Uv = a.U + (size_t)si.v * L;
-      gather<T, LT, NT, true>(sm, L, phi_slot, Uu, Uv);
+      T* Lu = a.Ulo ? a.Ulo + (size_t)si.u * L : nullptr;
+      T* Lv = a.Ulo ? a.Ulo + (size_t)si.v * L : nullptr;
+      gather<T, LT, NT, true>(sm, L, phi_slot, Uu, Uv, Lu, Lv);
       const bool last_u = a.trace && si.pos_u == a.deg[si.u] - 1;
       const bool last_v = a.trace && si.pos_v == a.deg[si.v] - 1;
-      handshake_passes<T, LT, NT, true>(x, sm, L, phi_slot, Uu, Uv, last_u || last_v);
+      handshake_passes<T, LT, NT, true>(x, sm, L, phi_slot, Uu, Uv, Lu, Lv, last_u || last_v);
       if (tid == 0) {
         st_dev(a.ver + si.u, it * a.deg[si.u] + si.pos_u + 1);
         st_dev(a.ver + si.v, it * a.deg[si.v] + si.pos_v + 1);
@@ -256,7 +319,7 @@ __global__ void __launch_bounds__(NT) k_persistent(HsArgs<T> a, int iters) {
   }
 }
 
-template <int LT, int NT, bool PHI_LDS, bool FULL>
+template <int LT, int NT, bool PHI_LDS, bool FULL, bool TRACE>
 __global__ void __launch_bounds__(NT + 128) k_persistent_mb(HsArgs<float> a, unsigned long long* __restrict__ mb,
                                                             int iters) {
   __shared__ SmemMB<LT, NT> sm;
@@ -271,8 +334,8 @@ __global__ void __launch_bounds__(NT + 128) k_persistent_mb(HsArgs<float> a, uns
       for (int k = tid; k < 2 * L; k += NT + 128) phi_lds[j * 2 * L + k] = a.phi[(size_t)slot * 2 * L + k];
   }
   __syncthreads();
-  MbView v{a.tables, a.phi, mb, a.slots, a.deg, a.trace, a.stamps, L, a.m, a.n};
-  if (!mb_run<LT, NT, PHI_LDS, FULL>(v, blockIdx.x, G, iters, sm, phi_lds, a.spin_limit, a.err)) return;
+  MbView v{a.tables, a.phi, mb, a.slots, a.deg, a.trace, a.trace_e, a.stamps, L, a.m, a.n};
+  if (!mb_run<LT, NT, PHI_LDS, FULL, TRACE>(v, blockIdx.x, G, iters, sm, phi_lds, a.spin_limit, a.err)) return;
   __syncthreads();
   if (PHI_LDS) {
     for (int slot = blockIdx.x, j = 0; slot < a.m; slot += G, ++j)
@@ -280,21 +343,23 @@ __global__ void __launch_bounds__(NT + 128) k_persistent_mb(HsArgs<float> a, uns
   }
 }
 
-// mailbox <- (U, version 0)
-__global__ void k_mb_init(const float* __restrict__ U, unsigned long long* __restrict__ mb, size_t count) {
+// mailbox <- (U, Ulo, version 0)
+__global__ void k_mb_init(const float* __restrict__ U, const float* __restrict__ Ulo,
+                          unsigned long long* __restrict__ mb, size_t count) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
-    mb[i] = ((unsigned long long)__float_as_uint(U[i]));
+    mb[i] = mb_pack(U[i], Ulo[i], 0u);
 }
 
-// U <- mailbox values; trace row of the last iteration from the final values
-__global__ void k_mb_fini(float* __restrict__ U, const unsigned long long* __restrict__ mb, int n, int L,
-                          double* __restrict__ trace_row) {
+// U, Ulo <- mailbox values; trace row of the last iteration from the final values
+__global__ void k_mb_fini(float* __restrict__ U, float* __restrict__ Ulo, const unsigned long long* __restrict__ mb,
+                          int n, int L, double* __restrict__ trace_row) {
   const int u = blockIdx.x;
   double mn = __builtin_inf();
   for (int s = threadIdx.x; s < L; s += 64) {
-    const float v = __uint_as_float((unsigned)mb[(size_t)u * L + s]);
-    U[(size_t)u * L + s] = v;
-    mn = __builtin_fmin(mn, (double)v);
+    const unsigned long long w = mb[(size_t)u * L + s];
+    U[(size_t)u * L + s] = mb_hi(w);
+    Ulo[(size_t)u * L + s] = mb_lo(w);
+    mn = __builtin_fmin(mn, (double)mb_hi(w) + (double)mb_lo(w));
   }
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) mn = __builtin_fmin(mn, __shfl_xor(mn, o, 64));
@@ -321,8 +386,17 @@ static hipError_t launch_mb_one(const HsArgs<float>& a, unsigned long long* mb, 
                                 size_t dyn_lds, hipStream_t st) {
   void* args[] = {(void*)&a, (void*)&mb, (void*)&iters};
   const bool full = a.L == LT;
-  const void* f = phi_in_lds ? (full ? (const void*)k_persistent_mb<LT, NT, true, true> : (const void*)k_persistent_mb<LT, NT, true, false>)
-                             : (full ? (const void*)k_persistent_mb<LT, NT, false, true> : (const void*)k_persistent_mb<LT, NT, false, false>);
+  const void* f;
+  if (a.trace)
+    f = phi_in_lds ? (full ? (const void*)k_persistent_mb<LT, NT, true, true, true>
+                           : (const void*)k_persistent_mb<LT, NT, true, false, true>)
+                   : (full ? (const void*)k_persistent_mb<LT, NT, false, true, true>
+                           : (const void*)k_persistent_mb<LT, NT, false, false, true>);
+  else
+    f = phi_in_lds ? (full ? (const void*)k_persistent_mb<LT, NT, true, true, false>
+                           : (const void*)k_persistent_mb<LT, NT, true, false, false>)
+                   : (full ? (const void*)k_persistent_mb<LT, NT, false, true, false>
+                           : (const void*)k_persistent_mb<LT, NT, false, false, false>);
   return hipLaunchCooperativeKernel(f, dim3(grid), dim3(NT + 128), args, dyn_lds, st);
 }
 
@@ -341,16 +415,17 @@ hipError_t launch_persistent_mb(const HsArgs<float>& a, unsigned long long* mb, 
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_mb_init(const float* U, unsigned long long* mb, size_t count, hipStream_t st) {
+hipError_t launch_mb_init(const float* U, const float* Ulo, unsigned long long* mb, size_t count, hipStream_t st) {
   size_t blocks = (count + 255) / 256;
   if (blocks > 1024) blocks = 1024;
   if (blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mb_init, dim3((unsigned)blocks), dim3(256), 0, st, U, mb, count);
+  hipLaunchKernelGGL(k_mb_init, dim3((unsigned)blocks), dim3(256), 0, st, U, Ulo, mb, count);
   return hipGetLastError();
 }
 
-hipError_t launch_mb_fini(float* U, const unsigned long long* mb, int n, int L, double* trace_row, hipStream_t st) {
-  hipLaunchKernelGGL(k_mb_fini, dim3(n), dim3(64), 0, st, U, mb, n, L, trace_row);
+hipError_t launch_mb_fini(float* U, float* Ulo, const unsigned long long* mb, int n, int L, double* trace_row,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_mb_fini, dim3(n), dim3(64), 0, st, U, Ulo, mb, n, L, trace_row);
   return hipGetLastError();
 }
 

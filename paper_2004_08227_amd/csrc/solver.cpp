@@ -56,6 +56,7 @@ struct mplpxx_solver {
   void* d_tables = nullptr;
   void* d_phi = nullptr;
   void* d_U = nullptr;
+  float* d_Ulo = nullptr;                // FP32: bf16 corrections of U (compensated sums)
   void* d_unaries = nullptr;
   SlotInfo* d_slots = nullptr;
   int* d_deg = nullptr;
@@ -69,6 +70,7 @@ struct mplpxx_solver {
   int* d_labels = nullptr;
   double* d_trace_nodes = nullptr;
   double* d_trace_out = nullptr;
+  float* d_trace_e = nullptr;            // FP32: [cap][m][8] edge terms of the trace
   int trace_cap = 0;
   unsigned long long* d_mb = nullptr;    // FP32 mailboxes of the persistent engine
   long long* d_stamps = nullptr;         // per-slot timestamps (profiling option)
@@ -79,6 +81,7 @@ struct mplpxx_solver {
   bool adj_ready = false;
   long long adj_iter_mark = -1;           // `iterations` right after the forward
   void* d_ck_U = nullptr;                 // [nck + 1][n][L] (last = final state)
+  float* d_ck_Ulo = nullptr;              // FP32: [nck + 1][n][L] corrections
   void* d_ck_phi = nullptr;               // [nck + 1][m][2][L]
   unsigned char* d_rec = nullptr;         // [every][m][3][L]
   void* d_Ub = nullptr;                   // [n][L]
@@ -108,7 +111,10 @@ struct mplpxx_solver {
     if (dtype == MPLPXX_F32 && engine() == ENGINE_PERSISTENT && nt > 512) nt = 512;
     return nt;
   }
+  int max_deg = 0;
   int engine() const {
+    // FP32 mailboxes carry 16-bit versions: degrees must stay below 2^16
+    if (dtype == MPLPXX_F32 && max_deg >= 65536) return ENGINE_STEP;
     if (engine_opt == ENGINE_STEP || engine_opt == ENGINE_PERSISTENT) return engine_opt;
     return ENGINE_PERSISTENT;
   }
@@ -123,9 +129,9 @@ struct mplpxx_solver {
 namespace {
 
 void free_all(mplpxx_solver* h) {
-  void* ptrs[] = {h->d_tables, h->d_phi, h->d_U, h->d_unaries, h->d_slots, h->d_deg, h->d_ver, h->d_err,
+  void* ptrs[] = {h->d_tables, h->d_phi, h->d_U, h->d_Ulo, h->d_ck_Ulo, h->d_unaries, h->d_slots, h->d_deg, h->d_ver, h->d_err,
                   h->d_node_ptr, h->d_inc, h->d_node_min, h->d_edge_min, h->d_scalar, h->d_labels,
-                  h->d_trace_nodes, h->d_trace_out, h->d_mb, h->d_stamps, h->d_ck_U, h->d_ck_phi,
+                  h->d_trace_nodes, h->d_trace_out, h->d_trace_e, h->d_mb, h->d_stamps, h->d_ck_U, h->d_ck_phi,
                   h->d_rec, h->d_Ub, h->d_pb, h->d_thb, h->d_slot_of_edge, h->d_edge_flip};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -134,11 +140,13 @@ void free_all(mplpxx_solver* h) {
   if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
 }
 
+// FP32 values must be finite with |x| <= MPLPXX_F32_MAX_COST (the FP32 engines
+// pad tables with 2^126 and rely on every real value staying far below it)
 bool finite_host(const void* p, size_t count, int dtype) {
   if (dtype == MPLPXX_F32) {
     const float* f = static_cast<const float*>(p);
     for (size_t i = 0; i < count; ++i)
-      if (!std::isfinite(f[i])) return false;
+      if (!(std::fabs(f[i]) <= (float)MPLPXX_F32_MAX_COST)) return false;
   } else {
     const double* f = static_cast<const double*>(p);
     for (size_t i = 0; i < count; ++i)
@@ -159,6 +167,8 @@ int prepare_solver_graph(mplpxx_solver* h, const int32_t* edges) {
   h->slots.swap(g.slots);
   h->flip.swap(g.flip);
   h->deg.swap(g.deg);
+  h->max_deg = 0;
+  for (int d : h->deg) h->max_deg = std::max(h->max_deg, d);
   return MPLPXX_OK;
 }
 
@@ -176,8 +186,8 @@ int create_impl(int32_t n, int32_t L, int64_t m, const int32_t* edges, const voi
   const size_t esz = dtype == MPLPXX_F32 ? 4 : 8;
   const size_t nL = (size_t)n * L, mLL = (size_t)m * L * L;
   if (!device_costs) {
-    if (!finite_host(unaries, nL, dtype)) return fail(MPLPXX_EINVAL, "non-finite unary cost");
-    if (m > 0 && !finite_host(pairwise, mLL, dtype)) return fail(MPLPXX_EINVAL, "non-finite pairwise cost");
+    if (!finite_host(unaries, nL, dtype)) return fail(MPLPXX_EINVAL, "non-finite (or, in FP32, above 1e18) unary cost");
+    if (m > 0 && !finite_host(pairwise, mLL, dtype)) return fail(MPLPXX_EINVAL, "non-finite (or, in FP32, above 1e18) pairwise cost");
   }
   mplpxx_solver* h = new (std::nothrow) mplpxx_solver();
   if (!h) return fail(MPLPXX_ENOMEM, "host allocation failed");
@@ -229,6 +239,8 @@ int create_impl(int32_t n, int32_t L, int64_t m, const int32_t* edges, const voi
   h->d_labels = dalloc<int>(n, &ae); TRY(ae);
   if (dtype == MPLPXX_F32) {
     h->d_mb = dalloc<unsigned long long>(nL, &ae);
+    TRY(ae);
+    h->d_Ulo = dalloc<float>(nL, &ae);
     TRY(ae);
   }
 
@@ -320,6 +332,7 @@ int create_impl(int32_t n, int32_t L, int64_t m, const int32_t* edges, const voi
     }
   }
   TRY(hipMemcpyAsync(h->d_U, h->d_unaries, nL * esz, hipMemcpyDeviceToDevice, st));
+  if (h->d_Ulo) TRY(hipMemsetAsync(h->d_Ulo, 0, nL * sizeof(float), st));
   TRY(hipStreamSynchronize(st));
 #undef TRY
   *out = h;
@@ -344,6 +357,7 @@ template <typename T> HsArgs<T> hs_args(mplpxx_solver* h, double* trace) {
   a.tables = static_cast<const T*>(h->d_tables);
   a.phi = static_cast<T*>(h->d_phi);
   a.U = static_cast<T*>(h->d_U);
+  a.Ulo = sizeof(T) == 4 ? reinterpret_cast<T*>(h->d_Ulo) : nullptr;
   a.slots = h->d_slots;
   a.deg = h->d_deg;
   a.ver = h->d_ver;
@@ -366,16 +380,20 @@ template <typename T> int iterate_t(mplpxx_solver* h, int k, double* trace_host)
     HIP_TRY(hipMalloc(&h->d_stamps, (size_t)h->m * kStampStride * sizeof(long long)));
     HIP_TRY(hipMemsetAsync(h->d_stamps, 0, (size_t)h->m * kStampStride * sizeof(long long), st));
   }
+  // FP32 traces add the edge terms of Eq. (3): rounding-level numbers, but
+  // with a bias, so over many edges they matter at the 1e-5 level
+  constexpr int kTraceW = 8;  // partial minima per slot (waves of the mailbox engine, at most 8)
+  const bool edge_terms = sizeof(T) == 4 && h->m > 0;
   if (trace_host && k > h->trace_cap) {
-    if (h->d_trace_nodes) (void)hipFree(h->d_trace_nodes);
-    if (h->d_trace_out) (void)hipFree(h->d_trace_out);
-    h->d_trace_nodes = nullptr;
-    h->d_trace_out = nullptr;
+    for (void** p : {(void**)&h->d_trace_nodes, (void**)&h->d_trace_out, (void**)&h->d_trace_e})
+      if (*p) { (void)hipFree(*p); *p = nullptr; }
     h->trace_cap = 0;
     HIP_TRY(hipMalloc(&h->d_trace_nodes, (size_t)k * h->n * sizeof(double)));
     HIP_TRY(hipMalloc(&h->d_trace_out, (size_t)k * sizeof(double)));
+    if (edge_terms) HIP_TRY(hipMalloc(&h->d_trace_e, (size_t)k * h->m * kTraceW * sizeof(float)));
     h->trace_cap = k;
   }
+  int trace_w = 1;
   const int engine = h->engine();
   const int LT = h->LT(), NT = h->NT();
   HIP_TRY(hipEventRecord(h->ev0, st));
@@ -387,19 +405,28 @@ template <typename T> int iterate_t(mplpxx_solver* h, int k, double* trace_host)
           const int b = h->step_ptr[s], c = h->step_ptr[s + 1] - b;
           HIP_TRY(launch_handshake<T>(a, ENGINE_STEP, LT, NT, b, c, 0, 1, st));
         }
-        if (trace_host)
-          HIP_TRY(launch_trace_nodes<T>(static_cast<const T*>(h->d_U), h->n, h->L, h->d_trace_nodes + (size_t)it * h->n, st));
+        if (trace_host) {
+          HIP_TRY(launch_trace_nodes<T>(static_cast<const T*>(h->d_U), a.Ulo, h->n, h->L,
+                                        h->d_trace_nodes + (size_t)it * h->n, st));
+          if (edge_terms)
+            HIP_TRY(launch_trace_edges<T>(static_cast<const T*>(h->d_tables), static_cast<const T*>(h->d_phi), h->m,
+                                          h->L, h->d_trace_e + (size_t)it * h->m, st));
+        }
       }
     } else if (sizeof(T) == 4) {
       // FP32: tagged mailboxes; messages stay in LDS when they fit
       HsArgs<float> a = hs_args<float>(h, trace_host ? h->d_trace_nodes : nullptr);
+      if (trace_host) {
+        a.trace_e = h->d_trace_e;
+        trace_w = NT / 64;
+      }
       const int G = h->grid();
       const size_t owned = ((size_t)h->m + G - 1) / G;
       const size_t phi_bytes = owned * 2 * h->L * sizeof(float);
       const int in_lds = phi_bytes <= kPhiLdsBudget ? 1 : 0;
-      HIP_TRY(launch_mb_init(static_cast<const float*>(h->d_U), h->d_mb, (size_t)h->n * h->L, st));
+      HIP_TRY(launch_mb_init(static_cast<const float*>(h->d_U), h->d_Ulo, h->d_mb, (size_t)h->n * h->L, st));
       HIP_TRY(launch_persistent_mb(a, h->d_mb, LT, NT, G, k, in_lds, in_lds ? phi_bytes : 0, st));
-      HIP_TRY(launch_mb_fini(static_cast<float*>(h->d_U), h->d_mb, h->n, h->L,
+      HIP_TRY(launch_mb_fini(static_cast<float*>(h->d_U), h->d_Ulo, h->d_mb, h->n, h->L,
                              trace_host ? h->d_trace_nodes + (size_t)(k - 1) * h->n : nullptr, st));
     } else {
       HsArgs<T> a = hs_args<T>(h, trace_host ? h->d_trace_nodes : nullptr);
@@ -411,8 +438,8 @@ template <typename T> int iterate_t(mplpxx_solver* h, int k, double* trace_host)
   h->timed = true;
   if (trace_host && k > 0) {
     // nodes without edges (all of them when m == 0) read U directly
-    HIP_TRY(launch_trace_sum<T>(h->d_trace_nodes, static_cast<const T*>(h->d_U), h->d_deg, h->n, h->L, k,
-                                h->d_trace_out, st));
+    HIP_TRY(launch_trace_sum<T>(h->d_trace_nodes, edge_terms ? h->d_trace_e : nullptr, h->m, trace_w,
+                                static_cast<const T*>(h->d_U), h->d_deg, h->n, h->L, k, h->d_trace_out, st));
   }
   h->iterations += k;
   if (!h->user_stream || trace_host) {
@@ -439,9 +466,10 @@ template <typename T> int adjoint_forward_t(mplpxx_solver* h, int K, int every, 
   const size_t nL = (size_t)h->n * h->L, mp = (size_t)h->m * 2 * h->L, esz = sizeof(T);
   const int nck = (K + every - 1) / every;
   // (re)allocate checkpoint and record storage
-  for (void** p : {&h->d_ck_U, &h->d_ck_phi, (void**)&h->d_rec})
+  for (void** p : {&h->d_ck_U, &h->d_ck_phi, (void**)&h->d_rec, (void**)&h->d_ck_Ulo})
     if (*p) { (void)hipFree(*p); *p = nullptr; }
   HIP_TRY(hipMalloc(&h->d_ck_U, (nck + 1) * nL * esz));
+  if (h->d_Ulo) HIP_TRY(hipMalloc((void**)&h->d_ck_Ulo, (nck + 1) * nL * sizeof(float)));
   HIP_TRY(hipMalloc(&h->d_ck_phi, std::max<size_t>(1, (nck + 1) * mp * esz)));
   HIP_TRY(hipMalloc(&h->d_rec, std::max<size_t>(1, (size_t)every * h->m * 3 * h->L)));
   if (!h->d_Ub) HIP_TRY(hipMalloc(&h->d_Ub, nL * esz));
@@ -457,18 +485,25 @@ template <typename T> int adjoint_forward_t(mplpxx_solver* h, int K, int every, 
   HIP_TRY(hipStreamSynchronize(st));
   HIP_TRY(hipMemsetAsync(h->d_phi, 0, mp * esz, st));
   HIP_TRY(hipMemcpyAsync(h->d_U, h->d_unaries, nL * esz, hipMemcpyDeviceToDevice, st));
+  if (h->d_Ulo) HIP_TRY(hipMemsetAsync(h->d_Ulo, 0, nL * sizeof(float), st));
   h->iterations = 0;
   for (int c = 0; c < nck; ++c) {
     HIP_TRY(hipMemcpyAsync((char*)h->d_ck_U + c * nL * esz, h->d_U, nL * esz, hipMemcpyDeviceToDevice, st));
+    if (h->d_Ulo)
+      HIP_TRY(hipMemcpyAsync(h->d_ck_Ulo + c * nL, h->d_Ulo, nL * sizeof(float), hipMemcpyDeviceToDevice, st));
     if (h->m) HIP_TRY(hipMemcpyAsync((char*)h->d_ck_phi + c * mp * esz, h->d_phi, mp * esz, hipMemcpyDeviceToDevice, st));
     const int seg = std::min(every, K - c * every);
     const int rc = iterate_t<T>(h, seg, nullptr);
     if (rc != MPLPXX_OK) return rc;
   }
   HIP_TRY(hipMemcpyAsync((char*)h->d_ck_U + nck * nL * esz, h->d_U, nL * esz, hipMemcpyDeviceToDevice, st));
+  if (h->d_Ulo)
+    HIP_TRY(hipMemcpyAsync(h->d_ck_Ulo + nck * nL, h->d_Ulo, nL * sizeof(float), hipMemcpyDeviceToDevice, st));
   if (h->m) HIP_TRY(hipMemcpyAsync((char*)h->d_ck_phi + nck * mp * esz, h->d_phi, mp * esz, hipMemcpyDeviceToDevice, st));
   // loss = sum_u min_s U_u in FP64 (node minima, then a fixed-order sum)
-  HIP_TRY(launch_adj_seed<T>(static_cast<const T*>(h->d_U), h->n, h->L, static_cast<T*>(h->d_Ub), h->d_node_min, st));
+  const T* lo = sizeof(T) == 4 ? reinterpret_cast<const T*>(h->d_Ulo) : nullptr;
+  HIP_TRY(launch_adj_seed<T>(static_cast<const T*>(h->d_U), lo, h->n, h->L, static_cast<T*>(h->d_Ub), h->d_node_min,
+                             st));
   HIP_TRY(hipStreamSynchronize(st));
   h->adj_K = K;
   h->adj_every = every;
@@ -476,12 +511,15 @@ template <typename T> int adjoint_forward_t(mplpxx_solver* h, int K, int every, 
   h->adj_ready = true;
   h->adj_iter_mark = h->iterations;
   if (loss) {
-    // fixed-order FP64 sum of the node minima
-    std::vector<double> mins(h->n);
-    HIP_TRY(hipMemcpy(mins.data(), h->d_node_min, h->n * sizeof(double), hipMemcpyDeviceToHost));
-    double acc = 0.0;
-    for (double v : mins) acc += v;
-    *loss = acc;
+    // the loss is the dual bound of Eq. (3) of the final state, recomputed
+    // in FP64 from the messages; it differs from sum_u min_s U_u only by the
+    // edge terms, which are zero in exact arithmetic (so they add nothing to
+    // the gradient) and rounding-level numbers in FP32
+    HIP_TRY(launch_dual<T>(static_cast<const T*>(h->d_unaries), static_cast<const T*>(h->d_tables),
+                           static_cast<const T*>(h->d_phi), h->d_node_ptr, h->d_inc, h->n, h->L, h->m, h->d_node_min,
+                           h->d_edge_min, h->d_scalar, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(hipMemcpy(loss, h->d_scalar, sizeof(double), hipMemcpyDeviceToHost));
   }
   return MPLPXX_OK;
 }
@@ -491,9 +529,12 @@ template <typename T> int adjoint_backward_t(mplpxx_solver* h, void* grad_u, voi
   const size_t nL = (size_t)h->n * h->L, mp = (size_t)h->m * 2 * h->L, esz = sizeof(T);
   const int K = h->adj_K, every = h->adj_every, nck = h->adj_nck;
   const size_t rec_it = (size_t)h->m * 3 * h->L;
+  T* lo = sizeof(T) == 4 ? reinterpret_cast<T*>(h->d_Ulo) : nullptr;
+  const T* ck_lo = sizeof(T) == 4 ? reinterpret_cast<const T*>(h->d_ck_Ulo) : nullptr;
   // seed from the final state
-  HIP_TRY(launch_adj_seed<T>(static_cast<const T*>((const void*)((char*)h->d_ck_U + nck * nL * esz)), h->n, h->L,
-                             static_cast<T*>(h->d_Ub), h->d_node_min, st));
+  HIP_TRY(launch_adj_seed<T>(static_cast<const T*>((const void*)((char*)h->d_ck_U + nck * nL * esz)),
+                             ck_lo ? ck_lo + nck * nL : nullptr, h->n, h->L, static_cast<T*>(h->d_Ub),
+                             h->d_node_min, st));
   if (h->m) {
     HIP_TRY(hipMemsetAsync(h->d_pb, 0, mp * esz, st));
     HIP_TRY(hipMemsetAsync(h->d_thb, 0, (size_t)h->m * h->L * h->L * esz, st));
@@ -501,11 +542,12 @@ template <typename T> int adjoint_backward_t(mplpxx_solver* h, void* grad_u, voi
   for (int c = nck - 1; c >= 0 && h->m > 0; --c) {
     const int seg = std::min(every, K - c * every);
     HIP_TRY(hipMemcpyAsync(h->d_U, (char*)h->d_ck_U + c * nL * esz, nL * esz, hipMemcpyDeviceToDevice, st));
+    if (lo) HIP_TRY(hipMemcpyAsync(lo, ck_lo + c * nL, nL * esz, hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipMemcpyAsync(h->d_phi, (char*)h->d_ck_phi + c * mp * esz, mp * esz, hipMemcpyDeviceToDevice, st));
     for (int i = 0; i < seg; ++i)
       for (int s = 0; s < h->S; ++s)
         HIP_TRY(launch_step_record<T>(static_cast<const T*>(h->d_tables), static_cast<T*>(h->d_phi),
-                                      static_cast<T*>(h->d_U), h->d_slots, h->L, h->step_ptr[s],
+                                      static_cast<T*>(h->d_U), lo, h->d_slots, h->L, h->step_ptr[s],
                                       h->step_ptr[s + 1] - h->step_ptr[s], h->d_rec + i * rec_it, st));
     for (int i = seg - 1; i >= 0; --i)
       for (int s = h->S - 1; s >= 0; --s)
@@ -519,11 +561,23 @@ template <typename T> int adjoint_backward_t(mplpxx_solver* h, void* grad_u, voi
     HIP_TRY(launch_pack_tables<T>(static_cast<const T*>(h->d_thb), static_cast<T*>(grad_pw), h->d_slot_of_edge,
                                   h->d_edge_flip, h->m, h->L, st));
   HIP_TRY(hipMemcpyAsync(h->d_U, (char*)h->d_ck_U + nck * nL * esz, nL * esz, hipMemcpyDeviceToDevice, st));
+  if (lo) HIP_TRY(hipMemcpyAsync(lo, ck_lo + nck * nL, nL * esz, hipMemcpyDeviceToDevice, st));
   if (h->m) HIP_TRY(hipMemcpyAsync(h->d_phi, (char*)h->d_ck_phi + nck * mp * esz, mp * esz, hipMemcpyDeviceToDevice, st));
   HIP_TRY(hipStreamSynchronize(st));
   return MPLPXX_OK;
 }
 
+}  // namespace
+
+namespace {
+// nearest bf16 value, ties to even (the rounding the device applies to U_comp)
+float bf16_round_host(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  u = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
+  std::memcpy(&x, &u, 4);
+  return x;
+}
 }  // namespace
 
 extern "C" {
@@ -650,11 +704,17 @@ int mplpxx_schedule(int32_t n, int64_t m, const int32_t* edges, int32_t* n_steps
   return MPLPXX_OK;
 }
 
-int mplpxx_get_state(mplpxx_solver* h, void* U, void* phi) {
+int mplpxx_get_state(mplpxx_solver* h, void* U, void* phi, float* U_comp) {
   if (!h) return fail(MPLPXX_EINVAL, "handle is NULL");
   HIP_TRY(hipStreamSynchronize(h->stream()));
   const size_t esz = h->esz, L = h->L;
   if (U) HIP_TRY(hipMemcpy(U, h->d_U, (size_t)h->n * L * esz, hipMemcpyDeviceToHost));
+  if (U_comp) {
+    if (h->d_Ulo)
+      HIP_TRY(hipMemcpy(U_comp, h->d_Ulo, (size_t)h->n * L * sizeof(float), hipMemcpyDeviceToHost));
+    else
+      std::fill(U_comp, U_comp + (size_t)h->n * L, 0.0f);
+  }
   if (phi && h->m) {
     std::vector<char> tmp((size_t)h->m * 2 * L * esz);
     HIP_TRY(hipMemcpy(tmp.data(), h->d_phi, tmp.size(), hipMemcpyDeviceToHost));
@@ -665,13 +725,23 @@ int mplpxx_get_state(mplpxx_solver* h, void* U, void* phi) {
   return MPLPXX_OK;
 }
 
-int mplpxx_set_state(mplpxx_solver* h, const void* U, const void* phi) {
+int mplpxx_set_state(mplpxx_solver* h, const void* U, const void* phi, const float* U_comp) {
   if (!h) return fail(MPLPXX_EINVAL, "handle is NULL");
+  if (U_comp && !U) return fail(MPLPXX_EINVAL, "U_comp needs U");
+  if (U_comp && !h->d_Ulo) return fail(MPLPXX_EINVAL, "U_comp is for FP32 handles only");
   HIP_TRY(hipStreamSynchronize(h->stream()));
-  const size_t esz = h->esz, L = h->L;
+  const size_t esz = h->esz, L = h->L, nL = (size_t)h->n * L;
   if (U) {
-    if (!finite_host(U, (size_t)h->n * L, h->dtype)) return fail(MPLPXX_EINVAL, "non-finite U");
-    HIP_TRY(hipMemcpyAsync(h->d_U, U, (size_t)h->n * L * esz, hipMemcpyHostToDevice, h->stream()));
+    if (!finite_host(U, nL, h->dtype)) return fail(MPLPXX_EINVAL, "non-finite U");
+    if (U_comp && !finite_host(U_comp, nL, MPLPXX_F32)) return fail(MPLPXX_EINVAL, "non-finite U_comp");
+    HIP_TRY(hipMemcpyAsync(h->d_U, U, nL * esz, hipMemcpyHostToDevice, h->stream()));
+    if (h->d_Ulo) {
+      std::vector<float> lo(nL, 0.0f);
+      if (U_comp)
+        for (size_t i = 0; i < nL; ++i) lo[i] = bf16_round_host(U_comp[i]);
+      HIP_TRY(hipMemcpyAsync(h->d_Ulo, lo.data(), nL * sizeof(float), hipMemcpyHostToDevice, h->stream()));
+      HIP_TRY(hipStreamSynchronize(h->stream()));
+    }
     HIP_TRY(hipStreamSynchronize(h->stream()));
   }
   if (phi && h->m) {

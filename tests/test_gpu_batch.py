@@ -37,7 +37,7 @@ def _alone(model, iters):
     with M.Solver.from_model(model) as s:
         s.set_option(M.OPT_ENGINE, M.ENGINE_PERSISTENT)
         s.iterate(iters)
-        return s.get_state()
+        return s.get_state(comp=True)
 
 
 @pytest.mark.parametrize("with_big_labels", [False, True])
@@ -50,12 +50,13 @@ def test_batch_equals_single_model_runs_and_oracle(with_big_labels):
     with M.Batch(models) as b:
         b.iterate(iters)
         duals = b.dual_bounds()
-        states = [b.get_state(i) for i in range(len(models))]
+        states = [b.get_state(i, comp=True) for i in range(len(models))]
         assert b.info("count") == len(models)
     for i, mo in enumerate(models):
-        U, phi = _alone(mo, iters) if mo.m else (mo.unaries, np.zeros((0, 2, mo.L), np.float32))
+        U, phi, c = _alone(mo, iters) if mo.m else (mo.unaries, np.zeros((0, 2, mo.L), np.float32), 0 * mo.unaries)
         assert np.array_equal(states[i][0], U), (i, mo.name)
         assert np.array_equal(states[i][1], phi), (i, mo.name)
+        assert np.array_equal(states[i][2], c), (i, mo.name)
         st, ref = oracle.run_model(mo, iters)
         d_ref = ref[-1] if mo.m else st.dual()
         assert abs(duals[i] - d_ref) <= 1e-5 * max(1.0, abs(d_ref)), (i, duals[i], d_ref)
@@ -110,7 +111,7 @@ def test_single_and_batched_match_oracle_where_workgroups_own_one_or_two_slots(n
     model = W.pose(n, L, seed=n * 131 + L)
     iters = 6
     st, ref = oracle.run_model(model, iters)
-    U1, p1 = _alone(model, iters)
+    U1, p1, c1 = _alone(model, iters)
     with M.Solver.from_model(model) as s:
         s.set_option(M.OPT_ENGINE, M.ENGINE_PERSISTENT)
         s.iterate(iters)
@@ -118,9 +119,9 @@ def test_single_and_batched_match_oracle_where_workgroups_own_one_or_two_slots(n
     with M.Batch([model, W.pose(20, 8, seed=1)]) as b:
         b.iterate(iters)
         d2 = b.dual_bounds()[0]
-        U2, p2 = b.get_state(0)
+        U2, p2, c2 = b.get_state(0, comp=True)
     assert abs(d1 - ref[-1]) <= 1e-5 * max(1.0, abs(ref[-1])), (d1, ref[-1])
-    assert np.array_equal(U1, U2) and np.array_equal(p1, p2)
+    assert np.array_equal(U1, U2) and np.array_equal(p1, p2) and np.array_equal(c1, c2)
     assert d1 == d2
 
 

@@ -102,25 +102,32 @@ def test_engines_and_tunings_are_bitwise_identical():
             s.set_option(M.OPT_THREADS, threads)
             s.set_option(M.OPT_GRID, grid)
             s.iterate(6)
-            states.append(s.get_state())
-    for U, phi in states[1:]:
+            states.append(s.get_state(comp=True))
+    for U, phi, c in states[1:]:
         assert np.array_equal(U, states[0][0]) and np.array_equal(phi, states[0][1])
+        assert np.array_equal(c, states[0][2])
 
 
-def test_checkpoint_resume_is_bitwise():
+@pytest.mark.parametrize("engine", [1, 2])
+def test_checkpoint_resume_is_bitwise(engine):
+    """State = (U, U_comp, phi): handing all three back resumes bit for bit,
+    also across engines."""
     model = W.pose(30, 32, seed=12)
-    _announce("resume")
+    _announce("resume", engine)
     with M.Solver.from_model(model) as a:
         a.iterate(10)
-        Ua, pa = a.get_state()
+        Ua, pa, ca = a.get_state(comp=True)
     with M.Solver.from_model(model) as b:
+        b.set_option(M.OPT_ENGINE, engine)
         b.iterate(5)
-        U5, p5 = b.get_state()
+        U5, p5, c5 = b.get_state(comp=True)
+    assert np.any(c5 != 0)
     with M.Solver.from_model(model) as c:
-        c.set_state(U5, p5)
+        c.set_option(M.OPT_ENGINE, 3 - engine)
+        c.set_state(U5, p5, c5)
         c.iterate(5)
-        Uc, pc = c.get_state()
-    assert np.array_equal(Ua, Uc) and np.array_equal(pa, pc)
+        Uc, pc, cc = c.get_state(comp=True)
+    assert np.array_equal(Ua, Uc) and np.array_equal(pa, pc) and np.array_equal(ca, cc)
 
 
 def test_reversed_edges_and_device_create():
@@ -240,6 +247,10 @@ def test_pose_k200_l64_full_size_200_iterations_matches_stored_oracle():
         d = s.dual_bound()
         U, _ = s.get_state()
     ref = np.array(g["trace"])
+    print("max rel trace error", np.max(np.abs(tr - ref) / np.abs(ref)), "final", (d - ref[-1]) / ref[-1], flush=True)
     assert np.max(np.abs(tr - ref) / np.abs(ref)) <= 1e-5
     assert abs(d - ref[-1]) <= 1e-5 * abs(ref[-1])
+    # the trace (compensated node minima + exact edge terms) is the certified
+    # bound of the same state up to FP64 summation
+    assert abs(tr[-1] - d) <= 1e-9 * abs(d)
     assert np.max(np.abs(U.min(axis=1) - np.array(g["node_min"]))) <= 1e-4
