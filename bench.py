@@ -55,6 +55,64 @@ def cpu_baseline(model, iters_sample):
                       f"edges of each matching)", "seconds": dt, "s_per_iter": dt / iters_sample}
 
 
+def bench_batched(M, W, iters=100):
+    """The 256-model pose mix in one persistent launch vs the same models
+    solved one after another with per-problem launches (same engine family,
+    same iterations); device times from HIP events."""
+    import torch
+    models = W.batched_mix(256, seed=0)
+    m_tot = sum(mo.m for mo in models)
+    bytes_it = sum(mo.m * algorithmic_bytes_per_update(mo.L) for mo in models)
+    with M.Batch(models) as b:
+        b.iterate(2)                      # plan, capture the graph, warm up
+        b.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.iterate(iters)
+        wall_b = time.perf_counter() - t0
+        ms_b = b.info("last_ms")
+        info = {k: b.info(k) for k in ("grid", "tasks", "teams", "max_team", "lds_tasks", "lds_bytes")}
+        d_b = b.dual_bounds()
+    ms_p = 0.0
+    t0 = time.perf_counter()
+    d_p = []
+    for mo in models:
+        with M.Solver.from_model(mo) as s:
+            s.iterate(iters)
+            ms_p += s.last_iterate_ms()
+            d_p.append(s.dual_bound())
+    wall_p = time.perf_counter() - t0
+    return {"workload": "batched_mix: 256 pose models, n ~ U{20..300}, L ~ U{8..64}, seed 0", "iterations": iters,
+            "edges": m_tot, "batched_ms": ms_b, "batched_wall_s": wall_b, "per_problem_ms": ms_p,
+            "per_problem_wall_s_incl_create": wall_p, "speedup": ms_p / ms_b,
+            "updates_per_s": m_tot * iters / (ms_b / 1e3),
+            "hbm_frac": bytes_it * iters / (ms_b / 1e3) / 1e9 / HBM_PEAK_GBS,
+            "max_dual_diff_vs_per_problem": float(np.max(np.abs(np.asarray(d_b) - np.asarray(d_p)))),
+            "plan": info}
+
+
+def bench_adjoint(M, W, K=50, every=10):
+    """Forward (K iterations with checkpoints) and backward of the
+    differentiation workload on an FP32 handle."""
+    import torch
+    model = W.uniform(100, 32, seed=0)
+    out = {"workload": "uniform n=100 L=32 seed 0, FP32 costs", "K": K, "every": every}
+    for f64 in (1, 0):
+        with M.Solver.from_model(model) as s:
+            s.set_option(M.OPT_ADJOINT_F64, f64)
+            s.adjoint_forward(K, every)
+            s.adjoint_backward()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            loss = s.adjoint_forward(K, every)
+            t1 = time.perf_counter()
+            s.adjoint_backward()
+            t2 = time.perf_counter()
+        key = "fp64_twin" if f64 else "fp32_run"
+        out[key] = {"loss": loss, "forward_s": t1 - t0, "backward_s": t2 - t1}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,6 +122,8 @@ def main():
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -145,6 +205,10 @@ def main():
             "note": "iterations to reach D* - eps|D*| read from the GPU trace (the oracle's trace agrees to 1e-5); "
                     "oracle seconds = those iterations x its measured seconds per iteration"}
     s.close()
+    if not args.no_batch:
+        result["batched"] = bench_batched(M, W)
+    if not args.no_adjoint:
+        result["adjoint"] = bench_adjoint(M, W)
     print(json.dumps(result))
 
 

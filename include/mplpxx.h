@@ -183,6 +183,8 @@ int mplpxx_iterate_trace(mplpxx_solver* h, int32_t k, double* trace);
 #define MPLPXX_OPT_GRID 3        /* workgroups of the persistent engine (0 auto) */
 #define MPLPXX_OPT_SPIN_LIMIT 4  /* device wait bound in polls (0 default) */
 #define MPLPXX_OPT_PROFILE 5     /* 1: record per-slot timestamps (persistent FP32 engine) */
+#define MPLPXX_OPT_ADJOINT_F64 6 /* FP32 handles: 1 (default) differentiate an FP64 run on the same costs
+                                    (exactly widened); 0: differentiate the FP32 run itself */
 int mplpxx_set_option(mplpxx_solver* h, int32_t key, int64_t value);
 
 /* Read-only facts about the handle. */
@@ -220,7 +222,16 @@ int mplpxx_last_iterate_ms(mplpxx_solver* h, double* ms);
  * bound D_K of Eq. (3) of the final state (as mplpxx_dual_bound).  After the
  * last sweep every edge's reparametrized pairwise term has minimum zero
  * (Sec. 4, after (H)), so in exact arithmetic D_K = sum_u min_s U_u(s); the
- * gradient below is that of this sum. */
+ * gradient below is that of this sum.
+ *
+ * FP32 handles with MPLPXX_OPT_ADJOINT_F64 = 1 (the default) differentiate
+ * an FP64 run on the same costs (widened exactly, kept in a second, FP64
+ * state inside the handle), and `loss` is that run's D_K.  Reason: D_K is
+ * piecewise linear with kinks at every scale, and the FP32 run, which
+ * rounds at the 1e-7 level, selects a neighbouring linear piece for a few
+ * percent of the minimizers; its gradient is exact for the FP32 iterates
+ * but differs from the FP64 one by about 1% along a generic direction.  The
+ * handle's own FP32 state still ends at its FP32 run of K iterations. */
 int mplpxx_adjoint_forward(mplpxx_solver* h, int32_t K, int32_t every, double* loss);
 
 /* Gradient of D_K with respect to the input costs, by reverse sweeps over
@@ -281,6 +292,8 @@ int mplpxx_batch_reset(mplpxx_batch* b);
 #define MPLPXX_BOPT_EDGE32_US 7      /*                                   L <= 32 */
 #define MPLPXX_BOPT_EDGE64_US 8      /*                                   L <= 64 */
 #define MPLPXX_BOPT_EDGE128_US 9     /*                                   L <= 128 */
+#define MPLPXX_BOPT_LDS 10           /* 1 (default): a model on one workgroup keeps its unaries in LDS
+                                        when they fit; 0: always through the mailboxes */
 int mplpxx_batch_set_option(mplpxx_batch* b, int32_t key, double value);
 
 #define MPLPXX_BINFO_COUNT 1
@@ -292,6 +305,8 @@ int mplpxx_batch_set_option(mplpxx_batch* b, int32_t key, double value);
 #define MPLPXX_BINFO_EDGES 7         /* total edges */
 #define MPLPXX_BINFO_LAST_MS 8       /* device time of the last batch_iterate (HIP events) */
 #define MPLPXX_BINFO_TABLE_BYTES 9   /* bytes of pairwise tables */
+#define MPLPXX_BINFO_LDS_TASKS 10    /* models run with LDS-resident unaries */
+#define MPLPXX_BINFO_LDS_BYTES 11    /* dynamic LDS per workgroup of the launch */
 int mplpxx_batch_get_info(mplpxx_batch* b, int32_t key, double* value);
 
 /* Frees the batch and its device memory; NULL is a no-op. */

@@ -24,12 +24,12 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "mplpxx.h")
 F32, F64 = 0, 1
 OK, EINVAL, ENOMEM, EDEVICE, ETIMEOUT, ESTATE = 0, -1, -2, -3, -4, -5
 MAX_LABELS = 128
-OPT_ENGINE, OPT_THREADS, OPT_GRID, OPT_SPIN_LIMIT, OPT_PROFILE = 1, 2, 3, 4, 5
+OPT_ENGINE, OPT_THREADS, OPT_GRID, OPT_SPIN_LIMIT, OPT_PROFILE, OPT_ADJOINT_F64 = 1, 2, 3, 4, 5, 6
 ENGINE_AUTO, ENGINE_STEP, ENGINE_PERSISTENT = 0, 1, 2
 BOPT = {"grid": 1, "graph": 2, "spin_limit": 3, "one_per_model": 4, "handoff_us": 5, "edge16_us": 6,
-        "edge32_us": 7, "edge64_us": 8, "edge128_us": 9}
+        "edge32_us": 7, "edge64_us": 8, "edge128_us": 9, "lds": 10}
 BINFO = {"count": 1, "grid": 2, "tasks": 3, "teams": 4, "max_team": 5, "plan_us": 6, "edges": 7, "last_ms": 8,
-         "table_bytes": 9}
+         "table_bytes": 9, "lds_tasks": 10, "lds_bytes": 11}
 INFO = {"n": 1, "L": 2, "m": 3, "steps": 4, "dtype": 5, "engine": 6, "grid": 7, "threads": 8, "iterations": 9,
         "wallclock_khz": 10}
 

@@ -5,8 +5,10 @@
 // Planning.  The work of model b per iteration is modelled as
 //   t_b(T) = S_b * (t_hand + t_edge(LT_b) / 2) + (m_b / T) * t_edge(LT_b)
 // for a team of T workgroups (S_b matchings, each needing one cross-workgroup
-// handoff; m_b / T edge updates per member, one after another), and never
-// less than the member's share of HBM traffic.  The planner binary-searches a
+// handoff; m_b / T edge updates per member, one after another), as
+//   t_b = m_b * t_edge(LT_b)
+// for a model on one workgroup with its unaries in LDS (no handoffs), and
+// never less than the member's share of HBM traffic.  The planner binary-searches a
 // makespan tau: every model gets the smallest team with t_b(T) <= tau (at most
 // one member per edge of its largest matching), teams take workgroups first,
 // and single-workgroup models are packed onto the least-loaded workgroups
@@ -55,6 +57,7 @@ struct mplpxx_batch {
   int* d_task_ptr = nullptr;
   int* d_err = nullptr;
   int* d_ticket = nullptr;
+  unsigned long long* d_sink = nullptr;  // [grid][384] scratch words of the workgroups
   int* d_node_model = nullptr;
   int* d_slot_model = nullptr;
   int* d_node_ptr = nullptr;
@@ -71,6 +74,10 @@ struct mplpxx_batch {
   double t_hand_us = 0.7;
   double t_edge_us[4] = {0.30, 0.45, 0.85, 2.0};  // LT 16, 32, 64, 128
   int one_per_model = 0;
+  int use_lds = 1;             // LDS-resident unaries for models on one workgroup
+  size_t lds_limit = 0;        // dynamic LDS a workgroup can have
+  size_t lds_bytes = 0;        // dynamic LDS of the launch
+  int lds_tasks = 0;
   bool plan_dirty = true;
   // execution
   hipStream_t stream = nullptr;
@@ -87,11 +94,15 @@ namespace {
 
 int lt_index(int lt) { return lt == 16 ? 0 : lt == 32 ? 1 : lt == 64 ? 2 : 3; }
 
+bool lds_fits(const mplpxx_batch* b, int i) {
+  return b->use_lds && lds_model_bytes(b->mh[i].n, b->mh[i].L) <= b->lds_limit;
+}
+
 double model_time(const mplpxx_batch* b, int i, int T, double bw_per_wg_bytes_us) {
   const ModelHost& h = b->mh[i];
   if (h.m == 0) return 0.0;
   const double te = b->t_edge_us[lt_index(h.lt)];
-  const double lat = h.S * (b->t_hand_us + 0.5 * te) + (double)h.m / T * te;
+  const double lat = (T == 1 && lds_fits(b, i)) ? h.m * te : h.S * (b->t_hand_us + 0.5 * te) + (double)h.m / T * te;
   const double bytes = (double)h.m * (4.0 * h.L * h.L + 16.0 * h.L) / T;
   return std::max(lat, bytes / bw_per_wg_bytes_us);
 }
@@ -152,7 +163,7 @@ double assign(const mplpxx_batch* b, double tau, int G, int team_cap, double bw,
   for (int i : singles) {
     Item it = pq.top();
     pq.pop();
-    wg_tasks[it.second].push_back(BatchTask{i, 0, 1, 0});
+    wg_tasks[it.second].push_back(BatchTask{i, 0, 1, lds_fits(b, i) ? 1 : 0});
     it.first += model_time(b, i, 1, bw);
     load[it.second] = it.first;
     pq.push(it);
@@ -161,7 +172,11 @@ double assign(const mplpxx_batch* b, double tau, int G, int team_cap, double bw,
 }
 
 int plan(mplpxx_batch* b) {
-  const int per_cu = batch_blocks_per_cu(b->max_lt);
+  // dynamic LDS: enough for the largest model that could keep its unaries there
+  size_t dyn = 0;
+  for (int i = 0; i < b->count; ++i)
+    if (b->mh[i].m > 0 && lds_fits(b, i)) dyn = std::max(dyn, lds_model_bytes(b->mh[i].n, b->mh[i].L));
+  const int per_cu = batch_blocks_per_cu(b->max_lt, dyn);
   if (per_cu < 1) return fail(MPLPXX_EDEVICE, "batched kernel does not fit on a compute unit");
   const int gmax = per_cu * b->num_cus;
   int G = b->grid_opt > 0 ? std::min(b->grid_opt, gmax) : gmax;
@@ -204,8 +219,11 @@ int plan(mplpxx_batch* b) {
   }
   if (b->d_tasks) (void)hipFree(b->d_tasks);
   if (b->d_task_ptr) (void)hipFree(b->d_task_ptr);
+  if (b->d_sink) (void)hipFree(b->d_sink);
   b->d_tasks = nullptr;
   b->d_task_ptr = nullptr;
+  b->d_sink = nullptr;
+  HIP_TRY(hipMalloc(&b->d_sink, (size_t)G * (256 + 128) * sizeof(unsigned long long)));
   HIP_TRY(hipMalloc(&b->d_tasks, std::max<size_t>(1, tasks.size()) * sizeof(BatchTask)));
   HIP_TRY(hipMalloc(&b->d_task_ptr, (G + 1) * sizeof(int)));
   // every copy and fill goes through the batch's own (non-blocking) stream, so
@@ -215,6 +233,9 @@ int plan(mplpxx_batch* b) {
   HIP_TRY(hipMemcpyAsync(b->d_task_ptr, ptr.data(), (G + 1) * sizeof(int), hipMemcpyHostToDevice, b->stream));
   HIP_TRY(hipStreamSynchronize(b->stream));
   b->grid = G;
+  b->lds_bytes = dyn;
+  b->lds_tasks = 0;
+  for (const BatchTask& t : tasks) b->lds_tasks += t.lds;
   b->ntasks = (int)tasks.size();
   b->nteams = bt;
   b->max_team = bm;
@@ -230,7 +251,7 @@ int plan(mplpxx_batch* b) {
 
 void free_batch(mplpxx_batch* b) {
   void* ptrs[] = {b->d_tables, b->d_phi, b->d_U, b->d_Ulo, b->d_unaries, b->d_mb, b->d_slots, b->d_deg, b->d_models,
-                  b->d_tasks, b->d_task_ptr, b->d_err, b->d_ticket, b->d_node_model, b->d_slot_model, b->d_node_ptr,
+                  b->d_tasks, b->d_task_ptr, b->d_err, b->d_ticket, b->d_sink, b->d_node_model, b->d_slot_model, b->d_node_ptr,
                   b->d_inc, b->d_node_min, b->d_edge_min, b->d_duals};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -251,13 +272,14 @@ hipError_t enqueue(mplpxx_batch* b, int k) {
   a.tasks = b->d_tasks;
   a.task_ptr = b->d_task_ptr;
   a.ticket = b->d_ticket;
+  a.sink = b->d_sink;
   a.err = b->d_err;
   a.spin_limit = b->spin_limit;
   hipError_t e = launch_fill_int(b->d_ticket, 0, 1, b->stream);
   if (e != hipSuccess) return e;
   e = launch_u_to_mb(b->d_U, b->d_Ulo, b->d_mb, (size_t)b->total_u, b->stream);
   if (e != hipSuccess) return e;
-  e = launch_batch(a, b->max_lt, b->grid, k, b->stream);
+  e = launch_batch(a, b->max_lt, b->grid, k, b->lds_bytes, b->stream);
   if (e != hipSuccess) return e;
   return launch_mb_to_u(b->d_U, b->d_Ulo, b->d_mb, (size_t)b->total_u, b->stream);
 }
@@ -345,6 +367,7 @@ int mplpxx_batch_create(int32_t count, const int32_t* n, const int32_t* L, const
   int dev = 0;
   TRY(hipGetDevice(&dev));
   TRY(hipDeviceGetAttribute(&b->num_cus, hipDeviceAttributeMultiprocessorCount, dev));
+  b->lds_limit = batch_lds_limit(b->max_lt);
   TRY(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
   TRY(hipEventCreate(&b->ev0));
   TRY(hipEventCreate(&b->ev1));
@@ -539,6 +562,10 @@ int mplpxx_batch_set_option(mplpxx_batch* b, int32_t key, double value) {
       b->one_per_model = value != 0;
       b->plan_dirty = true;
       return MPLPXX_OK;
+    case MPLPXX_BOPT_LDS:
+      b->use_lds = value != 0;
+      b->plan_dirty = true;
+      return MPLPXX_OK;
     case MPLPXX_BOPT_HANDOFF_US:
       if (!(value > 0)) return fail(MPLPXX_EINVAL, "handoff time must be > 0");
       b->t_hand_us = value;
@@ -573,6 +600,8 @@ int mplpxx_batch_get_info(mplpxx_batch* b, int32_t key, double* value) {
     case MPLPXX_BINFO_EDGES: *value = b->total_slots; return MPLPXX_OK;
     case MPLPXX_BINFO_LAST_MS: *value = b->last_ms; return MPLPXX_OK;
     case MPLPXX_BINFO_TABLE_BYTES: *value = (double)b->total_tables * sizeof(float); return MPLPXX_OK;
+    case MPLPXX_BINFO_LDS_TASKS: *value = b->lds_tasks; return MPLPXX_OK;
+    case MPLPXX_BINFO_LDS_BYTES: *value = (double)b->lds_bytes; return MPLPXX_OK;
     default: return fail(MPLPXX_EINVAL, "unknown batch info key %d", key);
   }
 }

@@ -4,7 +4,10 @@
 // engine (device_common.h).  A large model is split over a team of
 // workgroups (stride = team size, each member's first task, so the whole team
 // runs at once); small models are packed, one after another, into single
-// workgroups.  The host plans the tasks (batch.cpp).
+// workgroups.  A model that runs on one workgroup and whose unaries fit in
+// LDS keeps them there for the launch (no mailbox traffic, no waiting: the
+// workgroup orders its own updates with barriers).  The host plans the tasks
+// (batch.cpp).
 #include "device_common.h"
 
 namespace mplpxx {
@@ -18,12 +21,40 @@ template <int NT, int MAXLT> union BatchSmem {
 
 template <int LT, int NT>
 __device__ __forceinline__ bool run_task(const BatchArgs& b, const BatchModel& md, const BatchTask& task,
-                                         SmemMB<LT, NT>& sm, int iters) {
+                                         SmemMB<LT, NT>& sm, int iters, unsigned char* dyn) {
   if (threadIdx.x == 0) sm.abort_flag = 0;
+  MbView v{b.tables + uni(md.table_off), b.phi + uni(md.phi_off), b.mb + uni(md.u_off), b.slots + uni(md.slot_off),
+           b.deg + uni(md.node_off), nullptr, nullptr, nullptr, uni(md.L), uni(md.m), uni(md.n), nullptr, nullptr,
+           b.sink + (size_t)blockIdx.x * (NT + 128)};
+  // messages prefetched with the tables when the task owns at least
+  // DEPTH + 2 slots
+  constexpr int kDepth = LT <= 64 ? 2 : 1;
+  const int owned = (md.m - task.first + task.stride - 1) / task.stride;
+  const bool far = owned >= kDepth + 2;
+  if (!task.lds) {
+    __syncthreads();
+    return far ? mb_run<LT, NT, false, false, false, false, true>(v, task.first, task.stride, iters, sm, nullptr,
+                                                                  b.spin_limit, b.err)
+               : mb_run<LT, NT, false, false, false, false, false>(v, task.first, task.stride, iters, sm, nullptr,
+                                                                   b.spin_limit, b.err);
+  }
+  // the model's unaries into LDS (hi, and lo as bf16 bits), run, and back
+  const int nl = md.n * md.L;
+  v.lds_hi = reinterpret_cast<float*>(dyn);
+  v.lds_lo = reinterpret_cast<unsigned short*>(dyn + lds_lo_offset(md.n, md.L));
+  for (int i = threadIdx.x; i < nl; i += blockDim.x) {
+    const unsigned long long w = v.mb[i];
+    v.lds_hi[i] = mb_hi(w);
+    v.lds_lo[i] = (unsigned short)(__float_as_uint(mb_lo(w)) >> 16);
+  }
   __syncthreads();
-  MbView v{b.tables + md.table_off, b.phi + md.phi_off, b.mb + md.u_off, b.slots + md.slot_off,
-           b.deg + md.node_off, nullptr, nullptr, nullptr, md.L, md.m, md.n};
-  return mb_run<LT, NT, false, false, false>(v, task.first, task.stride, iters, sm, nullptr, b.spin_limit, b.err);
+  const bool ok = far ? mb_run<LT, NT, false, false, false, true, true>(v, 0, 1, iters, sm, nullptr, b.spin_limit, b.err)
+                     : mb_run<LT, NT, false, false, false, true, false>(v, 0, 1, iters, sm, nullptr, b.spin_limit,
+                                                                       b.err);
+  __syncthreads();
+  for (int i = threadIdx.x; i < nl; i += blockDim.x)
+    v.mb[i] = mb_pack(v.lds_hi[i], __uint_as_float((unsigned)v.lds_lo[i] << 16), 0u);
+  return ok;
 }
 
 // at least two waves per SIMD: one 6-wave workgroup per compute unit, with
@@ -32,6 +63,7 @@ template <int NT, int MAXLT>
 __global__ void __launch_bounds__(NT + 128, 2) k_batch(BatchArgs b, int iters) {
   __shared__ BatchSmem<NT, MAXLT> sm;
   __shared__ int s_wg;
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
   // logical workgroup = order of arrival: workgroups that hold a ticket have
   // started, so the first tickets (where the planner puts every team) run
   // together whatever order the hardware dispatches in
@@ -42,29 +74,46 @@ __global__ void __launch_bounds__(NT + 128, 2) k_batch(BatchArgs b, int iters) {
     const BatchTask task = b.tasks[t];
     const BatchModel md = b.models[task.model];
     bool ok = true;
-    if (md.lt == 16) ok = run_task<16, NT>(b, md, task, sm.s16, iters);
-    else if (md.lt == 32) ok = run_task<32, NT>(b, md, task, sm.s32, iters);
-    else if (md.lt == 64 || MAXLT == 64) ok = run_task<64, NT>(b, md, task, sm.s64, iters);
-    else ok = run_task<(MAXLT > 64 ? 128 : 64), NT>(b, md, task, sm.s128, iters);
+    if (md.lt == 16) ok = run_task<16, NT>(b, md, task, sm.s16, iters, dyn_lds);
+    else if (md.lt == 32) ok = run_task<32, NT>(b, md, task, sm.s32, iters, dyn_lds);
+    else if (md.lt == 64 || MAXLT == 64) ok = run_task<64, NT>(b, md, task, sm.s64, iters, dyn_lds);
+    else ok = run_task<(MAXLT > 64 ? 128 : 64), NT>(b, md, task, sm.s128, iters, dyn_lds);
     if (!ok) return;
     __syncthreads();  // shared memory is reused by the next task
   }
 }
 
-hipError_t launch_batch(const BatchArgs& b, int max_lt, int grid, int iters, hipStream_t st) {
+static const void* batch_kernel(int max_lt) {
+  return max_lt <= 64 ? (const void*)k_batch<256, 64> : (const void*)k_batch<256, 128>;
+}
+
+hipError_t launch_batch(const BatchArgs& b, int max_lt, int grid, int iters, size_t dyn_lds, hipStream_t st) {
   if (max_lt <= 64)
-    hipLaunchKernelGGL((k_batch<256, 64>), dim3(grid), dim3(256 + 128), 0, st, b, iters);
+    hipLaunchKernelGGL((k_batch<256, 64>), dim3(grid), dim3(256 + 128), dyn_lds, st, b, iters);
   else
-    hipLaunchKernelGGL((k_batch<256, 128>), dim3(grid), dim3(256 + 128), 0, st, b, iters);
+    hipLaunchKernelGGL((k_batch<256, 128>), dim3(grid), dim3(256 + 128), dyn_lds, st, b, iters);
   return hipGetLastError();
 }
 
-int batch_blocks_per_cu(int max_lt) {
+int batch_blocks_per_cu(int max_lt, size_t dyn_lds) {
   int nb = 0;
-  hipError_t e = max_lt <= 64
-                     ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_batch<256, 64>, 256 + 128, 0)
-                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_batch<256, 128>, 256 + 128, 0);
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel(max_lt), 256 + 128, dyn_lds);
   return e == hipSuccess ? nb : 0;
+}
+
+// largest dynamic LDS a workgroup of the batched kernel can have (raises the
+// kernel's limit to it)
+size_t batch_lds_limit(int max_lt) {
+  int dev = 0, per_block = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 0;
+  hipFuncAttributes fa{};
+  if (hipFuncGetAttributes(&fa, batch_kernel(max_lt)) != hipSuccess) return 0;
+  if ((size_t)per_block <= fa.sharedSizeBytes) return 0;
+  const size_t limit = (size_t)per_block - fa.sharedSizeBytes;
+  if (hipFuncSetAttribute(batch_kernel(max_lt), hipFuncAttributeMaxDynamicSharedMemorySize, (int)limit) != hipSuccess)
+    return 0;
+  return limit;
 }
 
 // mailbox <- (U, Ulo, version 0) and back

@@ -24,7 +24,7 @@ struct SlotInfo {
   int pos_v;   // same for v
   int deg_u;   // degree of u (updates of u per iteration)
   int deg_v;   // degree of v
-  int pad;
+  int step;    // index of its matching in the schedule
 };
 
 template <typename T> struct HsArgs {
@@ -39,6 +39,7 @@ template <typename T> struct HsArgs {
   double* trace;          // [iters][n] per-node minima after the node's last update, or null
   float* trace_e;         // [iters][m][W] FP32 mailbox engine: per-wave minima of the edge terms, or null
   long long* stamps;      // [m][4] wall-clock stamps of the last iteration, or null
+  unsigned long long* sink;  // FP32 mailbox engine: [grid][NT + 128] scratch words
   int L, m, n;
   long long spin_limit;
 };
@@ -60,7 +61,7 @@ struct BatchTask {
   int model;   // which model
   int first;   // first slot of the model this workgroup owns
   int stride;  // team size: the workgroup owns slots first, first+stride, ...
-  int pad;
+  int lds;     // 1: a whole model whose unaries live in this workgroup's LDS for the launch
 };
 struct BatchArgs {
   const float* tables;
@@ -72,11 +73,17 @@ struct BatchArgs {
   const BatchTask* tasks;
   const int* task_ptr;    // [G+1] task range of each logical workgroup
   int* ticket;            // start-order counter (zeroed before each launch)
+  unsigned long long* sink;  // [grid][NT + 128] scratch words
   int* err;
   long long spin_limit;
 };
-hipError_t launch_batch(const BatchArgs& b, int max_lt, int grid, int iters, hipStream_t st);
-int batch_blocks_per_cu(int max_lt);
+hipError_t launch_batch(const BatchArgs& b, int max_lt, int grid, int iters, size_t dyn_lds, hipStream_t st);
+int batch_blocks_per_cu(int max_lt, size_t dyn_lds);
+size_t batch_lds_limit(int max_lt);
+// LDS-resident unaries of one model in the batched engine: n*L hi values
+// (FP32), then, from this byte offset, n*L bf16 corrections
+__host__ __device__ inline size_t lds_lo_offset(int n, int L) { return ((size_t)n * L * 4 + 15) / 16 * 16; }
+__host__ __device__ inline size_t lds_model_bytes(int n, int L) { return lds_lo_offset(n, L) + (size_t)n * L * 2; }
 hipError_t launch_u_to_mb(const float* U, const float* Ulo, unsigned long long* mb, size_t count, hipStream_t st);
 hipError_t launch_mb_to_u(float* U, float* Ulo, const unsigned long long* mb, size_t count, hipStream_t st);
 hipError_t launch_batch_dual(const float* unaries, const float* tables, const float* phi, const BatchModel* models,
@@ -126,5 +133,7 @@ template <typename T>
 hipError_t launch_pack_tables(const T* src, T* dst, const int* slot_edge, const int* slot_flip, int m, int L,
                               hipStream_t st);
 hipError_t launch_fill_int(int* p, int value, size_t count, hipStream_t st);
+hipError_t launch_convert(const float* src, double* dst, size_t count, hipStream_t st);
+hipError_t launch_convert(const double* src, float* dst, size_t count, hipStream_t st);
 
 }  // namespace mplpxx

@@ -110,6 +110,35 @@ __device__ __forceinline__ void comp_update(float hi, float lo, float phi_old, f
   nlo = bf16_round(two_sum_err(s, c, nhi));
 }
 
+// Values every lane of the wave holds the same: readfirstlane tells the
+// compiler so, and loads through such pointers and indices become scalar
+// loads (scalar cache, lgkmcnt) instead of vector loads that share vmcnt with
+// the table prefetches.
+// (Offsets, not pointers: a pointer rebuilt from integers would lose its
+// address space and turn every access into a FLAT one.)
+//
+// ld_const: a load from data no thread writes during the kernel, through the
+// constant address space, so that a uniform address becomes one scalar load.
+__device__ __forceinline__ SlotInfo ld_const(const SlotInfo* p) {
+  const __attribute__((address_space(4))) int* q = (const __attribute__((address_space(4))) int*)p;
+  SlotInfo r;
+  r.e = q[0];
+  r.u = q[1];
+  r.v = q[2];
+  r.pos_u = q[3];
+  r.pos_v = q[4];
+  r.deg_u = q[5];
+  r.deg_v = q[6];
+  r.step = q[7];
+  return r;
+}
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ long long uni(long long x) {
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(unsigned long long)x);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)((unsigned long long)x >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
 // coherent (device-scope) accesses for data shared between workgroups
 __device__ __forceinline__ int ld_dev(const int* p) {
   return __hip_atomic_load(const_cast<int*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -137,6 +166,16 @@ template <typename T, int LT, int NT> struct TileShape {
   static constexpr int W = NT / 64;    // waves
   static_assert(BR >= 1 && BC >= 1 && RB * BR == LT, "tile shape");
 };
+
+// Table pad of the mailbox engine.  With pads = BIG = 2^126 and every real
+// value below 2^100 in magnitude, the three passes need no masks: a padded
+// column never wins a row minimum (BIG + a_v rounds to BIG); a padded row
+// gets p = BIG, b = -BIG/2 exactly, so it never wins a column minimum of a
+// real column (BIG - BIG/2 = BIG/2) and makes q = BIG/2 in every padded
+// column, which in turn never wins pass 3 (BIG - BIG/2).  All values stay
+// finite and every real minimum is the one over the real entries, so the
+// results are bitwise those of the unpadded tile.
+constexpr float kPadBig = 0x1p126f;
 
 // Loads the table of one slot into the register tile; pads take `pad`.
 template <typename T, int LT, int NT>
@@ -301,7 +340,94 @@ struct MbView {
   float* trace_e;               // [iters][m][W] per-wave minima of the edge terms, or null
   long long* stamps;            // [m][kStampStride] or null
   int L, m, n;
+  float* lds_hi;                // LDS-resident unaries (hi [n][L], lo as bf16 bits), or null
+  unsigned short* lds_lo;
+  unsigned long long* sink;     // this workgroup's scratch words [NT + 128] (see the output stores)
 };
+
+// The gather of the LDS-resident mode: hi, lo, centred values and reference
+// of one node from this workgroup's LDS copy of the unaries (no wait: the
+// workgroup itself produced them, ordered by its barriers).
+template <int LT>
+__device__ __forceinline__ void lds_gather(const float* hi_row, const unsigned short* lo_row, int L, float* dst_un,
+                                           float* dst_hi, float* dst_lo, float* dst_c) {
+  const int lane = threadIdx.x & 63;
+  constexpr int PER = (LT + 63) / 64;
+  float h[PER], l[PER];
+  float c = __builtin_inff();
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int s = lane + 64 * k;
+    const int sc = s < L ? s : L - 1;
+    h[k] = hi_row[sc];
+    l[k] = __uint_as_float((unsigned)lo_row[sc] << 16);
+    if (s < L) c = vmin(c, h[k]);
+  }
+  c = col4_min(row16_min(c));
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int s = lane + 64 * k;
+    if (s < L) {
+      dst_hi[s] = h[k];
+      dst_lo[s] = l[k];
+      dst_un[s] = (h[k] - c) + l[k];
+    }
+  }
+  if (lane == 0) *dst_c = c;
+}
+
+// Raw tile load for the mailbox engine: every lane loads, at clamped indices
+// (always inside the table), so no load is predicated and no destination
+// register is written twice; the pads are applied when the tile is used
+// (pad_tile).  A predicated load into a register that the pad value was
+// written to makes the compiler wait for every load in flight.
+template <int LT, int NT, bool FULL>
+__device__ __forceinline__ void load_tile_raw(const float* __restrict__ tab, int L,
+                                              float (&x)[TileShape<float, LT, NT>::BR][TileShape<float, LT, NT>::BC]) {
+  using S = TileShape<float, LT, NT>;
+  const int rb = threadIdx.x >> 4, cb = threadIdx.x & 15;
+  if (FULL && (S::BC % 4) == 0) {
+#pragma unroll
+    for (int i = 0; i < S::BR; ++i) {
+      const int s = rb * S::BR + i;
+#pragma unroll
+      for (int j = 0; j < S::BC; j += 4) {
+        const float4 v = *reinterpret_cast<const float4*>(tab + s * LT + cb * S::BC + j);
+        x[i][j] = v.x;
+        x[i][j + 1] = v.y;
+        x[i][j + 2] = v.z;
+        x[i][j + 3] = v.w;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < S::BR; ++i) {
+      const int s = rb * S::BR + i;
+      const int sc = (FULL || s < L) ? s : L - 1;
+#pragma unroll
+      for (int j = 0; j < S::BC; ++j) {
+        const int t = cb * S::BC + j;
+        const int tc = (FULL || t < L) ? t : L - 1;
+        x[i][j] = tab[sc * L + tc];
+      }
+    }
+  }
+}
+template <int LT, int NT, bool FULL>
+__device__ __forceinline__ void pad_tile(int L, float (&x)[TileShape<float, LT, NT>::BR][TileShape<float, LT, NT>::BC]) {
+  using S = TileShape<float, LT, NT>;
+  if (FULL) return;
+  const int rb = threadIdx.x >> 4, cb = threadIdx.x & 15;
+#pragma unroll
+  for (int i = 0; i < S::BR; ++i) {
+    const int s = rb * S::BR + i;
+#pragma unroll
+    for (int j = 0; j < S::BC; ++j) {
+      const int t = cb * S::BC + j;
+      x[i][j] = (s < L && t < L) ? x[i][j] : kPadBig;
+    }
+  }
+}
 
 // Messages of one slot for this thread's rows (into u) and columns (into v).
 template <int LT, int NT, bool PHI_LDS, bool FULL>
@@ -321,282 +447,363 @@ __device__ __forceinline__ void load_phi(const float* src, int L, float (&pu)[Ti
   }
 }
 
-// Table pad of the mailbox engine.  With pads = BIG = 2^126 and every real
-// value below 2^100 in magnitude, the three passes need no masks: a padded
-// column never wins a row minimum (BIG + a_v rounds to BIG); a padded row
-// gets p = BIG, b = -BIG/2 exactly, so it never wins a column minimum of a
-// real column (BIG - BIG/2 = BIG/2) and makes q = BIG/2 in every padded
-// column, which in turn never wins pass 3 (BIG - BIG/2).  All values stay
-// finite and every real minimum is the one over the real entries, so the
-// results are bitwise those of the unpadded tile.
-constexpr float kPadBig = 0x1p126f;
-
 // Runs `iters` iterations over the slots first, first+stride, ... of one
-// model.  Compute threads [0, NT) hold the table of the current slot in
-// registers and prefetch the next one together with its messages; threads
-// [NT, NT+128) are the two sync waves.  Returns false if a wait timed out
-// (the error word is set); every thread of the block returns the same value.
+// model: a flat sequence of owned*iters steps.  Compute threads [0, NT) hold
+// the table of the current step in registers; the tables of the next DEPTH
+// steps are in flight in a ring of DEPTH+1 register tiles whose roles rotate
+// (the loop is unrolled by the ring size, so no tile is ever copied and each
+// load has DEPTH steps to land).  The messages of the next step are
+// prefetched one step ahead.  Threads [NT, NT+128) are the two sync waves.
+// Returns false if a wait timed out (the error word is set); every thread of
+// the block returns the same value.
 //
 // Each new unary value (with its message) is finished by one compute lane:
 // row s = rb*BR + i by lane cb = i of row block rb, which holds r and the old
 // message for that row; the columns are shared out over the other lanes of
 // each wave, LT/W per wave, and each column lane keeps the old message of its
 // column in a register of its own.
-template <int LT, int NT, bool PHI_LDS, bool FULL, bool TRACE>
-__device__ __forceinline__ bool mb_run(const MbView& v, int first, int stride, int iters, SmemMB<LT, NT>& sm,
-                                       float* phi_lds, long long spin_limit, int* err) {
+//
+// LDSU: the whole model runs on this workgroup (first = 0, stride = 1) with
+// its unaries in LDS (v.lds_hi / v.lds_lo) instead of the mailboxes.  The
+// sync waves then read the next slot's nodes from LDS while the current slot
+// computes; that is safe inside a matching (its edges share no node), and
+// before the first slot of every matching all threads meet at one more
+// barrier, after the previous slot's results are written.
+template <int LT, int NT, bool PHI_LDS, bool FULL, bool TRACE, bool LDSU, bool PHI_FAR, int DEPTH = (LT <= 64 ? 2 : 1)>
+__device__ __forceinline__ bool mb_run(const MbView& v_in, int first_in, int stride_in, int iters_in,
+                                       SmemMB<LT, NT>& sm, float* phi_lds, long long spin_limit, int* err) {
   using S = TileShape<float, LT, NT>;
+  // sizes and positions are uniform over the workgroup (the pointers are
+  // formed from uniform offsets by the caller)
+  MbView v = v_in;
+  v.L = uni(v.L);
+  v.m = uni(v.m);
+  v.n = uni(v.n);
+  const int first = uni(first_in), stride = uni(stride_in), iters = uni(iters_in);
   const int tid = threadIdx.x;
   const int L = FULL ? LT : v.L;
   const int wave = tid >> 6;
-  const bool is_compute = tid < NT;
-  const bool is_sync_u = wave == NT / 64;
   const int rb = tid >> 4, cb = tid & 15, lane = tid & 63;
   if (first >= v.m) return true;
+  const int owned = (v.m - first + stride - 1) / stride;
+  const int total = owned * iters;
   auto phi_of = [&](int slot, int j) -> float* {
     return PHI_LDS ? phi_lds + (size_t)j * 2 * L : v.phi + (size_t)slot * 2 * L;
   };
-  // output lane of this thread (compute threads only)
+  // The two kinds of waves run separate loops with the same barriers per
+  // step (first barrier, mid-step barrier, and in the LDS-resident mode one
+  // more before each matching), so the compiler accounts for each loop's
+  // memory operations on their own.
+  if (tid >= NT) {
+    // ---- sync waves: wait for (or read) the step's two nodes ----
+    const bool is_sync_u = wave == NT / 64;
+    SlotInfo si = ld_const(v.slots + first);
+    int parity = 0, it = 0, j = 0;
+    for (int q = 0; q < total; ++q) {
+      const int slot = first + j * stride;
+      const unsigned want_u = (unsigned)(it * si.deg_u + si.pos_u);
+      const unsigned want_v = (unsigned)(it * si.deg_v + si.pos_v);
+      int nxt = slot + stride;
+      if (nxt >= v.m) nxt = first;
+      nxt = uni(nxt);
+      const bool last_iter = it == iters - 1;
+      const SlotInfo si_next = ld_const(v.slots + nxt);
+      if (v.stamps && last_iter && lane == 0 && is_sync_u) v.stamps[(size_t)slot * kStampStride + 0] = wall_clock64();
+      const int node = is_sync_u ? si.u : si.v;
+      const unsigned want = is_sync_u ? want_u : want_v;
+      float* dst = is_sync_u ? sm.uu[parity] : sm.uv[parity];
+      float* dst_hi = is_sync_u ? sm.uh[parity] : sm.vh[parity];
+      float* dst_lo = is_sync_u ? sm.ul[parity] : sm.vl[parity];
+      unsigned seen = 0;
+      if (LDSU) {
+        lds_gather<LT>(v.lds_hi + (size_t)node * L, v.lds_lo + (size_t)node * L, L, dst, dst_hi, dst_lo,
+                       &sm.cc[parity][is_sync_u ? 0 : 1]);
+      } else if (!sync_gather<LT>(v.mb + (size_t)node * L, L, want, dst, dst_hi, dst_lo,
+                                  &sm.cc[parity][is_sync_u ? 0 : 1], spin_limit, err, &seen)) {
+        if (lane == 0) {
+          // a wait may also end because another workgroup reported first
+          if (ld_dev(err) == 0 || seen != (want & 0xFFFFu)) report_timeout(err, slot, node, want & 0xFFFFu, seen);
+          sm.abort_flag = 1;
+        }
+      }
+      if (v.stamps && last_iter && lane == 0) v.stamps[(size_t)slot * kStampStride + (is_sync_u ? 1 : 2)] = wall_clock64();
+      __syncthreads();
+      if (sm.abort_flag) return false;
+      __syncthreads();  // the compute waves' mid-step barrier
+      // per-iteration trace: the first update of a node in iteration it
+      // sees the node's value at the end of iteration it-1
+      if (TRACE && it > 0) {
+        const bool first_upd = is_sync_u ? (si.pos_u == 0) : (si.pos_v == 0);
+        if (first_upd) {
+          const float* src = is_sync_u ? sm.uh[parity] : sm.vh[parity];
+          const float* src_lo = is_sync_u ? sm.ul[parity] : sm.vl[parity];
+          double mn = __builtin_inf();
+          for (int s2 = lane; s2 < L; s2 += 64) mn = __builtin_fmin(mn, (double)src[s2] + (double)src_lo[s2]);
+#pragma unroll
+          for (int o = 32; o >= 1; o >>= 1) mn = __builtin_fmin(mn, __shfl_xor(mn, o, 64));
+          if (lane == 0) v.trace[(size_t)(it - 1) * v.n + (is_sync_u ? si.u : si.v)] = mn;
+        }
+      }
+      // LDS-resident mode: the next slot starts a matching (or the next
+      // iteration) and may read what this slot wrote
+      if (LDSU && (si_next.step != si.step || nxt <= slot)) __syncthreads();
+      si = si_next;
+      parity ^= 1;
+      if (++j == owned) { j = 0; ++it; }
+    }
+    return true;
+  }
+
+  // ---- compute waves ----
+  // output lane of this thread
   constexpr int VPW = LT / S::W;
   static_assert(VPW <= 4 * (16 - S::BR), "column outputs per wave");
   const bool out_u = cb < S::BR;
   const int out_s = rb * S::BR + cb;
   const int lw = (rb & 3) * (16 - S::BR) + (cb - S::BR);
   const int out_t = wave * VPW + lw;
-  const bool out_v = is_compute && !out_u && lw < VPW && (FULL || out_t < L);
-  const bool out_uk = is_compute && out_u && (FULL || out_s < L);
+  const bool out_v = !out_u && lw < VPW && (FULL || out_t < L);
+  const bool out_uk = out_u && (FULL || out_s < L);
   const int out_i = out_u ? out_s : out_t;     // label of the output
   const int out_ic = out_i < L ? out_i : L - 1;  // in range for every lane
-  float x[S::BR][S::BC], y[S::BR][S::BC];
-  float pu[S::BR], pv[S::BC], npu[S::BR], npv[S::BC];
-  float pvo = 0.f, npvo = 0.f;  // old message of this lane's output column
-  if (is_compute) {
-    load_tile<float, LT, NT>(v.tables + (size_t)first * L * L, L, x, kPadBig);
-    load_phi<LT, NT, PHI_LDS, FULL>(phi_of(first, 0), L, pu, pv);
-    if (out_v) pvo = phi_of(first, 0)[L + out_t];
-  }
-  SlotInfo si = v.slots[first];
-  // slots owned: 1 -> the next slot is this one (its messages are the r, q
-  // just computed); 2 -> the next slot is the previous one, whose messages
-  // this workgroup wrote during the last slot: they are read after this
-  // slot's first barrier; >= 3 -> the next slot's messages were written two
-  // or more slots ago, behind two barriers, and are prefetched with its table.
-  // A column lane reads back only what it wrote itself, in program order.
-  const int owned = (v.m - first + stride - 1) / stride;
-  int parity = 0;
-  for (int it = 0; it < iters; ++it) {
-    int j = 0;
-    for (int slot = first; slot < v.m; slot += stride, ++j, parity ^= 1) {
-      const unsigned want_u = (unsigned)(it * si.deg_u + si.pos_u);
-      const unsigned want_v = (unsigned)(it * si.deg_v + si.pos_v);
-      int nxt = slot + stride, jn = j + 1;
-      if (nxt >= v.m) { nxt = first; jn = 0; }
-      const bool pref = nxt != slot && (it + 1 < iters || nxt > slot);
-      const bool last_iter = it == iters - 1;
-      // metadata of the next owned slot, off the dependency chain
-      const SlotInfo si_next = v.slots[nxt];
-      if (is_compute) {
-        // table of the next owned slot (its messages follow after the barrier,
-        // once this workgroup's earlier writes to them are ordered)
-        if (pref) {
-          load_tile<float, LT, NT>(v.tables + (size_t)nxt * L * L, L, y, kPadBig);
-          // (the very first slot's successor has not been written in this launch)
-          if (owned >= 3 || (it == 0 && j == 0)) load_phi<LT, NT, PHI_LDS, FULL>(phi_of(nxt, jn), L, npu, npv);
-          if (out_v) npvo = phi_of(nxt, jn)[L + out_t];
-        }
-#if MPLPXX_FINE_STAMPS
-        if (v.stamps && last_iter && tid == 0) v.stamps[(size_t)slot * kStampStride + 4] = wall_clock64();
-#endif
-      } else {
-        if (v.stamps && last_iter && lane == 0 && is_sync_u) v.stamps[(size_t)slot * kStampStride + 0] = wall_clock64();
-        const int node = is_sync_u ? si.u : si.v;
-        const unsigned want = is_sync_u ? want_u : want_v;
-        float* dst = is_sync_u ? sm.uu[parity] : sm.uv[parity];
-        float* dst_hi = is_sync_u ? sm.uh[parity] : sm.vh[parity];
-        float* dst_lo = is_sync_u ? sm.ul[parity] : sm.vl[parity];
-        unsigned seen = 0;
-        if (!sync_gather<LT>(v.mb + (size_t)node * L, L, want, dst, dst_hi, dst_lo, &sm.cc[parity][is_sync_u ? 0 : 1],
-                             spin_limit, err, &seen)) {
-          if (lane == 0) {
-            // a wait may also end because another workgroup reported first
-            if (ld_dev(err) == 0 || seen != (want & 0xFFFFu)) report_timeout(err, slot, node, want & 0xFFFFu, seen);
-            sm.abort_flag = 1;
-          }
-        }
-        if (v.stamps && last_iter && lane == 0) v.stamps[(size_t)slot * kStampStride + (is_sync_u ? 1 : 2)] = wall_clock64();
-      }
-      __syncthreads();
-      if (sm.abort_flag) return false;
-      if (is_compute && pref && owned == 2 && !(it == 0 && j == 0))
-        load_phi<LT, NT, PHI_LDS, FULL>(phi_of(nxt, jn), L, npu, npv);
-      if (is_compute) {
-#if MPLPXX_FINE_STAMPS
-        if (v.stamps && last_iter && tid == 0) v.stamps[(size_t)slot * kStampStride + 5] = wall_clock64();
-#endif
-        // a' = centred U - phi (padded labels read label L-1: any finite value works)
-        float av[S::BC], au[S::BR];
-#pragma unroll
-        for (int jj = 0; jj < S::BC; ++jj) {
-          const int t = cb * S::BC + jj;
-          av[jj] = sm.uv[parity][(FULL || t < L) ? t : L - 1] - pv[jj];
-        }
-#pragma unroll
-        for (int i = 0; i < S::BR; ++i) {
-          const int s = rb * S::BR + i;
-          au[i] = sm.uu[parity][(FULL || s < L) ? s : L - 1] - pu[i];
-        }
-        // the old value (hi, lo) and message of this lane's output; the shift
-        // between the centred passes and the messages
-        const float ohi = out_u ? sm.uh[parity][out_ic] : sm.vh[parity][out_ic];
-        const float olo = out_u ? sm.ul[parity][out_ic] : sm.vl[parity][out_ic];
-        const float delta = 0.5f * (sm.cc[parity][0] - sm.cc[parity][1]);
-        float ophi = pvo;
-        if (out_u) {
-          ophi = pu[0];
-#pragma unroll
-          for (int i = 1; i < S::BR; ++i)
-            if (cb == i) ophi = pu[i];
-        }
-        // pass 1: p(s) = min_t [th(s,t) + a_v(t)], b = (a_u - p) / 2
-        float b[S::BR];
-        {
-          float pm[S::BR];
-#pragma unroll
-          for (int i = 0; i < S::BR; ++i) {
-            float mn = x[i][0] + av[0];
-#pragma unroll
-            for (int jj = 1; jj < S::BC; ++jj) mn = vmin(mn, x[i][jj] + av[jj]);
-            pm[i] = mn;
-          }
-          row16_min_n<S::BR>(pm);
-#pragma unroll
-          for (int i = 0; i < S::BR; ++i) b[i] = 0.5f * (au[i] - pm[i]);
-        }
-        // pass 2: q(t) = min_s [th(s,t) + b(s)]
-        float q[S::BC];
-#pragma unroll
-        for (int jj = 0; jj < S::BC; ++jj) {
-          float mn = x[0][jj] + b[0];
-#pragma unroll
-          for (int i = 1; i < S::BR; ++i) mn = vmin(mn, x[i][jj] + b[i]);
-          q[jj] = col4_min(mn);
-        }
-        if (lane < 16) {
-#pragma unroll
-          for (int jj = 0; jj < S::BC; ++jj) sm.red[wave][cb * S::BC + jj] = q[jj];
-        }
-#if MPLPXX_FINE_STAMPS
-        if (v.stamps && last_iter && tid == 0) v.stamps[(size_t)slot * kStampStride + 6] = wall_clock64();
-#endif
-        __syncthreads();  // matched by the sync waves' barrier below
-#if MPLPXX_FINE_STAMPS
-        if (v.stamps && last_iter && tid == 0) v.stamps[(size_t)slot * kStampStride + 7] = wall_clock64();
-#endif
-#pragma unroll
-        for (int jj = 0; jj < S::BC; ++jj) {
-          const int t = cb * S::BC + jj;
-          float mn = sm.red[0][t];
-#pragma unroll
-          for (int w = 1; w < S::W; ++w) mn = vmin(mn, sm.red[w][t]);
-          q[jj] = mn;
-        }
-        // the output column's message q' + delta, q' reduced the same way
-        float omsg;
-        {
-          float mn = sm.red[0][out_ic];
-#pragma unroll
-          for (int w = 1; w < S::W; ++w) mn = vmin(mn, sm.red[w][out_ic]);
-          omsg = mn + delta;
-        }
-        // pass 3: r(s) = min_t [th(s,t) - q(t)]
-        float r[S::BR];
-#pragma unroll
-        for (int i = 0; i < S::BR; ++i) {
-          float mn = x[i][0] - q[0];
-#pragma unroll
-          for (int jj = 1; jj < S::BC; ++jj) mn = vmin(mn, x[i][jj] - q[jj]);
-          r[i] = mn;
-        }
-        row16_min_n<S::BR>(r);
-        if (TRACE) {
-          // edge term of Eq. (3) after this update from the stored messages
-          // rs = r' - delta, qs = q' + delta: min over real rows of
-          // (fl(th - qs) - rs) + err(th - qs), exact up to one rounding of a
-          // number near zero; padded rows are skipped, padded columns stay
-          // near BIG/2
-          float em = __builtin_inff();
-#pragma unroll
-          for (int i = 0; i < S::BR; ++i) {
-            const int s = rb * S::BR + i;
-            const float rs = r[i] - delta;
-            if (FULL || s < L) {
-#pragma unroll
-              for (int jj = 0; jj < S::BC; ++jj) {
-                const float qs = q[jj] + delta;
-                const float d = x[i][jj] - qs;
-                em = vmin(em, (d - rs) + two_sum_err(x[i][jj], -qs, d));
-              }
-            }
-          }
-          em = col4_min(row16_min(em));
-          if (lane == 0) v.trace_e[((size_t)it * v.m + slot) * S::W + wave] = em;
-        }
-        if (out_u) {
-          float rr = r[0];
-#pragma unroll
-          for (int i = 1; i < S::BR; ++i)
-            if (cb == i) rr = r[i];
-          omsg = rr - delta;
-        }
-        // push back: the new unary through the mailbox, the message to memory
-        float* phi_w = phi_of(slot, j);
-        if (out_uk || out_v) {
-          float nhi, nlo;
-          comp_update(ohi, olo, ophi, omsg, nhi, nlo);
-          const int node = out_u ? si.u : si.v;
-          const unsigned ver = (out_u ? want_u : want_v) + 1;
-          mb_store(v.mb + (size_t)node * L + out_i, mb_pack(nhi, nlo, ver));
-          phi_w[(out_u ? 0 : L) + out_i] = omsg;
-        }
-        if (v.stamps && last_iter && tid == 0) v.stamps[(size_t)slot * kStampStride + 3] = wall_clock64();
-        if (pref) {
-#pragma unroll
-          for (int i = 0; i < S::BR; ++i) {
-            pu[i] = npu[i];
-#pragma unroll
-            for (int jj = 0; jj < S::BC; ++jj) x[i][jj] = y[i][jj];
-          }
-#pragma unroll
-          for (int jj = 0; jj < S::BC; ++jj) pv[jj] = npv[jj];
-          pvo = npvo;
-        } else {
-          // the same slot comes next: its messages are the ones just made
-#pragma unroll
-          for (int i = 0; i < S::BR; ++i) pu[i] = r[i] - delta;
-#pragma unroll
-          for (int jj = 0; jj < S::BC; ++jj) pv[jj] = q[jj] + delta;
-          pvo = omsg;
-        }
-      } else {
-        // the sync waves take part in the compute waves' mid-slot barrier
-        __syncthreads();
-        // per-iteration trace: the first update of a node in iteration it
-        // sees the node's value at the end of iteration it-1
-        if (TRACE && it > 0) {
-          const bool first_upd = is_sync_u ? (si.pos_u == 0) : (si.pos_v == 0);
-          if (first_upd) {
-            const float* src = is_sync_u ? sm.uh[parity] : sm.vh[parity];
-            const float* src_lo = is_sync_u ? sm.ul[parity] : sm.vl[parity];
-            double mn = __builtin_inf();
-            for (int s2 = lane; s2 < L; s2 += 64) mn = __builtin_fmin(mn, (double)src[s2] + (double)src_lo[s2]);
-#pragma unroll
-            for (int o = 32; o >= 1; o >>= 1) mn = __builtin_fmin(mn, __shfl_xor(mn, o, 64));
-            if (lane == 0) v.trace[(size_t)(it - 1) * v.n + (is_sync_u ? si.u : si.v)] = mn;
-          }
-        }
-      }
-      si = si_next;
+  static_assert(DEPTH == 1 || DEPTH == 2, "prefetch depth");
+  constexpr int RING = DEPTH + 1;
+  float t0[S::BR][S::BC], t1[S::BR][S::BC], t2[S::BR][S::BC];
+  // old messages of a step: this thread's rows (into u) and columns (into
+  // v), and its output column's
+  struct PhiSet {
+    float pu[S::BR], pv[S::BC], pvo;
+  };
+  PhiSet f0, f1, f2;
+  auto load_phiset = [&](PhiSet& f, int jq) __attribute__((always_inline)) {
+    const float* src = phi_of(first + jq * stride, jq);
+    load_phi<LT, NT, PHI_LDS, FULL>(src, L, f.pu, f.pv);
+    f.pvo = src[L + out_ic];  // (used by column lanes only)
+  };
+  // The messages of step q + DEPTH are last written by this workgroup at
+  // step q + DEPTH - owned.  PHI_FAR (the caller guarantees owned >= DEPTH
+  // + 2): that step's writes are behind a barrier when step q starts, so
+  // they are prefetched DEPTH steps ahead with the tables.  Otherwise each
+  // step reads its own messages right after its first barrier.
+  // Positions (iteration, owned index) of the current step and of the step
+  // DEPTH ahead, advanced without divisions.
+  int it = 0, j = 0, jp = 0;
+  {
+    const int j1 = owned > 1 ? 1 : 0;
+    load_tile_raw<LT, NT, FULL>(v.tables + (size_t)first * L * L, L, t0);
+    if (DEPTH == 2) load_tile_raw<LT, NT, FULL>(v.tables + (size_t)(first + j1 * stride) * L * L, L, t1);
+    if (PHI_FAR) {
+      load_phiset(f0, 0);
+      if (DEPTH == 2) load_phiset(f1, j1);
     }
+    jp = DEPTH % owned;
+  }
+  SlotInfo si = ld_const(v.slots + first);
+  int parity = 0;
+  // one step: compute on tile xc with messages fc, start loading the table
+  // and messages of step q + DEPTH into xp, fp (the ring position used one
+  // step earlier, free again)
+  auto step = [&](float (&xc)[S::BR][S::BC], float (&xp)[S::BR][S::BC], PhiSet& fc, PhiSet& fp, int q)
+                  __attribute__((always_inline)) -> bool {
+    float (&pu)[S::BR] = fc.pu;
+    float (&pv)[S::BC] = fc.pv;
+    const int slot = first + j * stride;
+    const unsigned want_u = (unsigned)(it * si.deg_u + si.pos_u);
+    const unsigned want_v = (unsigned)(it * si.deg_v + si.pos_v);
+    int nxt = slot + stride;
+    if (nxt >= v.m) nxt = first;
+    nxt = uni(nxt);
+    const bool last_iter = it == iters - 1;
+    // metadata of the next owned slot, off the dependency chain
+    const SlotInfo si_next = ld_const(v.slots + nxt);
+    {
+      // (past the end: a harmless reload of the last step's table)
+      const int jq = q + DEPTH < total ? jp : owned - 1;
+      load_tile_raw<LT, NT, FULL>(v.tables + (size_t)(first + jq * stride) * L * L, L, xp);
+      if (PHI_FAR) load_phiset(fp, jq);
+    }
+#if MPLPXX_FINE_STAMPS
+    if (v.stamps && last_iter && tid == 0) v.stamps[(size_t)slot * kStampStride + 4] = wall_clock64();
+#endif
+    __syncthreads();
+    if (sm.abort_flag) return false;
+    if (!PHI_FAR) load_phiset(fc, j);
+    pad_tile<LT, NT, FULL>(L, xc);
+#if MPLPXX_FINE_STAMPS
+    if (v.stamps && last_iter && tid == 0) v.stamps[(size_t)slot * kStampStride + 5] = wall_clock64();
+#endif
+    // a' = centred U - phi (padded labels read label L-1: any finite value works)
+    float av[S::BC], au[S::BR];
+#pragma unroll
+    for (int jj = 0; jj < S::BC; ++jj) {
+      const int t = cb * S::BC + jj;
+      av[jj] = sm.uv[parity][(FULL || t < L) ? t : L - 1] - pv[jj];
+    }
+#pragma unroll
+    for (int i = 0; i < S::BR; ++i) {
+      const int s = rb * S::BR + i;
+      au[i] = sm.uu[parity][(FULL || s < L) ? s : L - 1] - pu[i];
+    }
+    // the old value (hi, lo) and message of this lane's output; the shift
+    // between the centred passes and the messages
+    const float ohi = out_u ? sm.uh[parity][out_ic] : sm.vh[parity][out_ic];
+    const float olo = out_u ? sm.ul[parity][out_ic] : sm.vl[parity][out_ic];
+    const float delta = 0.5f * (sm.cc[parity][0] - sm.cc[parity][1]);
+    float ophi = fc.pvo;
+    if (out_u) {
+      ophi = pu[0];
+#pragma unroll
+      for (int i = 1; i < S::BR; ++i)
+        if (cb == i) ophi = pu[i];
+    }
+    // pass 1: p(s) = min_t [th(s,t) + a_v(t)], b = (a_u - p) / 2
+    float b[S::BR];
+    {
+      float pm[S::BR];
+#pragma unroll
+      for (int i = 0; i < S::BR; ++i) {
+        float mn = xc[i][0] + av[0];
+#pragma unroll
+        for (int jj = 1; jj < S::BC; ++jj) mn = vmin(mn, xc[i][jj] + av[jj]);
+        pm[i] = mn;
+      }
+      row16_min_n<S::BR>(pm);
+#pragma unroll
+      for (int i = 0; i < S::BR; ++i) b[i] = 0.5f * (au[i] - pm[i]);
+    }
+    // pass 2: q(t) = min_s [th(s,t) + b(s)]
+    float qv[S::BC];
+#pragma unroll
+    for (int jj = 0; jj < S::BC; ++jj) {
+      float mn = xc[0][jj] + b[0];
+#pragma unroll
+      for (int i = 1; i < S::BR; ++i) mn = vmin(mn, xc[i][jj] + b[i]);
+      qv[jj] = col4_min(mn);
+    }
+    if (lane < 16) {
+#pragma unroll
+      for (int jj = 0; jj < S::BC; ++jj) sm.red[wave][cb * S::BC + jj] = qv[jj];
+    }
+#if MPLPXX_FINE_STAMPS
+    if (v.stamps && last_iter && tid == 0) v.stamps[(size_t)slot * kStampStride + 6] = wall_clock64();
+#endif
+    __syncthreads();  // mid-step barrier (the sync waves take part)
+#if MPLPXX_FINE_STAMPS
+    if (v.stamps && last_iter && tid == 0) v.stamps[(size_t)slot * kStampStride + 7] = wall_clock64();
+#endif
+#pragma unroll
+    for (int jj = 0; jj < S::BC; ++jj) {
+      const int t = cb * S::BC + jj;
+      float mn = sm.red[0][t];
+#pragma unroll
+      for (int w = 1; w < S::W; ++w) mn = vmin(mn, sm.red[w][t]);
+      qv[jj] = mn;
+    }
+    // the output column's message q' + delta, q' reduced the same way
+    float omsg;
+    {
+      float mn = sm.red[0][out_ic];
+#pragma unroll
+      for (int w = 1; w < S::W; ++w) mn = vmin(mn, sm.red[w][out_ic]);
+      omsg = mn + delta;
+    }
+    // pass 3: r(s) = min_t [th(s,t) - q(t)]
+    float r[S::BR];
+#pragma unroll
+    for (int i = 0; i < S::BR; ++i) {
+      float mn = xc[i][0] - qv[0];
+#pragma unroll
+      for (int jj = 1; jj < S::BC; ++jj) mn = vmin(mn, xc[i][jj] - qv[jj]);
+      r[i] = mn;
+    }
+    row16_min_n<S::BR>(r);
+    if (TRACE) {
+      // edge term of Eq. (3) after this update from the stored messages
+      // rs = r' - delta, qs = q' + delta: min over real rows of
+      // (fl(th - qs) - rs) + err(th - qs), exact up to one rounding of a
+      // number near zero; padded rows are skipped, padded columns stay
+      // near BIG/2
+      float em = __builtin_inff();
+#pragma unroll
+      for (int i = 0; i < S::BR; ++i) {
+        const int s = rb * S::BR + i;
+        const float rs = r[i] - delta;
+        if (FULL || s < L) {
+#pragma unroll
+          for (int jj = 0; jj < S::BC; ++jj) {
+            const float qs = qv[jj] + delta;
+            const float d = xc[i][jj] - qs;
+            em = vmin(em, (d - rs) + two_sum_err(xc[i][jj], -qs, d));
+          }
+        }
+      }
+      em = col4_min(row16_min(em));
+      if (lane == 0) v.trace_e[((size_t)it * v.m + slot) * S::W + wave] = em;
+    }
+    if (out_u) {
+      float rr = r[0];
+#pragma unroll
+      for (int i = 1; i < S::BR; ++i)
+        if (cb == i) rr = r[i];
+      omsg = rr - delta;
+    }
+    // push back: the new unary through the mailbox, the message to memory.
+    // Every lane issues the same global stores (lanes without an output
+    // write their own scratch word): a store that only some waves skip
+    // would leave the compiler unsure how many memory operations are in
+    // flight, and it would then wait for all of them, prefetches too.
+    float* phi_w = phi_of(slot, j);
+    const bool outk = out_uk || out_v;
+    float nhi, nlo;
+    comp_update(ohi, olo, ophi, omsg, nhi, nlo);
+    const int node = out_u ? si.u : si.v;
+    if (LDSU) {
+      if (outk) {
+        v.lds_hi[(size_t)node * L + out_i] = nhi;
+        v.lds_lo[(size_t)node * L + out_i] = (unsigned short)(__float_as_uint(nlo) >> 16);
+      }
+    } else {
+      const unsigned ver = (out_u ? want_u : want_v) + 1;
+      mb_store(outk ? v.mb + (size_t)node * L + out_i : v.sink + tid, mb_pack(nhi, nlo, ver));
+    }
+    if (PHI_LDS) {
+      if (outk) phi_w[(out_u ? 0 : L) + out_i] = omsg;
+    } else {
+      *(outk ? phi_w + (out_u ? 0 : L) + out_i : reinterpret_cast<float*>(v.sink + NT + (tid & 63))) = omsg;
+    }
+    {
+      const bool st = v.stamps && last_iter && tid == 0;
+      long long* dst = st ? v.stamps + (size_t)slot * kStampStride + 3
+                          : reinterpret_cast<long long*>(v.sink + NT + 64 + (tid & 63));
+      *dst = st ? (long long)wall_clock64() : 0;
+    }
+    // LDS-resident mode: the next slot starts a matching (or the next
+    // iteration) and may read what this slot wrote
+    if (LDSU && (si_next.step != si.step || nxt <= slot)) __syncthreads();
+    si = si_next;
+    parity ^= 1;
+    if (++j == owned) { j = 0; ++it; }
+    if (++jp == owned) jp = 0;
+    return true;
+  };
+  // whole turns of the ring in the loop (every path through its body issues
+  // the same memory operations, so the compiler can count the loads in
+  // flight exactly), then the remaining steps
+  int q = 0;
+  if (RING == 2) {
+    for (; q + 2 <= total; q += 2) {
+      if (!step(t0, t1, f0, f1, q)) return false;
+      if (!step(t1, t0, f1, f0, q + 1)) return false;
+    }
+    if (q < total && !step(t0, t1, f0, f1, q)) return false;
+  } else {
+    for (; q + 3 <= total; q += 3) {
+      if (!step(t0, t2, f0, f2, q)) return false;
+      if (!step(t1, t0, f1, f0, q + 1)) return false;
+      if (!step(t2, t1, f2, f1, q + 2)) return false;
+    }
+    if (q < total && !step(t0, t2, f0, f2, q)) return false;
+    if (q + 1 < total && !step(t1, t0, f1, f0, q + 1)) return false;
   }
   return true;
 }

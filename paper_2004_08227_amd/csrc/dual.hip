@@ -7,6 +7,8 @@
 //   edge term  min_{s,t} [theta_e(s,t) - phi_e[0](s) - phi_e[1](t)]
 // with every sum in FP64 (Eq. (2) and Eq. (3)).  All reductions use a fixed
 // order, so the result is deterministic.
+#include <algorithm>
+
 #include "common.h"
 
 namespace mplpxx {
@@ -303,6 +305,26 @@ hipError_t launch_pack_tables(const T* src, T* dst, const int* slot_edge, const 
 __global__ void k_fill_int(int* __restrict__ p, int value, size_t count) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
     p[i] = value;
+}
+
+template <typename S, typename D>
+__global__ void k_convert(const S* __restrict__ src, D* __restrict__ dst, size_t count) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = (D)src[i];
+}
+
+hipError_t launch_convert(const float* src, double* dst, size_t count, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  const size_t blocks = std::min<size_t>((count + 255) / 256, 4096);
+  hipLaunchKernelGGL((k_convert<float, double>), dim3((unsigned)blocks), dim3(256), 0, st, src, dst, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_convert(const double* src, float* dst, size_t count, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  const size_t blocks = std::min<size_t>((count + 255) / 256, 4096);
+  hipLaunchKernelGGL((k_convert<double, float>), dim3((unsigned)blocks), dim3(256), 0, st, src, dst, count);
+  return hipGetLastError();
 }
 
 hipError_t launch_fill_int(int* p, int value, size_t count, hipStream_t st) {

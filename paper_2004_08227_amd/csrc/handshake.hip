@@ -319,7 +319,7 @@ __global__ void __launch_bounds__(NT) k_persistent(HsArgs<T> a, int iters) {
   }
 }
 
-template <int LT, int NT, bool PHI_LDS, bool FULL, bool TRACE>
+template <int LT, int NT, bool PHI_LDS, bool FULL, bool TRACE, bool PHI_FAR>
 __global__ void __launch_bounds__(NT + 128) k_persistent_mb(HsArgs<float> a, unsigned long long* __restrict__ mb,
                                                             int iters) {
   __shared__ SmemMB<LT, NT> sm;
@@ -334,8 +334,11 @@ __global__ void __launch_bounds__(NT + 128) k_persistent_mb(HsArgs<float> a, uns
       for (int k = tid; k < 2 * L; k += NT + 128) phi_lds[j * 2 * L + k] = a.phi[(size_t)slot * 2 * L + k];
   }
   __syncthreads();
-  MbView v{a.tables, a.phi, mb, a.slots, a.deg, a.trace, a.trace_e, a.stamps, L, a.m, a.n};
-  if (!mb_run<LT, NT, PHI_LDS, FULL, TRACE>(v, blockIdx.x, G, iters, sm, phi_lds, a.spin_limit, a.err)) return;
+  MbView v{a.tables, a.phi, mb, a.slots, a.deg, a.trace, a.trace_e, a.stamps, L, a.m, a.n, nullptr, nullptr,
+           a.sink + (size_t)blockIdx.x * (NT + 128)};
+  if (!mb_run<LT, NT, PHI_LDS, FULL, TRACE, false, PHI_FAR>(v, blockIdx.x, G, iters, sm, phi_lds, a.spin_limit,
+                                                            a.err))
+    return;
   __syncthreads();
   if (PHI_LDS) {
     for (int slot = blockIdx.x, j = 0; slot < a.m; slot += G, ++j)
@@ -386,17 +389,18 @@ static hipError_t launch_mb_one(const HsArgs<float>& a, unsigned long long* mb, 
                                 size_t dyn_lds, hipStream_t st) {
   void* args[] = {(void*)&a, (void*)&mb, (void*)&iters};
   const bool full = a.L == LT;
-  const void* f;
-  if (a.trace)
-    f = phi_in_lds ? (full ? (const void*)k_persistent_mb<LT, NT, true, true, true>
-                           : (const void*)k_persistent_mb<LT, NT, true, false, true>)
-                   : (full ? (const void*)k_persistent_mb<LT, NT, false, true, true>
-                           : (const void*)k_persistent_mb<LT, NT, false, false, true>);
-  else
-    f = phi_in_lds ? (full ? (const void*)k_persistent_mb<LT, NT, true, true, false>
-                           : (const void*)k_persistent_mb<LT, NT, true, false, false>)
-                   : (full ? (const void*)k_persistent_mb<LT, NT, false, true, false>
-                           : (const void*)k_persistent_mb<LT, NT, false, false, false>);
+  // messages prefetched with the tables when every workgroup owns at least
+  // DEPTH + 2 slots (the engine's rule; DEPTH is 2 for tiles up to 64)
+  const int depth = LT <= 64 ? 2 : 1;
+  const bool far = (a.m / grid) >= depth + 2;
+#define MPLPXX_PICK(TR, FA)                                                                          \
+  (phi_in_lds ? (full ? (const void*)k_persistent_mb<LT, NT, true, true, TR, FA>                     \
+                      : (const void*)k_persistent_mb<LT, NT, true, false, TR, FA>)                   \
+              : (full ? (const void*)k_persistent_mb<LT, NT, false, true, TR, FA>                    \
+                      : (const void*)k_persistent_mb<LT, NT, false, false, TR, FA>))
+  const void* f = a.trace ? (far ? MPLPXX_PICK(true, true) : MPLPXX_PICK(true, false))
+                          : (far ? MPLPXX_PICK(false, true) : MPLPXX_PICK(false, false));
+#undef MPLPXX_PICK
   return hipLaunchCooperativeKernel(f, dim3(grid), dim3(NT + 128), args, dyn_lds, st);
 }
 

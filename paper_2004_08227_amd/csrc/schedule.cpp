@@ -117,6 +117,8 @@ int prepare_graph(int n, int m, const int32_t* edges, GraphPrep& g) {
     g.slots[i].deg_u = g.deg[g.slots[i].u];
     g.slots[i].deg_v = g.deg[g.slots[i].v];
   }
+  for (int k = 0; k < g.S; ++k)
+    for (int i = g.step_ptr[k]; i < g.step_ptr[k + 1]; ++i) g.slots[i].step = k;
   return MPLPXX_OK;
 }
 

@@ -73,6 +73,8 @@ struct mplpxx_solver {
   float* d_trace_e = nullptr;            // FP32: [cap][m][8] edge terms of the trace
   int trace_cap = 0;
   unsigned long long* d_mb = nullptr;    // FP32 mailboxes of the persistent engine
+  unsigned long long* d_sink = nullptr;  // scratch words of its workgroups
+  size_t sink_words = 0;
   long long* d_stamps = nullptr;         // per-slot timestamps (profiling option)
   bool profile = false;
   int wallclock_khz = 0;
@@ -89,6 +91,8 @@ struct mplpxx_solver {
   void* d_thb = nullptr;                  // [m][L][L]
   int* d_slot_of_edge = nullptr;          // [m]
   int* d_edge_flip = nullptr;             // [m]
+  int adjoint_f64 = 1;                    // FP32 handles: differentiate an FP64 run
+  mplpxx_solver* shadow = nullptr;        // the FP64 twin for that (same graph, widened costs)
   // execution
   hipStream_t user_stream = nullptr;
   hipStream_t own_stream = nullptr;
@@ -131,7 +135,7 @@ namespace {
 void free_all(mplpxx_solver* h) {
   void* ptrs[] = {h->d_tables, h->d_phi, h->d_U, h->d_Ulo, h->d_ck_Ulo, h->d_unaries, h->d_slots, h->d_deg, h->d_ver, h->d_err,
                   h->d_node_ptr, h->d_inc, h->d_node_min, h->d_edge_min, h->d_scalar, h->d_labels,
-                  h->d_trace_nodes, h->d_trace_out, h->d_trace_e, h->d_mb, h->d_stamps, h->d_ck_U, h->d_ck_phi,
+                  h->d_trace_nodes, h->d_trace_out, h->d_trace_e, h->d_mb, h->d_sink, h->d_stamps, h->d_ck_U, h->d_ck_phi,
                   h->d_rec, h->d_Ub, h->d_pb, h->d_thb, h->d_slot_of_edge, h->d_edge_flip};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -421,6 +425,15 @@ template <typename T> int iterate_t(mplpxx_solver* h, int k, double* trace_host)
         trace_w = NT / 64;
       }
       const int G = h->grid();
+      const size_t words = (size_t)G * (NT + 128);
+      if (h->sink_words < words) {
+        if (h->d_sink) (void)hipFree(h->d_sink);
+        h->d_sink = nullptr;
+        h->sink_words = 0;
+        HIP_TRY(hipMalloc(&h->d_sink, words * sizeof(unsigned long long)));
+        h->sink_words = words;
+      }
+      a.sink = h->d_sink;
       const size_t owned = ((size_t)h->m + G - 1) / G;
       const size_t phi_bytes = owned * 2 * h->L * sizeof(float);
       const int in_lds = phi_bytes <= kPhiLdsBudget ? 1 : 0;
@@ -570,6 +583,49 @@ template <typename T> int adjoint_backward_t(mplpxx_solver* h, void* grad_u, voi
 }  // namespace
 
 namespace {
+// FP64 twin of an FP32 handle: the same graph and costs widened exactly, in
+// the caller's layout (tables unpacked from slot order), created on the
+// handle's stream
+int make_shadow(mplpxx_solver* h) {
+  hipStream_t st = h->stream();
+  const size_t nL = (size_t)h->n * h->L, mLL = (size_t)h->m * h->L * h->L;
+  std::vector<int32_t> edges(2 * (size_t)h->m);
+  for (int e = 0; e < h->m; ++e) {
+    const SlotInfo& si = h->slots[h->slot_of_edge[e]];
+    edges[2 * e] = h->flip[e] ? si.v : si.u;
+    edges[2 * e + 1] = h->flip[e] ? si.u : si.v;
+  }
+  double* u64 = nullptr;
+  double* t64 = nullptr;
+  double* p64 = nullptr;
+  int* d_soe = nullptr;
+  int* d_flip = nullptr;
+  auto cleanup = [&]() {
+    for (void* p : {(void*)u64, (void*)t64, (void*)p64, (void*)d_soe, (void*)d_flip})
+      if (p) (void)hipFree(p);
+  };
+  hipError_t e = hipMalloc(&u64, std::max<size_t>(1, nL) * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&t64, std::max<size_t>(1, mLL) * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&p64, std::max<size_t>(1, mLL) * sizeof(double));
+  if (e == hipSuccess && h->m) e = hipMalloc(&d_soe, h->m * sizeof(int));
+  if (e == hipSuccess && h->m) e = hipMalloc(&d_flip, h->m * sizeof(int));
+  if (e == hipSuccess && h->m)
+    e = hipMemcpyAsync(d_soe, h->slot_of_edge.data(), h->m * sizeof(int), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && h->m) e = hipMemcpyAsync(d_flip, h->flip.data(), h->m * sizeof(int), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = launch_convert(static_cast<const float*>(h->d_unaries), u64, nL, st);
+  if (e == hipSuccess && h->m) e = launch_convert(static_cast<const float*>(h->d_tables), t64, mLL, st);
+  if (e == hipSuccess && h->m) e = launch_pack_tables<double>(t64, p64, d_soe, d_flip, h->m, h->L, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    cleanup();
+    return fail(e == hipErrorOutOfMemory ? MPLPXX_ENOMEM : MPLPXX_EDEVICE, "FP64 twin: %s", hipGetErrorString(e));
+  }
+  const int rc = create_impl(h->n, h->L, h->m, h->m ? edges.data() : nullptr, u64, h->m ? p64 : nullptr, MPLPXX_F64,
+                             true, st, &h->shadow);
+  cleanup();
+  return rc;
+}
+
 // nearest bf16 value, ties to even (the rounding the device applies to U_comp)
 float bf16_round_host(float x) {
   uint32_t u;
@@ -609,6 +665,29 @@ int mplpxx_adjoint_forward(mplpxx_solver* h, int32_t K, int32_t every, double* l
   if (!h) return fail(MPLPXX_EINVAL, "handle is NULL");
   if (K < 1 || every < 1) return fail(MPLPXX_EINVAL, "K and every must be >= 1");
   h->adj_ready = false;
+  if (h->dtype == MPLPXX_F32 && h->adjoint_f64) {
+    if (!h->shadow) {
+      const int rc = make_shadow(h);
+      if (rc != MPLPXX_OK) return rc;
+    }
+    int rc = adjoint_forward_t<double>(h->shadow, K, every, loss);
+    if (rc != MPLPXX_OK) return rc;
+    // the handle's own FP32 run of K iterations from phi = 0
+    hipStream_t st = h->stream();
+    const size_t nL = (size_t)h->n * h->L;
+    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(hipMemsetAsync(h->d_phi, 0, (size_t)h->m * 2 * h->L * sizeof(float), st));
+    HIP_TRY(hipMemcpyAsync(h->d_U, h->d_unaries, nL * sizeof(float), hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemsetAsync(h->d_Ulo, 0, nL * sizeof(float), st));
+    h->iterations = 0;
+    rc = iterate_t<float>(h, K, nullptr);
+    if (rc != MPLPXX_OK) return rc;
+    rc = sync_and_check(h);
+    if (rc != MPLPXX_OK) return rc;
+    h->adj_ready = true;
+    h->adj_iter_mark = h->iterations;
+    return MPLPXX_OK;
+  }
   return h->dtype == MPLPXX_F32 ? adjoint_forward_t<float>(h, K, every, loss) : adjoint_forward_t<double>(h, K, every, loss);
 }
 
@@ -616,6 +695,31 @@ int mplpxx_adjoint_backward(mplpxx_solver* h, void* grad_unaries, void* grad_pai
   if (!h) return fail(MPLPXX_EINVAL, "handle is NULL");
   if (!h->adj_ready || h->iterations != h->adj_iter_mark)
     return fail(MPLPXX_ESTATE, "no adjoint forward to differentiate (call mplpxx_adjoint_forward first)");
+  if (h->dtype == MPLPXX_F32 && h->adjoint_f64) {
+    // FP64 gradients of the twin, narrowed into the caller's FP32 buffers
+    hipStream_t st = h->stream();
+    const size_t nL = (size_t)h->n * h->L, mLL = (size_t)h->m * h->L * h->L;
+    double* gu = nullptr;
+    double* gp = nullptr;
+    HIP_TRY(hipMalloc(&gu, std::max<size_t>(1, nL) * sizeof(double)));
+    if (hipMalloc(&gp, std::max<size_t>(1, mLL) * sizeof(double)) != hipSuccess) {
+      (void)hipFree(gu);
+      return fail(MPLPXX_ENOMEM, "gradient buffers");
+    }
+    int rc = adjoint_backward_t<double>(h->shadow, grad_unaries ? gu : nullptr, grad_pairwise ? gp : nullptr);
+    hipError_t e = hipSuccess;
+    if (rc == MPLPXX_OK) {
+      HIP_TRY(hipStreamSynchronize(h->shadow->stream()));
+      if (grad_unaries) e = launch_convert(gu, static_cast<float*>(grad_unaries), nL, st);
+      if (e == hipSuccess && grad_pairwise && mLL) e = launch_convert(gp, static_cast<float*>(grad_pairwise), mLL, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
+    (void)hipFree(gu);
+    (void)hipFree(gp);
+    if (rc != MPLPXX_OK) return rc;
+    if (e != hipSuccess) return fail(MPLPXX_EDEVICE, "gradient narrowing: %s", hipGetErrorString(e));
+    return MPLPXX_OK;
+  }
   return h->dtype == MPLPXX_F32 ? adjoint_backward_t<float>(h, grad_unaries, grad_pairwise)
                                 : adjoint_backward_t<double>(h, grad_unaries, grad_pairwise);
 }
@@ -654,6 +758,7 @@ int mplpxx_decode(mplpxx_solver* h, int32_t* labels, double* energy) {
 void mplpxx_destroy(mplpxx_solver* h) {
   if (!h) return;
   (void)hipStreamSynchronize(h->stream());
+  if (h->shadow) mplpxx_destroy(h->shadow);
   free_all(h);
   delete h;
 }
@@ -784,6 +889,10 @@ int mplpxx_set_option(mplpxx_solver* h, int32_t key, int64_t value) {
       return MPLPXX_OK;
     case MPLPXX_OPT_PROFILE:
       h->profile = value != 0;
+      return MPLPXX_OK;
+    case MPLPXX_OPT_ADJOINT_F64:
+      h->adjoint_f64 = value != 0;
+      h->adj_ready = false;
       return MPLPXX_OK;
     default:
       return fail(MPLPXX_EINVAL, "unknown option %d", key);

@@ -10,8 +10,9 @@ Outputs (JSON, one file per workload):
   pose_k200_l64.json        dual trace of 200 iterations, final node minima
   potts_er_n1000_l16.json   dual traces (30 iterations) at 5/25/50/100 % density
   batched_mix_samples.json  100-iteration traces of 8 models of the 256-model mix
-  adjoint_uniform_k100_l32.json  central differences of D_50 along seeded
-                            directions and coordinates, two step sizes
+  adjoint_uniform_k100_l32.json  central and one-sided differences of D_50
+                            along seeded dense and sparse directions and
+                            coordinates, three step sizes each
 """
 import json
 import os
@@ -88,43 +89,69 @@ def adjoint_directions(model, count, seed):
             for _ in range(count)]
 
 
+def adjoint_sparse_directions(model, count, seed, support=32):
+    """Directions on `support` random coordinates (half unaries, half pairwise)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        du = np.zeros_like(model.unaries)
+        dp = np.zeros_like(model.pairwise)
+        du.flat[rng.choice(du.size, support // 2, replace=False)] = rng.standard_normal(support // 2)
+        dp.flat[rng.choice(dp.size, support // 2, replace=False)] = rng.standard_normal(support // 2)
+        out.append((du, dp))
+    return out
+
+
 def adjoint_coords(model, count, seed):
+    """Coordinates: a third unary entries, the rest pairwise entries."""
     rng = np.random.default_rng(seed)
     nu = model.unaries.size
-    tot = nu + model.pairwise.size
-    return [int(c) for c in rng.choice(tot, size=count, replace=False)]
+    cu = rng.choice(nu, size=count // 3, replace=False)
+    cp = nu + rng.choice(model.pairwise.size, size=count - count // 3, replace=False)
+    return [int(c) for c in np.concatenate([cu, cp])]
 
 
 def make_adjoint():
+    """D_K is piecewise linear in the costs with kinks at every scale along a
+    generic direction, so each check stores, for several step sizes h, the
+    central difference and both one-sided differences."""
     K, every = 50, 10
     model = W.uniform(100, 32, seed=0)
     base = model.astype(np.float64)
+    nu = base.unaries.size
 
     def D(du, dp):
         mo = W.Model(base.n, base.L, base.edges, base.unaries + du, base.pairwise + dp)
         return oracle.dual_after(mo, K, nthreads=THREADS)
 
-    out = {"workload": "uniform n=100 L=32 seed=0 (FP32 inputs promoted to FP64)", "K": K, "every": every,
-           "D": D(0.0, 0.0), "directions": [], "coords": []}
-    for h in (1e-6, 1e-7):
-        fds = []
-        for du, dp in adjoint_directions(base, 8, 7):
-            fds.append((D(h * du, h * dp) - D(-h * du, -h * dp)) / (2 * h))
-        out["directions"].append({"h": h, "seed": 7, "count": 8, "fd": fds})
-        print("directions h", h, flush=True)
-    nu = base.unaries.size
-    for h in (1e-6, 1e-7):
-        fds = []
-        for c in adjoint_coords(base, 16, 11):
-            du = np.zeros_like(base.unaries)
-            dp = np.zeros_like(base.pairwise)
-            if c < nu:
-                du.flat[c] = 1.0
-            else:
-                dp.flat[c - nu] = 1.0
-            fds.append((D(h * du, h * dp) - D(-h * du, -h * dp)) / (2 * h))
-        out["coords"].append({"h": h, "seed": 11, "count": 16, "fd": fds})
-        print("coords h", h, flush=True)
+    D0 = D(0.0, 0.0)
+
+    def diffs(du, dp, hs):
+        rows = []
+        for h in hs:
+            p, m = D(h * du, h * dp), D(-h * du, -h * dp)
+            rows.append({"h": h, "central": (p - m) / (2 * h), "right": (p - D0) / h, "left": (D0 - m) / h})
+        return rows
+
+    out = {"workload": "uniform n=100 L=32 seed=0 (FP32 inputs promoted to FP64)", "K": K, "every": every, "D": D0,
+           "dense": {"seed": 7, "count": 8, "fd": []}, "sparse": {"seed": 9, "count": 8, "support": 32, "fd": []},
+           "coords": {"seed": 11, "count": 24, "index": [], "fd": []}}
+    for du, dp in adjoint_directions(base, 8, 7):
+        out["dense"]["fd"].append(diffs(du, dp, (1e-7, 1e-8, 1e-9)))
+    print("dense directions", flush=True)
+    for du, dp in adjoint_sparse_directions(base, 8, 9):
+        out["sparse"]["fd"].append(diffs(du, dp, (1e-6, 1e-7, 1e-8)))
+    print("sparse directions", flush=True)
+    for c in adjoint_coords(base, 24, 11):
+        du = np.zeros_like(base.unaries)
+        dp = np.zeros_like(base.pairwise)
+        if c < nu:
+            du.flat[c] = 1.0
+        else:
+            dp.flat[c - nu] = 1.0
+        out["coords"]["index"].append(c)
+        out["coords"]["fd"].append(diffs(du, dp, (1e-6, 1e-7, 1e-8)))
+    print("coordinates", flush=True)
     dump("adjoint_uniform_k100_l32.json", out)
 
 

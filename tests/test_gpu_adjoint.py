@@ -24,8 +24,9 @@ def _announce(*a):
     print("CASE", *a, flush=True)
 
 
-def _grad(model, K, every):
+def _grad(model, K, every, adjoint_f64=1):
     with M.Solver.from_model(model) as s:
+        s.set_option(M.OPT_ADJOINT_F64, adjoint_f64)
         loss = s.adjoint_forward(K, every)
         gu, gp = s.adjoint_backward()
     return loss, gu, gp
@@ -62,43 +63,80 @@ def test_fp64_adjoint_matches_finite_differences_per_coordinate():
 
 
 def test_checkpoint_spacing_and_repeats_are_bitwise_identical():
-    for dtype in (np.float64, np.float32):
+    for dtype, f64 in ((np.float64, 1), (np.float32, 1), (np.float32, 0)):
         model = W.uniform(14, 6, seed=22, dtype=dtype)
-        _announce("checkpoints", dtype.__name__)
+        _announce("checkpoints", dtype.__name__, f64)
         ref = None
         for every in (1, 3, 7, 10):
-            loss, gu, gp = _grad(model, 7, every)
+            loss, gu, gp = _grad(model, 7, every, f64)
             if ref is None:
                 ref = (loss, gu, gp)
             else:
                 assert loss == ref[0] and np.array_equal(gu, ref[1]) and np.array_equal(gp, ref[2])
 
 
+def _fd_ok(g, rows):
+    """D_K is piecewise linear with kinks at every scale along a generic
+    direction: accept the adjoint value if, for some stored step size h, it
+    matches the central difference, or lies between the two one-sided
+    differences, within 1e-4 relative."""
+    for r in rows:
+        tol = 1e-4 * max(1.0, abs(r["central"]))
+        lo, hi = min(r["left"], r["right"]), max(r["left"], r["right"])
+        if abs(g - r["central"]) <= tol or lo - tol <= g <= hi + tol:
+            return True
+    return False
+
+
 def test_fp32_adjoint_matches_stored_finite_differences_full_size():
+    """The differentiation workload (n=100, L=32, K=50, checkpoints every 10)
+    on an FP32 handle: loss and gradient (of the FP64 twin run, the default)
+    against FP64 finite differences of the oracle along 8 dense and 8 sparse
+    seeded directions and 24 coordinates."""
+    import sys
     path = os.path.join(GOLD, "adjoint_uniform_k100_l32.json")
-    if not os.path.exists(path):
-        pytest.skip("golden file missing")
     g = json.load(open(path))
+    sys.path.insert(0, GOLD)
+    import make_golden as MG
     _announce("fp32 adjoint n=100 L=32 K=50")
     model = W.uniform(100, 32, seed=0)
     loss, gu, gp = _grad(model, g["K"], g["every"])
     assert abs(loss - g["D"]) <= 1e-5 * abs(g["D"])
     base = model.astype(np.float64)
-    rng = np.random.default_rng(g["directions"][0]["seed"])
-    dirs = [(rng.standard_normal(base.unaries.shape), rng.standard_normal(base.pairwise.shape))
-            for _ in range(g["directions"][0]["count"])]
-    for k, (du, dp) in enumerate(dirs):
-        proj = float((gu.astype(np.float64) * du).sum() + (gp.astype(np.float64) * dp).sum())
-        fds = [d["fd"][k] for d in g["directions"]]
-        ok = [abs(proj - fd) <= 1e-4 * max(1.0, abs(fd)) for fd in fds]
-        assert any(ok), (k, proj, fds)
-    rng = np.random.default_rng(g["coords"][0]["seed"])
-    nu = base.unaries.size
-    coords = rng.choice(nu + base.pairwise.size, size=g["coords"][0]["count"], replace=False)
-    flat = np.concatenate([gu.ravel(), gp.ravel()]).astype(np.float64)
-    for k, c in enumerate(coords):
-        fds = [d["fd"][k] for d in g["coords"]]
-        assert any(abs(flat[c] - fd) <= 1e-4 * max(1.0, abs(fd)) for fd in fds), (k, c, flat[c], fds)
+    gu64, gp64 = gu.astype(np.float64), gp.astype(np.float64)
+    bad = []
+    for name, dirs in (("dense", MG.adjoint_directions(base, g["dense"]["count"], g["dense"]["seed"])),
+                       ("sparse", MG.adjoint_sparse_directions(base, g["sparse"]["count"], g["sparse"]["seed"],
+                                                               g["sparse"]["support"]))):
+        for k, (du, dp) in enumerate(dirs):
+            proj = float((gu64 * du).sum() + (gp64 * dp).sum())
+            if not _fd_ok(proj, g[name]["fd"][k]):
+                bad.append((name, k, proj, g[name]["fd"][k]))
+    flat = np.concatenate([gu64.ravel(), gp64.ravel()])
+    assert g["coords"]["index"] == MG.adjoint_coords(base, g["coords"]["count"], g["coords"]["seed"])
+    for k, c in enumerate(g["coords"]["index"]):
+        if not _fd_ok(float(flat[c]), g["coords"]["fd"][k]):
+            bad.append(("coord", c, float(flat[c]), g["coords"]["fd"][k]))
+    assert not bad, bad
+
+
+def test_fp32_run_adjoint_is_close_to_the_fp64_twin():
+    """The gradient of the FP32 run itself (OPT_ADJOINT_F64 = 0) picks a
+    neighbouring linear piece for the minimizers that FP32 rounding flips;
+    it stays within a few percent of the FP64 twin's gradient, and its loss
+    within 1e-5 of the oracle's."""
+    path = os.path.join(GOLD, "adjoint_uniform_k100_l32.json")
+    g = json.load(open(path))
+    _announce("fp32-run adjoint vs fp64 twin")
+    model = W.uniform(100, 32, seed=0)
+    l32, gu32, gp32 = _grad(model, g["K"], g["every"], 0)
+    l64, gu64, gp64 = _grad(model, g["K"], g["every"], 1)
+    assert abs(l32 - g["D"]) <= 1e-5 * abs(g["D"])
+    a = np.concatenate([gu32.ravel(), gp32.ravel()]).astype(np.float64)
+    b = np.concatenate([gu64.ravel(), gp64.ravel()]).astype(np.float64)
+    rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+    print("fp32-run vs fp64-twin gradient: rel L2", rel, "entries equal", float(np.mean(a == b)), flush=True)
+    assert rel <= 3e-2
 
 
 def test_orientation_and_degenerate_models():

@@ -66,7 +66,8 @@ def test_plans_and_graph_replays_are_bitwise_identical():
     models = _mixed_models(seed=1, count=10)
     results = []
     for opts in [dict(graph=0), dict(graph=1), dict(one_per_model=1), dict(grid=5), dict(grid=3, one_per_model=1),
-                 dict(handoff_us=5.0, edge64_us=0.1)]:
+                 dict(handoff_us=5.0, edge64_us=0.1), dict(lds=0), dict(lds=0, one_per_model=1),
+                 dict(lds=1, one_per_model=1, grid=2)]:
         _announce("plan", opts)
         with M.Batch(models) as b:
             for k, v in opts.items():
