@@ -372,8 +372,8 @@ int mplpxx_batch_create(int32_t count, const int32_t* n, const int32_t* L, const
   TRY(hipEventCreate(&b->ev0));
   TRY(hipEventCreate(&b->ev1));
   auto alloc = [&](void** p, size_t bytes) { return hipMalloc(p, bytes > 0 ? bytes : 16); };
-  TRY(alloc((void**)&b->d_tables, (size_t)b->total_tables * sizeof(float)));
-  TRY(alloc((void**)&b->d_phi, (size_t)b->total_phi * sizeof(float)));
+  TRY(alloc((void**)&b->d_tables, ((size_t)b->total_tables + kTailPad) * sizeof(float)));
+  TRY(alloc((void**)&b->d_phi, ((size_t)b->total_phi + kTailPad) * sizeof(float)));
   TRY(alloc((void**)&b->d_U, (size_t)b->total_u * sizeof(float)));
   TRY(alloc((void**)&b->d_Ulo, (size_t)b->total_u * sizeof(float)));
   TRY(alloc((void**)&b->d_unaries, (size_t)b->total_u * sizeof(float)));
@@ -391,7 +391,8 @@ int mplpxx_batch_create(int32_t count, const int32_t* n, const int32_t* L, const
   TRY(alloc((void**)&b->d_edge_min, (size_t)b->total_slots * sizeof(double)));
   TRY(alloc((void**)&b->d_duals, (size_t)count * sizeof(double)));
   hipStream_t cs = b->stream;
-  TRY(hipMemsetAsync(b->d_phi, 0, (size_t)b->total_phi * sizeof(float), cs));
+  TRY(hipMemsetAsync(b->d_phi, 0, ((size_t)b->total_phi + kTailPad) * sizeof(float), cs));
+  TRY(hipMemsetAsync(b->d_tables + b->total_tables, 0, kTailPad * sizeof(float), cs));
   TRY(hipMemsetAsync(b->d_err, 0, 8 * sizeof(int), cs));
   // per model: packed tables (slot order, transposed where given as (v, u)),
   // unaries, slot metadata, degrees, incidence lists, node/slot maps

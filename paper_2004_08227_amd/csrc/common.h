@@ -17,6 +17,12 @@ enum { ENGINE_AUTO = 0, ENGINE_STEP = 1, ENGINE_PERSISTENT = 2 };
 constexpr int kStampStride = MPLPXX_FINE_STAMPS ? 8 : 4;
 
 // One entry per schedule slot (slot i = i-th edge of the schedule queue).
+// Elements allocated (zeroed) past the end of every tables and messages
+// array: the FP32 engines load whole tile rows without clamping the column
+// index, so a row of a table (or of a slot's messages) may read up to LT
+// elements into whatever follows it.
+constexpr size_t kTailPad = 256;
+
 struct SlotInfo {
   int e;       // index of the edge in the caller's edge list
   int u, v;    // its nodes, u < v

@@ -400,16 +400,16 @@ __device__ __forceinline__ void load_tile_raw(const float* __restrict__ tab, int
       }
     }
   } else {
+    // rows clamped, columns not: a row segment runs on into the next row
+    // (or past the table, into the allocation's zeroed tail); those entries
+    // are replaced by the pad in pad_tile.  One address per row, immediate
+    // offsets for the columns.
 #pragma unroll
     for (int i = 0; i < S::BR; ++i) {
       const int s = rb * S::BR + i;
-      const int sc = (FULL || s < L) ? s : L - 1;
+      const float* row = tab + ((FULL || s < L) ? s : L - 1) * L + cb * S::BC;
 #pragma unroll
-      for (int j = 0; j < S::BC; ++j) {
-        const int t = cb * S::BC + j;
-        const int tc = (FULL || t < L) ? t : L - 1;
-        x[i][j] = tab[sc * L + tc];
-      }
+      for (int j = 0; j < S::BC; ++j) x[i][j] = row[j];
     }
   }
 }
@@ -435,15 +435,24 @@ __device__ __forceinline__ void load_phi(const float* src, int L, float (&pu)[Ti
                                          float (&pv)[TileShape<float, LT, NT>::BC]) {
   using S = TileShape<float, LT, NT>;
   const int rb = threadIdx.x >> 4, cb = threadIdx.x & 15;
+  if (PHI_LDS) {
 #pragma unroll
-  for (int i = 0; i < S::BR; ++i) {
-    const int s = rb * S::BR + i;
-    pu[i] = src[(FULL || s < L) ? s : L - 1];
-  }
+    for (int i = 0; i < S::BR; ++i) {
+      const int s = rb * S::BR + i;
+      pu[i] = src[(FULL || s < L) ? s : L - 1];
+    }
 #pragma unroll
-  for (int jj = 0; jj < S::BC; ++jj) {
-    const int t = cb * S::BC + jj;
-    pv[jj] = src[L + ((FULL || t < L) ? t : L - 1)];
+    for (int jj = 0; jj < S::BC; ++jj) {
+      const int t = cb * S::BC + jj;
+      pv[jj] = src[L + ((FULL || t < L) ? t : L - 1)];
+    }
+  } else {
+    // global messages: no clamping (padded labels read the following
+    // messages or the allocation's zeroed tail; any finite value will do)
+#pragma unroll
+    for (int i = 0; i < S::BR; ++i) pu[i] = src[rb * S::BR + i];
+#pragma unroll
+    for (int jj = 0; jj < S::BC; ++jj) pv[jj] = src[L + cb * S::BC + jj];
   }
 }
 

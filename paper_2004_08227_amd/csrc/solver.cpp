@@ -227,8 +227,8 @@ int create_impl(int32_t n, int32_t L, int64_t m, const int32_t* edges, const voi
   TRY(hipEventCreate(&h->ev0));
   TRY(hipEventCreate(&h->ev1));
   hipError_t ae = hipSuccess;
-  h->d_tables = dalloc<char>(mLL * esz, &ae); TRY(ae);
-  h->d_phi = dalloc<char>((size_t)m * 2 * L * esz, &ae); TRY(ae);
+  h->d_tables = dalloc<char>(mLL * esz + kTailPad * esz, &ae); TRY(ae);
+  h->d_phi = dalloc<char>((size_t)m * 2 * L * esz + kTailPad * esz, &ae); TRY(ae);
   h->d_U = dalloc<char>(nL * esz, &ae); TRY(ae);
   h->d_unaries = dalloc<char>(nL * esz, &ae); TRY(ae);
   h->d_slots = dalloc<SlotInfo>(m, &ae); TRY(ae);
@@ -267,7 +267,8 @@ int create_impl(int32_t n, int32_t L, int64_t m, const int32_t* edges, const voi
   if (m) TRY(hipMemcpyAsync(h->d_inc, inc.data(), inc.size() * sizeof(int), hipMemcpyHostToDevice, st));
   if (m) TRY(hipMemcpyAsync(h->d_slots, h->slots.data(), m * sizeof(SlotInfo), hipMemcpyHostToDevice, st));
   TRY(hipMemcpyAsync(h->d_deg, h->deg.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
-  TRY(hipMemsetAsync(h->d_phi, 0, (size_t)m * 2 * L * esz, st));
+  TRY(hipMemsetAsync(h->d_phi, 0, (size_t)m * 2 * L * esz + kTailPad * esz, st));
+  TRY(hipMemsetAsync(static_cast<char*>(h->d_tables) + mLL * esz, 0, kTailPad * esz, st));
   TRY(hipMemsetAsync(h->d_err, 0, 8 * sizeof(int), st));
 
   if (!device_costs) {
