@@ -28,6 +28,37 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "edge-block updates/s + HBM GB/s fraction; time-to-dual-bound vs plain, 1 MI355X"
 
+# HBM traffic of the measured kernel from rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE runs (profiles/k_persistent_mb_pose_k200_l64.md): KiB per
+# iteration of the pose n=200/L=64 launch, and the factors that map each
+# counter to bytes, from the same counters on a 1 GiB copy.  Valid only for
+# the kernel sources they were taken on (hash below); otherwise null.
+TRAFFIC = {"src_sha": "79df13ca27063fbf", "fetch_kib_per_iter": 3768746.375 / 20, "fetch_scale": 2.0,
+           "write_kib_per_iter": 806080.125 / 20, "write_scale": 1.0}
+TRAFFIC_SRCS = ("paper_2004_08227_amd/csrc/common.h", "paper_2004_08227_amd/csrc/device_common.h",
+                "paper_2004_08227_amd/csrc/handshake.hip")
+
+
+def kernel_src_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SRCS:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(iters):
+    """HBM bytes of one launch of `iters` iterations, or None if the kernel
+    changed since the counters were taken."""
+    try:
+        if kernel_src_sha() != TRAFFIC["src_sha"]:
+            return None
+    except OSError:
+        return None
+    kib = TRAFFIC["fetch_kib_per_iter"] * TRAFFIC["fetch_scale"] + TRAFFIC["write_kib_per_iter"] * TRAFFIC["write_scale"]
+    return kib * 1024.0 * iters
+
 
 def algorithmic_bytes_per_update(L, esz=4):
     # read-only L x L table + read and write the edge's 2L messages
@@ -124,6 +155,7 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=8)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--only-batch", action="store_true", help="run only the batched-mix section")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -132,6 +164,10 @@ def main():
     import torch
     import paper_2004_08227_amd as M
     from paper_2004_08227_amd import workloads as W
+
+    if args.only_batch:
+        print(json.dumps({"batched": bench_batched(M, W)}))
+        return
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     n, L, seed = 200, 64, 0
@@ -188,7 +224,8 @@ def main():
         "hbm_frac": gbs / HBM_PEAK_GBS,
         "dual_bound": d_final,
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic(K) if s.info("engine") == 2 else None,
+                     "traffic_unit": "bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated)",
                      "kernel": (f"k_persistent_mb<{L},{s.info('threads')},...>" if s.info("engine") == 2
                                 else f"k_step<float,{L},{s.info('threads')}>"),
                      "bytes_per_update": B, "updates_per_launch": m * K if s.info("engine") == 2 else m // s.info("steps")},
@@ -196,14 +233,24 @@ def main():
     if not args.no_cpu:
         cb = cpu_baseline(model, args.cpu_iters)
         result["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
-        d_star = float(trace.max())
+        # the oracle's own trajectory: its stored 200-iteration trace on this
+        # model (written by tests/golden/make_golden.py from the oracle alone)
+        ref = None
+        gold = os.path.join(ROOT, "tests", "golden", "pose_k200_l64.json")
+        if os.path.exists(gold):
+            g = json.load(open(gold))
+            if g.get("workload") == "pose n=200 L=64 seed=0":
+                ref = np.asarray(g["trace"][:K])
+        d_star = float(max(trace.max(), ref.max() if ref is not None else -np.inf))
         eps = [1e-1, 1e-2, 1e-3, 1e-4, 1e-5]
         gpu_tt = time_to_bound(trace, t_iter, d_star, eps)
-        cpu_tt = time_to_bound(trace, cb["s_per_iter"], d_star, eps)
+        cpu_tt = time_to_bound(ref if ref is not None else trace, cb["s_per_iter"], d_star, eps)
         result["time_to_dual_bound"] = {
             "d_star": d_star, "eps_rel": eps, "gpu_s": gpu_tt, "plain_oracle_s": cpu_tt,
-            "note": "iterations to reach D* - eps|D*| read from the GPU trace (the oracle's trace agrees to 1e-5); "
-                    "oracle seconds = those iterations x its measured seconds per iteration"}
+            "oracle_cores": cb["cores"],
+            "note": "seconds until the dual bound reaches D* - eps|D*| (D* = best value of either run after "
+                    f"{K} iterations): GPU = its trace's iterations x its measured time per iteration; plain "
+                    "oracle = the iterations of its own stored trace x its measured seconds per iteration"}
     s.close()
     if not args.no_batch:
         result["batched"] = bench_batched(M, W)
