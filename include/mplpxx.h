@@ -294,6 +294,19 @@ int mplpxx_batch_reset(mplpxx_batch* b);
 #define MPLPXX_BOPT_EDGE128_US 9     /*                                   L <= 128 */
 #define MPLPXX_BOPT_LDS 10           /* 1 (default): a model on one workgroup keeps its unaries in LDS
                                         when they fit; 0: always through the mailboxes */
+#define MPLPXX_BOPT_ENGINE 11        /* 0 (default): the wave engine when every L <= 64, else the
+                                        workgroup engine; 1: workgroup engine (one update at a time per
+                                        workgroup, the single-model engine's kernel code); 2: wave engine
+                                        (one update per wavefront, many in flight per workgroup; L <= 64,
+                                        else MPLPXX_EINVAL when the plan is made) */
+#define MPLPXX_BOPT_WAVE_EDGE16_US 12 /* wave-engine planner: workgroup time per edge update, L <= 16 */
+#define MPLPXX_BOPT_WAVE_EDGE32_US 13 /*                                                      L <= 32 */
+#define MPLPXX_BOPT_WAVE_EDGE64_US 14 /*                                                      L <= 64 */
+#define MPLPXX_BOPT_WAVE_LAT_LDS_US 15 /* wave-engine planner: latency of one update, unaries in LDS */
+#define MPLPXX_BOPT_WAVE_LAT_MB_US 16  /* wave-engine planner: latency of one update through mailboxes */
+#define MPLPXX_BOPT_QUEUE 17         /* 1 (default): models on one workgroup are taken, longest first,
+                                        from a shared queue by whichever workgroup is free; 0: packed
+                                        onto workgroups by the planner */
 int mplpxx_batch_set_option(mplpxx_batch* b, int32_t key, double value);
 
 #define MPLPXX_BINFO_COUNT 1
@@ -307,7 +320,21 @@ int mplpxx_batch_set_option(mplpxx_batch* b, int32_t key, double value);
 #define MPLPXX_BINFO_TABLE_BYTES 9   /* bytes of pairwise tables */
 #define MPLPXX_BINFO_LDS_TASKS 10    /* models run with LDS-resident unaries */
 #define MPLPXX_BINFO_LDS_BYTES 11    /* dynamic LDS per workgroup of the launch */
+#define MPLPXX_BINFO_ENGINE 12       /* engine of the plan: 1 workgroup, 2 wave */
+#define MPLPXX_BINFO_WAVES 13        /* wave engine: waves (workers) per workgroup */
+#define MPLPXX_BINFO_WG_MAX_US 14    /* last launch: longest start-to-end time of a workgroup (us) */
+#define MPLPXX_BINFO_WG_MEAN_US 15   /* last launch: mean start-to-end time of the workgroups (us) */
 int mplpxx_batch_get_info(mplpxx_batch* b, int32_t key, double* value);
+
+/* Where the last launch spent its time, per logical workgroup w (0 <= w <
+ * MPLPXX_BINFO_GRID): start_end_us[2w], start_end_us[2w+1] = its start and
+ * end in microseconds after the earliest start (device clock, 10 ns
+ * resolution; caller-owned, 2 * grid doubles); team_model[w] = the model of
+ * its own (team) task, -1 if it ran only tasks from the shared queue
+ * (caller-owned, grid entries, may be NULL).  Before any launch of the
+ * current plan the times are 0.  Errors: MPLPXX_EINVAL for a NULL handle or
+ * start_end_us, MPLPXX_EDEVICE if the copy fails. */
+int mplpxx_batch_wg_profile(mplpxx_batch* b, double* start_end_us, int32_t* team_model);
 
 /* Frees the batch and its device memory; NULL is a no-op. */
 void mplpxx_batch_destroy(mplpxx_batch* b);

@@ -27,9 +27,12 @@ MAX_LABELS = 128
 OPT_ENGINE, OPT_THREADS, OPT_GRID, OPT_SPIN_LIMIT, OPT_PROFILE, OPT_ADJOINT_F64 = 1, 2, 3, 4, 5, 6
 ENGINE_AUTO, ENGINE_STEP, ENGINE_PERSISTENT = 0, 1, 2
 BOPT = {"grid": 1, "graph": 2, "spin_limit": 3, "one_per_model": 4, "handoff_us": 5, "edge16_us": 6,
-        "edge32_us": 7, "edge64_us": 8, "edge128_us": 9, "lds": 10}
+        "edge32_us": 7, "edge64_us": 8, "edge128_us": 9, "lds": 10, "engine": 11, "wave_edge16_us": 12,
+        "wave_edge32_us": 13, "wave_edge64_us": 14, "wave_lat_lds_us": 15, "wave_lat_mb_us": 16,
+        "queue": 17}
 BINFO = {"count": 1, "grid": 2, "tasks": 3, "teams": 4, "max_team": 5, "plan_us": 6, "edges": 7, "last_ms": 8,
-         "table_bytes": 9, "lds_tasks": 10, "lds_bytes": 11}
+         "table_bytes": 9, "lds_tasks": 10, "lds_bytes": 11, "engine": 12, "waves": 13,
+         "wg_max_us": 14, "wg_mean_us": 15}
 INFO = {"n": 1, "L": 2, "m": 3, "steps": 4, "dtype": 5, "engine": 6, "grid": 7, "threads": 8, "iterations": 9,
         "wallclock_khz": 10}
 
@@ -93,6 +96,7 @@ def lib():
         "mplpxx_batch_reset": (ctypes.c_int, [vp]),
         "mplpxx_batch_set_option": (ctypes.c_int, [vp, i32, dbl]),
         "mplpxx_batch_get_info": (ctypes.c_int, [vp, i32, ctypes.POINTER(dbl)]),
+        "mplpxx_batch_wg_profile": (ctypes.c_int, [vp, vp, vp]),
         "mplpxx_batch_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
@@ -353,3 +357,13 @@ class Batch:
         v = ctypes.c_double()
         _check(lib().mplpxx_batch_get_info(self._h, BINFO[key], ctypes.byref(v)))
         return v.value
+
+    def wg_profile(self):
+        """(start_end_us [grid, 2], team_model [grid]) of the last launch:
+        each logical workgroup's start and end (microseconds after the
+        earliest start) and the model of its own team task (-1: queue only)."""
+        g = int(self.info("grid"))
+        se = np.zeros((g, 2), np.float64)
+        tm = np.zeros(g, np.int32)
+        _check(lib().mplpxx_batch_wg_profile(self._h, se.ctypes.data, tm.ctypes.data))
+        return se, tm

@@ -8,12 +8,22 @@
 // handoff; m_b / T edge updates per member, one after another), as
 //   t_b = m_b * t_edge(LT_b)
 // for a model on one workgroup with its unaries in LDS (no handoffs), and
-// never less than the member's share of HBM traffic.  The planner binary-searches a
-// makespan tau: every model gets the smallest team with t_b(T) <= tau (at most
-// one member per edge of its largest matching), teams take workgroups first,
-// and single-workgroup models are packed onto the least-loaded workgroups
-// (longest first).  The constants t_hand and t_edge are options, so a tuner
-// can calibrate them; they change only the assignment, never the results.
+// never less than the member's share of HBM traffic.  The planner
+// binary-searches a makespan tau: every model gets the smallest team with
+// t_b(T) <= tau (at most one member per edge of its largest matching), teams
+// take the first workgroups, and single-workgroup models are packed, longest
+// first, onto the least-loaded workgroups (which tau is feasible).  By default
+// the single-workgroup models then go, longest first, to a shared queue from
+// which every workgroup takes the next model once its own tasks are done, so
+// errors in the time estimates do not unbalance the launch.  The time
+// constants are options, so a tuner can calibrate them; they change only the
+// assignment, never the results.
+//
+// Engines.  With every L <= 64 the launch runs the wave engine (one edge
+// update per wavefront, twelve workers per workgroup; wave_engine.h), whose
+// time model is in wave_model_time; otherwise the workgroup engine (the
+// mailbox engine's kernel code, one update at a time per workgroup).  Both
+// give every model bitwise the results of the single-model engine.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -27,6 +37,7 @@
 #include "common.h"
 #include "host_util.h"
 #include "schedule.h"
+#include "wave_batch.h"
 
 using namespace mplpxx;
 
@@ -57,7 +68,8 @@ struct mplpxx_batch {
   int* d_task_ptr = nullptr;
   int* d_err = nullptr;
   int* d_ticket = nullptr;
-  unsigned long long* d_sink = nullptr;  // [grid][384] scratch words of the workgroups
+  unsigned long long* d_sink = nullptr;  // scratch words of the workgroups
+  long long* d_wg_time = nullptr;        // [grid][2] clocks of the last launch
   int* d_node_model = nullptr;
   int* d_slot_model = nullptr;
   int* d_node_ptr = nullptr;
@@ -74,10 +86,23 @@ struct mplpxx_batch {
   double t_hand_us = 0.7;
   double t_edge_us[4] = {0.30, 0.45, 0.85, 2.0};  // LT 16, 32, 64, 128
   int one_per_model = 0;
+  int use_queue = 1;           // single-workgroup models from a shared queue (else statically packed)
+  int qbegin = 0, qlen = 0;
+  std::vector<int> wg_team_model;  // model of each workgroup's own task, -1 none
   int use_lds = 1;             // LDS-resident unaries for models on one workgroup
   size_t lds_limit = 0;        // dynamic LDS a workgroup can have
   size_t lds_bytes = 0;        // dynamic LDS of the launch
   int lds_tasks = 0;
+  // wave engine (one wave per edge update; models with L <= 64)
+  int engine_opt = 0;          // 0 auto, 1 workgroup (mailbox) engine, 2 wave engine
+  bool wave = false;           // the plan runs the wave engine
+  double wv_edge_us[3] = {0.05, 0.08, 0.13};  // workgroup time per edge update besides its bytes, LT 16, 32, 64
+  double wv_lat_lds_us = 2.4;  // latency of one update, unaries in LDS
+  double wv_lat_mb_us = 2.0;   // latency of one update through the mailboxes
+  size_t wv_static = 0;        // static LDS of the wave kernel
+  size_t wv_lds_limit = 0;     // dynamic LDS a workgroup of the wave kernel can have
+  size_t wv_lds_cap = 0;       // dynamic LDS that keeps the kernel's register-limited occupancy
+  int wv_waves = 8;
   bool plan_dirty = true;
   // execution
   hipStream_t stream = nullptr;
@@ -95,12 +120,31 @@ namespace {
 int lt_index(int lt) { return lt == 16 ? 0 : lt == 32 ? 1 : lt == 64 ? 2 : 3; }
 
 bool lds_fits(const mplpxx_batch* b, int i) {
-  return b->use_lds && lds_model_bytes(b->mh[i].n, b->mh[i].L) <= b->lds_limit;
+  if (!b->use_lds) return false;
+  if (b->wave) return wv_lds_bytes(b->mh[i].n, b->mh[i].L) <= b->wv_lds_cap;
+  return lds_model_bytes(b->mh[i].n, b->mh[i].L) <= b->lds_limit;
+}
+
+// Wave engine: a team of T workgroups is T * NW workers.  Per iteration a
+// model needs m / T edge updates of workgroup time, each t_w(LT) plus its
+// bytes at the workgroup's share of the achievable HBM bandwidth (about 3/4
+// of the nominal 8 TB/s), and S matchings one after another, each of
+// ceil(max_step / (T NW)) rounds of one update latency.
+double wave_model_time(const mplpxx_batch* b, int i, int T, double bw_per_wg_bytes_us) {
+  const ModelHost& h = b->mh[i];
+  const double tw = b->wv_edge_us[std::min(2, lt_index(h.lt))];
+  const double lat = (T == 1 && lds_fits(b, i)) ? b->wv_lat_lds_us : b->wv_lat_mb_us;
+  const double workers = (double)T * b->wv_waves;
+  const double chain = h.S * std::ceil(h.max_step / workers) * lat;
+  const double bytes = 4.0 * h.L * h.L + 16.0 * h.L;
+  const double work = (double)h.m / T * (tw + bytes / (0.75 * bw_per_wg_bytes_us));
+  return std::max(chain, work);
 }
 
 double model_time(const mplpxx_batch* b, int i, int T, double bw_per_wg_bytes_us) {
   const ModelHost& h = b->mh[i];
   if (h.m == 0) return 0.0;
+  if (b->wave) return wave_model_time(b, i, T, bw_per_wg_bytes_us);
   const double te = b->t_edge_us[lt_index(h.lt)];
   const double lat = (T == 1 && lds_fits(b, i)) ? h.m * te : h.S * (b->t_hand_us + 0.5 * te) + (double)h.m / T * te;
   const double bytes = (double)h.m * (4.0 * h.L * h.L + 16.0 * h.L) / T;
@@ -123,13 +167,14 @@ double assign(const mplpxx_batch* b, double tau, int G, int team_cap, double bw,
     int T = 1;
     if (!b->one_per_model) {
       // smallest team meeting tau (model_time decreases with T)
+      const double target = tau;
       int lo = 1, hi = tmax;
-      if (model_time(b, i, tmax, bw) > tau) {
+      if (model_time(b, i, tmax, bw) > target) {
         T = tmax;
       } else {
         while (lo < hi) {
           const int mid = (lo + hi) / 2;
-          if (model_time(b, i, mid, bw) <= tau) hi = mid; else lo = mid + 1;
+          if (model_time(b, i, mid, bw) <= target) hi = mid; else lo = mid + 1;
         }
         T = lo;
       }
@@ -172,11 +217,25 @@ double assign(const mplpxx_batch* b, double tau, int G, int team_cap, double bw,
 }
 
 int plan(mplpxx_batch* b) {
+  if (b->engine_opt == 2 && b->max_lt > 64) return fail(MPLPXX_EINVAL, "the wave engine takes models with L <= 64");
+  b->wave = b->engine_opt == 2 || (b->engine_opt == 0 && b->max_lt <= 64);
+  if (b->wave) {
+    // LDS-resident models only as large as keeps the register-limited
+    // number of workgroups per compute unit
+    int dev = 0, cu_lds = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cu_lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess)
+      return fail(MPLPXX_EDEVICE, "device query failed");
+    const int o = std::max(1, wbatch_blocks_per_cu(0));
+    const size_t share = (size_t)cu_lds / o;
+    b->wv_lds_cap = share > b->wv_static + 256 ? std::min(b->wv_lds_limit, share - b->wv_static - 256) : 0;
+  }
   // dynamic LDS: enough for the largest model that could keep its unaries there
   size_t dyn = 0;
   for (int i = 0; i < b->count; ++i)
-    if (b->mh[i].m > 0 && lds_fits(b, i)) dyn = std::max(dyn, lds_model_bytes(b->mh[i].n, b->mh[i].L));
-  const int per_cu = batch_blocks_per_cu(b->max_lt, dyn);
+    if (b->mh[i].m > 0 && lds_fits(b, i))
+      dyn = std::max(dyn, b->wave ? wv_lds_bytes(b->mh[i].n, b->mh[i].L) : lds_model_bytes(b->mh[i].n, b->mh[i].L));
+  const int per_cu = b->wave ? wbatch_blocks_per_cu(dyn) : batch_blocks_per_cu(b->max_lt, dyn);
   if (per_cu < 1) return fail(MPLPXX_EDEVICE, "batched kernel does not fit on a compute unit");
   const int gmax = per_cu * b->num_cus;
   int G = b->grid_opt > 0 ? std::min(b->grid_opt, gmax) : gmax;
@@ -211,19 +270,40 @@ int plan(mplpxx_batch* b) {
       lo = mid;
     }
   }
-  std::vector<BatchTask> tasks;
+  // each workgroup's own tasks; with the queue, the single-workgroup tasks
+  // (stride 1) go, longest first as packed, to the shared queue instead
+  std::vector<BatchTask> tasks, queued;
   std::vector<int> ptr(G + 1, 0);
   for (int w = 0; w < G; ++w) {
-    for (const BatchTask& t : best[w]) tasks.push_back(t);
+    for (const BatchTask& t : best[w]) {
+      if (b->use_queue && t.stride == 1) queued.push_back(t);
+      else tasks.push_back(t);
+    }
     ptr[w + 1] = (int)tasks.size();
   }
+  if (b->use_queue) {
+    std::stable_sort(queued.begin(), queued.end(), [&](const BatchTask& x, const BatchTask& y) {
+      return model_time(b, x.model, 1, bw) > model_time(b, y.model, 1, bw);
+    });
+  }
+  b->wg_team_model.assign(G, -1);
+  for (int w = 0; w < G; ++w)
+    if (ptr[w + 1] > ptr[w]) b->wg_team_model[w] = tasks[ptr[w]].model;
+  b->qbegin = (int)tasks.size();
+  b->qlen = (int)queued.size();
+  tasks.insert(tasks.end(), queued.begin(), queued.end());
   if (b->d_tasks) (void)hipFree(b->d_tasks);
   if (b->d_task_ptr) (void)hipFree(b->d_task_ptr);
   if (b->d_sink) (void)hipFree(b->d_sink);
+  if (b->d_wg_time) (void)hipFree(b->d_wg_time);
   b->d_tasks = nullptr;
   b->d_task_ptr = nullptr;
   b->d_sink = nullptr;
-  HIP_TRY(hipMalloc(&b->d_sink, (size_t)G * (256 + 128) * sizeof(unsigned long long)));
+  b->d_wg_time = nullptr;
+  const size_t sink_words = b->wave ? wbatch_sink_words() : (size_t)(256 + 128);
+  HIP_TRY(hipMalloc(&b->d_sink, (size_t)G * sink_words * sizeof(unsigned long long)));
+  HIP_TRY(hipMalloc(&b->d_wg_time, (size_t)G * 2 * sizeof(long long)));
+  HIP_TRY(hipMemsetAsync(b->d_wg_time, 0, (size_t)G * 2 * sizeof(long long), b->stream));
   HIP_TRY(hipMalloc(&b->d_tasks, std::max<size_t>(1, tasks.size()) * sizeof(BatchTask)));
   HIP_TRY(hipMalloc(&b->d_task_ptr, (G + 1) * sizeof(int)));
   // every copy and fill goes through the batch's own (non-blocking) stream, so
@@ -251,8 +331,8 @@ int plan(mplpxx_batch* b) {
 
 void free_batch(mplpxx_batch* b) {
   void* ptrs[] = {b->d_tables, b->d_phi, b->d_U, b->d_Ulo, b->d_unaries, b->d_mb, b->d_slots, b->d_deg, b->d_models,
-                  b->d_tasks, b->d_task_ptr, b->d_err, b->d_ticket, b->d_sink, b->d_node_model, b->d_slot_model, b->d_node_ptr,
-                  b->d_inc, b->d_node_min, b->d_edge_min, b->d_duals};
+                  b->d_tasks, b->d_task_ptr, b->d_err, b->d_ticket, b->d_sink, b->d_wg_time, b->d_node_model,
+                  b->d_slot_model, b->d_node_ptr, b->d_inc, b->d_node_min, b->d_edge_min, b->d_duals};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
@@ -273,13 +353,17 @@ hipError_t enqueue(mplpxx_batch* b, int k) {
   a.task_ptr = b->d_task_ptr;
   a.ticket = b->d_ticket;
   a.sink = b->d_sink;
+  a.wg_time = b->d_wg_time;
   a.err = b->d_err;
   a.spin_limit = b->spin_limit;
-  hipError_t e = launch_fill_int(b->d_ticket, 0, 1, b->stream);
+  a.qbegin = b->qbegin;
+  a.qlen = b->qlen;
+  hipError_t e = launch_fill_int(b->d_ticket, 0, 2, b->stream);
   if (e != hipSuccess) return e;
   e = launch_u_to_mb(b->d_U, b->d_Ulo, b->d_mb, (size_t)b->total_u, b->stream);
   if (e != hipSuccess) return e;
-  e = launch_batch(a, b->max_lt, b->grid, k, b->lds_bytes, b->stream);
+  e = b->wave ? launch_wbatch(a, b->grid, k, b->lds_bytes, b->stream)
+              : launch_batch(a, b->max_lt, b->grid, k, b->lds_bytes, b->stream);
   if (e != hipSuccess) return e;
   return launch_mb_to_u(b->d_U, b->d_Ulo, b->d_mb, (size_t)b->total_u, b->stream);
 }
@@ -368,6 +452,8 @@ int mplpxx_batch_create(int32_t count, const int32_t* n, const int32_t* L, const
   TRY(hipGetDevice(&dev));
   TRY(hipDeviceGetAttribute(&b->num_cus, hipDeviceAttributeMultiprocessorCount, dev));
   b->lds_limit = batch_lds_limit(b->max_lt);
+  b->wv_lds_limit = wbatch_lds_limit(&b->wv_static);
+  b->wv_waves = wbatch_waves();
   TRY(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
   TRY(hipEventCreate(&b->ev0));
   TRY(hipEventCreate(&b->ev1));
@@ -382,7 +468,7 @@ int mplpxx_batch_create(int32_t count, const int32_t* n, const int32_t* L, const
   TRY(alloc((void**)&b->d_deg, (size_t)b->total_nodes * sizeof(int)));
   TRY(alloc((void**)&b->d_models, (size_t)count * sizeof(BatchModel)));
   TRY(alloc((void**)&b->d_err, 8 * sizeof(int)));
-  TRY(alloc((void**)&b->d_ticket, sizeof(int)));
+  TRY(alloc((void**)&b->d_ticket, 2 * sizeof(int)));
   TRY(alloc((void**)&b->d_node_model, (size_t)b->total_nodes * sizeof(int)));
   TRY(alloc((void**)&b->d_slot_model, (size_t)b->total_slots * sizeof(int)));
   TRY(alloc((void**)&b->d_node_ptr, (size_t)b->total_csr * sizeof(int)));
@@ -580,9 +666,54 @@ int mplpxx_batch_set_option(mplpxx_batch* b, int32_t key, double value) {
       b->t_edge_us[key - MPLPXX_BOPT_EDGE16_US] = value;
       b->plan_dirty = true;
       return MPLPXX_OK;
+    case MPLPXX_BOPT_QUEUE:
+      b->use_queue = value != 0;
+      b->plan_dirty = true;
+      return MPLPXX_OK;
+    case MPLPXX_BOPT_ENGINE:
+      if (value != 0 && value != 1 && value != 2) return fail(MPLPXX_EINVAL, "engine must be 0, 1 or 2");
+      b->engine_opt = (int)value;
+      b->plan_dirty = true;
+      return MPLPXX_OK;
+    case MPLPXX_BOPT_WAVE_EDGE16_US:
+    case MPLPXX_BOPT_WAVE_EDGE32_US:
+    case MPLPXX_BOPT_WAVE_EDGE64_US:
+      if (!(value > 0)) return fail(MPLPXX_EINVAL, "edge time must be > 0");
+      b->wv_edge_us[key - MPLPXX_BOPT_WAVE_EDGE16_US] = value;
+      b->plan_dirty = true;
+      return MPLPXX_OK;
+    case MPLPXX_BOPT_WAVE_LAT_LDS_US:
+      if (!(value > 0)) return fail(MPLPXX_EINVAL, "latency must be > 0");
+      b->wv_lat_lds_us = value;
+      b->plan_dirty = true;
+      return MPLPXX_OK;
+    case MPLPXX_BOPT_WAVE_LAT_MB_US:
+      if (!(value > 0)) return fail(MPLPXX_EINVAL, "latency must be > 0");
+      b->wv_lat_mb_us = value;
+      b->plan_dirty = true;
+      return MPLPXX_OK;
     default:
       return fail(MPLPXX_EINVAL, "unknown batch option %d", key);
   }
+}
+
+int mplpxx_batch_wg_profile(mplpxx_batch* b, double* start_end_us, int32_t* team_model) {
+  if (!b || !start_end_us) return fail(MPLPXX_EINVAL, "NULL argument");
+  if (b->plan_dirty) {
+    const int rc = plan(b);
+    if (rc != MPLPXX_OK) return rc;
+  }
+  std::vector<long long> t((size_t)b->grid * 2);
+  HIP_TRY(hipMemcpyAsync(t.data(), b->d_wg_time, t.size() * sizeof(long long), hipMemcpyDeviceToHost, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  long long t0 = t.empty() ? 0 : t[0];
+  for (int w = 0; w < b->grid; ++w) t0 = std::min(t0, t[2 * w]);
+  for (int w = 0; w < b->grid; ++w) {
+    start_end_us[2 * w] = (double)(t[2 * w] - t0) / 100.0;
+    start_end_us[2 * w + 1] = (double)(t[2 * w + 1] - t0) / 100.0;
+    if (team_model) team_model[w] = b->wg_team_model[w];
+  }
+  return MPLPXX_OK;
 }
 
 int mplpxx_batch_get_info(mplpxx_batch* b, int32_t key, double* value) {
@@ -603,6 +734,23 @@ int mplpxx_batch_get_info(mplpxx_batch* b, int32_t key, double* value) {
     case MPLPXX_BINFO_TABLE_BYTES: *value = (double)b->total_tables * sizeof(float); return MPLPXX_OK;
     case MPLPXX_BINFO_LDS_TASKS: *value = b->lds_tasks; return MPLPXX_OK;
     case MPLPXX_BINFO_LDS_BYTES: *value = (double)b->lds_bytes; return MPLPXX_OK;
+    case MPLPXX_BINFO_ENGINE: *value = b->wave ? 2 : 1; return MPLPXX_OK;
+    case MPLPXX_BINFO_WAVES: *value = b->wave ? b->wv_waves : 4; return MPLPXX_OK;
+    case MPLPXX_BINFO_WG_MAX_US:
+    case MPLPXX_BINFO_WG_MEAN_US: {
+      // start-to-end time of the workgroups in the last launch (100 MHz clock)
+      std::vector<long long> t((size_t)b->grid * 2);
+      HIP_TRY(hipMemcpyAsync(t.data(), b->d_wg_time, t.size() * sizeof(long long), hipMemcpyDeviceToHost, b->stream));
+      HIP_TRY(hipStreamSynchronize(b->stream));
+      double mx = 0.0, sum = 0.0;
+      for (int w = 0; w < b->grid; ++w) {
+        const double d = (double)(t[2 * w + 1] - t[2 * w]) / 100.0;
+        mx = std::max(mx, d);
+        sum += d;
+      }
+      *value = key == MPLPXX_BINFO_WG_MAX_US ? mx : sum / std::max(1, b->grid);
+      return MPLPXX_OK;
+    }
     default: return fail(MPLPXX_EINVAL, "unknown batch info key %d", key);
   }
 }

@@ -8,7 +8,14 @@
 // LDS keeps them there for the launch (no mailbox traffic, no waiting: the
 // workgroup orders its own updates with barriers).  The host plans the tasks
 // (batch.cpp).
+//
+// Two kernels run such task lists: k_batch, whose workgroups run the mailbox
+// engine (one update at a time, any L), and k_wbatch, whose waves each run
+// whole updates on the wave engine (L <= 64, many updates in flight per
+// compute unit).
 #include "device_common.h"
+#include "wave_engine.h"
+#include "wave_batch.h"
 
 namespace mplpxx {
 
@@ -33,9 +40,9 @@ __device__ __forceinline__ bool run_task(const BatchArgs& b, const BatchModel& m
   const bool far = owned >= kDepth + 2;
   if (!task.lds) {
     __syncthreads();
-    return far ? mb_run<LT, NT, false, false, false, false, true>(v, task.first, task.stride, iters, sm, nullptr,
+    return far ? mb_run<LT, NT, false, false, false, false, true, kDepth>(v, task.first, task.stride, iters, sm, nullptr,
                                                                   b.spin_limit, b.err)
-               : mb_run<LT, NT, false, false, false, false, false>(v, task.first, task.stride, iters, sm, nullptr,
+               : mb_run<LT, NT, false, false, false, false, false, kDepth>(v, task.first, task.stride, iters, sm, nullptr,
                                                                    b.spin_limit, b.err);
   }
   // the model's unaries into LDS (hi, and lo as bf16 bits), run, and back
@@ -48,8 +55,8 @@ __device__ __forceinline__ bool run_task(const BatchArgs& b, const BatchModel& m
     v.lds_lo[i] = (unsigned short)(__float_as_uint(mb_lo(w)) >> 16);
   }
   __syncthreads();
-  const bool ok = far ? mb_run<LT, NT, false, false, false, true, true>(v, 0, 1, iters, sm, nullptr, b.spin_limit, b.err)
-                     : mb_run<LT, NT, false, false, false, true, false>(v, 0, 1, iters, sm, nullptr, b.spin_limit,
+  const bool ok = far ? mb_run<LT, NT, false, false, false, true, true, kDepth>(v, 0, 1, iters, sm, nullptr, b.spin_limit, b.err)
+                     : mb_run<LT, NT, false, false, false, true, false, kDepth>(v, 0, 1, iters, sm, nullptr, b.spin_limit,
                                                                        b.err);
   __syncthreads();
   for (int i = threadIdx.x; i < nl; i += blockDim.x)
@@ -57,20 +64,42 @@ __device__ __forceinline__ bool run_task(const BatchArgs& b, const BatchModel& m
   return ok;
 }
 
+// A workgroup runs its own tasks (the planner gives each team member its
+// share of a team model), then takes single-workgroup tasks from the shared
+// queue, one at a time in queue order (longest first), until it is empty:
+// whichever workgroup is free next runs the next one, so the load balances
+// itself whatever the planner's time estimates.  Sets [t, end) to the next
+// task; false when the queue is empty.
+__device__ __forceinline__ bool next_queued(const BatchArgs& b, int& s_q, int& t, int& end) {
+  if (threadIdx.x == 0) s_q = atomicAdd(b.ticket + 1, 1);
+  __syncthreads();
+  const int q = s_q;
+  __syncthreads();  // every thread has read s_q before it is written again
+  if (q >= b.qlen) return false;
+  t = b.qbegin + q;
+  end = t + 1;
+  return true;
+}
+
 // at least two waves per SIMD: one 6-wave workgroup per compute unit, with
 // registers for every tile size without spills
 template <int NT, int MAXLT>
 __global__ void __launch_bounds__(NT + 128, 2) k_batch(BatchArgs b, int iters) {
   __shared__ BatchSmem<NT, MAXLT> sm;
-  __shared__ int s_wg;
+  __shared__ int s_wg, s_q;
   extern __shared__ __align__(16) unsigned char dyn_lds[];
   // logical workgroup = order of arrival: workgroups that hold a ticket have
   // started, so the first tickets (where the planner puts every team) run
   // together whatever order the hardware dispatches in
-  if (threadIdx.x == 0) s_wg = atomicAdd(b.ticket, 1);
+  if (threadIdx.x == 0) {
+    s_wg = atomicAdd(b.ticket, 1);
+    b.wg_time[2 * s_wg] = wall_clock64();
+  }
   __syncthreads();
   const int wg = s_wg;
-  for (int t = b.task_ptr[wg]; t < b.task_ptr[wg + 1]; ++t) {
+  int t = b.task_ptr[wg], end = b.task_ptr[wg + 1];
+  for (;;) {
+    if (t == end && !next_queued(b, s_q, t, end)) break;
     const BatchTask task = b.tasks[t];
     const BatchModel md = b.models[task.model];
     bool ok = true;
@@ -78,9 +107,11 @@ __global__ void __launch_bounds__(NT + 128, 2) k_batch(BatchArgs b, int iters) {
     else if (md.lt == 32) ok = run_task<32, NT>(b, md, task, sm.s32, iters, dyn_lds);
     else if (md.lt == 64 || MAXLT == 64) ok = run_task<64, NT>(b, md, task, sm.s64, iters, dyn_lds);
     else ok = run_task<(MAXLT > 64 ? 128 : 64), NT>(b, md, task, sm.s128, iters, dyn_lds);
-    if (!ok) return;
+    if (!ok) break;
     __syncthreads();  // shared memory is reused by the next task
+    ++t;
   }
+  if (threadIdx.x == 0) b.wg_time[2 * wg + 1] = wall_clock64();
 }
 
 static const void* batch_kernel(int max_lt) {
@@ -112,6 +143,120 @@ size_t batch_lds_limit(int max_lt) {
   if ((size_t)per_block <= fa.sharedSizeBytes) return 0;
   const size_t limit = (size_t)per_block - fa.sharedSizeBytes;
   if (hipFuncSetAttribute(batch_kernel(max_lt), hipFuncAttributeMaxDynamicSharedMemorySize, (int)limit) != hipSuccess)
+    return 0;
+  return limit;
+}
+
+// ---------------------------------------------------------------------------
+// The batched launch on the wave engine (wave_engine.h): every wave of a
+// workgroup is a worker.  Task (first, stride) of a team of `stride`
+// workgroups gives wave w of the member the slots first + w stride,
+// first + (w + NW) stride, ...; a whole model on one workgroup (stride 1)
+// deals its slots to the NW waves round-robin.
+// ---------------------------------------------------------------------------
+// twelve workers per compute unit: one 12-wave workgroup at three waves per
+// SIMD (168 registers hold the 64-label tile and its working vectors).
+// Measured on the batched pose mix, this beats 8 waves at two per SIMD and
+// two workgroups per compute unit (6 waves each, or 8 at four per SIMD,
+// which spills the 64-label path).
+#ifndef MPLPXX_WV_WAVES
+#define MPLPXX_WV_WAVES 12
+#endif
+#ifndef MPLPXX_WV_WPE
+#define MPLPXX_WV_WPE 3
+#endif
+constexpr int kWvWaves = MPLPXX_WV_WAVES;
+constexpr int kWvSink = 192;  // scratch words per wave
+
+template <int LT>
+__device__ __forceinline__ void wv_task(const BatchArgs& b, const BatchModel& md, const BatchTask& task,
+                                        WvScratch& scr, int iters, unsigned char* dyn, int* abort) {
+  const int wave = threadIdx.x >> 6;
+  WvView v{b.tables + uni(md.table_off), b.phi + uni(md.phi_off), b.mb + uni(md.u_off), b.slots + uni(md.slot_off),
+           uni(md.L), uni(md.m), uni(md.n), nullptr, nullptr, nullptr,
+           b.sink + ((size_t)blockIdx.x * kWvWaves + wave) * kWvSink};
+  const int first = uni(task.first + wave * task.stride);
+  const int stride = uni(task.stride * kWvWaves);
+  const int owned = first < md.m ? (md.m - first + stride - 1) / stride : 0;
+  const bool far = owned >= 2;
+  if (!task.lds) {
+    if (far) (void)wv_run<LT, false, true>(v, first, stride, iters, scr, b.spin_limit, b.err, abort);
+    else (void)wv_run<LT, false, false>(v, first, stride, iters, scr, b.spin_limit, b.err, abort);
+    return;
+  }
+  // the model's unaries and update counters into LDS, run, and back
+  const int nl = md.n * md.L;
+  v.lds_hi = reinterpret_cast<float*>(dyn);
+  v.lds_lo = reinterpret_cast<unsigned short*>(dyn + lds_lo_offset(md.n, md.L));
+  v.lds_ver = reinterpret_cast<int*>(dyn + wv_ver_offset(md.n, md.L));
+  for (int i = threadIdx.x; i < nl; i += blockDim.x) {
+    const unsigned long long w = v.mb[i];
+    v.lds_hi[i] = mb_hi(w);
+    v.lds_lo[i] = (unsigned short)(__float_as_uint(mb_lo(w)) >> 16);
+  }
+  for (int i = threadIdx.x; i < md.n; i += blockDim.x) v.lds_ver[i] = 0;
+  __syncthreads();
+  if (far) (void)wv_run<LT, true, true>(v, first, stride, iters, scr, b.spin_limit, b.err, abort);
+  else (void)wv_run<LT, true, false>(v, first, stride, iters, scr, b.spin_limit, b.err, abort);
+  __syncthreads();
+  for (int i = threadIdx.x; i < nl; i += blockDim.x)
+    v.mb[i] = mb_pack(v.lds_hi[i], __uint_as_float((unsigned)v.lds_lo[i] << 16), 0u);
+}
+
+__global__ void __launch_bounds__(kWvWaves * 64, MPLPXX_WV_WPE) k_wbatch(BatchArgs b, int iters) {
+  __shared__ WvScratch scr[kWvWaves];
+  __shared__ int s_wg, s_abort, s_q;
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
+  if (threadIdx.x == 0) {
+    s_wg = atomicAdd(b.ticket, 1);
+    s_abort = 0;
+    b.wg_time[2 * s_wg] = wall_clock64();
+  }
+  __syncthreads();
+  const int wg = s_wg;
+  WvScratch& my = scr[threadIdx.x >> 6];
+  int t = b.task_ptr[wg], end = b.task_ptr[wg + 1];
+  for (;;) {
+    if (t == end && !next_queued(b, s_q, t, end)) break;
+    const BatchTask task = b.tasks[t];
+    const BatchModel md = b.models[task.model];
+    if (md.lt == 16) wv_task<16>(b, md, task, my, iters, dyn_lds, &s_abort);
+    else if (md.lt == 32) wv_task<32>(b, md, task, my, iters, dyn_lds, &s_abort);
+    else wv_task<64>(b, md, task, my, iters, dyn_lds, &s_abort);
+    __syncthreads();  // LDS is reused by the next task; every wave has stopped
+    if (*(volatile int*)&s_abort) break;
+    ++t;
+  }
+  if (threadIdx.x == 0) b.wg_time[2 * wg + 1] = wall_clock64();
+}
+
+int wbatch_waves() { return kWvWaves; }
+size_t wbatch_sink_words() { return (size_t)kWvWaves * kWvSink; }
+
+hipError_t launch_wbatch(const BatchArgs& b, int grid, int iters, size_t dyn_lds, hipStream_t st) {
+  hipLaunchKernelGGL(k_wbatch, dim3(grid), dim3(kWvWaves * 64), dyn_lds, st, b, iters);
+  return hipGetLastError();
+}
+
+int wbatch_blocks_per_cu(size_t dyn_lds) {
+  int nb = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_wbatch, kWvWaves * 64, dyn_lds);
+  return e == hipSuccess ? nb : 0;
+}
+
+// static LDS of the wave kernel, and the largest dynamic LDS it can have
+// (raises the kernel's limit to it)
+size_t wbatch_lds_limit(size_t* static_bytes) {
+  int dev = 0, per_block = 0;
+  if (static_bytes) *static_bytes = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 0;
+  hipFuncAttributes fa{};
+  if (hipFuncGetAttributes(&fa, (const void*)k_wbatch) != hipSuccess) return 0;
+  if (static_bytes) *static_bytes = fa.sharedSizeBytes;
+  if ((size_t)per_block <= fa.sharedSizeBytes) return 0;
+  const size_t limit = (size_t)per_block - fa.sharedSizeBytes;
+  if (hipFuncSetAttribute((const void*)k_wbatch, hipFuncAttributeMaxDynamicSharedMemorySize, (int)limit) != hipSuccess)
     return 0;
   return limit;
 }

@@ -78,8 +78,10 @@ struct BatchArgs {
   const BatchModel* models;
   const BatchTask* tasks;
   const int* task_ptr;    // [G+1] task range of each logical workgroup
-  int* ticket;            // start-order counter (zeroed before each launch)
-  unsigned long long* sink;  // [grid][NT + 128] scratch words
+  int* ticket;            // [0] start-order counter, [1] queue head (both zeroed before each launch)
+  int qbegin, qlen;       // tasks[qbegin, qbegin + qlen): single-workgroup tasks taken in order by free workgroups
+  unsigned long long* sink;  // scratch words of the workgroups (stores of lanes without an output)
+  long long* wg_time;        // [grid][2] start and end clock of each logical workgroup
   int* err;
   long long spin_limit;
 };

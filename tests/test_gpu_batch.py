@@ -1,10 +1,12 @@
-"""GPU tests of the batched engine (many models in one persistent launch).
+"""GPU tests of the batched engines (many models in one persistent launch).
 
 Every model of a batch must end bitwise equal to the same model solved alone
 by the single-model persistent engine (same per-edge arithmetic, same
-schedule), and its dual bound must match the FP64 oracle to 1e-5.  Graph
-replays are checked against plain launches after every replay, with other
-device work in between; planning options must not change any bit."""
+schedule), whichever batched engine runs it (the workgroup engine, one update
+at a time per workgroup, or the wave engine, one update per wavefront), and
+its dual bound must match the FP64 oracle to 1e-5.  Graph replays are checked
+against plain launches after every replay, with other device work in
+between; planning options and the engine must not change any bit."""
 import numpy as np
 import pytest
 
@@ -40,15 +42,17 @@ def _alone(model, iters):
         return s.get_state(comp=True)
 
 
-@pytest.mark.parametrize("with_big_labels", [False, True])
-def test_batch_equals_single_model_runs_and_oracle(with_big_labels):
-    _announce("batch vs single", with_big_labels)
+@pytest.mark.parametrize("with_big_labels,engine", [(False, 0), (False, 1), (True, 0)])
+def test_batch_equals_single_model_runs_and_oracle(with_big_labels, engine):
+    _announce("batch vs single", with_big_labels, engine)
     models = _mixed_models()
     if with_big_labels:
         models.append(W.uniform(9, 100, seed=3))
     iters = 7
     with M.Batch(models) as b:
+        b.set_option("engine", engine)
         b.iterate(iters)
+        assert b.info("engine") == (1 if with_big_labels or engine == 1 else 2)
         duals = b.dual_bounds()
         states = [b.get_state(i, comp=True) for i in range(len(models))]
         assert b.info("count") == len(models)
@@ -67,7 +71,10 @@ def test_plans_and_graph_replays_are_bitwise_identical():
     results = []
     for opts in [dict(graph=0), dict(graph=1), dict(one_per_model=1), dict(grid=5), dict(grid=3, one_per_model=1),
                  dict(handoff_us=5.0, edge64_us=0.1), dict(lds=0), dict(lds=0, one_per_model=1),
-                 dict(lds=1, one_per_model=1, grid=2)]:
+                 dict(lds=1, one_per_model=1, grid=2), dict(engine=1), dict(engine=1, lds=0),
+                 dict(engine=1, one_per_model=1, grid=3), dict(engine=2, wave_lat_mb_us=50.0, wave_edge64_us=0.01),
+                 dict(engine=2, lds=0, grid=7), dict(engine=2, wave_lat_lds_us=0.01, one_per_model=1),
+                 dict(queue=0), dict(queue=0, engine=1), dict(queue=0, one_per_model=1, grid=4)]:
         _announce("plan", opts)
         with M.Batch(models) as b:
             for k, v in opts.items():
@@ -86,10 +93,12 @@ def test_plans_and_graph_replays_are_bitwise_identical():
                 assert np.array_equal(U0, U1) and np.array_equal(p0, p1)
 
 
-def test_batch_reset_and_timeout():
-    _announce("batch reset/timeout")
+@pytest.mark.parametrize("engine", [1, 2])
+def test_batch_reset_and_timeout(engine):
+    _announce("batch reset/timeout", engine)
     models = _mixed_models(seed=2, count=6)
     with M.Batch(models) as b:
+        b.set_option("engine", engine)
         b.iterate(3)
         d3 = b.dual_bounds()
         b.reset()
@@ -146,3 +155,47 @@ def test_batched_mix_samples_match_stored_oracle_traces():
         i = int(key)
         ref = rec["trace"][-1]
         assert abs(duals[i] - ref) <= 1e-5 * max(1.0, abs(ref)), (i, rec["n"], rec["L"], duals[i], ref)
+
+
+def test_wave_engine_rejects_more_than_64_labels():
+    _announce("wave engine L > 64")
+    with M.Batch([W.pose(6, 8, seed=1), W.uniform(5, 65, seed=2)]) as b:
+        b.set_option("engine", 2)
+        with pytest.raises(M.MplpError) as ei:
+            b.iterate(1)
+        assert ei.value.code == M.EINVAL
+        b.set_option("engine", 0)             # auto: the workgroup engine
+        b.iterate(1)
+        assert b.info("engine") == 1
+
+
+@pytest.mark.parametrize("team", [False, True])
+def test_wave_engine_ownership_edges(team):
+    """Workers that own no slot, one slot (messages loaded at their own
+    step) or two (loaded one slot ahead), models with fewer edges than
+    waves, a single-label model and L = 1, 16, 17, 32, 33, 64 tiles, in LDS
+    mode (one workgroup per model) and as teams through the mailboxes."""
+    _announce("wave ownership", team)
+    models = [W.pose(n, L, seed=7 * n + L) for n, L in ((2, 1), (3, 16), (4, 17), (5, 32), (6, 33), (7, 64),
+                                                          (12, 5), (17, 64), (40, 9))]
+    iters = 5
+    with M.Batch(models) as b:
+        b.set_option("engine", 2)
+        if team:
+            b.set_option("lds", 0)
+            b.set_option("wave_lat_mb_us", 1000.0)   # latency-bound plan: the largest teams
+        else:
+            b.set_option("one_per_model", 1)
+        b.iterate(iters)
+        if team:
+            assert b.info("max_team") > 1
+        else:
+            assert b.info("lds_tasks") == len(models)
+        states = [b.get_state(i, comp=True) for i in range(len(models))]
+        duals = b.dual_bounds()
+    for i, mo in enumerate(models):
+        U, phi, c = _alone(mo, iters)
+        assert np.array_equal(states[i][0], U) and np.array_equal(states[i][1], phi), (i, mo.name)
+        assert np.array_equal(states[i][2], c), (i, mo.name)
+        st, ref = oracle.run_model(mo, iters)
+        assert abs(duals[i] - ref[-1]) <= 1e-5 * max(1.0, abs(ref[-1])), (i, duals[i], ref[-1])
