@@ -33,8 +33,8 @@ METRIC = "edge-block updates/s + HBM GB/s fraction; time-to-dual-bound vs plain,
 # iteration of the pose n=200/L=64 launch, and the factors that map each
 # counter to bytes, from the same counters on a 1 GiB copy.  Valid only for
 # the kernel sources they were taken on (hash below); otherwise null.
-TRAFFIC = {"src_sha": "79df13ca27063fbf", "fetch_kib_per_iter": 3768746.375 / 20, "fetch_scale": 2.0,
-           "write_kib_per_iter": 806080.125 / 20, "write_scale": 1.0}
+TRAFFIC = {"src_sha": "c27a6113bf373e47", "fetch_kib_per_iter": 3769340.8125 / 20, "fetch_scale": 2.0,
+           "write_kib_per_iter": 806079.375 / 20, "write_scale": 1.0}
 TRAFFIC_SRCS = ("paper_2004_08227_amd/csrc/common.h", "paper_2004_08227_amd/csrc/device_common.h",
                 "paper_2004_08227_amd/csrc/handshake.hip")
 
@@ -86,10 +86,11 @@ def cpu_baseline(model, iters_sample):
                       f"edges of each matching)", "seconds": dt, "s_per_iter": dt / iters_sample}
 
 
-def bench_batched(M, W, iters=100):
+def bench_batched(M, W, iters=100, per_problem=True):
     """The 256-model pose mix in one persistent launch vs the same models
-    solved one after another with per-problem launches (same engine family,
-    same iterations); device times from HIP events."""
+    solved one after another with one launch per model: with the
+    single-model engine (Solver), and as one-model batches on the batched
+    engine; same iterations, device times from HIP events."""
     import torch
     models = W.batched_mix(256, seed=0)
     m_tot = sum(mo.m for mo in models)
@@ -102,8 +103,17 @@ def bench_batched(M, W, iters=100):
         b.iterate(iters)
         wall_b = time.perf_counter() - t0
         ms_b = b.info("last_ms")
-        info = {k: b.info(k) for k in ("grid", "tasks", "teams", "max_team", "lds_tasks", "lds_bytes")}
+        info = {k: b.info(k) for k in ("engine", "waves", "grid", "tasks", "teams", "max_team", "lds_tasks",
+                                       "lds_bytes", "plan_us")}
+        info["wg_busy_max_ms"] = b.info("wg_max_us") / 1e3
+        info["wg_busy_mean_ms"] = b.info("wg_mean_us") / 1e3
         d_b = b.dual_bounds()
+    out = {"workload": "batched_mix: 256 pose models, n ~ U{20..300}, L ~ U{8..64}, seed 0", "iterations": iters,
+           "edges": m_tot, "batched_ms": ms_b, "batched_wall_s": wall_b,
+           "updates_per_s": m_tot * iters / (ms_b / 1e3),
+           "hbm_frac": bytes_it * iters / (ms_b / 1e3) / 1e9 / HBM_PEAK_GBS, "plan": info}
+    if not per_problem:
+        return out
     ms_p = 0.0
     t0 = time.perf_counter()
     d_p = []
@@ -113,13 +123,35 @@ def bench_batched(M, W, iters=100):
             ms_p += s.last_iterate_ms()
             d_p.append(s.dual_bound())
     wall_p = time.perf_counter() - t0
-    return {"workload": "batched_mix: 256 pose models, n ~ U{20..300}, L ~ U{8..64}, seed 0", "iterations": iters,
-            "edges": m_tot, "batched_ms": ms_b, "batched_wall_s": wall_b, "per_problem_ms": ms_p,
-            "per_problem_wall_s_incl_create": wall_p, "speedup": ms_p / ms_b,
-            "updates_per_s": m_tot * iters / (ms_b / 1e3),
-            "hbm_frac": bytes_it * iters / (ms_b / 1e3) / 1e9 / HBM_PEAK_GBS,
-            "max_dual_diff_vs_per_problem": float(np.max(np.abs(np.asarray(d_b) - np.asarray(d_p)))),
-            "plan": info}
+    out.update({"per_problem_ms": ms_p, "per_problem_wall_s_incl_create": wall_p, "speedup": ms_p / ms_b,
+                "max_dual_diff_vs_per_problem": float(np.max(np.abs(np.asarray(d_b) - np.asarray(d_p))))})
+    # the same per-problem launches, each model as a batch of one (the
+    # batched engine spreading a single model over the whole GPU)
+    ms_q = 0.0
+    d_q = []
+    for mo in models:
+        with M.Batch([mo]) as b1:
+            b1.iterate(iters)
+            ms_q += b1.info("last_ms")
+            d_q.append(b1.dual_bounds()[0])
+    out["per_problem_one_model_batches_ms"] = ms_q
+    out["speedup_vs_one_model_batches"] = ms_q / ms_b
+    out["max_dual_diff_vs_one_model_batches"] = float(np.max(np.abs(np.asarray(d_b) - np.asarray(d_q))))
+    return out
+
+
+def copy_calibration():
+    """A plain 1 GiB device copy, three times: the reference for the HBM
+    byte counters (run under rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)."""
+    import torch
+    n = 256 * 1024 * 1024
+    a = torch.empty(n, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": "3 x 1 GiB device copy done"}))
 
 
 def bench_adjoint(M, W, K=50, every=10):
@@ -156,17 +188,25 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--only-batch", action="store_true", help="run only the batched-mix section")
+    ap.add_argument("--no-per-problem", action="store_true",
+                    help="batched section without the per-problem comparison runs")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only a 3 x 1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     import torch
     import paper_2004_08227_amd as M
     from paper_2004_08227_amd import workloads as W
 
     if args.only_batch:
-        print(json.dumps({"batched": bench_batched(M, W)}))
+        print(json.dumps({"batched": bench_batched(M, W, per_problem=not args.no_per_problem)}))
         return
 
     assert torch.cuda.is_available(), "bench needs a GPU"
@@ -253,7 +293,7 @@ def main():
                     "oracle = the iterations of its own stored trace x its measured seconds per iteration"}
     s.close()
     if not args.no_batch:
-        result["batched"] = bench_batched(M, W)
+        result["batched"] = bench_batched(M, W, per_problem=not args.no_per_problem)
     if not args.no_adjoint:
         result["adjoint"] = bench_adjoint(M, W)
     print(json.dumps(result))
