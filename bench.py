@@ -140,6 +140,57 @@ def bench_batched(M, W, iters=100, per_problem=True):
     return out
 
 
+def bench_c2(M, W, iters=30, with_cpu=True):
+    """Sparsification study: Potts + noise on G(n = 1000, p), L = 16, at four
+    densities; the single-model engine, `iters` iterations from phi = 0.
+    Time-to-bound against the oracle's own stored traces (written by
+    tests/golden/make_golden.py from the oracle alone) x its measured seconds
+    per iteration on this host."""
+    import torch
+    gold = os.path.join(ROOT, "tests", "golden", "potts_er_n1000_l16.json")
+    g = json.load(open(gold)) if os.path.exists(gold) else None
+    out = {"workload": "potts_er: n=1000, L=16, Potts w~U[0.1,1] + U[0,0.2) noise, unaries U[0,1), seed 0",
+           "iterations": iters, "densities": {}}
+    for p in (0.05, 0.25, 0.5, 1.0):
+        model = W.potts_er(1000, 16, p, seed=0)
+        B = algorithmic_bytes_per_update(model.L)
+        with M.Solver.from_model(model) as s:
+            U0, phi0 = s.get_state()
+            s.iterate(1)
+            s.set_state(U0, phi0)
+            torch.cuda.synchronize()
+            s.iterate(iters)
+            ms = s.last_iterate_ms()
+            s.set_state(U0, phi0)
+            tr = s.iterate_trace(iters)
+            steps = s.info("steps")
+            eng = s.info("engine")
+        t = ms / 1e3
+        rec = {"m": model.m, "matchings": steps, "engine": eng, "ms_per_iter": ms / iters,
+               "updates_per_s": model.m * iters / t, "hbm_gbs": model.m * iters * B / t / 1e9,
+               "hbm_frac": model.m * iters * B / t / 1e9 / HBM_PEAK_GBS, "dual": float(tr[-1])}
+        ref = None
+        if g is not None and str(p) in g["traces"] and g["traces"][str(p)]["m"] == model.m:
+            ref = np.asarray(g["traces"][str(p)]["trace"][:iters])
+            rec["max_rel_diff_vs_oracle_trace"] = float(np.max(np.abs(tr[:ref.size] - ref) / np.maximum(1.0, np.abs(ref))))
+        if with_cpu:
+            import oracle
+            threads = min(oracle.max_threads(), os.cpu_count() or 1)
+            st = oracle.State(model)
+            t0 = time.perf_counter()
+            st.run(1, rule="H", nthreads=threads)
+            s_it = time.perf_counter() - t0
+            d_star = float(max(tr.max(), ref.max() if ref is not None else -np.inf))
+            eps = [1e-1, 1e-2, 1e-3, 1e-4, 1e-5]
+            rec["oracle_s_per_iter"] = s_it
+            rec["oracle_cores"] = threads
+            rec["time_to_dual_bound"] = {"d_star": d_star, "gpu_s": time_to_bound(tr, t / iters, d_star, eps),
+                                         "plain_oracle_s": time_to_bound(ref if ref is not None else tr, s_it, d_star, eps)}
+        out["densities"][str(p)] = rec
+        del model
+    return out
+
+
 def copy_calibration():
     """A plain 1 GiB device copy, three times: the reference for the HBM
     byte counters (run under rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)."""
@@ -184,9 +235,10 @@ def main():
     ap.add_argument("--engine", type=int, default=0)
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--cpu-iters", type=int, default=200)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-c2", action="store_true", help="skip the sparsification section (n=1000, L=16, 4 densities)")
     ap.add_argument("--only-batch", action="store_true", help="run only the batched-mix section")
     ap.add_argument("--no-per-problem", action="store_true",
                     help="batched section without the per-problem comparison runs")
@@ -294,6 +346,8 @@ def main():
     s.close()
     if not args.no_batch:
         result["batched"] = bench_batched(M, W, per_problem=not args.no_per_problem)
+    if not args.no_c2:
+        result["c2"] = bench_c2(M, W, with_cpu=not args.no_cpu)
     if not args.no_adjoint:
         result["adjoint"] = bench_adjoint(M, W)
     print(json.dumps(result))

@@ -254,3 +254,25 @@ def test_pose_k200_l64_full_size_200_iterations_matches_stored_oracle():
     # bound of the same state up to FP64 summation
     assert abs(tr[-1] - d) <= 1e-9 * abs(d)
     assert np.max(np.abs(U.min(axis=1) - np.array(g["node_min"]))) <= 1e-4
+
+
+@pytest.mark.parametrize("density", [0.05, 0.25, 0.5, 1.0])
+def test_potts_er_n1000_l16_full_size_matches_stored_oracle(density):
+    """The sparsification workload at full size (n = 1000, L = 16, 30
+    iterations): the per-iteration dual trace against the oracle's stored
+    trace, to 1e-5 relative, at each density."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "potts_er_n1000_l16.json")
+    g = json.load(open(path))
+    rec = g["traces"][str(density)]
+    _announce("potts_er n=1000 L=16", density)
+    model = W.potts_er(1000, 16, density, seed=0)
+    assert model.m == rec["m"]
+    ref = np.asarray(rec["trace"])
+    with M.Solver.from_model(model) as s:
+        assert s.info("steps") == rec["steps"]
+        tr = s.iterate_trace(g["iters"])
+        d = s.dual_bound()
+    assert np.max(np.abs(tr - ref) / np.maximum(1.0, np.abs(ref))) <= 1e-5
+    assert _rel(d, ref[-1]) <= 1e-5, (d, ref[-1])
