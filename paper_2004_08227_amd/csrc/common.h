@@ -109,6 +109,7 @@ hipError_t launch_adj_step(const SlotInfo* slots, int L, int slot_begin, int cou
 template <typename T>
 hipError_t launch_adj_seed(const T* U, const T* Ulo, int n, int L, T* Ub, double* node_min, hipStream_t st);
 
+int max_blocks_per_cu_mb(int LT, int NT);
 template <typename T>
 hipError_t launch_handshake(const HsArgs<T>& a, int engine, int LT, int NT, int slot_begin, int count, int grid,
                             int iters, hipStream_t st);

@@ -381,7 +381,9 @@ static hipError_t launch_one(const HsArgs<T>& a, int engine, int slot_begin, int
     return hipGetLastError();
   }
   void* args[] = {(void*)&a, (void*)&iters};
-  return hipLaunchCooperativeKernel((const void*)k_persistent<T, LT, NT>, dim3(grid), dim3(NT), args, 0, st);
+  const hipError_t e = hipLaunchCooperativeKernel((const void*)k_persistent<T, LT, NT>, dim3(grid), dim3(NT), args, 0, st);
+  if (e != hipSuccess) (void)hipGetLastError();  // (see launch_mb_one)
+  return e;
 }
 
 template <int LT, int NT>
@@ -401,7 +403,31 @@ static hipError_t launch_mb_one(const HsArgs<float>& a, unsigned long long* mb, 
   const void* f = a.trace ? (far ? MPLPXX_PICK(true, true) : MPLPXX_PICK(true, false))
                           : (far ? MPLPXX_PICK(false, true) : MPLPXX_PICK(false, false));
 #undef MPLPXX_PICK
-  return hipLaunchCooperativeKernel(f, dim3(grid), dim3(NT + 128), args, dyn_lds, st);
+  const hipError_t e = hipLaunchCooperativeKernel(f, dim3(grid), dim3(NT + 128), args, dyn_lds, st);
+  // a refused launch returns its error here; clear the runtime's copy so
+  // that it is not reported again by the next call's error check
+  if (e != hipSuccess) (void)hipGetLastError();
+  return e;
+}
+
+// workgroups of the FP32 mailbox kernel that fit on one compute unit (no
+// dynamic LDS)
+int max_blocks_per_cu_mb(int LT, int NT) {
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+#define MPLPXX_CASE(lt, nt)                                                                                  \
+  if (LT == lt && NT == nt)                                                                                  \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_persistent_mb<lt, nt, false, false, false, true>, \
+                                                     nt + 128, 0);
+  MPLPXX_CASE(16, 256)
+  MPLPXX_CASE(32, 256)
+  MPLPXX_CASE(32, 512)
+  MPLPXX_CASE(64, 256)
+  MPLPXX_CASE(64, 512)
+  MPLPXX_CASE(128, 256)
+  MPLPXX_CASE(128, 512)
+#undef MPLPXX_CASE
+  return e == hipSuccess ? nb : 0;
 }
 
 hipError_t launch_persistent_mb(const HsArgs<float>& a, unsigned long long* mb, int LT, int NT, int grid, int iters,

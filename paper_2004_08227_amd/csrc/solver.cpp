@@ -116,14 +116,22 @@ struct mplpxx_solver {
     return nt;
   }
   int max_deg = 0;
+  int max_step = 1;  // edges of the largest matching
   int engine() const {
     // FP32 mailboxes carry 16-bit versions: degrees must stay below 2^16
     if (dtype == MPLPXX_F32 && max_deg >= 65536) return ENGINE_STEP;
     if (engine_opt == ENGINE_STEP || engine_opt == ENGINE_PERSISTENT) return engine_opt;
     return ENGINE_PERSISTENT;
   }
+  // FP32 mailbox engine: one workgroup per compute unit, or, when a matching
+  // has more edges than there are compute units, one workgroup per edge of
+  // the largest matching as far as they fit (each workgroup then runs about
+  // one update per matching instead of several one after another)
+  bool mb_engine() const { return dtype == MPLPXX_F32 && engine() == ENGINE_PERSISTENT; }
   int grid() const {
     int g = grid_opt > 0 ? grid_opt : num_cus;
+    if (grid_opt == 0 && mb_engine() && max_step > num_cus)
+      g = std::max(num_cus, std::min(max_step, max_blocks_per_cu_mb(LT(), NT()) * num_cus));
     if (g > m) g = m;
     if (g < 1) g = 1;
     return g;
@@ -173,6 +181,8 @@ int prepare_solver_graph(mplpxx_solver* h, const int32_t* edges) {
   h->deg.swap(g.deg);
   h->max_deg = 0;
   for (int d : h->deg) h->max_deg = std::max(h->max_deg, d);
+  h->max_step = 1;
+  for (int s = 0; s < h->S; ++s) h->max_step = std::max(h->max_step, h->step_ptr[s + 1] - h->step_ptr[s]);
   return MPLPXX_OK;
 }
 
@@ -437,7 +447,9 @@ template <typename T> int iterate_t(mplpxx_solver* h, int k, double* trace_host)
       a.sink = h->d_sink;
       const size_t owned = ((size_t)h->m + G - 1) / G;
       const size_t phi_bytes = owned * 2 * h->L * sizeof(float);
-      const int in_lds = phi_bytes <= kPhiLdsBudget ? 1 : 0;
+      // (more than one workgroup per compute unit: messages in HBM, so that
+      // the workgroups' LDS never limits how many fit)
+      const int in_lds = phi_bytes <= kPhiLdsBudget && G <= h->num_cus ? 1 : 0;
       HIP_TRY(launch_mb_init(static_cast<const float*>(h->d_U), h->d_Ulo, h->d_mb, (size_t)h->n * h->L, st));
       HIP_TRY(launch_persistent_mb(a, h->d_mb, LT, NT, G, k, in_lds, in_lds ? phi_bytes : 0, st));
       HIP_TRY(launch_mb_fini(static_cast<float*>(h->d_U), h->d_Ulo, h->d_mb, h->n, h->L,
@@ -878,8 +890,9 @@ int mplpxx_set_option(mplpxx_solver* h, int32_t key, int64_t value) {
       return MPLPXX_OK;
     case MPLPXX_OPT_GRID: {
       if (value < 0) return fail(MPLPXX_EINVAL, "grid must be >= 0");
-      const int nb = h->dtype == MPLPXX_F32 ? max_blocks_per_cu<float>(ENGINE_PERSISTENT, h->LT(), h->NT())
-                                            : max_blocks_per_cu<double>(ENGINE_PERSISTENT, h->LT(), h->NT());
+      const int nb = h->mb_engine() ? max_blocks_per_cu_mb(h->LT(), h->NT())
+                     : h->dtype == MPLPXX_F32 ? max_blocks_per_cu<float>(ENGINE_PERSISTENT, h->LT(), h->NT())
+                                              : max_blocks_per_cu<double>(ENGINE_PERSISTENT, h->LT(), h->NT());
       if (value > (int64_t)nb * h->num_cus) return fail(MPLPXX_EINVAL, "grid %lld exceeds co-resident limit %d", (long long)value, nb * h->num_cus);
       h->grid_opt = (int)value;
       return MPLPXX_OK;

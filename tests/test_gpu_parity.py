@@ -276,3 +276,31 @@ def test_potts_er_n1000_l16_full_size_matches_stored_oracle(density):
         d = s.dual_bound()
     assert np.max(np.abs(tr - ref) / np.maximum(1.0, np.abs(ref))) <= 1e-5
     assert _rel(d, ref[-1]) <= 1e-5, (d, ref[-1])
+
+
+def test_large_matchings_default_grid_is_bitwise_identical():
+    """Matchings larger than the number of compute units: the FP32 mailbox
+    engine's default grid grows to one workgroup per edge of the largest
+    matching (messages then in HBM); the state must be bitwise the one of
+    one workgroup per compute unit and of the per-matching engine."""
+    _announce("large matchings grid")
+    model = W.potts_er(700, 16, 0.08, seed=11)
+    iters = 4
+    states = []
+    for opts in ({}, {M.OPT_ENGINE: M.ENGINE_STEP}):
+        with M.Solver.from_model(model) as s:
+            for k, v in opts.items():
+                s.set_option(k, v)
+            s.iterate(iters)
+            states.append((s.get_state(comp=True), s.info("grid"), s.dual_bound()))
+    with M.Solver.from_model(model) as s:
+        s.set_option(M.OPT_GRID, 256)
+        s.iterate(iters)
+        states.append((s.get_state(comp=True), s.info("grid"), s.dual_bound()))
+    assert states[0][1] > 256, states[0][1]
+    for (st, g, d) in states[1:]:
+        for a, b in zip(states[0][0], st):
+            assert np.array_equal(a, b)
+        assert d == states[0][2]
+    st, ref = oracle.run_model(model, iters)
+    assert _rel(states[0][2], ref[-1]) <= 1e-5
