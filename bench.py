@@ -36,7 +36,7 @@ METRIC = "edge-block updates/s + HBM GB/s fraction; time-to-dual-bound vs plain,
 TRAFFIC = {"src_sha": "7dd597ed421feec3", "fetch_kib_per_iter": 3770642.0625 / 20, "fetch_scale": 2.0,
            "write_kib_per_iter": 806081.5 / 20, "write_scale": 1.0}
 TRAFFIC_SRCS = ("paper_2004_08227_amd/csrc/common.h", "paper_2004_08227_amd/csrc/device_common.h",
-                "paper_2004_08227_amd/csrc/handshake.hip")
+                "paper_2004_08227_amd/csrc/step_common.h", "paper_2004_08227_amd/csrc/handshake.hip")
 
 
 def kernel_src_sha():
@@ -191,6 +191,42 @@ def bench_c2(M, W, iters=30, with_cpu=True):
     return out
 
 
+def bench_rules(M, W, iters=200):
+    """MPLP (M) and uniform (U) against MPLP++ (H) from the same start (phi =
+    0): dual traces of `iters` iterations, each rule on the per-matching
+    engine (same kernel structure, one launch per matching), and (H) also on
+    the persistent engine; seconds to reach D* - eps|D*|, D* the best final
+    dual of all runs, from each run's own time per iteration."""
+    out = {}
+    for key, model in (("pose_k200_l64", W.pose(200, 64, seed=0)),
+                       ("potts_er_n1000_l16_p0.25", W.potts_er(1000, 16, 0.25, seed=0))):
+        runs = {}
+        for name, rule, engine in (("H_persistent", M.RULE_H, M.ENGINE_PERSISTENT), ("H", M.RULE_H, M.ENGINE_STEP),
+                                   ("M", M.RULE_M, M.ENGINE_STEP), ("U", M.RULE_U, M.ENGINE_STEP)):
+            with M.Solver.from_model(model) as s:
+                s.set_option(M.OPT_ENGINE, engine)
+                s.set_option(M.OPT_RULE, rule)
+                U0, phi0 = s.get_state()
+                s.iterate(1)
+                s.set_state(U0, phi0)
+                s.iterate(iters)
+                t_it = s.last_iterate_ms() / 1e3 / iters
+                s.set_state(U0, phi0)
+                tr = s.iterate_trace(iters)
+            runs[name] = (tr, t_it)
+        d_star = float(max(tr.max() for tr, _ in runs.values()))
+        eps = [1e-1, 1e-2, 1e-3, 1e-4, 1e-5]
+        rec = {"m": model.m, "iterations": iters, "d_star": d_star, "eps_rel": eps}
+        for name, (tr, t_it) in runs.items():
+            rec[name] = {"s_per_iter": t_it, "final_dual": float(tr[-1]), "time_to_bound_s": time_to_bound(tr, t_it, d_star, eps),
+                         "iterations_to_bound": {f"{e:g}": (None if not np.any(tr >= d_star - e * abs(d_star))
+                                                            else int(np.flatnonzero(tr >= d_star - e * abs(d_star))[0]) + 1)
+                                                 for e in eps}}
+        out[key] = rec
+        del model
+    return out
+
+
 def copy_calibration():
     """A plain 1 GiB device copy, three times: the reference for the HBM
     byte counters (run under rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)."""
@@ -239,6 +275,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-c2", action="store_true", help="skip the sparsification section (n=1000, L=16, 4 densities)")
+    ap.add_argument("--no-rules", action="store_true", help="skip the MPLP / uniform vs MPLP++ comparison")
     ap.add_argument("--only-batch", action="store_true", help="run only the batched-mix section")
     ap.add_argument("--no-per-problem", action="store_true",
                     help="batched section without the per-problem comparison runs")
@@ -350,6 +387,8 @@ def main():
         result["c2"] = bench_c2(M, W, with_cpu=not args.no_cpu)
     if not args.no_adjoint:
         result["adjoint"] = bench_adjoint(M, W)
+    if not args.no_rules:
+        result["rules"] = bench_rules(M, W)
     print(json.dumps(result))
 
 

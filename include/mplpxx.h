@@ -185,6 +185,18 @@ int mplpxx_iterate_trace(mplpxx_solver* h, int32_t k, double* trace);
 #define MPLPXX_OPT_PROFILE 5     /* 1: record per-slot timestamps (persistent FP32 engine) */
 #define MPLPXX_OPT_ADJOINT_F64 6 /* FP32 handles: 1 (default) differentiate an FP64 run on the same costs
                                     (exactly widened); 0: differentiate the FP32 run itself */
+/* The BCA-update applied to every edge (Sec. 4), unlike the options above a
+ * change of the method: MPLPXX_RULE_H (default) the MPLP++ handshake (H);
+ * MPLPXX_RULE_M the MPLP update (M), both nodes get half of the row and
+ * column minima of the aggregated cost; MPLPXX_RULE_U the uniform update
+ * (U), both nodes get half of its overall minimum.  (M) and (U) run on the
+ * per-matching engine whatever MPLPXX_OPT_ENGINE says; the adjoint and the
+ * batch API take (H) only (mplpxx_adjoint_forward returns MPLPXX_EINVAL
+ * under another rule). */
+#define MPLPXX_OPT_RULE 7
+#define MPLPXX_RULE_H 0
+#define MPLPXX_RULE_M 1
+#define MPLPXX_RULE_U 2
 int mplpxx_set_option(mplpxx_solver* h, int32_t key, int64_t value);
 
 /* Read-only facts about the handle. */

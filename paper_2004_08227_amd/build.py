@@ -17,7 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmplpxx.so")
 
-SOURCES = ["solver.cpp", "batch.cpp", "schedule.cpp", "handshake.hip", "dual.hip", "batch.hip", "adjoint.hip"]
+SOURCES = ["solver.cpp", "batch.cpp", "schedule.cpp", "handshake.hip", "dual.hip", "batch.hip", "adjoint.hip",
+           "rules.hip"]
 ARCH = os.environ.get("MPLPXX_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -30,7 +31,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wno-unused-comman
 # +inf and no pass can form inf - inf.  Telling the compiler so lets min
 # reductions skip the quieting of their operands and fold into DPP forms;
 # on non-NaN operands the results are bitwise the same.
-EXTRA = {"handshake.hip": ["-fno-honor-nans"], "batch.hip": ["-fno-honor-nans"]}
+EXTRA = {"handshake.hip": ["-fno-honor-nans"], "batch.hip": ["-fno-honor-nans"], "rules.hip": ["-fno-honor-nans"]}
 
 
 def _compile(src: str, build_dir: str = BUILD, defines=()) -> str:

@@ -110,6 +110,9 @@ template <typename T>
 hipError_t launch_adj_seed(const T* U, const T* Ulo, int n, int L, T* Ub, double* node_min, hipStream_t st);
 
 int max_blocks_per_cu_mb(int LT, int NT);
+// the (M) and (U) updates on the per-matching engine (rules.hip); rule 1 = M, 2 = U
+template <typename T>
+hipError_t launch_step_rule(const HsArgs<T>& a, int rule, int LT, int NT, int slot_begin, int count, hipStream_t st);
 template <typename T>
 hipError_t launch_handshake(const HsArgs<T>& a, int engine, int LT, int NT, int slot_begin, int count, int grid,
                             int iters, hipStream_t st);

@@ -98,6 +98,7 @@ struct mplpxx_solver {
   hipStream_t own_stream = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   int engine_opt = ENGINE_AUTO;
+  int rule = MPLPXX_RULE_H;  // BCA-update (Sec. 4)
   int threads_opt = 0;
   int grid_opt = 0;
   long long spin_limit = 1ll << 22;
@@ -120,6 +121,7 @@ struct mplpxx_solver {
   int engine() const {
     // FP32 mailboxes carry 16-bit versions: degrees must stay below 2^16
     if (dtype == MPLPXX_F32 && max_deg >= 65536) return ENGINE_STEP;
+    if (rule != MPLPXX_RULE_H) return ENGINE_STEP;  // (M), (U): per-matching engine only
     if (engine_opt == ENGINE_STEP || engine_opt == ENGINE_PERSISTENT) return engine_opt;
     return ENGINE_PERSISTENT;
   }
@@ -418,7 +420,8 @@ template <typename T> int iterate_t(mplpxx_solver* h, int k, double* trace_host)
       for (int it = 0; it < k; ++it) {
         for (int s = 0; s < h->S; ++s) {
           const int b = h->step_ptr[s], c = h->step_ptr[s + 1] - b;
-          HIP_TRY(launch_handshake<T>(a, ENGINE_STEP, LT, NT, b, c, 0, 1, st));
+          if (h->rule == MPLPXX_RULE_H) HIP_TRY(launch_handshake<T>(a, ENGINE_STEP, LT, NT, b, c, 0, 1, st));
+          else HIP_TRY(launch_step_rule<T>(a, h->rule, LT, NT, b, c, st));
         }
         if (trace_host) {
           HIP_TRY(launch_trace_nodes<T>(static_cast<const T*>(h->d_U), a.Ulo, h->n, h->L,
@@ -677,6 +680,7 @@ int mplpxx_iterate_trace(mplpxx_solver* h, int32_t k, double* trace) {
 int mplpxx_adjoint_forward(mplpxx_solver* h, int32_t K, int32_t every, double* loss) {
   if (!h) return fail(MPLPXX_EINVAL, "handle is NULL");
   if (K < 1 || every < 1) return fail(MPLPXX_EINVAL, "K and every must be >= 1");
+  if (h->rule != MPLPXX_RULE_H) return fail(MPLPXX_EINVAL, "the adjoint takes the (H) update only");
   h->adj_ready = false;
   if (h->dtype == MPLPXX_F32 && h->adjoint_f64) {
     if (!h->shadow) {
@@ -906,6 +910,12 @@ int mplpxx_set_option(mplpxx_solver* h, int32_t key, int64_t value) {
       return MPLPXX_OK;
     case MPLPXX_OPT_ADJOINT_F64:
       h->adjoint_f64 = value != 0;
+      h->adj_ready = false;
+      return MPLPXX_OK;
+    case MPLPXX_OPT_RULE:
+      if (value != MPLPXX_RULE_H && value != MPLPXX_RULE_M && value != MPLPXX_RULE_U)
+        return fail(MPLPXX_EINVAL, "rule must be MPLPXX_RULE_H, _M or _U");
+      h->rule = (int)value;
       h->adj_ready = false;
       return MPLPXX_OK;
     default:
