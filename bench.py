@@ -149,12 +149,16 @@ def bench_c2(M, W, iters=30, with_cpu=True):
     import torch
     gold = os.path.join(ROOT, "tests", "golden", "potts_er_n1000_l16.json")
     g = json.load(open(gold)) if os.path.exists(gold) else None
+    gold2 = os.path.join(ROOT, "tests", "golden", "potts_er_n1000_l16_sched.json")
+    g2 = json.load(open(gold2)) if os.path.exists(gold2) else None
     out = {"workload": "potts_er: n=1000, L=16, Potts w~U[0.1,1] + U[0,0.2) noise, unaries U[0,1), seed 0",
-           "iterations": iters, "densities": {}}
-    for p in (0.05, 0.25, 0.5, 1.0):
+           "iterations": iters, "densities": {}, "colour_schedule": {}}
+    runs = [(p, "greedy") for p in (0.01, 0.05, 0.25, 0.5, 1.0)] + [(p, "color") for p in (0.01, 0.05, 0.25, 0.5)]
+    for p, kind in runs:
         model = W.potts_er(1000, 16, p, seed=0)
         B = algorithmic_bytes_per_update(model.L)
-        with M.Solver.from_model(model) as s:
+        sched = M.SCHED_COLOR if kind == "color" else M.SCHED_AUTO
+        with M.Solver.from_model(model, schedule=sched) as s:
             U0, phi0 = s.get_state()
             s.iterate(1)
             s.set_state(U0, phi0)
@@ -170,13 +174,16 @@ def bench_c2(M, W, iters=30, with_cpu=True):
                "updates_per_s": model.m * iters / t, "hbm_gbs": model.m * iters * B / t / 1e9,
                "hbm_frac": model.m * iters * B / t / 1e9 / HBM_PEAK_GBS, "dual": float(tr[-1])}
         ref = None
-        if g is not None and str(p) in g["traces"] and g["traces"][str(p)]["m"] == model.m:
+        if kind == "greedy" and g is not None and str(p) in g["traces"] and g["traces"][str(p)]["m"] == model.m:
             ref = np.asarray(g["traces"][str(p)]["trace"][:iters])
+        elif g2 is not None and f"{kind}_{p}" in g2["runs"] and g2["runs"][f"{kind}_{p}"]["m"] == model.m:
+            ref = np.asarray(g2["runs"][f"{kind}_{p}"]["trace"][:iters])
+        if ref is not None:
             rec["max_rel_diff_vs_oracle_trace"] = float(np.max(np.abs(tr[:ref.size] - ref) / np.maximum(1.0, np.abs(ref))))
         if with_cpu:
             import oracle
             threads = min(oracle.max_threads(), os.cpu_count() or 1)
-            st = oracle.State(model)
+            st = oracle.State(model, schedule_kind=kind)
             t0 = time.perf_counter()
             st.run(1, rule="H", nthreads=threads)
             s_it = time.perf_counter() - t0
@@ -186,7 +193,7 @@ def bench_c2(M, W, iters=30, with_cpu=True):
             rec["oracle_cores"] = threads
             rec["time_to_dual_bound"] = {"d_star": d_star, "gpu_s": time_to_bound(tr, t / iters, d_star, eps),
                                          "plain_oracle_s": time_to_bound(ref if ref is not None else tr, s_it, d_star, eps)}
-        out["densities"][str(p)] = rec
+        (out["densities"] if kind == "greedy" else out["colour_schedule"])[str(p)] = rec
         del model
     return out
 

@@ -86,6 +86,32 @@ typedef struct mplpxx_solver mplpxx_solver;
 int mplpxx_create(int32_t n, int32_t L, int64_t m, const int32_t* edges, const void* unaries,
                   const void* pairwise, int32_t dtype, mplpxx_solver** out);
 
+/* Schedule kinds (Alg. 1, Sec. 6, asks for a queue of matchings covering
+ * every edge once; the paper leaves the matchings' construction open).
+ * A complete graph always gets the round-robin 1-factorization (n - 1
+ * rounds for even n, the minimum).  Any other graph gets
+ *   MPLPXX_SCHED_AUTO, MPLPXX_SCHED_GREEDY: greedy maximal matchings, each
+ *     round scanning the remaining edges in ascending (u, v) order;
+ *   MPLPXX_SCHED_COLOR: the colour classes of a proper edge colouring with
+ *     at most Delta + 1 colours (Misra and Gries' constructive proof of
+ *     Vizing's theorem), one round per colour in colour order, with every
+ *     choice fixed (edges coloured in ascending (u, v) with u as the fan's
+ *     centre; smallest free colours; the fan extended by the neighbour whose
+ *     edge has the smallest colour free on the fan's last node; the path
+ *     from u alternating d, c swapped; the first fan node that takes d
+ *     rotated in).  Fewer rounds than the greedy matchings on irregular or
+ *     dense graphs: a shorter chain of dependent steps per iteration, and a
+ *     different (equally valid) order of the updates.
+ * Edges inside a round are listed in ascending (u, v). */
+#define MPLPXX_SCHED_AUTO 0
+#define MPLPXX_SCHED_GREEDY 1
+#define MPLPXX_SCHED_COLOR 2
+
+/* mplpxx_create with a schedule kind (above); MPLPXX_EINVAL for an unknown
+ * kind, else the same errors. */
+int mplpxx_create_sched(int32_t n, int32_t L, int64_t m, const int32_t* edges, const void* unaries,
+                        const void* pairwise, int32_t dtype, int32_t schedule, mplpxx_solver** out);
+
 /* Same as mplpxx_create, but unaries and pairwise are DEVICE pointers (for
  * example torch tensor storage) in the same layout; edges stay on the host.
  * The library copies the costs into its own layout before returning, so the
@@ -147,6 +173,11 @@ int mplpxx_get_schedule(mplpxx_solver* h, int32_t* n_steps, int32_t* step_ptr, i
  * MPLPXX_EINVAL for the graph errors listed under mplpxx_create. */
 int mplpxx_schedule(int32_t n, int64_t m, const int32_t* edges, int32_t* n_steps, int32_t* step_ptr,
                     int32_t* order);
+
+/* Host-only: the schedule of the given kind (MPLPXX_SCHED_*), as
+ * mplpxx_create_sched would build it; otherwise as mplpxx_schedule. */
+int mplpxx_schedule_kind(int32_t n, int64_t m, const int32_t* edges, int32_t schedule, int32_t* n_steps,
+                         int32_t* step_ptr, int32_t* order);
 
 /* Copies the state (U [n][L], phi [m][2][L], see above) to / from HOST
  * buffers of the handle's dtype.  Any pointer may be NULL to skip it.

@@ -70,6 +70,8 @@ def _load():
         lib.orc_canonicalize.restype = ctypes.c_int
         lib.orc_schedule.argtypes = [ctypes.c_int, ctypes.c_int64, _i32p, _i32p, _i32p]
         lib.orc_schedule.restype = ctypes.c_int
+        lib.orc_schedule_kind.argtypes = [ctypes.c_int, ctypes.c_int64, _i32p, ctypes.c_int, _i32p, _i32p]
+        lib.orc_schedule_kind.restype = ctypes.c_int
         lib.orc_update.argtypes = [ctypes.c_int, ctypes.c_int, _f64p, _f64p, _f64p]
         lib.orc_update.restype = ctypes.c_int
         lib.orc_dual.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, _f64p, _f64p]
@@ -117,14 +119,19 @@ def canonicalize(n, L, edges, unaries, pairwise):
     return e_out, pw_out
 
 
-def schedule(n, edges):
-    """Alg. 1: returns (step_ptr int32 [S+1], order int32 [m])."""
+def schedule(n, edges, kind="greedy"):
+    """Alg. 1 on canonical edges (u < v): returns (step_ptr int32 [S+1],
+    order int32 [m]).  kind "greedy": round-robin for a complete graph,
+    greedy maximal matchings otherwise; "color": round-robin for a complete
+    graph, the colour classes of a Delta + 1 edge colouring otherwise."""
     lib = _load()
     edges = _i32(edges).reshape(-1, 2)
     m = edges.shape[0]
     step_ptr = np.zeros(m + 2, dtype=np.int32)
     order = np.zeros(max(m, 1), dtype=np.int32)
-    S = lib.orc_schedule(n, m, edges, step_ptr, order)
+    if kind not in ("greedy", "color"):
+        raise OracleError(f"unknown schedule kind {kind}")
+    S = lib.orc_schedule_kind(n, m, edges, 0 if kind == "greedy" else 1, step_ptr, order)
     if S < 0:
         raise OracleError(f"schedule failed (code {S})")
     return step_ptr[:S + 1].copy(), order[:m].copy()
@@ -157,14 +164,14 @@ def dual(Tu, Te):
 class State:
     """Reparametrized costs theta^phi (Eq. 2) of one model plus its schedule."""
 
-    def __init__(self, model, step_ptr=None, order=None):
+    def __init__(self, model, step_ptr=None, order=None, schedule_kind="greedy"):
         self.n = int(model.n)
         self.L = int(model.L)
         self.edges, self.pairwise = canonicalize(self.n, self.L, model.edges, model.unaries, model.pairwise)
         self.unaries = _f64(model.unaries).reshape(self.n, self.L).copy()
         self.m = int(self.edges.shape[0])
         if step_ptr is None:
-            step_ptr, order = schedule(self.n, self.edges)
+            step_ptr, order = schedule(self.n, self.edges, schedule_kind)
         self.step_ptr = _i32(step_ptr)
         self.order = _i32(order)
         self.Tu = self.unaries.copy()
@@ -222,8 +229,8 @@ def bruteforce(model):
     return float(en), best
 
 
-def run_model(model, iters, rule="H", trace=True, nthreads=1):
-    st = State(model)
+def run_model(model, iters, rule="H", trace=True, nthreads=1, schedule_kind="greedy"):
+    st = State(model, schedule_kind=schedule_kind)
     tr = st.run(iters, rule=rule, trace=trace, nthreads=nthreads)
     return st, tr
 

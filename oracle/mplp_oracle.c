@@ -186,6 +186,164 @@ int orc_schedule(int n, int64_t m, const int32_t* edges, int32_t* step_ptr, int3
 }
 
 /* ------------------------------------------------------------------ */
+/* Alternative schedule: the colour classes of an edge colouring with   */
+/* at most Delta + 1 colours (Vizing's bound, by Misra and Gries'       */
+/* constructive proof), one matching per colour.  Every choice is fixed */
+/* so that the schedule depends on the edge set only:                   */
+/*  - edges are coloured one by one in ascending (u, v), u < v; the fan */
+/*    is centred at u and starts at v;                                  */
+/*  - a free colour of a node is always its smallest free colour;       */
+/*  - the fan grows, while it can, by the neighbour y of u (not yet in  */
+/*    the fan) whose edge u-y carries the smallest colour that is free  */
+/*    at the fan's current last node;                                   */
+/*  - with c free at u and d free at the fan's last node, the maximal   */
+/*    path leaving u by its d edge and then alternating c, d, ... has   */
+/*    its two colours exchanged;                                        */
+/*  - the fan is then cut after its first node where d is free (and up  */
+/*    to which it is still a fan), each edge of that prefix takes the   */
+/*    colour of the next one, and the cut node's edge gets d.           */
+/* Complete graphs keep the round-robin schedule.                      */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    int n, C;
+    int32_t* owner;   /* owner[x * C + c]: the node joined to x by colour c, or -1 */
+    int32_t* colour;  /* colour of edge id, or -1 */
+    const int32_t* edges;
+    const int32_t* id;  /* id[u * n + v], u < v */
+} colouring;
+
+static int32_t edge_between(const colouring* k, int a, int b) {
+    int u = a < b ? a : b, v = a < b ? b : a;
+    return k->id[(size_t)u * k->n + v];
+}
+static int is_free(const colouring* k, int x, int c) { return k->owner[(size_t)x * k->C + c] < 0; }
+static int smallest_free(const colouring* k, int x) {
+    int c = 0;
+    while (!is_free(k, x, c)) ++c;
+    return c;
+}
+static void paint(colouring* k, int a, int b, int c) {
+    int32_t e = edge_between(k, a, b);
+    int old = k->colour[e];
+    if (old >= 0) {
+        k->owner[(size_t)a * k->C + old] = -1;
+        k->owner[(size_t)b * k->C + old] = -1;
+    }
+    k->colour[e] = c;
+    if (c >= 0) {
+        k->owner[(size_t)a * k->C + c] = b;
+        k->owner[(size_t)b * k->C + c] = a;
+    }
+}
+
+static void colour_one_edge(colouring* k, int u, int v, int32_t* fan, char* infan, int32_t* path) {
+    int len = 0;
+    fan[len++] = v;
+    infan[v] = 1;
+    for (;;) {
+        int x = fan[len - 1], grown = 0;
+        for (int c = 0; c < k->C && !grown; ++c) {
+            if (!is_free(k, x, c)) continue;
+            int y = k->owner[(size_t)u * k->C + c];
+            if (y < 0 || infan[y]) continue;
+            fan[len++] = y;
+            infan[y] = 1;
+            grown = 1;
+        }
+        if (!grown) break;
+    }
+    for (int i = 0; i < len; ++i) infan[fan[i]] = 0;
+    int c = smallest_free(k, u);
+    int d = smallest_free(k, fan[len - 1]);
+    if (c != d) {
+        /* collect the path's nodes, then exchange its colours */
+        int np = 0, x = u, want = d;
+        path[np++] = u;
+        while (!is_free(k, x, want)) {
+            int y = k->owner[(size_t)x * k->C + want];
+            path[np++] = y;
+            x = y;
+            want = (want == d) ? c : d;
+        }
+        /* uncolour all path edges first, then recolour each with the other colour */
+        int* was = (int*)malloc(sizeof(int) * (size_t)(np > 1 ? np - 1 : 1));
+        for (int i = 0; i + 1 < np; ++i) {
+            was[i] = k->colour[edge_between(k, path[i], path[i + 1])];
+            paint(k, path[i], path[i + 1], -1);
+        }
+        for (int i = 0; i + 1 < np; ++i) paint(k, path[i], path[i + 1], was[i] == c ? d : c);
+        free(was);
+    }
+    int w = -1;
+    for (int i = 0; i < len; ++i) {
+        if (i > 0) {
+            int ci = k->colour[edge_between(k, u, fan[i])];
+            if (ci < 0 || !is_free(k, fan[i - 1], ci)) break;
+        }
+        if (is_free(k, fan[i], d)) { w = i; break; }
+    }
+    if (w < 0) w = 0; /* not reached for a proper colouring */
+    for (int i = 0; i < w; ++i) {
+        int cn = k->colour[edge_between(k, u, fan[i + 1])];
+        paint(k, u, fan[i + 1], -1);
+        paint(k, u, fan[i], cn);
+    }
+    paint(k, u, fan[w], d);
+}
+
+/* Same contract as orc_schedule; kind 0 = orc_schedule's rule, 1 = the
+ * colouring above (complete graphs: round-robin either way). */
+int orc_schedule_kind(int n, int64_t m, const int32_t* edges, int kind, int32_t* step_ptr, int32_t* order) {
+    if (kind == 0 || m == 0 || m == (int64_t)n * (n - 1) / 2) return orc_schedule(n, m, edges, step_ptr, order);
+    if (kind != 1 || n < 1 || m < 0) return ORC_EINVAL;
+    int32_t* id = (int32_t*)malloc(sizeof(int32_t) * (size_t)n * n);
+    int32_t* deg = (int32_t*)calloc((size_t)n, sizeof(int32_t));
+    if (!id || !deg) { free(id); free(deg); return ORC_ENOMEM; }
+    for (int64_t i = 0; i < (int64_t)n * n; ++i) id[i] = -1;
+    int maxdeg = 0;
+    for (int64_t e = 0; e < m; ++e) {
+        id[(size_t)edges[2 * e] * n + edges[2 * e + 1]] = (int32_t)e;
+        if (++deg[edges[2 * e]] > maxdeg) maxdeg = deg[edges[2 * e]];
+        if (++deg[edges[2 * e + 1]] > maxdeg) maxdeg = deg[edges[2 * e + 1]];
+    }
+    colouring k;
+    k.n = n;
+    k.C = maxdeg + 1;
+    k.edges = edges;
+    k.id = id;
+    k.owner = (int32_t*)malloc(sizeof(int32_t) * (size_t)n * k.C);
+    k.colour = (int32_t*)malloc(sizeof(int32_t) * (size_t)m);
+    int32_t* fan = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t* path = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
+    char* infan = (char*)calloc((size_t)n, 1);
+    if (!k.owner || !k.colour || !fan || !path || !infan) {
+        free(id); free(deg); free(k.owner); free(k.colour); free(fan); free(path); free(infan);
+        return ORC_ENOMEM;
+    }
+    for (int64_t i = 0; i < (int64_t)n * k.C; ++i) k.owner[i] = -1;
+    for (int64_t e = 0; e < m; ++e) k.colour[e] = -1;
+    for (int u = 0; u < n; ++u)
+        for (int v = u + 1; v < n; ++v)
+            if (id[(size_t)u * n + v] >= 0) colour_one_edge(&k, u, v, fan, infan, path);
+    /* one round per colour, edges ascending (u, v) inside a round */
+    int S = 0;
+    int64_t pos = 0;
+    for (int c = 0; c < k.C; ++c) {
+        int64_t start = pos;
+        for (int u = 0; u < n; ++u)
+            for (int v = u + 1; v < n; ++v) {
+                int32_t e = id[(size_t)u * n + v];
+                if (e >= 0 && k.colour[e] == c) order[pos++] = e;
+            }
+        if (pos > start) step_ptr[S++] = (int32_t)start;
+    }
+    step_ptr[S] = (int32_t)pos;
+    free(id); free(deg); free(k.owner); free(k.colour); free(fan); free(path); free(infan);
+    return pos == m ? S : ORC_EINVAL;
+}
+
+/* ------------------------------------------------------------------ */
 /* BCA updates on one edge (Sec. 4).  Te is the edge's reparametrized   */
 /* L x L table, Tu_u / Tu_v the current reparametrized unaries of its   */
 /* two nodes; g, hu, hv are scratch.                                    */

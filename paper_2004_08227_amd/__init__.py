@@ -26,6 +26,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ETIMEOUT, ESTATE = 0, -1, -2, -3, -4, -5
 MAX_LABELS = 128
 OPT_ENGINE, OPT_THREADS, OPT_GRID, OPT_SPIN_LIMIT, OPT_PROFILE, OPT_ADJOINT_F64, OPT_RULE = 1, 2, 3, 4, 5, 6, 7
 RULE_H, RULE_M, RULE_U = 0, 1, 2
+SCHED_AUTO, SCHED_GREEDY, SCHED_COLOR = 0, 1, 2
 ENGINE_AUTO, ENGINE_STEP, ENGINE_PERSISTENT = 0, 1, 2
 BOPT = {"grid": 1, "graph": 2, "spin_limit": 3, "one_per_model": 4, "handoff_us": 5, "edge16_us": 6,
         "edge32_us": 7, "edge64_us": 8, "edge128_us": 9, "lds": 10, "engine": 11, "wave_edge16_us": 12,
@@ -71,6 +72,7 @@ def lib():
     pp = ctypes.POINTER(ctypes.c_void_p)
     sig = {
         "mplpxx_create": (ctypes.c_int, [i32, i32, i64, vp, vp, vp, i32, pp]),
+        "mplpxx_create_sched": (ctypes.c_int, [i32, i32, i64, vp, vp, vp, i32, i32, pp]),
         "mplpxx_create_device": (ctypes.c_int, [i32, i32, i64, vp, vp, vp, i32, vp, pp]),
         "mplpxx_iterate": (ctypes.c_int, [vp, i32]),
         "mplpxx_iterate_trace": (ctypes.c_int, [vp, i32, vp]),
@@ -83,6 +85,7 @@ def lib():
         "mplpxx_get_schedule": (ctypes.c_int, [vp, vp, vp, vp]),
         "mplpxx_get_state": (ctypes.c_int, [vp, vp, vp, vp]),
         "mplpxx_schedule": (ctypes.c_int, [i32, i64, vp, vp, vp, vp]),
+        "mplpxx_schedule_kind": (ctypes.c_int, [i32, i64, vp, i32, vp, vp, vp]),
         "mplpxx_set_state": (ctypes.c_int, [vp, vp, vp, vp]),
         "mplpxx_set_option": (ctypes.c_int, [vp, i32, i64]),
         "mplpxx_get_info": (ctypes.c_int, [vp, i32, ctypes.POINTER(i64)]),
@@ -117,14 +120,16 @@ def _ptr(a):
     return None if a is None else ctypes.c_void_p(a.ctypes.data)
 
 
-def schedule(n, edges):
-    """Host-only schedule of Alg. 1 for a graph: (step_ptr [S+1], order [m])."""
+def schedule(n, edges, kind=0):
+    """Host-only schedule of Alg. 1 for a graph: (step_ptr [S+1], order [m]);
+    kind: SCHED_AUTO, SCHED_GREEDY or SCHED_COLOR."""
     edges = np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
     m = edges.shape[0]
     S = ctypes.c_int32()
     sp = np.zeros(m + 1, dtype=np.int32)
     order = np.zeros(max(m, 1), dtype=np.int32)
-    _check(lib().mplpxx_schedule(int(n), int(m), _ptr(edges) if m else None, ctypes.byref(S), _ptr(sp), _ptr(order)))
+    _check(lib().mplpxx_schedule_kind(int(n), int(m), _ptr(edges) if m else None, int(kind), ctypes.byref(S),
+                                      _ptr(sp), _ptr(order)))
     return sp[:S.value + 1].copy(), order[:m].copy()
 
 
@@ -132,7 +137,7 @@ class Solver:
     """One model: ``Solver(n, L, edges, unaries, pairwise)`` with host numpy
     arrays (float32 or float64), or ``Solver.from_torch`` with device tensors."""
 
-    def __init__(self, n, L, edges, unaries, pairwise, dtype=None, _handle=None):
+    def __init__(self, n, L, edges, unaries, pairwise, dtype=None, _handle=None, schedule=0):
         self._h = None
         if _handle is not None:
             self._h = _handle
@@ -149,9 +154,9 @@ class Solver:
             if un.size != n * L or pw.size != m * L * L:
                 raise ValueError("unaries must hold n*L and pairwise m*L*L values")
             h = ctypes.c_void_p()
-            _check(lib().mplpxx_create(int(n), int(L), int(m), _ptr(edges) if m else None, _ptr(un),
-                                       _ptr(pw) if m else None, F32 if dt == np.float32 else F64,
-                                       ctypes.byref(h)))
+            _check(lib().mplpxx_create_sched(int(n), int(L), int(m), _ptr(edges) if m else None, _ptr(un),
+                                             _ptr(pw) if m else None, F32 if dt == np.float32 else F64,
+                                             int(schedule), ctypes.byref(h)))
             self._h = h
         self.n = self.info("n")
         self.L = self.info("L")
@@ -159,8 +164,8 @@ class Solver:
         self.dtype = np.float32 if self.info("dtype") == F32 else np.float64
 
     @classmethod
-    def from_model(cls, model):
-        return cls(model.n, model.L, model.edges, model.unaries, model.pairwise)
+    def from_model(cls, model, schedule=0):
+        return cls(model.n, model.L, model.edges, model.unaries, model.pairwise, schedule=schedule)
 
     @classmethod
     def from_torch(cls, n, L, edges, unaries, pairwise, stream=None):

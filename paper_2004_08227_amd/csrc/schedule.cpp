@@ -5,6 +5,24 @@
 // graph gets greedy maximal matchings, each round scanning the remaining
 // edges in ascending (u, v) order and keeping an edge when both of its nodes
 // are still free.  Edges inside one round are listed in ascending (u, v).
+//
+// On request (kind MPLPXX_SCHED_COLOR) a graph that is not complete gets
+// instead the matchings of a proper edge colouring with at most Delta + 1
+// colours (Misra and Gries' constructive proof of Vizing's theorem), one
+// round per colour in colour order: fewer rounds than the greedy matchings
+// when the graph is irregular or dense, i.e. a shorter chain of dependent
+// steps per iteration.  Every choice is fixed so that the schedule is a
+// function of the edge set alone (the oracle implements the same rule):
+//  * edges are coloured in ascending (u, v), u < v, with u the fan's centre;
+//  * "a colour free on x" is the smallest colour no edge at x has;
+//  * the fan F = [v, ...] is extended, while possible, by the neighbour y
+//    not yet in F whose edge (u, y) has the smallest colour that is free on
+//    the fan's last node;
+//  * c = the colour free on u, d = the colour free on the fan's last node;
+//    the path from u whose edges alternate d, c, d, ... is swapped c <-> d;
+//  * w = the first node of F (in fan order) on which d is free and up to
+//    which F is still a fan; the prefix up to w is rotated (each edge takes
+//    the colour of the next fan edge) and (u, w) gets d.
 #include <algorithm>
 #include <cstdint>
 #include <vector>
@@ -16,8 +34,112 @@ namespace mplpxx {
 
 static inline int64_t key_of(int u, int v, int64_t n) { return (int64_t)u * n + v; }
 
+// Misra-Gries edge colouring; colour[e] in [0, Delta].  at[x * C + c] = the
+// edge of colour c at node x, or -1.
+static void color_edges(int n, const std::vector<int>& eu, const std::vector<int>& ev, const std::vector<int>& by_key,
+                        std::vector<int>& colour, int& ncolours) {
+  const int64_t m = (int64_t)eu.size();
+  std::vector<int> deg(n, 0);
+  for (int64_t e = 0; e < m; ++e) {
+    ++deg[eu[e]];
+    ++deg[ev[e]];
+  }
+  const int C = *std::max_element(deg.begin(), deg.end()) + 1;
+  ncolours = C;
+  colour.assign(m, -1);
+  std::vector<int> at((size_t)n * C, -1);
+  auto other = [&](int e, int x) { return eu[e] == x ? ev[e] : eu[e]; };
+  auto free_on = [&](int x, int c) { return at[(size_t)x * C + c] < 0; };
+  auto first_free = [&](int x) {
+    int c = 0;
+    while (!free_on(x, c)) ++c;
+    return c;
+  };
+  auto set_colour = [&](int e, int c) {
+    if (colour[e] >= 0) {
+      at[(size_t)eu[e] * C + colour[e]] = -1;
+      at[(size_t)ev[e] * C + colour[e]] = -1;
+    }
+    colour[e] = c;
+    if (c >= 0) {
+      at[(size_t)eu[e] * C + c] = e;
+      at[(size_t)ev[e] * C + c] = e;
+    }
+  };
+  std::vector<int> fan, fan_edge, path;
+  std::vector<char> in_fan(n, 0);
+  for (int e0 : by_key) {
+    const int u = eu[e0], v = ev[e0];
+    // maximal fan of u starting at v
+    fan.assign(1, v);
+    fan_edge.assign(1, e0);
+    in_fan[v] = 1;
+    for (;;) {
+      const int x = fan.back();
+      int next = -1, next_e = -1;
+      for (int c = 0; c < C; ++c) {
+        if (!free_on(x, c)) continue;
+        const int e = at[(size_t)u * C + c];
+        if (e < 0) continue;
+        const int y = other(e, u);
+        if (in_fan[y]) continue;
+        next = y;
+        next_e = e;
+        break;
+      }
+      if (next < 0) break;
+      fan.push_back(next);
+      fan_edge.push_back(next_e);
+      in_fan[next] = 1;
+    }
+    for (int y : fan) in_fan[y] = 0;
+    const int c = first_free(u);
+    const int d = first_free(fan.back());
+    if (c != d) {
+      // the path from u alternating d, c, d, ...: swap its colours
+      path.clear();
+      int x = u, want = d;
+      for (;;) {
+        const int e = at[(size_t)x * C + want];
+        if (e < 0) break;
+        path.push_back(e);
+        x = other(e, x);
+        want = want == d ? c : d;
+      }
+      for (int e : path) set_colour(e, colour[e] == c ? -2 : -3);   // clear first
+      for (int e : path) {
+        const int was = colour[e];
+        colour[e] = -1;
+        set_colour(e, was == -2 ? d : c);
+      }
+    }
+    // w: the first fan node with d free, up to which F is still a fan
+    size_t wi = 0;
+    bool found = false;
+    for (size_t i = 0; i < fan.size(); ++i) {
+      if (i > 0) {
+        const int ci = colour[fan_edge[i]];
+        if (ci < 0 || !free_on(fan[i - 1], ci)) break;
+      }
+      if (free_on(fan[i], d)) {
+        wi = i;
+        found = true;
+        break;
+      }
+    }
+    if (!found) wi = 0;  // (cannot happen for a proper colouring; keeps the loop total)
+    // rotate the prefix: edge i takes the colour of edge i + 1, (u, w) gets d
+    for (size_t i = 0; i < wi; ++i) {
+      const int cn = colour[fan_edge[i + 1]];
+      set_colour(fan_edge[i + 1], -1);
+      set_colour(fan_edge[i], cn);
+    }
+    set_colour(fan_edge[wi], d);
+  }
+}
+
 void build_schedule(int n, const std::vector<int>& eu, const std::vector<int>& ev, std::vector<int>& step_ptr,
-                    std::vector<int>& order) {
+                    std::vector<int>& order, int kind) {
   const int64_t m = (int64_t)eu.size();
   step_ptr.clear();
   order.clear();
@@ -37,6 +159,19 @@ void build_schedule(int n, const std::vector<int>& eu, const std::vector<int>& e
   };
   auto by_uv = [&](int a, int b) { return key_of(eu[a], ev[a], n) < key_of(eu[b], ev[b], n); };
 
+  if (kind == MPLPXX_SCHED_COLOR && m != (int64_t)n * (n - 1) / 2) {
+    std::vector<int> colour;
+    int C = 0;
+    color_edges(n, eu, ev, by_key, colour, C);
+    std::vector<std::vector<int>> rounds(C);
+    for (int e : by_key) rounds[colour[e]].push_back(e);   // ascending (u, v) within a colour
+    for (const auto& r : rounds) {
+      if (r.empty()) continue;
+      order.insert(order.end(), r.begin(), r.end());
+      step_ptr.push_back((int)order.size());
+    }
+    return;
+  }
   if (m == (int64_t)n * (n - 1) / 2) {
     // round-robin: a ring of N-1 positions plus a fixed node N-1; with odd n
     // the fixed node is a dummy and its partner sits the round out
@@ -77,7 +212,7 @@ void build_schedule(int n, const std::vector<int>& eu, const std::vector<int>& e
   }
 }
 
-int prepare_graph(int n, int m, const int32_t* edges, GraphPrep& g) {
+int prepare_graph(int n, int m, const int32_t* edges, GraphPrep& g, int kind) {
   std::vector<int> eu(m), ev(m);
   g.flip.assign(m, 0);
   for (int e = 0; e < m; ++e) {
@@ -96,7 +231,7 @@ int prepare_graph(int n, int m, const int32_t* edges, GraphPrep& g) {
       if (keys[e] == keys[e - 1])
         return fail(MPLPXX_EINVAL, "duplicate edge (%lld, %lld)", (long long)(keys[e] / n), (long long)(keys[e] % n));
   }
-  build_schedule(n, eu, ev, g.step_ptr, g.order);
+  build_schedule(n, eu, ev, g.step_ptr, g.order, kind);
   g.S = (int)g.step_ptr.size() - 1;
   if ((int)g.order.size() != m) return fail(MPLPXX_EINVAL, "internal: schedule does not cover the edges");
   g.slot_of_edge.assign(m, -1);

@@ -6,8 +6,10 @@
 
 namespace mplpxx {
 // eu[e] < ev[e] for every edge; fills step_ptr (S+1 entries) and order (m).
+// kind: MPLPXX_SCHED_AUTO / _GREEDY (round-robin for complete graphs, greedy
+// matchings otherwise) or MPLPXX_SCHED_COLOR (edge colouring otherwise).
 void build_schedule(int n, const std::vector<int>& eu, const std::vector<int>& ev, std::vector<int>& step_ptr,
-                    std::vector<int>& order);
+                    std::vector<int>& order, int kind = 0);
 
 // A validated graph with its schedule and per-slot metadata.
 struct GraphPrep {
@@ -21,5 +23,5 @@ struct GraphPrep {
 
 // Validates edges (range, self loops, duplicates) and builds the schedule;
 // returns MPLPXX_OK or MPLPXX_EINVAL (with the message in mplpxx_last_error).
-int prepare_graph(int n, int m, const int32_t* edges, GraphPrep& g);
+int prepare_graph(int n, int m, const int32_t* edges, GraphPrep& g, int kind = 0);
 }  // namespace mplpxx

@@ -99,6 +99,7 @@ struct mplpxx_solver {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   int engine_opt = ENGINE_AUTO;
   int rule = MPLPXX_RULE_H;  // BCA-update (Sec. 4)
+  int sched = MPLPXX_SCHED_AUTO;  // schedule kind of Alg. 1
   int threads_opt = 0;
   int grid_opt = 0;
   long long spin_limit = 1ll << 22;
@@ -172,7 +173,7 @@ bool finite_host(const void* p, size_t count, int dtype) {
 // Validates the graph and fills orientation, schedule, slot metadata.
 int prepare_solver_graph(mplpxx_solver* h, const int32_t* edges) {
   GraphPrep g;
-  const int rc = prepare_graph(h->n, h->m, edges, g);
+  const int rc = prepare_graph(h->n, h->m, edges, g, h->sched);
   if (rc != MPLPXX_OK) return rc;
   h->S = g.S;
   h->step_ptr.swap(g.step_ptr);
@@ -189,7 +190,8 @@ int prepare_solver_graph(mplpxx_solver* h, const int32_t* edges) {
 }
 
 int create_impl(int32_t n, int32_t L, int64_t m, const int32_t* edges, const void* unaries, const void* pairwise,
-                int32_t dtype, bool device_costs, hipStream_t copy_stream, mplpxx_solver** out) {
+                int32_t dtype, bool device_costs, hipStream_t copy_stream, mplpxx_solver** out,
+                int32_t sched = MPLPXX_SCHED_AUTO) {
   if (!out) return fail(MPLPXX_EINVAL, "out is NULL");
   *out = nullptr;
   if (dtype != MPLPXX_F32 && dtype != MPLPXX_F64) return fail(MPLPXX_EINVAL, "unknown dtype %d", dtype);
@@ -198,6 +200,8 @@ int create_impl(int32_t n, int32_t L, int64_t m, const int32_t* edges, const voi
   if (m < 0 || m > (int64_t)n * (n - 1) / 2) return fail(MPLPXX_EINVAL, "m must be in [0, n(n-1)/2] (got %lld)", (long long)m);
   if (m > 0x3fffffff) return fail(MPLPXX_EINVAL, "too many edges");
   if (!unaries) return fail(MPLPXX_EINVAL, "unaries is NULL");
+  if (sched != MPLPXX_SCHED_AUTO && sched != MPLPXX_SCHED_GREEDY && sched != MPLPXX_SCHED_COLOR)
+    return fail(MPLPXX_EINVAL, "unknown schedule kind %d", sched);
   if (m > 0 && (!edges || !pairwise)) return fail(MPLPXX_EINVAL, "edges/pairwise is NULL");
   const size_t esz = dtype == MPLPXX_F32 ? 4 : 8;
   const size_t nL = (size_t)n * L, mLL = (size_t)m * L * L;
@@ -212,6 +216,7 @@ int create_impl(int32_t n, int32_t L, int64_t m, const int32_t* edges, const voi
   h->m = (int)m;
   h->dtype = dtype;
   h->esz = esz;
+  h->sched = sched;
   int rc = prepare_solver_graph(h, edges);
   if (rc != MPLPXX_OK) {
     delete h;
@@ -637,7 +642,7 @@ int make_shadow(mplpxx_solver* h) {
     return fail(e == hipErrorOutOfMemory ? MPLPXX_ENOMEM : MPLPXX_EDEVICE, "FP64 twin: %s", hipGetErrorString(e));
   }
   const int rc = create_impl(h->n, h->L, h->m, h->m ? edges.data() : nullptr, u64, h->m ? p64 : nullptr, MPLPXX_F64,
-                             true, st, &h->shadow);
+                             true, st, &h->shadow, h->sched);
   cleanup();
   return rc;
 }
@@ -662,6 +667,11 @@ int mplpxx_create(int32_t n, int32_t L, int64_t m, const int32_t* edges, const v
 int mplpxx_create_device(int32_t n, int32_t L, int64_t m, const int32_t* edges, const void* unaries_dev,
                          const void* pairwise_dev, int32_t dtype, void* hip_stream, mplpxx_solver** out) {
   return create_impl(n, L, m, edges, unaries_dev, pairwise_dev, dtype, true, static_cast<hipStream_t>(hip_stream), out);
+}
+
+int mplpxx_create_sched(int32_t n, int32_t L, int64_t m, const int32_t* edges, const void* unaries,
+                        const void* pairwise, int32_t dtype, int32_t schedule, mplpxx_solver** out) {
+  return create_impl(n, L, m, edges, unaries, pairwise, dtype, false, nullptr, out, schedule);
 }
 
 int mplpxx_iterate(mplpxx_solver* h, int32_t k) {
@@ -811,6 +821,13 @@ int mplpxx_get_schedule(mplpxx_solver* h, int32_t* n_steps, int32_t* step_ptr, i
 
 int mplpxx_schedule(int32_t n, int64_t m, const int32_t* edges, int32_t* n_steps, int32_t* step_ptr,
                     int32_t* order) {
+  return mplpxx_schedule_kind(n, m, edges, MPLPXX_SCHED_AUTO, n_steps, step_ptr, order);
+}
+
+int mplpxx_schedule_kind(int32_t n, int64_t m, const int32_t* edges, int32_t schedule, int32_t* n_steps,
+                         int32_t* step_ptr, int32_t* order) {
+  if (schedule != MPLPXX_SCHED_AUTO && schedule != MPLPXX_SCHED_GREEDY && schedule != MPLPXX_SCHED_COLOR)
+    return fail(MPLPXX_EINVAL, "unknown schedule kind %d", schedule);
   if (n < 1) return fail(MPLPXX_EINVAL, "n must be >= 1 (got %d)", n);
   if (m < 0 || m > (int64_t)n * (n - 1) / 2 || m > 0x3fffffff)
     return fail(MPLPXX_EINVAL, "m must be in [0, n(n-1)/2] (got %lld)", (long long)m);
@@ -818,6 +835,7 @@ int mplpxx_schedule(int32_t n, int64_t m, const int32_t* edges, int32_t* n_steps
   mplpxx_solver tmp;
   tmp.n = n;
   tmp.m = (int)m;
+  tmp.sched = schedule;
   int rc = prepare_solver_graph(&tmp, edges);
   if (rc != MPLPXX_OK) return rc;
   if (n_steps) *n_steps = tmp.S;

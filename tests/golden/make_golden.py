@@ -4,11 +4,15 @@ Everything here is computed by the FP64 CPU oracle (``oracle/``) on inputs
 from the seeded generators (``paper_2004_08227_amd/workloads.py``); nothing
 comes from the HIP path.  Run from the repository root:
 
-    python tests/golden/make_golden.py [all|pose|potts|batch|adjoint]
+    python tests/golden/make_golden.py [all|pose|potts|potts_sched|batch|adjoint]
 
 Outputs (JSON, one file per workload):
   pose_k200_l64.json        dual trace of 200 iterations, final node minima
   potts_er_n1000_l16.json   dual traces (30 iterations) at 5/25/50/100 % density
+  potts_er_n1000_l16_sched.json  the same workload under both schedules of
+                            the oracle (greedy matchings, Delta + 1 edge
+                            colouring) at 1/5/25/50 % density: schedule
+                            sizes and 30-iteration dual traces
   batched_mix_samples.json  100-iteration traces of 8 models of the 256-model mix
   adjoint_uniform_k100_l32.json  central and one-sided differences of D_50
                             along seeded dense and sparse directions and
@@ -57,6 +61,20 @@ def make_potts():
                                  "trace": st.run(30, trace=True, nthreads=THREADS).tolist()}
         print("potts", p, flush=True)
     dump("potts_er_n1000_l16.json", out)
+
+
+def make_potts_sched():
+    out = {"workload": "potts_er n=1000 L=16 seed=0", "iters": 30, "runs": {}}
+    for kind in ("greedy", "color"):
+        for p in (0.01, 0.05, 0.25, 0.5):
+            if kind == "greedy" and p != 0.01:
+                continue  # the greedy traces at 5/25/50 % are in potts_er_n1000_l16.json
+            model = W.potts_er(1000, 16, p, seed=0)
+            st = oracle.State(model, schedule_kind=kind)
+            out["runs"][f"{kind}_{p}"] = {"m": model.m, "steps": st.n_steps,
+                                          "trace": st.run(30, trace=True, nthreads=THREADS).tolist()}
+            print("potts", kind, p, st.n_steps, flush=True)
+    dump("potts_er_n1000_l16_sched.json", out)
 
 
 def batch_samples():
@@ -162,6 +180,8 @@ if __name__ == "__main__":
         make_pose()
     if what in ("all", "potts"):
         make_potts()
+    if what in ("all", "potts_sched"):
+        make_potts_sched()
     if what in ("all", "batch"):
         make_batch()
     if what in ("all", "adjoint"):

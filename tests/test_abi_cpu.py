@@ -122,6 +122,24 @@ def test_host_schedule_equals_oracle_schedule(kind, args):
     assert np.array_equal(sp, sp_o) and np.array_equal(order, ord_o)
 
 
+@pytest.mark.parametrize("n,p,seed", [(12, 0.3, 0), (40, 0.1, 1), (60, 0.5, 2), (200, 0.05, 3), (1000, 0.01, 4),
+                                      (1000, 0.05, 0), (9, 0.95, 5)])
+def test_host_colour_schedule_equals_oracle_colour_schedule(n, p, seed):
+    """The library's and the oracle's edge colourings are written
+    separately; with every choice of the rule fixed they must agree exactly,
+    whatever the input order and orientation of the edges."""
+    edges = W.potts_er(n, 2, p, seed=seed).edges
+    rng = np.random.default_rng(seed)
+    edges = edges[rng.permutation(edges.shape[0])]
+    flip = rng.random(edges.shape[0]) < 0.5
+    edges[flip] = edges[flip][:, ::-1]
+    sp, order = M.schedule(n, edges, M.SCHED_COLOR)
+    sp_o, ord_o = oracle.schedule(n, np.sort(edges, axis=1).astype(np.int32), "color")
+    assert np.array_equal(sp, sp_o) and np.array_equal(order, ord_o)
+    deg = np.bincount(edges.ravel(), minlength=n)
+    assert len(sp) - 1 <= deg.max() + 1
+
+
 def test_host_schedule_rejects_bad_graphs():
     with pytest.raises(M.MplpError):
         M.schedule(3, np.array([[0, 1], [1, 0]], np.int32))

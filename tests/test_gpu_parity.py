@@ -304,3 +304,54 @@ def test_large_matchings_default_grid_is_bitwise_identical():
         assert d == states[0][2]
     st, ref = oracle.run_model(model, iters)
     assert _rel(states[0][2], ref[-1]) <= 1e-5
+
+
+def _sched_runs():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "potts_er_n1000_l16_sched.json")
+    return json.load(open(path)) if os.path.exists(path) else None
+
+
+@pytest.mark.parametrize("run", ["greedy_0.01", "color_0.01", "color_0.05", "color_0.25", "color_0.5"])
+def test_potts_er_n1000_l16_schedules_match_stored_oracle(run):
+    """The sparsification workload under both schedules (greedy matchings,
+    Delta + 1 edge colouring), 30 iterations at full size, against the
+    oracle's stored traces under the same schedule: same number of
+    matchings, traces within 1e-5."""
+    g = _sched_runs()
+    if g is None:
+        pytest.skip("golden file missing")
+    rec = g["runs"][run]
+    kind, p = run.split("_")
+    _announce("potts_er n=1000 L=16 schedule", run)
+    model = W.potts_er(1000, 16, float(p), seed=0)
+    assert model.m == rec["m"]
+    sched = M.SCHED_COLOR if kind == "color" else M.SCHED_GREEDY
+    with M.Solver.from_model(model, schedule=sched) as s:
+        assert s.info("steps") == rec["steps"]
+        tr = s.iterate_trace(g["iters"])
+    ref = np.asarray(rec["trace"])
+    assert np.max(np.abs(tr - ref) / np.maximum(1.0, np.abs(ref))) <= 1e-5
+
+
+def test_colour_schedule_fp64_and_adjoint_twin():
+    """FP64 under the colour schedule matches the oracle under the same
+    schedule to 1e-12, and an FP32 handle's adjoint (which differentiates
+    an FP64 twin built from it) follows the handle's schedule: its loss is
+    the oracle's D_K under that schedule."""
+    _announce("colour schedule fp64 + adjoint twin")
+    base = W.potts_er(60, 8, 0.3, seed=21)
+    m64 = W.Model(base.n, base.L, base.edges, base.unaries.astype(np.float64), base.pairwise.astype(np.float64), "c64")
+    st, ref = oracle.run_model(m64, 8, schedule_kind="color")
+    with M.Solver.from_model(m64, schedule=M.SCHED_COLOR) as s:
+        sp, order = s.schedule()
+        sp_o, ord_o = oracle.schedule(m64.n, np.sort(m64.edges, axis=1).astype(np.int32), "color")
+        assert np.array_equal(sp, sp_o) and np.array_equal(order, ord_o)
+        tr = s.iterate_trace(8)
+    assert np.max(np.abs(tr - ref) / np.maximum(1.0, np.abs(ref))) <= 1e-12
+    K = 6
+    st2, ref2 = oracle.run_model(base, K, schedule_kind="color")
+    with M.Solver.from_model(base, schedule=M.SCHED_COLOR) as s:
+        loss = s.adjoint_forward(K, 2)
+    assert _rel(loss, ref2[-1]) <= 1e-11, (loss, ref2[-1])

@@ -44,6 +44,11 @@ MUTANTS = [
      "double x = src[(size_t)s * L + t];"),
     ("duplicates accepted", "if (keys[e] == keys[e - 1]) { free(keys); return ORC_EINVAL; }", ""),
     ("brute force skips labellings", "while (i < n && ++y[i] == L) y[i++] = 0;", "while (i < n && (y[i] += 2) >= L) y[i++] = 0;"),
+    ("colouring: d free on the fan's first node", "int d = smallest_free(k, fan[len - 1]);", "int d = smallest_free(k, fan[0]);"),
+    ("colouring: no path swap", "for (int i = 0; i + 1 < np; ++i) paint(k, path[i], path[i + 1], was[i] == c ? d : c);",
+     "for (int i = 0; i + 1 < np; ++i) paint(k, path[i], path[i + 1], was[i]);"),
+    ("colouring: fan not rotated", "        paint(k, u, fan[i], cn);\n", "        paint(k, u, fan[i + 1], cn);\n"),
+    ("colouring: largest colour first", "for (int c = 0; c < k->C && !grown; ++c) {", "for (int c = k->C - 1; c >= 0 && !grown; --c) {"),
 ]
 
 
