@@ -234,6 +234,29 @@ def bench_rules(M, W, iters=200):
     return out
 
 
+def bench_gap(M, W, iters=200):
+    """Anytime primal-dual gap on the pose model: after each iteration the
+    certified dual (Eq. 3) and the energy of the Eq. (5) rounding."""
+    model = W.pose(200, 64, seed=0)
+    with M.Solver.from_model(model) as s:
+        s.iterate_gap(2)                       # warm up (compiles nothing; first-use allocations)
+    with M.Solver.from_model(model) as s:
+        t0 = time.perf_counter()
+        d, e, _ = s.iterate_gap(iters)
+        wall = time.perf_counter() - t0
+    best_e = np.minimum.accumulate(e)
+    best_d = np.maximum.accumulate(d)
+    gap = (best_e - best_d) / np.abs(best_d)
+    out = {"workload": "pose n=200 L=64 seed 0", "iterations": iters, "wall_s": wall,
+           "final_dual": float(d[-1]), "best_energy": float(e.min()), "best_energy_iteration": int(np.argmin(e)) + 1,
+           "final_rel_gap": float(gap[-1]),
+           "iterations_to_rel_gap": {f"{g:g}": (None if not np.any(gap <= g) else int(np.flatnonzero(gap <= g)[0]) + 1)
+                                     for g in (1e-1, 3e-2, 1e-2, 3e-3, 1e-3)},
+           "energy_at": {str(i): float(e[i - 1]) for i in (1, 10, 50, 100, 200) if i <= iters},
+           "dual_at": {str(i): float(d[i - 1]) for i in (1, 10, 50, 100, 200) if i <= iters}}
+    return out
+
+
 def copy_calibration():
     """A plain 1 GiB device copy, three times: the reference for the HBM
     byte counters (run under rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)."""
@@ -283,6 +306,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-c2", action="store_true", help="skip the sparsification section (n=1000, L=16, 4 densities)")
     ap.add_argument("--no-rules", action="store_true", help="skip the MPLP / uniform vs MPLP++ comparison")
+    ap.add_argument("--no-gap", action="store_true", help="skip the anytime primal-dual gap section")
     ap.add_argument("--only-batch", action="store_true", help="run only the batched-mix section")
     ap.add_argument("--no-per-problem", action="store_true",
                     help="batched section without the per-problem comparison runs")
@@ -396,6 +420,8 @@ def main():
         result["adjoint"] = bench_adjoint(M, W)
     if not args.no_rules:
         result["rules"] = bench_rules(M, W)
+    if not args.no_gap:
+        result["gap"] = bench_gap(M, W)
     print(json.dumps(result))
 
 

@@ -141,6 +141,19 @@ int mplpxx_dual_bound(mplpxx_solver* h, double* out);
  * that labelling on the original costs, accumulated in FP64. */
 int mplpxx_decode(mplpxx_solver* h, int32_t* labels, double* energy);
 
+/* Anytime primal-dual gap: runs k >= 1 iterations and after each one
+ * records the certified dual bound of Eq. (3) (as mplpxx_dual_bound) in
+ * dual[i] and the Eq. (1) energy of the rounding of Eq. (5) (as
+ * mplpxx_decode) in energy[i]; best_labels (may be NULL) receives the
+ * labelling of the lowest energy seen (the earliest on ties).  Every
+ * energy[i] >= every dual[j] (weak duality), so min energy - max dual is a
+ * certified bound on the distance of both to the optimum.  All three are
+ * HOST buffers (dual, energy: k doubles; best_labels: n int32).  Costs one
+ * dual and one rounding per iteration on top of the iteration itself.
+ * Errors: MPLPXX_EINVAL (k < 1, NULL dual or energy), MPLPXX_ENOMEM, and
+ * those of mplpxx_iterate. */
+int mplpxx_iterate_gap(mplpxx_solver* h, int32_t k, double* dual, double* energy, int32_t* best_labels);
+
 /* Frees the handle and all its device memory; NULL is a no-op.  Waits for
  * queued work on the handle's stream first. */
 void mplpxx_destroy(mplpxx_solver* h);

@@ -93,6 +93,7 @@ def lib():
         "mplpxx_get_step_profile": (ctypes.c_int, [vp, vp]),
         "mplpxx_adjoint_forward": (ctypes.c_int, [vp, i32, i32, ctypes.POINTER(dbl)]),
         "mplpxx_adjoint_backward": (ctypes.c_int, [vp, vp, vp]),
+        "mplpxx_iterate_gap": (ctypes.c_int, [vp, i32, vp, vp, vp]),
         "mplpxx_batch_create": (ctypes.c_int, [i32, vp, vp, vp, vp, vp, vp, pp]),
         "mplpxx_batch_iterate": (ctypes.c_int, [vp, i32]),
         "mplpxx_batch_dual_bounds": (ctypes.c_int, [vp, vp]),
@@ -257,6 +258,15 @@ class Solver:
         v = ctypes.c_int64()
         _check(lib().mplpxx_get_info(self._h, INFO[key], ctypes.byref(v)))
         return v.value
+
+    def iterate_gap(self, k):
+        """k iterations; after each the certified dual (Eq. 3) and the energy
+        of the Eq. (5) rounding.  Returns (dual [k], energy [k], best labels)."""
+        d = np.zeros(k, np.float64)
+        e = np.zeros(k, np.float64)
+        lab = np.zeros(self.n, np.int32)
+        _check(lib().mplpxx_iterate_gap(self._h, int(k), d.ctypes.data, e.ctypes.data, lab.ctypes.data))
+        return d, e, lab
 
     def adjoint_forward(self, K, every=10):
         """K iterations from phi = 0 with checkpoints every `every`; returns

@@ -782,6 +782,70 @@ int mplpxx_decode(mplpxx_solver* h, int32_t* labels, double* energy) {
   return MPLPXX_OK;
 }
 
+int mplpxx_iterate_gap(mplpxx_solver* h, int32_t k, double* dual, double* energy, int32_t* best_labels) {
+  if (!h) return fail(MPLPXX_EINVAL, "handle is NULL");
+  if (k < 1) return fail(MPLPXX_EINVAL, "k must be >= 1");
+  if (!dual || !energy) return fail(MPLPXX_EINVAL, "dual or energy is NULL");
+  hipStream_t st = h->stream();
+  double* d_gap = nullptr;  // [k] duals, then [k] energies
+  int* d_lab = nullptr;     // [k][n] labellings
+  auto release = [&]() {
+    (void)hipStreamSynchronize(st);
+    if (d_gap) (void)hipFree(d_gap);
+    if (d_lab) (void)hipFree(d_lab);
+  };
+  if (hipMalloc(&d_gap, (size_t)2 * k * sizeof(double)) != hipSuccess ||
+      hipMalloc(&d_lab, (size_t)k * h->n * sizeof(int)) != hipSuccess) {
+    release();
+    return fail(MPLPXX_ENOMEM, "no device memory for the gap trace");
+  }
+  for (int it = 0; it < k; ++it) {
+    int rc = h->dtype == MPLPXX_F32 ? iterate_t<float>(h, 1, nullptr) : iterate_t<double>(h, 1, nullptr);
+    if (rc != MPLPXX_OK) {
+      release();
+      return rc;
+    }
+    hipError_t e;
+    if (h->dtype == MPLPXX_F32) {
+      e = launch_dual<float>((const float*)h->d_unaries, (const float*)h->d_tables, (const float*)h->d_phi,
+                             h->d_node_ptr, h->d_inc, h->n, h->L, h->m, h->d_node_min, h->d_edge_min, d_gap + it, st);
+      if (e == hipSuccess)
+        e = launch_decode<float>((const float*)h->d_unaries, (const float*)h->d_tables, (const float*)h->d_phi,
+                                 h->d_slots, h->d_node_ptr, h->d_inc, h->n, h->L, h->m, d_lab + (size_t)it * h->n,
+                                 d_gap + k + it, st);
+    } else {
+      e = launch_dual<double>((const double*)h->d_unaries, (const double*)h->d_tables, (const double*)h->d_phi,
+                              h->d_node_ptr, h->d_inc, h->n, h->L, h->m, h->d_node_min, h->d_edge_min, d_gap + it, st);
+      if (e == hipSuccess)
+        e = launch_decode<double>((const double*)h->d_unaries, (const double*)h->d_tables, (const double*)h->d_phi,
+                                  h->d_slots, h->d_node_ptr, h->d_inc, h->n, h->L, h->m, d_lab + (size_t)it * h->n,
+                                  d_gap + k + it, st);
+    }
+    if (e != hipSuccess) {
+      release();
+      return fail(MPLPXX_EDEVICE, "gap trace: %s", hipGetErrorString(e));
+    }
+  }
+  int rc = sync_and_check(h);
+  if (rc != MPLPXX_OK) {
+    release();
+    return rc;
+  }
+  std::vector<double> buf((size_t)2 * k);
+  hipError_t e = hipMemcpy(buf.data(), d_gap, buf.size() * sizeof(double), hipMemcpyDeviceToHost);
+  int best = 0;
+  for (int it = 0; it < k; ++it) {
+    dual[it] = buf[it];
+    energy[it] = buf[k + it];
+    if (energy[it] < energy[best]) best = it;
+  }
+  if (e == hipSuccess && best_labels)
+    e = hipMemcpy(best_labels, d_lab + (size_t)best * h->n, (size_t)h->n * sizeof(int), hipMemcpyDeviceToHost);
+  release();
+  if (e != hipSuccess) return fail(MPLPXX_EDEVICE, "gap trace copy: %s", hipGetErrorString(e));
+  return MPLPXX_OK;
+}
+
 void mplpxx_destroy(mplpxx_solver* h) {
   if (!h) return;
   (void)hipStreamSynchronize(h->stream());

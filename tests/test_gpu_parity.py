@@ -355,3 +355,29 @@ def test_colour_schedule_fp64_and_adjoint_twin():
     with M.Solver.from_model(base, schedule=M.SCHED_COLOR) as s:
         loss = s.adjoint_forward(K, 2)
     assert _rel(loss, ref2[-1]) <= 1e-11, (loss, ref2[-1])
+
+
+@pytest.mark.parametrize("which", ["tiny_fp64", "pose_fp32"])
+def test_iterate_gap_is_dual_and_rounding_after_each_iteration(which):
+    """mplpxx_iterate_gap records, after every iteration, exactly what
+    mplpxx_dual_bound and mplpxx_decode give at that point; weak duality
+    holds (every energy >= every dual); the best labelling's energy is its
+    Eq. (1) energy by the oracle; on the tiny model the brute-force optimum
+    lies between the best dual and the best energy."""
+    _announce("iterate_gap", which)
+    model = W.tiny(0) if which == "tiny_fp64" else W.pose(30, 8, seed=5)
+    k = 12
+    with M.Solver.from_model(model) as s:
+        d, e, lab = s.iterate_gap(k)
+    with M.Solver.from_model(model) as s2:
+        for it in range(k):
+            s2.iterate(1)
+            assert s2.dual_bound() == d[it]
+            labels, en = s2.decode()
+            assert en == e[it]
+    assert e.min() >= d.max() - 1e-12 * abs(d.max())
+    best = int(np.argmin(e))
+    assert abs(oracle.State(model).energy(lab) - e[best]) <= 1e-9 * max(1.0, abs(e[best]))
+    if which == "tiny_fp64":
+        e_map, _ = oracle.bruteforce(model)
+        assert d.max() <= e_map + 1e-12 and e.min() >= e_map - 1e-12
