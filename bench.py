@@ -288,8 +288,10 @@ def bench_adjoint(M, W, K=50, every=10):
             t1 = time.perf_counter()
             s.adjoint_backward()
             t2 = time.perf_counter()
+            mem = s.info("adjoint_bytes")
         key = "fp64_twin" if f64 else "fp32_run"
-        out[key] = {"loss": loss, "forward_s": t1 - t0, "backward_s": t2 - t1}
+        out[key] = {"loss": loss, "forward_s": t1 - t0, "backward_s": t2 - t1, "adjoint_device_bytes": mem,
+                    "model_device_bytes": model.m * (4 * model.L * model.L + 8 * model.L) + model.n * model.L * 12}
     return out
 
 

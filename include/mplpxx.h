@@ -254,6 +254,9 @@ int mplpxx_set_option(mplpxx_solver* h, int32_t key, int64_t value);
 #define MPLPXX_INFO_THREADS 8    /* threads per workgroup */
 #define MPLPXX_INFO_ITERATIONS 9 /* iterations run since create / set_state */
 #define MPLPXX_INFO_WALLCLOCK_KHZ 10 /* device wall-clock rate of the timestamps */
+#define MPLPXX_INFO_ADJOINT_BYTES 11 /* device bytes held for the adjoint after mplpxx_adjoint_forward
+                                        (checkpoints, argmin records, adjoint buffers; for an FP32 handle
+                                        differentiating its FP64 twin, also the twin's costs and state) */
 int mplpxx_get_info(mplpxx_solver* h, int32_t key, int64_t* value);
 
 /* Per-slot timestamps of the last iteration of the last iterate call of the

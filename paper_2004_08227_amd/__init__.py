@@ -36,7 +36,7 @@ BINFO = {"count": 1, "grid": 2, "tasks": 3, "teams": 4, "max_team": 5, "plan_us"
          "table_bytes": 9, "lds_tasks": 10, "lds_bytes": 11, "engine": 12, "waves": 13,
          "wg_max_us": 14, "wg_mean_us": 15}
 INFO = {"n": 1, "L": 2, "m": 3, "steps": 4, "dtype": 5, "engine": 6, "grid": 7, "threads": 8, "iterations": 9,
-        "wallclock_khz": 10}
+        "wallclock_khz": 10, "adjoint_bytes": 11}
 
 _lib = None
 

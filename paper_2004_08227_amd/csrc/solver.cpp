@@ -89,6 +89,7 @@ struct mplpxx_solver {
   void* d_Ub = nullptr;                   // [n][L]
   void* d_pb = nullptr;                   // [m][2][L]
   void* d_thb = nullptr;                  // [m][L][L]
+  size_t adj_bytes = 0;                   // device bytes of the adjoint buffers above
   int* d_slot_of_edge = nullptr;          // [m]
   int* d_edge_flip = nullptr;             // [m]
   int adjoint_f64 = 1;                    // FP32 handles: differentiate an FP64 run
@@ -509,6 +510,9 @@ template <typename T> int adjoint_forward_t(mplpxx_solver* h, int K, int every, 
   if (!h->d_Ub) HIP_TRY(hipMalloc(&h->d_Ub, nL * esz));
   if (!h->d_pb) HIP_TRY(hipMalloc(&h->d_pb, std::max<size_t>(1, mp * esz)));
   if (!h->d_thb) HIP_TRY(hipMalloc(&h->d_thb, std::max<size_t>(1, (size_t)h->m * h->L * h->L * esz)));
+  h->adj_bytes = (nck + 1) * nL * esz + (h->d_Ulo ? (nck + 1) * nL * sizeof(float) : 0) + (nck + 1) * mp * esz +
+                 (size_t)every * h->m * 3 * h->L + nL * esz + mp * esz + (size_t)h->m * h->L * h->L * esz +
+                 (size_t)h->m * 2 * sizeof(int);
   if (!h->d_slot_of_edge && h->m) {
     HIP_TRY(hipMalloc(&h->d_slot_of_edge, h->m * sizeof(int)));
     HIP_TRY(hipMalloc(&h->d_edge_flip, h->m * sizeof(int)));
@@ -1018,6 +1022,15 @@ int mplpxx_get_info(mplpxx_solver* h, int32_t key, int64_t* value) {
     case MPLPXX_INFO_THREADS: *value = h->NT(); return MPLPXX_OK;
     case MPLPXX_INFO_ITERATIONS: *value = h->iterations; return MPLPXX_OK;
     case MPLPXX_INFO_WALLCLOCK_KHZ: *value = h->wallclock_khz; return MPLPXX_OK;
+    case MPLPXX_INFO_ADJOINT_BYTES: {
+      // the handle's own adjoint buffers, plus, for an FP32 handle that
+      // differentiates its FP64 twin, the twin's costs, state and buffers
+      size_t b = h->adj_bytes;
+      if (const mplpxx_solver* t = h->shadow)
+        b += t->adj_bytes + (size_t)t->n * t->L * 8 * 2 + (size_t)t->m * t->L * t->L * 8 + (size_t)t->m * 2 * t->L * 8;
+      *value = (int64_t)b;
+      return MPLPXX_OK;
+    }
     default: return fail(MPLPXX_EINVAL, "unknown info key %d", key);
   }
 }

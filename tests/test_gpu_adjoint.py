@@ -189,3 +189,27 @@ def test_autograd_function():
     assert float(loss) == np.float32(l2)
     assert np.array_equal(un.grad.cpu().numpy(), 2.0 * gu)
     assert np.array_equal(pw.grad.cpu().numpy(), 2.0 * gp)
+
+
+def test_adjoint_memory_is_reported():
+    """MPLPXX_INFO_ADJOINT_BYTES after a forward: checkpoints (K/every + 1
+    copies of U and phi), one segment of argmin records (3 L bytes per edge
+    and iteration), the adjoint buffers; an FP32 handle differentiating its
+    FP64 twin adds the twin's costs and state."""
+    _announce("adjoint bytes")
+    n, L, K, every = 12, 5, 9, 4
+    m64 = W.uniform(n, L, seed=3, dtype=np.float64)
+    m = m64.m
+    nck = (K + every - 1) // every
+    nL, mp = n * L, m * 2 * L
+    own64 = (nck + 1) * nL * 8 + (nck + 1) * mp * 8 + every * m * 3 * L + nL * 8 + mp * 8 + m * L * L * 8 + m * 8
+    with M.Solver.from_model(m64) as s:
+        assert s.info("adjoint_bytes") == 0
+        s.adjoint_forward(K, every)
+        assert s.info("adjoint_bytes") == own64
+    m32 = W.uniform(n, L, seed=3, dtype=np.float32)
+    with M.Solver.from_model(m32) as s:
+        s.set_option(M.OPT_ADJOINT_F64, 1)
+        s.adjoint_forward(K, every)
+        twin = own64 + nL * 8 * 2 + m * L * L * 8 + mp * 8
+        assert s.info("adjoint_bytes") == twin
