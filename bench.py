@@ -257,6 +257,49 @@ def bench_gap(M, W, iters=200):
     return out
 
 
+def bench_potts(M, W, iters=50, mix_count=64):
+    """Structured Potts passes (one weight per edge, O(L) per pass) against
+    the dense wave engine on the expanded tables w [s != t]: one complete
+    pose-size model (n = 200, L = 64) as a batch of one, and the first
+    `mix_count` sizes of the batched mix (complete graphs).  Same
+    iterations from phi = 0; device times from HIP events; the duals of the
+    two runs must be bitwise equal."""
+    def run(models, potts):
+        with M.Batch(models, potts=potts) as b:
+            b.iterate(2)
+            b.reset()
+            b.iterate(iters)
+            ms = b.info("last_ms")
+            d = b.dual_bounds()
+            tb = b.info("table_bytes")
+        return ms, d, tb
+
+    out = {"iterations": iters}
+    sizes = W.batched_mix(mix_count, seed=0, models=False)
+    cases = [("pose_size_complete_n200_l64", [(200, 64)]),
+             (f"mix_{mix_count}_complete", sizes)]
+    for name, sz in cases:
+        pairs = [W.potts_pure(n, L, 1.0, seed=7 + i) for i, (n, L) in enumerate(sz)]
+        m_tot = sum(p[0].m for p in pairs)
+        bp = sum(p[0].m * (4 + 16 * p[0].L) for p in pairs)
+        bd = sum(p[0].m * algorithmic_bytes_per_update(p[0].L) for p in pairs)
+        weights, dense = [p[0] for p in pairs], [p[1] for p in pairs]
+        del pairs
+        ms_p, d_p, tb_p = run(weights, True)
+        ms_d, d_d, tb_d = run(dense, False)
+        del weights, dense
+        out[name] = {"models": len(sz), "edges": m_tot, "potts_ms_per_iter": ms_p / iters,
+                     "dense_ms_per_iter": ms_d / iters, "speedup": ms_d / ms_p,
+                     "potts_updates_per_s": m_tot * iters / (ms_p / 1e3),
+                     "dense_updates_per_s": m_tot * iters / (ms_d / 1e3),
+                     "potts_bytes_per_update": bp / m_tot, "dense_bytes_per_update": bd / m_tot,
+                     "potts_hbm_frac": bp * iters / (ms_p / 1e3) / 1e9 / HBM_PEAK_GBS,
+                     "dense_hbm_frac": bd * iters / (ms_d / 1e3) / 1e9 / HBM_PEAK_GBS,
+                     "potts_table_bytes": tb_p, "dense_table_bytes": tb_d,
+                     "duals_bitwise_equal": bool(np.array_equal(d_p, d_d))}
+    return out
+
+
 def copy_calibration():
     """A plain 1 GiB device copy, three times: the reference for the HBM
     byte counters (run under rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)."""
@@ -309,6 +352,8 @@ def main():
     ap.add_argument("--no-c2", action="store_true", help="skip the sparsification section (n=1000, L=16, 4 densities)")
     ap.add_argument("--no-rules", action="store_true", help="skip the MPLP / uniform vs MPLP++ comparison")
     ap.add_argument("--no-gap", action="store_true", help="skip the anytime primal-dual gap section")
+    ap.add_argument("--no-potts", action="store_true", help="skip the structured Potts vs dense section")
+    ap.add_argument("--only-potts", action="store_true", help="run only the structured Potts section")
     ap.add_argument("--only-batch", action="store_true", help="run only the batched-mix section")
     ap.add_argument("--no-per-problem", action="store_true",
                     help="batched section without the per-problem comparison runs")
@@ -327,6 +372,9 @@ def main():
     import paper_2004_08227_amd as M
     from paper_2004_08227_amd import workloads as W
 
+    if args.only_potts:
+        print(json.dumps({"potts": bench_potts(M, W)}))
+        return
     if args.only_batch:
         print(json.dumps({"batched": bench_batched(M, W, per_problem=not args.no_per_problem)}))
         return
@@ -424,6 +472,8 @@ def main():
         result["rules"] = bench_rules(M, W)
     if not args.no_gap:
         result["gap"] = bench_gap(M, W)
+    if not args.no_potts:
+        result["potts"] = bench_potts(M, W)
     print(json.dumps(result))
 
 

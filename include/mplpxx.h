@@ -323,6 +323,21 @@ int mplpxx_batch_create(int32_t count, const int32_t* n, const int32_t* L, const
                         const int32_t* const* edges, const float* const* unaries, const float* const* pairwise,
                         mplpxx_batch** out);
 
+/* A batch of Potts models (Sec. 4 notes that the message-passing
+ * minimization takes O(L) for such pairwise terms): the pairwise term of
+ * edge e is w_e [s != t], given as weights[i] = HOST float [m[i]] (one
+ * weight per edge, in the edge order of edges[i]); everything else as
+ * mplpxx_batch_create.  The passes then take O(L) per update instead of
+ * O(L^2) (minimum and second minimum over the labels) and read 4 bytes of
+ * pairwise data instead of 4 L^2; every result is bitwise the one of the
+ * dense engine on the table w_e [s != t] (a weight of -0 counts as +0).
+ * Runs on the wave engine: L[i] <= 64 (else MPLPXX_EINVAL), and
+ * MPLPXX_BOPT_ENGINE = 1 is rejected when the plan is made.  A batch holds
+ * either dense models or Potts models. */
+int mplpxx_batch_create_potts(int32_t count, const int32_t* n, const int32_t* L, const int64_t* m,
+                              const int32_t* const* edges, const float* const* unaries, const float* const* weights,
+                              mplpxx_batch** out);
+
 /* Runs k >= 0 BCA-iterations (Sec. 5) of every model of the batch in one
  * persistent launch (by default replayed from a hipGraph captured for this
  * k), and waits for it.  Each model's results are bitwise those of

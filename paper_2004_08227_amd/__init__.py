@@ -95,6 +95,7 @@ def lib():
         "mplpxx_adjoint_backward": (ctypes.c_int, [vp, vp, vp]),
         "mplpxx_iterate_gap": (ctypes.c_int, [vp, i32, vp, vp, vp]),
         "mplpxx_batch_create": (ctypes.c_int, [i32, vp, vp, vp, vp, vp, vp, pp]),
+        "mplpxx_batch_create_potts": (ctypes.c_int, [i32, vp, vp, vp, vp, vp, vp, pp]),
         "mplpxx_batch_iterate": (ctypes.c_int, [vp, i32]),
         "mplpxx_batch_dual_bounds": (ctypes.c_int, [vp, vp]),
         "mplpxx_batch_get_state": (ctypes.c_int, [vp, i32, vp, vp, vp]),
@@ -304,9 +305,11 @@ class Solver:
 
 
 class Batch:
-    """Many independent FP32 models solved together (``mplpxx_batch_*``)."""
+    """Many independent FP32 models solved together (``mplpxx_batch_*``).
+    ``potts=True``: every model's ``pairwise`` is a weight per edge [m]
+    (pairwise term w_e [s != t], ``mplpxx_batch_create_potts``)."""
 
-    def __init__(self, models):
+    def __init__(self, models, potts=False):
         count = len(models)
         self.models = models
         self.n = np.array([mo.n for mo in models], dtype=np.int32)
@@ -320,13 +323,15 @@ class Batch:
             e = np.ascontiguousarray(mo.edges, dtype=np.int32)
             u = np.ascontiguousarray(mo.unaries, dtype=np.float32)
             pw = np.ascontiguousarray(mo.pairwise, dtype=np.float32)
+            if potts and pw.size != mo.m:
+                raise ValueError("Potts models take one weight per edge")
             keep += [e, u, pw]
             e_ptrs[i] = e.ctypes.data if mo.m else None
             u_ptrs[i] = u.ctypes.data
             p_ptrs[i] = pw.ctypes.data if mo.m else None
         h = ctypes.c_void_p()
-        _check(lib().mplpxx_batch_create(count, _ptr(self.n), _ptr(self.L), _ptr(self.m), e_ptrs, u_ptrs, p_ptrs,
-                                         ctypes.byref(h)))
+        create = lib().mplpxx_batch_create_potts if potts else lib().mplpxx_batch_create
+        _check(create(count, _ptr(self.n), _ptr(self.L), _ptr(self.m), e_ptrs, u_ptrs, p_ptrs, ctypes.byref(h)))
         self._h = h
         self.count = count
 

@@ -43,6 +43,7 @@ using namespace mplpxx;
 
 struct ModelHost {
   int n, L, m, S, lt;
+  int potts = 0;                   // Potts pairwise terms (one weight per edge)
   int max_step;                    // edges of the largest matching
   std::vector<int> slot_of_edge;   // for state export
 };
@@ -103,6 +104,7 @@ struct mplpxx_batch {
   size_t wv_lds_limit = 0;     // dynamic LDS a workgroup of the wave kernel can have
   size_t wv_lds_cap = 0;       // dynamic LDS that keeps the kernel's register-limited occupancy
   int wv_waves = 8;
+  bool potts = false;          // a batch of Potts models (one weight per edge)
   bool plan_dirty = true;
   // execution
   hipStream_t stream = nullptr;
@@ -136,7 +138,7 @@ double wave_model_time(const mplpxx_batch* b, int i, int T, double bw_per_wg_byt
   const double lat = (T == 1 && lds_fits(b, i)) ? b->wv_lat_lds_us : b->wv_lat_mb_us;
   const double workers = (double)T * b->wv_waves;
   const double chain = h.S * std::ceil(h.max_step / workers) * lat;
-  const double bytes = 4.0 * h.L * h.L + 16.0 * h.L;
+  const double bytes = (h.potts ? 4.0 : 4.0 * h.L * h.L) + 16.0 * h.L;
   const double work = (double)h.m / T * (tw + bytes / (0.75 * bw_per_wg_bytes_us));
   return std::max(chain, work);
 }
@@ -218,6 +220,9 @@ double assign(const mplpxx_batch* b, double tau, int G, int team_cap, double bw,
 
 int plan(mplpxx_batch* b) {
   if (b->engine_opt == 2 && b->max_lt > 64) return fail(MPLPXX_EINVAL, "the wave engine takes models with L <= 64");
+  bool any_potts = false;
+  for (const ModelHost& h : b->mh) any_potts = any_potts || h.potts;
+  if (any_potts && b->engine_opt == 1) return fail(MPLPXX_EINVAL, "Potts models run on the wave engine only");
   b->wave = b->engine_opt == 2 || (b->engine_opt == 0 && b->max_lt <= 64);
   if (b->wave) {
     // LDS-resident models only as large as keeps the register-limited
@@ -226,7 +231,7 @@ int plan(mplpxx_batch* b) {
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cu_lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess)
       return fail(MPLPXX_EDEVICE, "device query failed");
-    const int o = std::max(1, wbatch_blocks_per_cu(0));
+    const int o = std::max(1, wbatch_blocks_per_cu(0, b->potts));
     const size_t share = (size_t)cu_lds / o;
     b->wv_lds_cap = share > b->wv_static + 256 ? std::min(b->wv_lds_limit, share - b->wv_static - 256) : 0;
   }
@@ -235,7 +240,7 @@ int plan(mplpxx_batch* b) {
   for (int i = 0; i < b->count; ++i)
     if (b->mh[i].m > 0 && lds_fits(b, i))
       dyn = std::max(dyn, b->wave ? wv_lds_bytes(b->mh[i].n, b->mh[i].L) : lds_model_bytes(b->mh[i].n, b->mh[i].L));
-  const int per_cu = b->wave ? wbatch_blocks_per_cu(dyn) : batch_blocks_per_cu(b->max_lt, dyn);
+  const int per_cu = b->wave ? wbatch_blocks_per_cu(dyn, b->potts) : batch_blocks_per_cu(b->max_lt, dyn);
   if (per_cu < 1) return fail(MPLPXX_EDEVICE, "batched kernel does not fit on a compute unit");
   const int gmax = per_cu * b->num_cus;
   int G = b->grid_opt > 0 ? std::min(b->grid_opt, gmax) : gmax;
@@ -362,7 +367,7 @@ hipError_t enqueue(mplpxx_batch* b, int k) {
   if (e != hipSuccess) return e;
   e = launch_u_to_mb(b->d_U, b->d_Ulo, b->d_mb, (size_t)b->total_u, b->stream);
   if (e != hipSuccess) return e;
-  e = b->wave ? launch_wbatch(a, b->grid, k, b->lds_bytes, b->stream)
+  e = b->wave ? launch_wbatch(a, b->grid, k, b->lds_bytes, b->potts, b->stream)
               : launch_batch(a, b->max_lt, b->grid, k, b->lds_bytes, b->stream);
   if (e != hipSuccess) return e;
   return launch_mb_to_u(b->d_U, b->d_Ulo, b->d_mb, (size_t)b->total_u, b->stream);
@@ -372,9 +377,9 @@ hipError_t enqueue(mplpxx_batch* b, int k) {
 
 extern "C" {
 
-int mplpxx_batch_create(int32_t count, const int32_t* n, const int32_t* L, const int64_t* m,
+static int create_batch(int32_t count, const int32_t* n, const int32_t* L, const int64_t* m,
                         const int32_t* const* edges, const float* const* unaries, const float* const* pairwise,
-                        mplpxx_batch** out) {
+                        bool potts, mplpxx_batch** out) {
   if (!out) return fail(MPLPXX_EINVAL, "out is NULL");
   *out = nullptr;
   if (count < 1) return fail(MPLPXX_EINVAL, "count must be >= 1");
@@ -387,6 +392,7 @@ int mplpxx_batch_create(int32_t count, const int32_t* n, const int32_t* L, const
     return code;
   };
   b->count = count;
+  b->potts = potts;
   b->mh.resize(count);
   b->md.resize(count);
   std::vector<GraphPrep> preps(count);
@@ -397,10 +403,11 @@ int mplpxx_batch_create(int32_t count, const int32_t* n, const int32_t* L, const
     if (m[i] > 0 && (!edges || !pairwise || !edges[i] || !pairwise[i]))
       return bail(fail(MPLPXX_EINVAL, "model %d: NULL edges or pairwise", i));
     if (!unaries[i]) return bail(fail(MPLPXX_EINVAL, "model %d: NULL unaries", i));
+    if (potts && L[i] > 64) return bail(fail(MPLPXX_EINVAL, "model %d: Potts models take L <= 64", i));
     for (size_t k = 0; k < (size_t)n[i] * L[i]; ++k)
       if (!(std::fabs(unaries[i][k]) <= (float)MPLPXX_F32_MAX_COST))
         return bail(fail(MPLPXX_EINVAL, "model %d: non-finite or too large unary", i));
-    for (size_t k = 0; k < (size_t)m[i] * L[i] * L[i]; ++k)
+    for (size_t k = 0; k < (size_t)m[i] * (potts ? 1 : (size_t)L[i] * L[i]); ++k)
       if (!(std::fabs(pairwise[i][k]) <= (float)MPLPXX_F32_MAX_COST))
         return bail(fail(MPLPXX_EINVAL, "model %d: non-finite or too large pairwise", i));
     const int rc = prepare_graph(n[i], (int)m[i], m[i] ? edges[i] : nullptr, preps[i]);
@@ -412,6 +419,7 @@ int mplpxx_batch_create(int32_t count, const int32_t* n, const int32_t* L, const
     h.n = n[i];
     h.L = L[i];
     h.m = (int)m[i];
+    h.potts = potts ? 1 : 0;
     h.S = preps[i].S;
     h.lt = next_tile(L[i]);
     h.max_step = 1;
@@ -432,7 +440,8 @@ int mplpxx_batch_create(int32_t count, const int32_t* n, const int32_t* L, const
     d.lt = h.lt;
     d.csr_off = b->total_csr;
     d.inc_off = b->total_inc;
-    b->total_tables += (long long)h.m * h.L * h.L;
+    d.potts = h.potts;
+    b->total_tables += (long long)h.m * (potts ? 1 : (long long)h.L * h.L);
     b->total_phi += (long long)h.m * 2 * h.L;
     b->total_u += (long long)h.n * h.L;
     b->total_slots += h.m;
@@ -452,7 +461,7 @@ int mplpxx_batch_create(int32_t count, const int32_t* n, const int32_t* L, const
   TRY(hipGetDevice(&dev));
   TRY(hipDeviceGetAttribute(&b->num_cus, hipDeviceAttributeMultiprocessorCount, dev));
   b->lds_limit = batch_lds_limit(b->max_lt);
-  b->wv_lds_limit = wbatch_lds_limit(&b->wv_static);
+  b->wv_lds_limit = wbatch_lds_limit(&b->wv_static, b->potts);
   b->wv_waves = wbatch_waves();
   TRY(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
   TRY(hipEventCreate(&b->ev0));
@@ -488,13 +497,15 @@ int mplpxx_batch_create(int32_t count, const int32_t* n, const int32_t* L, const
     const ModelHost& h = b->mh[i];
     const BatchModel& d = b->md[i];
     const GraphPrep& g = preps[i];
-    const size_t tl = (size_t)h.L * h.L;
+    const size_t tl = potts ? 1 : (size_t)h.L * h.L;
     packed.resize((size_t)h.m * tl);
     for (int s = 0; s < h.m; ++s) {
       const int e = g.order[s];
       const float* src = pairwise[i] + (size_t)e * tl;
       float* dst = packed.data() + (size_t)s * tl;
-      if (!g.flip[e]) {
+      if (potts) {
+        *dst = src[0] + 0.0f;  // (a weight of -0 is stored as +0: the table it stands for is the same)
+      } else if (!g.flip[e]) {
         std::memcpy(dst, src, tl * sizeof(float));
       } else {
         for (int r = 0; r < h.L; ++r)
@@ -537,6 +548,18 @@ int mplpxx_batch_create(int32_t count, const int32_t* n, const int32_t* L, const
   if (rc != MPLPXX_OK) return bail(rc);
   *out = b;
   return MPLPXX_OK;
+}
+
+int mplpxx_batch_create(int32_t count, const int32_t* n, const int32_t* L, const int64_t* m,
+                        const int32_t* const* edges, const float* const* unaries, const float* const* pairwise,
+                        mplpxx_batch** out) {
+  return create_batch(count, n, L, m, edges, unaries, pairwise, false, out);
+}
+
+int mplpxx_batch_create_potts(int32_t count, const int32_t* n, const int32_t* L, const int64_t* m,
+                              const int32_t* const* edges, const float* const* unaries, const float* const* weights,
+                              mplpxx_batch** out) {
+  return create_batch(count, n, L, m, edges, unaries, weights, true, out);
 }
 
 int mplpxx_batch_iterate(mplpxx_batch* b, int32_t k) {

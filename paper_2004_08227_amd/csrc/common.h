@@ -62,6 +62,7 @@ struct BatchModel {
   int n, L, m, lt;      // sizes and register tile (16, 32, 64 or 128)
   int csr_off;          // first node_ptr entry (n+1 per model)
   int inc_off;          // first incidence entry (2m per model)
+  int potts;            // 1: pairwise terms w_e [s != t], one weight per slot at table_off + slot
 };
 struct BatchTask {
   int model;   // which model

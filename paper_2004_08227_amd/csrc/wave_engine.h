@@ -132,6 +132,77 @@ __device__ __forceinline__ int opaque(int x) {
   return x;
 }
 
+// ---------------------------------------------------------------------------
+// Potts pairwise terms th(s,t) = w [s != t] (Sec. 4: the message-passing
+// minimization then takes O(L)).  Every pass of (H) has the form
+//   y(s) = min_t fl(th(s,t) + x(t)) = min( fl(0 + x(s)), fl(w + min_{t != s} x(t)) ),
+// exactly, because fl(w + .) is monotone: the minimum over t != s of the
+// rounded sums is the rounded sum with the minimum.  So the passes need,
+// per label s, the minimum of x over the other labels: the smallest value
+// when s is not where it is attained, else the second smallest.  Pass 3,
+// min_t fl(th(s,t) - q(t)), is the same with x = -q (exact negation).  The
+// results are bitwise the dense passes on the table w [s != t]: no
+// candidate of either is -0 (fl(+0 + x) and fl(w + x), w != -0, never
+// are), so the minima agree whatever a minimum makes of signed zeros.
+// The diagonal term is added as a +0 the compiler cannot see: a visible
+// constant lets it rewrite fl(0 - q) under a minimum as -q, which is -0
+// for q = +0.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float opaque_zero() {
+  float z = 0.0f;
+  asm volatile("" : "+v"(z));
+  return z;
+}
+// scalar load of read-only data through the constant address space
+__device__ __forceinline__ float ld_const_f(const float* p) {
+  return *(const __attribute__((address_space(4))) float*)p;
+}
+// (m1, m2) <- the two smallest of the multiset {m1, m2} + {o1, o2}, each
+// pair being the two smallest of a group of lanes (a repeated value counts
+// twice)
+__device__ __forceinline__ void min2_merge(float& m1, float& m2, float o1, float o2) {
+  const float hi = __builtin_fmaxf(m1, o1);
+  m1 = vmin(m1, o1);
+  m2 = vmin(hi, vmin(m2, o2));
+}
+template <int CTRL> __device__ __forceinline__ void min2_dpp(float& m1, float& m2) {
+  min2_merge(m1, m2, dpp_f<CTRL>(m1), dpp_f<CTRL>(m2));
+}
+// per lane (label) s: min over the real labels t != s of x(t) (+inf if
+// none).  The two smallest values of the wave, m1 <= m2, by a butterfly
+// over the lanes (DPP within rows of 16, then the row swaps); a label
+// holding m1 gets m2 (equal to m1 when the minimum is repeated), any other
+// label m1.  Which zero a minimum of +0 and -0 returns does not matter
+// here: the result only enters fl(w + .) with w != -0.
+__device__ __forceinline__ float min_other(float x, bool real) {
+  const float kInf = __builtin_inff();
+  float m1 = real ? x : kInf;
+  float m2;
+  {
+    const float o = dpp_f<0xB1>(m1);   // lane ^ 1 (m2 is +inf on both sides)
+    m2 = __builtin_fmaxf(m1, o);
+    m1 = vmin(m1, o);
+  }
+  min2_dpp<0x4E>(m1, m2);              // lane ^ 2
+  min2_dpp<0x141>(m1, m2);             // row_half_mirror: the other quad of the octet
+  min2_dpp<0x140>(m1, m2);             // row_mirror: the other octet of the row
+  {
+    auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(m1), __float_as_uint(m1), false, false);
+    auto b = __builtin_amdgcn_permlane16_swap(__float_as_uint(m2), __float_as_uint(m2), false, false);
+    m1 = __uint_as_float(a[0]);
+    m2 = __uint_as_float(b[0]);
+    min2_merge(m1, m2, __uint_as_float(a[1]), __uint_as_float(b[1]));
+  }
+  {
+    auto a = __builtin_amdgcn_permlane32_swap(__float_as_uint(m1), __float_as_uint(m1), false, false);
+    auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(m2), __float_as_uint(m2), false, false);
+    m1 = __uint_as_float(a[0]);
+    m2 = __uint_as_float(b[0]);
+    min2_merge(m1, m2, __uint_as_float(a[1]), __uint_as_float(b[1]));
+  }
+  return (real && x == m1) ? m2 : m1;
+}
+
 // Runs `iters` iterations over the slots first, first + stride, ... of one
 // model on this wave.  Returns false if a wait timed out or another worker
 // gave up (then *abort is set for the workgroup and err for the launch).
@@ -140,11 +211,14 @@ __device__ __forceinline__ int opaque(int x) {
 // table one slot ahead (a second register tile); LT = 64 loads each table at
 // the start of its own update, and other waves of the compute unit cover the
 // latency.
-template <int LT, bool LDSU, bool PHI_FAR>
+//
+// POTTS: the model's pairwise terms are w_e [s != t] with one weight per
+// slot in v.tables (see above); the passes run in label order, no tile.
+template <int LT, bool LDSU, bool PHI_FAR, bool POTTS = false>
 __device__ __forceinline__ bool wv_run(const WvView& v_in, int first_in, int stride_in, int iters_in,
                                        WvScratch& scr, long long spin_limit, int* err, int* abort) {
   constexpr int B = WvShape<LT>::B;
-  constexpr bool PRE = LT <= 32;
+  constexpr bool PRE = LT <= 32 && !POTTS;
   WvView v = v_in;
   v.L = uni(v.L);
   v.m = uni(v.m);
@@ -191,7 +265,8 @@ __device__ __forceinline__ bool wv_run(const WvView& v_in, int first_in, int str
         gv = p[L + li];
       }
     };
-    if (!PRE) wv_load_tile<LT>(v.tables + (size_t)slot * L * L, L, rbl, cbl, xc);
+    if (!PRE && !POTTS) wv_load_tile<LT>(v.tables + (size_t)slot * L * L, L, rbl, cbl, xc);
+    const float w = POTTS ? ld_const_f(v.tables + slot) : 0.f;
     if (!PHI_FAR) {
       const float* p = v.phi + (size_t)slot * 2 * L;
       fu = p[li];
@@ -253,72 +328,87 @@ __device__ __forceinline__ bool wv_run(const WvView& v_in, int first_in, int str
         prefetch();
       }
     }
-    // ---- centred a' in label order, then into the grid ----
     const float c_u = wave_min(lout ? hu : kInf);
     const float c_v = wave_min(lout ? hv : kInf);
     const float delta = 0.5f * (c_u - c_v);
-    scr.au[lane] = lout ? ((hu - c_u) + lu) - fu : 0x1p127f;
-    scr.av[lane] = lout ? ((hv - c_v) + lv) - fv : kPadBig;
-    wave_sync();
-    float au[B], av[B];
-#pragma unroll
-    for (int i = 0; i < B; ++i) au[i] = scr.au[rb * B + i];
-#pragma unroll
-    for (int jj = 0; jj < B; ++jj) av[jj] = scr.av[cb * B + jj];
-    // pass 1: p(s) = min_t [th(s,t) + a_v(t)], b = (a_u - p) / 2
-    float b[B];
-    {
-      float pm[B];
-#pragma unroll
+    float phu, phv;
+    if constexpr (POTTS) {
+      // centred a' in label order; the three passes by min_other
+      const float au = ((hu - c_u) + lu) - fu;
+      const float av = ((hv - c_v) + lv) - fv;
+      const float z = opaque_zero();   // th(s,s)
+      const float p = vmin(z + av, w + min_other(av, lout));
+      const float b = 0.5f * (au - p);
+      const float q = vmin(z + b, w + min_other(b, lout));
+      const float nq = -q;
+      const float r = vmin(z - q, w + min_other(nq, lout));
+      phu = r - delta;   // new message into u
+      phv = q + delta;   // new message into v
+    } else {
+      // ---- centred a' in label order, then into the grid ----
+      scr.au[lane] = lout ? ((hu - c_u) + lu) - fu : 0x1p127f;
+      scr.av[lane] = lout ? ((hv - c_v) + lv) - fv : kPadBig;
+      wave_sync();
+      float au[B], av[B];
+  #pragma unroll
+      for (int i = 0; i < B; ++i) au[i] = scr.au[rb * B + i];
+  #pragma unroll
+      for (int jj = 0; jj < B; ++jj) av[jj] = scr.av[cb * B + jj];
+      // pass 1: p(s) = min_t [th(s,t) + a_v(t)], b = (a_u - p) / 2
+      float b[B];
+      {
+        float pm[B];
+  #pragma unroll
+        for (int i = 0; i < B; ++i) {
+          float mn = xc[i][0] + av[0];
+  #pragma unroll
+          for (int jj = 1; jj < B; ++jj) mn = vmin(mn, xc[i][jj] + av[jj]);
+          pm[i] = mn;
+        }
+        oct_min_n<B>(pm);
+  #pragma unroll
+        for (int i = 0; i < B; ++i) b[i] = 0.5f * (au[i] - pm[i]);
+      }
+      // pass 2: q(t) = min_s [th(s,t) + b(s)]
+      float qv[B];
+  #pragma unroll
+      for (int jj = 0; jj < B; ++jj) {
+        float mn = xc[0][jj] + b[0];
+  #pragma unroll
+        for (int i = 1; i < B; ++i) mn = vmin(mn, xc[i][jj] + b[i]);
+        qv[jj] = mn;
+      }
+      stripe_min_n<B>(qv);
+      float qm[B];
+  #pragma unroll
+      for (int jj = 0; jj < B; ++jj) qm[jj] = cbl * B + jj < L ? qv[jj] : -kPadBig;
+      // pass 3: r(s) = min_t [th(s,t) - q(t)]
+      float r[B];
+  #pragma unroll
       for (int i = 0; i < B; ++i) {
-        float mn = xc[i][0] + av[0];
-#pragma unroll
-        for (int jj = 1; jj < B; ++jj) mn = vmin(mn, xc[i][jj] + av[jj]);
-        pm[i] = mn;
+        float mn = xc[i][0] - qm[0];
+  #pragma unroll
+        for (int jj = 1; jj < B; ++jj) mn = vmin(mn, xc[i][jj] - qm[jj]);
+        r[i] = mn;
       }
-      oct_min_n<B>(pm);
-#pragma unroll
-      for (int i = 0; i < B; ++i) b[i] = 0.5f * (au[i] - pm[i]);
-    }
-    // pass 2: q(t) = min_s [th(s,t) + b(s)]
-    float qv[B];
-#pragma unroll
-    for (int jj = 0; jj < B; ++jj) {
-      float mn = xc[0][jj] + b[0];
-#pragma unroll
-      for (int i = 1; i < B; ++i) mn = vmin(mn, xc[i][jj] + b[i]);
-      qv[jj] = mn;
-    }
-    stripe_min_n<B>(qv);
-    float qm[B];
-#pragma unroll
-    for (int jj = 0; jj < B; ++jj) qm[jj] = cbl * B + jj < L ? qv[jj] : -kPadBig;
-    // pass 3: r(s) = min_t [th(s,t) - q(t)]
-    float r[B];
-#pragma unroll
-    for (int i = 0; i < B; ++i) {
-      float mn = xc[i][0] - qm[0];
-#pragma unroll
-      for (int jj = 1; jj < B; ++jj) mn = vmin(mn, xc[i][jj] - qm[jj]);
-      r[i] = mn;
-    }
-    oct_min_n<B>(r);
-    // ---- results back to label order ----
-    {
-      // (every lane of an octet holds the same r, every lane of a stripe
-      // the same q: one lane of each writes its B values)
-      if (cb == 0) {
-#pragma unroll
-        for (int i = 0; i < B; ++i) scr.rr[rb * B + i] = r[i];
+      oct_min_n<B>(r);
+      // ---- results back to label order ----
+      {
+        // (every lane of an octet holds the same r, every lane of a stripe
+        // the same q: one lane of each writes its B values)
+        if (cb == 0) {
+  #pragma unroll
+          for (int i = 0; i < B; ++i) scr.rr[rb * B + i] = r[i];
+        }
+        if (rb == 0) {
+  #pragma unroll
+          for (int jj = 0; jj < B; ++jj) scr.qq[cb * B + jj] = qv[jj];
+        }
       }
-      if (rb == 0) {
-#pragma unroll
-        for (int jj = 0; jj < B; ++jj) scr.qq[cb * B + jj] = qv[jj];
-      }
+      wave_sync();
+      phu = scr.rr[li] - delta;   // new message into u
+      phv = scr.qq[li] + delta;   // new message into v
     }
-    wave_sync();
-    const float phu = scr.rr[li] - delta;   // new message into u
-    const float phv = scr.qq[li] + delta;   // new message into v
     float nhu, nlu, nhv, nlv;
     comp_update(hu, lu, fu, phu, nhu, nlu);
     comp_update(hv, lv, fv, phv, nhv, nlv);

@@ -162,6 +162,27 @@ def potts_er(n: int, L: int, density: float, seed: int = 0, dtype=np.float32) ->
                  f"potts_er_n{n}_L{L}_p{density}_s{seed}")
 
 
+def potts_pure(n: int, L: int, density: float, seed: int = 0, w_range=(0.1, 1.0)):
+    """Potts model w_uv [s != t] on G(n, density) (complete for density >= 1),
+    w_uv ~ U[w_range], unaries U[0,1): (weights model, dense model) with the
+    same edges and unaries; the dense model's tables are the expansion
+    of the weights, w_uv off the diagonal and exactly +0 on it (FP32)."""
+    rng = np.random.default_rng(seed)
+    unaries = rng.random((n, L)).astype(np.float32)
+    if density >= 1.0:
+        edges = complete_edges(n)
+    else:
+        iu = np.triu_indices(n, 1)
+        keep = rng.random(iu[0].shape[0]) < density
+        edges = np.stack([iu[0][keep], iu[1][keep]], axis=1).astype(np.int32)
+    w = rng.uniform(w_range[0], w_range[1], size=edges.shape[0]).astype(np.float32)
+    name = f"potts_pure_n{n}_L{L}_p{density}_s{seed}"
+    weights = Model(n, L, edges, unaries, w, name + "_weights")
+    eye = np.eye(L, dtype=bool)[None, :, :]
+    dense = Model(n, L, edges, unaries, np.where(eye, np.float32(0.0), w[:, None, None]).astype(np.float32), name)
+    return weights, dense
+
+
 def batched_mix(count: int = 256, seed: int = 0, n_range=(20, 300), L_range=(8, 64),
                 dtype=np.float32, models: bool = True):
     """Sizes (and, if ``models``, the models) of the batched pose-shaped mix.

@@ -1,0 +1,154 @@
+"""GPU tests of the structured Potts passes of the wave engine (Sec. 4: with
+pairwise terms w [s != t] the message-passing minimization takes O(L)).
+
+A batch built from one weight per edge (``mplpxx_batch_create_potts``) must
+end bitwise equal to the dense batch on the expanded tables w [s != t], in
+LDS mode and as teams through the mailboxes, on ties, negative and zero
+weights, L = 1 and ragged L; its dual bounds must match the FP64 oracle on
+the dense model to 1e-5.  The workgroup engine and L > 64 are refused."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2004_08227_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+M = pytest.importorskip("paper_2004_08227_amd")
+
+
+def _announce(*a):
+    print("CASE", *a, flush=True)
+
+
+def _pairs(seed=0):
+    """(weights model, dense model) pairs over the label counts the wave
+    engine's lane grid has to cover: 1, 2, ragged, 16, 33, 64."""
+    out = []
+    for k, (n, L, dens) in enumerate([(2, 1, 1.0), (5, 2, 1.0), (9, 7, 0.6), (12, 16, 1.0), (30, 33, 0.3),
+                                       (16, 64, 1.0), (40, 13, 0.2), (3, 64, 1.0)]):
+        out.append(W.potts_pure(n, L, dens, seed=seed + k))
+    return out
+
+
+def _run(models, potts, iters, opts):
+    with M.Batch(models, potts=potts) as b:
+        for k, v in opts.items():
+            b.set_option(k, v)
+        b.iterate(iters)
+        info = dict(engine=b.info("engine"), lds_tasks=b.info("lds_tasks"), max_team=b.info("max_team"))
+        states = [b.get_state(i, comp=True) for i in range(len(models))]
+        duals = b.dual_bounds()
+    return states, duals, info
+
+
+MODES = {"lds": dict(engine=2, one_per_model=1),
+         "team": dict(engine=2, lds=0, wave_lat_mb_us=1000.0),   # latency-bound plan: the largest teams
+         "auto": dict()}
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+def test_potts_batch_is_bitwise_the_dense_batch(mode):
+    _announce("potts vs dense", mode)
+    pairs = _pairs()
+    weights = [p[0] for p in pairs]
+    dense = [p[1] for p in pairs]
+    iters = 6
+    sp, dp, ip = _run(weights, True, iters, MODES[mode])
+    sd, dd, idn = _run(dense, False, iters, MODES[mode])
+    assert ip["engine"] == 2 and idn["engine"] == 2
+    if mode == "lds":
+        assert ip["lds_tasks"] == len(pairs)
+    if mode == "team":
+        assert ip["max_team"] > 1
+    for i in range(len(pairs)):
+        for a, b in zip(sp[i], sd[i]):
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), (i, dense[i].name)
+    assert np.array_equal(dp, dd)
+    for i, mo in enumerate(dense):
+        st, ref = oracle.run_model(mo, iters)
+        assert abs(dp[i] - ref[-1]) <= 1e-5 * max(1.0, abs(ref[-1])), (i, dp[i], ref[-1])
+
+
+def test_potts_ties_negative_and_zero_weights():
+    """Integer unaries (many labels tie for the minimum, so the second
+    minimum equals the first), negative weights, +0 and -0 weights."""
+    _announce("potts ties / signs")
+    rng = np.random.default_rng(5)
+    pairs = []
+    for k, (n, L) in enumerate([(10, 8), (14, 64), (6, 33)]):
+        w_model, _ = W.potts_pure(n, L, 1.0, seed=50 + k, w_range=(-0.5, 1.0))
+        un = rng.integers(0, 3, size=(n, L)).astype(np.float32)
+        w = w_model.pairwise.copy()
+        w[::5] = 0.0
+        w[1::7] = -0.0
+        w[2::9] = np.round(w[2::9])         # integer weights: ties through the passes too
+        eye = np.eye(L, dtype=bool)[None]
+        pw = np.where(eye, np.float32(0.0), w[:, None, None]).astype(np.float32)
+        pairs.append((W.Model(n, L, w_model.edges, un, w, "ties_w"), W.Model(n, L, w_model.edges, un, pw, "ties")))
+    iters = 8
+    for mode in ("lds", "team"):
+        sp, dp, _ = _run([p[0] for p in pairs], True, iters, MODES[mode])
+        sd, dd, _ = _run([p[1] for p in pairs], False, iters, MODES[mode])
+        for i in range(len(pairs)):
+            for a, b in zip(sp[i], sd[i]):
+                assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), (mode, i)
+        assert np.array_equal(dp, dd)
+    for i, (_, mo) in enumerate(pairs):
+        st, ref = oracle.run_model(mo, iters)
+        assert abs(dp[i] - ref[-1]) <= 1e-5 * max(1.0, abs(ref[-1])), (i, dp[i], ref[-1])
+
+
+def test_potts_full_size_complete_graph():
+    """A complete Potts model at the pose size (200 nodes, 64 labels, 19900
+    edges) with a mix of smaller ones: bitwise the dense batch, and the
+    dual after 3 iterations within 1e-5 of the oracle on the dense model."""
+    _announce("potts full size")
+    pairs = [W.potts_pure(200, 64, 1.0, seed=11), W.potts_pure(120, 40, 0.5, seed=12),
+             W.potts_pure(60, 21, 1.0, seed=13)]
+    iters = 3
+    sp, dp, _ = _run([p[0] for p in pairs], True, iters, {})
+    sd, dd, _ = _run([p[1] for p in pairs], False, iters, {})
+    for i in range(len(pairs)):
+        for a, b in zip(sp[i], sd[i]):
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), i
+    assert np.array_equal(dp, dd)
+    st, ref = oracle.run_model(pairs[0][1], iters)
+    assert abs(dp[0] - ref[-1]) <= 1e-5 * max(1.0, abs(ref[-1])), (dp[0], ref[-1])
+
+
+def test_potts_engine_and_size_errors():
+    _announce("potts errors")
+    w, _ = W.potts_pure(6, 8, 1.0, seed=1)
+    with M.Batch([w], potts=True) as b:
+        b.set_option("engine", 1)
+        with pytest.raises(M.MplpError) as ei:
+            b.iterate(1)
+        assert ei.value.code == M.EINVAL
+        b.set_option("engine", 0)
+        b.iterate(1)
+        assert b.info("engine") == 2
+        assert b.info("table_bytes") == 4 * w.m
+    big, _ = W.potts_pure(4, 65, 1.0, seed=2)
+    with pytest.raises(M.MplpError) as ei:
+        M.Batch([big], potts=True)
+    assert ei.value.code == M.EINVAL
+    with pytest.raises(ValueError):
+        M.Batch([W.pose(4, 8, seed=1)], potts=True)
+
+
+def test_potts_zero_messages_are_positive_zero():
+    """All-zero unaries: every pass yields exactly 0 and every message is
+    +0, as on the dense table (whose diagonal term is +0): the structured
+    pass must not turn fl(0 - q) into -q, which is -0 for q = +0."""
+    _announce("potts signed zeros")
+    n, L = 5, 6
+    w_model, d_model = W.potts_pure(n, L, 1.0, seed=3)
+    z = np.zeros((n, L), np.float32)
+    pair = (W.Model(n, L, w_model.edges, z, w_model.pairwise, "zero_w"),
+            W.Model(n, L, d_model.edges, z, d_model.pairwise, "zero"))
+    for mode in ("lds", "team"):
+        sp, dp, _ = _run([pair[0]], True, 3, MODES[mode])
+        sd, dd, _ = _run([pair[1]], False, 3, MODES[mode])
+        assert not np.signbit(sd[0][1]).any() and not np.any(sd[0][1])
+        for a, b in zip(sp[0], sd[0]):
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), mode
