@@ -33,8 +33,8 @@ METRIC = "edge-block updates/s + HBM GB/s fraction; time-to-dual-bound vs plain,
 # iteration of the pose n=200/L=64 launch, and the factors that map each
 # counter to bytes, from the same counters on a 1 GiB copy.  Valid only for
 # the kernel sources they were taken on (hash below); otherwise null.
-TRAFFIC = {"src_sha": "00903df3bd1e0707", "fetch_kib_per_iter": 3769170.0625 / 20, "fetch_scale": 2.0,
-           "write_kib_per_iter": 806081.125 / 20, "write_scale": 1.0}
+TRAFFIC = {"src_sha": "0eac0afad3edddce", "fetch_kib_per_iter": 3768732.625 / 20, "fetch_scale": 2.0,
+           "write_kib_per_iter": 806079.25 / 20, "write_scale": 1.0}
 TRAFFIC_SRCS = ("paper_2004_08227_amd/csrc/common.h", "paper_2004_08227_amd/csrc/device_common.h",
                 "paper_2004_08227_amd/csrc/step_common.h", "paper_2004_08227_amd/csrc/handshake.hip")
 
@@ -260,8 +260,10 @@ def bench_gap(M, W, iters=200):
 def bench_potts(M, W, iters=50, mix_count=64):
     """Structured Potts passes (one weight per edge, O(L) per pass) against
     the dense wave engine on the expanded tables w [s != t]: one complete
-    pose-size model (n = 200, L = 64) as a batch of one, and the first
-    `mix_count` sizes of the batched mix (complete graphs).  Same
+    pose-size model (n = 200, L = 64) as a batch of one, the first
+    `mix_count` sizes of the batched mix (complete graphs), and the
+    sparsification shape (n = 1000, L = 16, G(n, p)) as a batch of one;
+    one-model cases also time the dense model on the single-model engine.  Same
     iterations from phi = 0; device times from HIP events; the duals of the
     two runs must be bitwise equal."""
     def run(models, potts):
@@ -276,10 +278,11 @@ def bench_potts(M, W, iters=50, mix_count=64):
 
     out = {"iterations": iters}
     sizes = W.batched_mix(mix_count, seed=0, models=False)
-    cases = [("pose_size_complete_n200_l64", [(200, 64)]),
-             (f"mix_{mix_count}_complete", sizes)]
+    cases = [("pose_size_complete_n200_l64", [(200, 64, 1.0)]),
+             (f"mix_{mix_count}_complete", [(n, L, 1.0) for n, L in sizes])]
+    cases += [(f"c2_shape_n1000_l16_p{p}", [(1000, 16, p)]) for p in (0.05, 0.25, 1.0)]
     for name, sz in cases:
-        pairs = [W.potts_pure(n, L, 1.0, seed=7 + i) for i, (n, L) in enumerate(sz)]
+        pairs = [W.potts_pure(n, L, p, seed=7 + i) for i, (n, L, p) in enumerate(sz)]
         m_tot = sum(p[0].m for p in pairs)
         bp = sum(p[0].m * (4 + 16 * p[0].L) for p in pairs)
         bd = sum(p[0].m * algorithmic_bytes_per_update(p[0].L) for p in pairs)
@@ -287,6 +290,15 @@ def bench_potts(M, W, iters=50, mix_count=64):
         del pairs
         ms_p, d_p, tb_p = run(weights, True)
         ms_d, d_d, tb_d = run(dense, False)
+        ms_s = None
+        if len(dense) == 1:
+            # the same dense model on the single-model engine
+            with M.Solver.from_model(dense[0]) as s1:
+                U0, phi0 = s1.get_state()
+                s1.iterate(2)
+                s1.set_state(U0, phi0)
+                s1.iterate(iters)
+                ms_s = s1.last_iterate_ms()
         del weights, dense
         out[name] = {"models": len(sz), "edges": m_tot, "potts_ms_per_iter": ms_p / iters,
                      "dense_ms_per_iter": ms_d / iters, "speedup": ms_d / ms_p,
@@ -297,6 +309,9 @@ def bench_potts(M, W, iters=50, mix_count=64):
                      "dense_hbm_frac": bd * iters / (ms_d / 1e3) / 1e9 / HBM_PEAK_GBS,
                      "potts_table_bytes": tb_p, "dense_table_bytes": tb_d,
                      "duals_bitwise_equal": bool(np.array_equal(d_p, d_d))}
+        if ms_s is not None:
+            out[name]["dense_single_model_engine_ms_per_iter"] = ms_s / iters
+            out[name]["speedup_vs_single_model_engine"] = ms_s / ms_p
     return out
 
 

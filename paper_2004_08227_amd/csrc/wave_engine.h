@@ -173,8 +173,10 @@ template <int CTRL> __device__ __forceinline__ void min2_dpp(float& m1, float& m
 // over the lanes (DPP within rows of 16, then the row swaps); a label
 // holding m1 gets m2 (equal to m1 when the minimum is repeated), any other
 // label m1.  Which zero a minimum of +0 and -0 returns does not matter
-// here: the result only enters fl(w + .) with w != -0.
-__device__ __forceinline__ float min_other(float x, bool real) {
+// here: the result only enters fl(w + .) with w != -0.  With L <= 16 every
+// label is in the first row of 16 lanes and the row swaps are skipped;
+// with L <= 32, the second one (L is the same on every lane).
+__device__ __forceinline__ float min_other(float x, bool real, int L) {
   const float kInf = __builtin_inff();
   float m1 = real ? x : kInf;
   float m2;
@@ -186,14 +188,14 @@ __device__ __forceinline__ float min_other(float x, bool real) {
   min2_dpp<0x4E>(m1, m2);              // lane ^ 2
   min2_dpp<0x141>(m1, m2);             // row_half_mirror: the other quad of the octet
   min2_dpp<0x140>(m1, m2);             // row_mirror: the other octet of the row
-  {
+  if (L > 16) {
     auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(m1), __float_as_uint(m1), false, false);
     auto b = __builtin_amdgcn_permlane16_swap(__float_as_uint(m2), __float_as_uint(m2), false, false);
     m1 = __uint_as_float(a[0]);
     m2 = __uint_as_float(b[0]);
     min2_merge(m1, m2, __uint_as_float(a[1]), __uint_as_float(b[1]));
   }
-  {
+  if (L > 32) {
     auto a = __builtin_amdgcn_permlane32_swap(__float_as_uint(m1), __float_as_uint(m1), false, false);
     auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(m2), __float_as_uint(m2), false, false);
     m1 = __uint_as_float(a[0]);
@@ -337,11 +339,11 @@ __device__ __forceinline__ bool wv_run(const WvView& v_in, int first_in, int str
       const float au = ((hu - c_u) + lu) - fu;
       const float av = ((hv - c_v) + lv) - fv;
       const float z = opaque_zero();   // th(s,s)
-      const float p = vmin(z + av, w + min_other(av, lout));
+      const float p = vmin(z + av, w + min_other(av, lout, L));
       const float b = 0.5f * (au - p);
-      const float q = vmin(z + b, w + min_other(b, lout));
+      const float q = vmin(z + b, w + min_other(b, lout, L));
       const float nq = -q;
-      const float r = vmin(z - q, w + min_other(nq, lout));
+      const float r = vmin(z - q, w + min_other(nq, lout, L));
       phu = r - delta;   // new message into u
       phv = q + delta;   // new message into v
     } else {

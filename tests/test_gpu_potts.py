@@ -22,10 +22,11 @@ def _announce(*a):
 
 def _pairs(seed=0):
     """(weights model, dense model) pairs over the label counts the wave
-    engine's lane grid has to cover: 1, 2, ragged, 16, 33, 64."""
+    engine's lanes have to cover: 1, 2, ragged, and both sides of the
+    row boundaries 16 and 32 of the second-minimum butterfly, up to 64."""
     out = []
-    for k, (n, L, dens) in enumerate([(2, 1, 1.0), (5, 2, 1.0), (9, 7, 0.6), (12, 16, 1.0), (30, 33, 0.3),
-                                       (16, 64, 1.0), (40, 13, 0.2), (3, 64, 1.0)]):
+    for k, (n, L, dens) in enumerate([(2, 1, 1.0), (5, 2, 1.0), (9, 7, 0.6), (12, 16, 1.0), (8, 17, 1.0),
+                                       (10, 32, 0.8), (30, 33, 0.3), (16, 64, 1.0), (40, 13, 0.2), (3, 64, 1.0)]):
         out.append(W.potts_pure(n, L, dens, seed=seed + k))
     return out
 
