@@ -86,6 +86,41 @@ def cpu_baseline(model, iters_sample):
                       f"edges of each matching)", "seconds": dt, "s_per_iter": dt / iters_sample}
 
 
+def oracle_one_thread(model, iters_sample=4):
+    """Seconds per iteration of the oracle on one host thread (a short
+    sample, for the single-thread time-to-bound)."""
+    import oracle
+    st = oracle.State(model)
+    t0 = time.perf_counter()
+    st.run(iters_sample, rule="H", nthreads=1)
+    return (time.perf_counter() - t0) / iters_sample
+
+
+def measured_stream_peak(gib=4, reps=5):
+    """Device streaming rates measured with plain torch kernels on a
+    `gib` GiB FP32 tensor (median of `reps`, torch events on torch's
+    stream): a full read (sum) and a copy (read + write)."""
+    import torch
+    n = gib * (1 << 28)
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    out = {}
+    for name, fn, nbytes in (("read_gbs", lambda: a.sum(), 4 * n), ("copy_gbs", lambda: b.copy_(a), 8 * n)):
+        fn()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1) / 1e3)
+        out[name] = nbytes / float(np.median(ts)) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_batched(M, W, iters=100, per_problem=True):
     """The 256-model pose mix in one persistent launch vs the same models
     solved one after another with one launch per model: with the
@@ -368,6 +403,7 @@ def main():
     ap.add_argument("--no-rules", action="store_true", help="skip the MPLP / uniform vs MPLP++ comparison")
     ap.add_argument("--no-gap", action="store_true", help="skip the anytime primal-dual gap section")
     ap.add_argument("--no-potts", action="store_true", help="skip the structured Potts vs dense section")
+    ap.add_argument("--no-stream", action="store_true", help="skip the measured streaming-rate reference")
     ap.add_argument("--only-potts", action="store_true", help="run only the structured Potts section")
     ap.add_argument("--only-batch", action="store_true", help="run only the batched-mix section")
     ap.add_argument("--no-per-problem", action="store_true",
@@ -458,6 +494,9 @@ def main():
     if not args.no_cpu:
         cb = cpu_baseline(model, args.cpu_iters)
         result["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        s1 = oracle_one_thread(model)
+        result["oracle_one_thread"] = {"s_per_iter": s1, "value": m / s1, "unit": "edge updates/s",
+                                       "sample": "4 iterations from phi=0, 1 host thread"}
         # the oracle's own trajectory: its stored 200-iteration trace on this
         # model (written by tests/golden/make_golden.py from the oracle alone)
         ref = None
@@ -470,13 +509,19 @@ def main():
         eps = [1e-1, 1e-2, 1e-3, 1e-4, 1e-5]
         gpu_tt = time_to_bound(trace, t_iter, d_star, eps)
         cpu_tt = time_to_bound(ref if ref is not None else trace, cb["s_per_iter"], d_star, eps)
+        cpu1_tt = time_to_bound(ref if ref is not None else trace, s1, d_star, eps)
         result["time_to_dual_bound"] = {
             "d_star": d_star, "eps_rel": eps, "gpu_s": gpu_tt, "plain_oracle_s": cpu_tt,
-            "oracle_cores": cb["cores"],
+            "plain_oracle_one_thread_s": cpu1_tt, "oracle_cores": cb["cores"],
             "note": "seconds until the dual bound reaches D* - eps|D*| (D* = best value of either run after "
                     f"{K} iterations): GPU = its trace's iterations x its measured time per iteration; plain "
                     "oracle = the iterations of its own stored trace x its measured seconds per iteration"}
     s.close()
+    if not args.no_stream:
+        sp = measured_stream_peak()
+        result["measured_stream"] = dict(sp, frac_of_measured_read=gbs / sp["read_gbs"],
+                                         note="torch sum (read) and copy_ (read + write) over 4 GiB; the roofline "
+                                              "peak stays the published 8 TB/s")
     if not args.no_batch:
         result["batched"] = bench_batched(M, W, per_problem=not args.no_per_problem)
     if not args.no_c2:
