@@ -86,6 +86,20 @@ def cpu_baseline(model, iters_sample):
                       f"edges of each matching)", "seconds": dt, "s_per_iter": dt / iters_sample}
 
 
+def host_cpu():
+    """Model name and logical CPU count of the host (from /proc/cpuinfo)."""
+    name = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": name, "logical_cpus": os.cpu_count()}
+
+
 def oracle_one_thread(model, iters_sample=4):
     """Seconds per iteration of the oracle on one host thread (a short
     sample, for the single-thread time-to-bound)."""
@@ -494,6 +508,7 @@ def main():
     if not args.no_cpu:
         cb = cpu_baseline(model, args.cpu_iters)
         result["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        result["host_cpu"] = host_cpu()
         s1 = oracle_one_thread(model)
         result["oracle_one_thread"] = {"s_per_iter": s1, "value": m / s1, "unit": "edge updates/s",
                                        "sample": "4 iterations from phi=0, 1 host thread"}
