@@ -153,3 +153,26 @@ def test_potts_zero_messages_are_positive_zero():
         assert not np.signbit(sd[0][1]).any() and not np.any(sd[0][1])
         for a, b in zip(sp[0], sd[0]):
             assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), mode
+
+
+@pytest.mark.parametrize("mode", ["lds", "team"])
+def test_potts_reset_and_timeout(mode):
+    """A spin limit of 1 (set from the host) makes the waits of the Potts
+    kernel give up: the launch reports MPLPXX_ETIMEOUT and every wave exits;
+    after a reset the batch reproduces its first run bit for bit."""
+    _announce("potts reset/timeout", mode)
+    weights = [p[0] for p in _pairs(seed=3)]
+    with M.Batch(weights, potts=True) as b:
+        for k, v in MODES[mode].items():
+            b.set_option(k, v)
+        b.iterate(3)
+        d3 = b.dual_bounds()
+        b.reset()
+        b.set_option("spin_limit", 1)
+        with pytest.raises(M.MplpError) as ei:
+            b.iterate(3)
+        assert ei.value.code == M.ETIMEOUT
+        b.set_option("spin_limit", 0)
+        b.reset()
+        b.iterate(3)
+        assert np.array_equal(b.dual_bounds(), d3)
