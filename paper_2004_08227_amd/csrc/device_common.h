@@ -758,9 +758,11 @@ __device__ __forceinline__ bool mb_run(const MbView& v_in, int first_in, int str
     }
     // push back: the new unary through the mailbox, the message to memory.
     // Every lane issues the same global stores (lanes without an output
-    // write their own scratch word): a store that only some waves skip
-    // would leave the compiler unsure how many memory operations are in
-    // flight, and it would then wait for all of them, prefetches too.
+    // write one scratch word per wave, so that a store instruction touches
+    // no more cache lines than its real outputs need): a store that only
+    // some waves skip would leave the compiler unsure how many memory
+    // operations are in flight, and it would then wait for all of them,
+    // prefetches too.
     float* phi_w = phi_of(slot, j);
     const bool outk = out_uk || out_v;
     float nhi, nlo;
@@ -773,17 +775,17 @@ __device__ __forceinline__ bool mb_run(const MbView& v_in, int first_in, int str
       }
     } else {
       const unsigned ver = (out_u ? want_u : want_v) + 1;
-      mb_store(outk ? v.mb + (size_t)node * L + out_i : v.sink + tid, mb_pack(nhi, nlo, ver));
+      mb_store(outk ? v.mb + (size_t)node * L + out_i : v.sink + (tid & ~63), mb_pack(nhi, nlo, ver));
     }
     if (PHI_LDS) {
       if (outk) phi_w[(out_u ? 0 : L) + out_i] = omsg;
     } else {
-      *(outk ? phi_w + (out_u ? 0 : L) + out_i : reinterpret_cast<float*>(v.sink + NT + (tid & 63))) = omsg;
+      *(outk ? phi_w + (out_u ? 0 : L) + out_i : reinterpret_cast<float*>(v.sink + NT + (tid >> 6))) = omsg;
     }
     {
       const bool st = v.stamps && last_iter && tid == 0;
       long long* dst = st ? v.stamps + (size_t)slot * kStampStride + 3
-                          : reinterpret_cast<long long*>(v.sink + NT + 64 + (tid & 63));
+                          : reinterpret_cast<long long*>(v.sink + NT + 64 + (tid >> 6));
       *dst = st ? (long long)wall_clock64() : 0;
     }
     // LDS-resident mode: the next slot starts a matching (or the next
