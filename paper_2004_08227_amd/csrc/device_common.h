@@ -510,8 +510,8 @@ __device__ __forceinline__ bool mb_run(const MbView& v_in, int first_in, int str
     int parity = 0, it = 0, j = 0;
     for (int q = 0; q < total; ++q) {
       const int slot = first + j * stride;
-      const unsigned want_u = (unsigned)(it * si.deg_u + si.pos_u);
-      const unsigned want_v = (unsigned)(it * si.deg_v + si.pos_v);
+      const unsigned want_u = (unsigned)it * (unsigned)si.deg_u + (unsigned)si.pos_u;
+      const unsigned want_v = (unsigned)it * (unsigned)si.deg_v + (unsigned)si.pos_v;
       int nxt = slot + stride;
       if (nxt >= v.m) nxt = first;
       nxt = uni(nxt);
@@ -617,8 +617,8 @@ __device__ __forceinline__ bool mb_run(const MbView& v_in, int first_in, int str
     float (&pu)[S::BR] = fc.pu;
     float (&pv)[S::BC] = fc.pv;
     const int slot = first + j * stride;
-    const unsigned want_u = (unsigned)(it * si.deg_u + si.pos_u);
-    const unsigned want_v = (unsigned)(it * si.deg_v + si.pos_v);
+    const unsigned want_u = (unsigned)it * (unsigned)si.deg_u + (unsigned)si.pos_u;
+    const unsigned want_v = (unsigned)it * (unsigned)si.deg_v + (unsigned)si.pos_v;
     int nxt = slot + stride;
     if (nxt >= v.m) nxt = first;
     nxt = uni(nxt);

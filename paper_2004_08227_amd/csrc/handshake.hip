@@ -212,9 +212,11 @@ __global__ void __launch_bounds__(NT) k_persistent(HsArgs<T> a, int iters) {
       const int waiter_v = (NT >= 128) ? 64 : 1;
       if (tid == 0 || tid == waiter_v) {
         const int node = (tid == 0) ? si.u : si.v;
-        const int want = it * a.deg[node] + ((tid == 0) ? si.pos_u : si.pos_v);
+        // (counts modulo 2^32; a waiter is fewer than deg updates behind, so
+        // the signed difference orders them)
+        const unsigned want = (unsigned)it * (unsigned)a.deg[node] + (unsigned)((tid == 0) ? si.pos_u : si.pos_v);
         long long spins = 0;
-        while (ld_dev(a.ver + node) < want) {
+        while ((int)((unsigned)ld_dev(a.ver + node) - want) < 0) {
           if (++spins > a.spin_limit || ((spins & 1023) == 0 && ld_dev(a.err) != 0)) {
             atomicCAS(a.err, 0, MPLPXX_ETIMEOUT);
             sm.abort_flag = 1;
@@ -234,8 +236,8 @@ __global__ void __launch_bounds__(NT) k_persistent(HsArgs<T> a, int iters) {
       const bool last_v = a.trace && si.pos_v == a.deg[si.v] - 1;
       handshake_passes<T, LT, NT, true>(x, sm, L, phi_slot, Uu, Uv, Lu, Lv, last_u || last_v);
       if (tid == 0) {
-        st_dev(a.ver + si.u, it * a.deg[si.u] + si.pos_u + 1);
-        st_dev(a.ver + si.v, it * a.deg[si.v] + si.pos_v + 1);
+        st_dev(a.ver + si.u, (int)((unsigned)it * (unsigned)a.deg[si.u] + (unsigned)si.pos_u + 1u));
+        st_dev(a.ver + si.v, (int)((unsigned)it * (unsigned)a.deg[si.v] + (unsigned)si.pos_v + 1u));
       }
       // next table of this workgroup (the same slot again in the next
       // iteration when it owns a single slot)

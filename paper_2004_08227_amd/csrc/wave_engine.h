@@ -255,8 +255,8 @@ __device__ __forceinline__ bool wv_run(const WvView& v_in, int first_in, int str
     // (lane positions recomputed per update: loop-invariant row offsets and
     // pads would hold registers the 64-label tile needs)
     const int ln = opaque(threadIdx.x) & 63, rbl = ln >> 3, cbl = ln & 7;
-    const unsigned want_u = (unsigned)(it * si.deg_u + si.pos_u);
-    const unsigned want_v = (unsigned)(it * si.deg_v + si.pos_v);
+    const unsigned want_u = (unsigned)it * (unsigned)si.deg_u + (unsigned)si.pos_u;
+    const unsigned want_v = (unsigned)it * (unsigned)si.deg_v + (unsigned)si.pos_v;
     const int nslot = uni(first + jn * stride);
     const SlotInfo si_next = ld_const(v.slots + nslot);
     auto prefetch = [&]() __attribute__((always_inline)) {
