@@ -159,3 +159,35 @@ def test_pose_table_generator_c_and_numpy_agree_bitwise():
         a = W.pose_tables(e, P, Q, 0.04, use_c=True)
         b = W.pose_tables(e, P, Q, 0.04, use_c=False)
         assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+@pytest.mark.parametrize("case", ["nan_w", "inf_w", "big_w", "L65", "self", "nan_u", "dense_inf"])
+def test_batch_inputs_rejected_without_device_work(case):
+    """Batch creation validates every model before any device work: a
+    non-finite or too large Potts weight, a Potts model with L > 64, a bad
+    edge, a non-finite unary (Potts), and a non-finite dense table."""
+    w, d = W.potts_pure(6, 5, 1.0, seed=1)
+    weights, un, edges, L = w.pairwise.copy(), w.unaries.copy(), w.edges.copy(), w.L
+    potts = case != "dense_inf"
+    pw = weights if potts else d.pairwise.copy()
+    if case == "nan_w":
+        pw[3] = np.nan
+    elif case == "inf_w":
+        pw[0] = -np.inf
+    elif case == "big_w":
+        pw[1] = 1e30
+    elif case == "L65":
+        L = 65
+        un = np.zeros((w.n, L), np.float32)
+    elif case == "self":
+        edges[2] = [4, 4]
+    elif case == "nan_u":
+        un[2, 1] = np.nan
+    elif case == "dense_inf":
+        pw[5, 1, 2] = np.inf
+    good = W.potts_pure(4, 3, 1.0, seed=2)[0 if potts else 1]
+    bad = W.Model(w.n, L, edges, un, pw, "bad")
+    with pytest.raises(M.MplpError) as ei:
+        M.Batch([good, bad], potts=potts)
+    assert ei.value.code == M.EINVAL
+    assert "model 1" in str(ei.value)
