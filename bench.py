@@ -36,7 +36,8 @@ METRIC = "edge-block updates/s + HBM GB/s fraction; time-to-dual-bound vs plain,
 TRAFFIC = {"src_sha": "d375b65b025d1274", "fetch_kib_per_iter": 3769236.5625 / 20, "fetch_scale": 2.0,
            "write_kib_per_iter": 457708.03125 / 20, "write_scale": 1.0}
 TRAFFIC_SRCS = ("paper_2004_08227_amd/csrc/common.h", "paper_2004_08227_amd/csrc/device_common.h",
-                "paper_2004_08227_amd/csrc/step_common.h", "paper_2004_08227_amd/csrc/handshake.hip")
+                "paper_2004_08227_amd/csrc/step_common.h", "paper_2004_08227_amd/csrc/potts_passes.h",
+                "paper_2004_08227_amd/csrc/potts_mb.h", "paper_2004_08227_amd/csrc/handshake.hip")
 
 
 def kernel_src_sha():
@@ -312,7 +313,8 @@ def bench_potts(M, W, iters=50, mix_count=64):
     pose-size model (n = 200, L = 64) as a batch of one, the first
     `mix_count` sizes of the batched mix (complete graphs), and the
     sparsification shape (n = 1000, L = 16, G(n, p)) as a batch of one;
-    one-model cases also time the dense model on the single-model engine.  Same
+    one-model cases also run on the single-model mailbox engine, dense and
+    Potts (mplpxx_create_potts).  Same
     iterations from phi = 0; device times from HIP events; the duals of the
     two runs must be bitwise equal."""
     def run(models, potts):
@@ -339,15 +341,18 @@ def bench_potts(M, W, iters=50, mix_count=64):
         del pairs
         ms_p, d_p, tb_p = run(weights, True)
         ms_d, d_d, tb_d = run(dense, False)
-        ms_s = None
+        ms_s = ms_sp = None
         if len(dense) == 1:
-            # the same dense model on the single-model engine
-            with M.Solver.from_model(dense[0]) as s1:
-                U0, phi0 = s1.get_state()
-                s1.iterate(2)
-                s1.set_state(U0, phi0)
-                s1.iterate(iters)
-                ms_s = s1.last_iterate_ms()
+            # the same model on the single-model mailbox engine, dense and Potts
+            def single(make):
+                with make() as s1:
+                    U0, phi0 = s1.get_state()
+                    s1.iterate(2)
+                    s1.set_state(U0, phi0)
+                    s1.iterate(iters)
+                    return s1.last_iterate_ms(), s1.dual_bound()
+            ms_s, d_s = single(lambda: M.Solver.from_model(dense[0]))
+            ms_sp, d_sp = single(lambda: M.Solver.from_potts(weights[0]))
         del weights, dense
         out[name] = {"models": len(sz), "edges": m_tot, "potts_ms_per_iter": ms_p / iters,
                      "dense_ms_per_iter": ms_d / iters, "speedup": ms_d / ms_p,
@@ -361,6 +366,9 @@ def bench_potts(M, W, iters=50, mix_count=64):
         if ms_s is not None:
             out[name]["dense_single_model_engine_ms_per_iter"] = ms_s / iters
             out[name]["speedup_vs_single_model_engine"] = ms_s / ms_p
+            out[name]["potts_single_model_engine_ms_per_iter"] = ms_sp / iters
+            out[name]["potts_single_vs_dense_single_speedup"] = ms_s / ms_sp
+            out[name]["single_model_duals_bitwise_equal"] = bool(d_s == d_sp)
     return out
 
 

@@ -112,6 +112,22 @@ int mplpxx_create(int32_t n, int32_t L, int64_t m, const int32_t* edges, const v
 int mplpxx_create_sched(int32_t n, int32_t L, int64_t m, const int32_t* edges, const void* unaries,
                         const void* pairwise, int32_t dtype, int32_t schedule, mplpxx_solver** out);
 
+/* A model with Potts pairwise terms theta_uv(s, t) = w_uv [s != t] (Sec. 4
+ * notes that message passing then takes O(L)): weights = HOST float [m],
+ * one weight per edge in the order of edges (any sign; -0 counts as +0);
+ * unaries as for mplpxx_create (FP32).  The handle runs on the persistent
+ * mailbox engine with one compute wave per workgroup in label order (three
+ * passes of a minimum / second-minimum reduction over the lanes instead of
+ * the L x L tile); its results are bitwise those of an FP32 handle created
+ * with the expanded tables.  dual_bound, decode, iterate_gap, get/set_state,
+ * schedule and step profile work as for dense handles.  Errors: those of
+ * mplpxx_create, and MPLPXX_EINVAL for L > 64 or a node degree >= 65536;
+ * later, MPLPXX_EINVAL from mplpxx_iterate_trace, mplpxx_adjoint_forward,
+ * MPLPXX_OPT_ENGINE = per-matching, MPLPXX_OPT_THREADS != 0 and
+ * MPLPXX_OPT_RULE other than (H). */
+int mplpxx_create_potts(int32_t n, int32_t L, int64_t m, const int32_t* edges, const float* unaries,
+                        const float* weights, mplpxx_solver** out);
+
 /* Same as mplpxx_create, but unaries and pairwise are DEVICE pointers (for
  * example torch tensor storage) in the same layout; edges stay on the host.
  * The library copies the costs into its own layout before returning, so the

@@ -96,6 +96,7 @@ def lib():
         "mplpxx_iterate_gap": (ctypes.c_int, [vp, i32, vp, vp, vp]),
         "mplpxx_batch_create": (ctypes.c_int, [i32, vp, vp, vp, vp, vp, vp, pp]),
         "mplpxx_batch_create_potts": (ctypes.c_int, [i32, vp, vp, vp, vp, vp, vp, pp]),
+        "mplpxx_create_potts": (ctypes.c_int, [i32, i32, i64, vp, vp, vp, pp]),
         "mplpxx_batch_iterate": (ctypes.c_int, [vp, i32]),
         "mplpxx_batch_dual_bounds": (ctypes.c_int, [vp, vp]),
         "mplpxx_batch_get_state": (ctypes.c_int, [vp, i32, vp, vp, vp]),
@@ -168,6 +169,21 @@ class Solver:
     @classmethod
     def from_model(cls, model, schedule=0):
         return cls(model.n, model.L, model.edges, model.unaries, model.pairwise, schedule=schedule)
+
+    @classmethod
+    def from_potts(cls, model):
+        """A Potts model (``mplpxx_create_potts``): ``model.pairwise`` holds
+        one weight per edge [m] (pairwise term w_e [s != t]); FP32."""
+        edges = np.ascontiguousarray(model.edges, dtype=np.int32).reshape(-1, 2)
+        m = edges.shape[0]
+        un = np.ascontiguousarray(model.unaries, dtype=np.float32)
+        w = np.ascontiguousarray(model.pairwise, dtype=np.float32)
+        if un.size != model.n * model.L or w.size != m:
+            raise ValueError("unaries must hold n*L and weights m values")
+        h = ctypes.c_void_p()
+        _check(lib().mplpxx_create_potts(int(model.n), int(model.L), int(m), _ptr(edges) if m else None, _ptr(un),
+                                         _ptr(w) if m else None, ctypes.byref(h)))
+        return cls(model.n, model.L, None, None, None, _handle=h)
 
     @classmethod
     def from_torch(cls, n, L, edges, unaries, pairwise, stream=None):

@@ -34,7 +34,7 @@ struct SlotInfo {
 };
 
 template <typename T> struct HsArgs {
-  const T* tables;        // [m][L][L] slot order, read-only
+  const T* tables;        // [m][L][L] slot order, read-only (Potts models: [m] weights)
   T* phi;                 // [m][2][L] slot order
   T* U;                   // [n][L]
   T* Ulo;                 // [n][L] FP32 only: bf16 correction of U (U = U + Ulo), else null
@@ -121,6 +121,10 @@ template <typename T> int max_blocks_per_cu(int engine, int LT, int NT);
 // FP32 persistent engine with tagged mailboxes
 hipError_t launch_persistent_mb(const HsArgs<float>& a, unsigned long long* mb, int LT, int NT, int grid, int iters,
                                 int phi_in_lds, size_t dyn_lds, hipStream_t st);
+// the same for Potts models (one weight per slot, L <= 64; potts_mb.h)
+int max_blocks_per_cu_mb_potts();
+hipError_t launch_persistent_mb_potts(const HsArgs<float>& a, unsigned long long* mb, int grid, int iters,
+                                      int phi_in_lds, size_t dyn_lds, hipStream_t st);
 hipError_t launch_mb_init(const float* U, const float* Ulo, unsigned long long* mb, size_t count, hipStream_t st);
 hipError_t launch_mb_fini(float* U, float* Ulo, const unsigned long long* mb, int n, int L, double* trace_row,
                           hipStream_t st);
@@ -128,7 +132,7 @@ hipError_t launch_mb_fini(float* U, float* Ulo, const unsigned long long* mb, in
 // dual bound, traces, decode (dual.hip)
 template <typename T>
 hipError_t launch_dual(const T* unaries, const T* tables, const T* phi, const int* node_ptr, const int* inc, int n,
-                       int L, int m, double* node_min, double* edge_min, double* out, hipStream_t st);
+                       int L, int m, double* node_min, double* edge_min, double* out, hipStream_t st, int potts = 0);
 template <typename T>
 hipError_t launch_trace_nodes(const T* U, const T* Ulo, int n, int L, double* row, hipStream_t st);
 template <typename T>
@@ -139,7 +143,8 @@ hipError_t launch_trace_sum(double* trace_nodes, const float* trace_e, int m, in
                             hipStream_t st);
 template <typename T>
 hipError_t launch_decode(const T* unaries, const T* tables, const T* phi, const SlotInfo* slots, const int* node_ptr,
-                         const int* inc, int n, int L, int m, int* labels, double* energy, hipStream_t st);
+                         const int* inc, int n, int L, int m, int* labels, double* energy, hipStream_t st,
+                         int potts = 0);
 template <typename T>
 hipError_t launch_check_finite(const T* p, size_t count, int* flag, hipStream_t st);
 template <typename T>

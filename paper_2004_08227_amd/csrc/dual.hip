@@ -51,19 +51,25 @@ __global__ void __launch_bounds__(128) k_node_terms(const T* __restrict__ unarie
   if (s == 0) node_min[u] = mn;
 }
 
+// th(s, t) of the edge in `slot`: its table, or, for Potts models (one
+// weight per slot), w [s != t]
+template <typename T>
+__device__ __forceinline__ T table_at(const T* tables, int slot, int L, int s, int t, int potts) {
+  return potts ? (s == t ? T(0) : tables[slot]) : tables[(size_t)slot * L * L + (size_t)s * L + t];
+}
+
 // edge terms: one workgroup per slot
 template <typename T>
 __global__ void __launch_bounds__(256) k_edge_terms(const T* __restrict__ tables, const T* __restrict__ phi, int L,
-                                                    double* __restrict__ edge_min) {
+                                                    int potts, double* __restrict__ edge_min) {
   __shared__ double sh[256];
   const int slot = blockIdx.x;
-  const T* tab = tables + (size_t)slot * L * L;
   const T* p0 = phi + (size_t)slot * 2 * L;
   const T* p1 = p0 + L;
   double mn = __builtin_inf();
   for (int i = threadIdx.x; i < L * L; i += 256) {
     const int s = i / L, t = i - s * L;
-    mn = dmin(mn, (double)tab[i] - (double)p0[s] - (double)p1[t]);
+    mn = dmin(mn, (double)table_at(tables, slot, L, s, t, potts) - (double)p0[s] - (double)p1[t]);
   }
   mn = block_reduce<256, true>(mn, sh);
   if (threadIdx.x == 0) edge_min[slot] = mn;
@@ -82,9 +88,9 @@ __global__ void __launch_bounds__(1024) k_sum2(const double* __restrict__ a, int
 
 template <typename T>
 hipError_t launch_dual(const T* unaries, const T* tables, const T* phi, const int* node_ptr, const int* inc, int n,
-                       int L, int m, double* node_min, double* edge_min, double* out, hipStream_t st) {
+                       int L, int m, double* node_min, double* edge_min, double* out, hipStream_t st, int potts) {
   hipLaunchKernelGGL(k_node_terms<T>, dim3(n), dim3(128), 0, st, unaries, phi, node_ptr, inc, L, node_min);
-  if (m > 0) hipLaunchKernelGGL(k_edge_terms<T>, dim3(m), dim3(256), 0, st, tables, phi, L, edge_min);
+  if (m > 0) hipLaunchKernelGGL(k_edge_terms<T>, dim3(m), dim3(256), 0, st, tables, phi, L, potts, edge_min);
   hipLaunchKernelGGL(k_sum2, dim3(1), dim3(1024), 0, st, node_min, n, edge_min, m, out);
   return hipGetLastError();
 }
@@ -190,7 +196,7 @@ template <typename T>
 __global__ void __launch_bounds__(1024) k_decode(const T* __restrict__ unaries, const T* __restrict__ tables,
                                                  const T* __restrict__ phi, const SlotInfo* __restrict__ slots,
                                                  const int* __restrict__ node_ptr, const int* __restrict__ inc, int n,
-                                                 int L, int m, int* __restrict__ labels,
+                                                 int L, int m, int potts, int* __restrict__ labels,
                                                  double* __restrict__ energy) {
   constexpr int NW = 16;
   __shared__ double part[NW][MPLPXX_MAX_LABELS];
@@ -210,7 +216,7 @@ __global__ void __launch_bounds__(1024) k_decode(const T* __restrict__ unaries, 
         if (side == 1) {
           // u is the upper node: add theta^phi_{vu}(x*_v, x) for v < u
           const int yv = labels[slots[slot].u];
-          acc += (double)tables[(size_t)slot * L * L + (size_t)yv * L + x] - (double)p[yv] - (double)p[L + x];
+          acc += (double)table_at(tables, slot, L, yv, x, potts) - (double)p[yv] - (double)p[L + x];
         }
       }
       part[w][x] = acc;
@@ -243,7 +249,7 @@ __global__ void __launch_bounds__(1024) k_decode(const T* __restrict__ unaries, 
   for (int u = tid; u < n; u += 1024) acc += (double)unaries[(size_t)u * L + labels[u]];
   for (int slot = tid; slot < m; slot += 1024) {
     const SlotInfo si = slots[slot];
-    acc += (double)tables[(size_t)slot * L * L + (size_t)labels[si.u] * L + labels[si.v]];
+    acc += (double)table_at(tables, slot, L, labels[si.u], labels[si.v], potts);
   }
   acc = block_reduce<1024, false>(acc, sh);
   if (tid == 0) *energy = acc;
@@ -252,9 +258,10 @@ __global__ void __launch_bounds__(1024) k_decode(const T* __restrict__ unaries, 
 
 template <typename T>
 hipError_t launch_decode(const T* unaries, const T* tables, const T* phi, const SlotInfo* slots, const int* node_ptr,
-                         const int* inc, int n, int L, int m, int* labels, double* energy, hipStream_t st) {
+                         const int* inc, int n, int L, int m, int* labels, double* energy, hipStream_t st,
+                         int potts) {
   hipLaunchKernelGGL(k_decode<T>, dim3(1), dim3(1024), 0, st, unaries, tables, phi, slots, node_ptr, inc, n, L, m,
-                     labels, energy);
+                     potts, labels, energy);
   return hipGetLastError();
 }
 
@@ -337,13 +344,13 @@ hipError_t launch_fill_int(int* p, int value, size_t count, hipStream_t st) {
 
 #define MPLPXX_INST(T)                                                                                              \
   template hipError_t launch_dual<T>(const T*, const T*, const T*, const int*, const int*, int, int, int, double*,  \
-                                     double*, double*, hipStream_t);                                              \
+                                     double*, double*, hipStream_t, int);                                         \
   template hipError_t launch_trace_nodes<T>(const T*, const T*, int, int, double*, hipStream_t);                             \
   template hipError_t launch_trace_edges<T>(const T*, const T*, int, int, float*, hipStream_t);               \
   template hipError_t launch_trace_sum<T>(double*, const float*, int, int, const T*, const int*, int, int, int,   \
                                           double*, hipStream_t);     \
   template hipError_t launch_decode<T>(const T*, const T*, const T*, const SlotInfo*, const int*, const int*, int, \
-                                       int, int, int*, double*, hipStream_t);                                      \
+                                       int, int, int*, double*, hipStream_t, int);                                 \
   template hipError_t launch_check_finite<T>(const T*, size_t, int*, hipStream_t);                                 \
   template hipError_t launch_pack_tables<T>(const T*, T*, const int*, const int*, int, int, hipStream_t);
 MPLPXX_INST(float)

@@ -35,6 +35,7 @@
 #include <type_traits>
 
 #include "step_common.h"
+#include "potts_mb.h"
 
 namespace mplpxx {
 // The three passes on a register tile; a_u / a_v must be in smem.  Writes
@@ -278,6 +279,33 @@ __global__ void __launch_bounds__(NT + 128) k_persistent_mb(HsArgs<float> a, uns
   }
 }
 
+// Potts models (one weight per slot, L <= 64): one compute wave in label
+// order plus the two sync waves (potts_mb.h)
+template <bool PHI_LDS>
+__global__ void __launch_bounds__(kPottsNT + 128) k_persistent_mb_potts(HsArgs<float> a, unsigned long long* __restrict__ mb,
+                                                                       int iters) {
+  __shared__ SmemMB<64, kPottsNT> sm;
+  extern __shared__ float phi_lds[];
+  const int tid = threadIdx.x;
+  const int L = a.L;
+  const int G = gridDim.x;
+  if (blockIdx.x >= a.m) return;
+  if (tid == 0) sm.abort_flag = 0;
+  if (PHI_LDS) {
+    for (int slot = blockIdx.x, j = 0; slot < a.m; slot += G, ++j)
+      for (int k = tid; k < 2 * L; k += kPottsNT + 128) phi_lds[j * 2 * L + k] = a.phi[(size_t)slot * 2 * L + k];
+  }
+  __syncthreads();
+  MbView v{a.tables, a.phi, mb, a.slots, a.deg, nullptr, nullptr, a.stamps, L, a.m, a.n, nullptr, nullptr,
+           a.sink + (size_t)blockIdx.x * (kPottsNT + 128)};
+  if (!mb_run_potts<PHI_LDS>(v, blockIdx.x, G, iters, sm, phi_lds, a.spin_limit, a.err)) return;
+  __syncthreads();
+  if (PHI_LDS) {
+    for (int slot = blockIdx.x, j = 0; slot < a.m; slot += G, ++j)
+      for (int k = tid; k < 2 * L; k += kPottsNT + 128) a.phi[(size_t)slot * 2 * L + k] = phi_lds[j * 2 * L + k];
+  }
+}
+
 // mailbox <- (U, Ulo, version 0)
 __global__ void k_mb_init(const float* __restrict__ U, const float* __restrict__ Ulo,
                           unsigned long long* __restrict__ mb, size_t count) {
@@ -375,6 +403,22 @@ hipError_t launch_persistent_mb(const HsArgs<float>& a, unsigned long long* mb, 
   MPLPXX_CASE(128, 512)
 #undef MPLPXX_CASE
   return hipErrorInvalidValue;
+}
+
+int max_blocks_per_cu_mb_potts() {
+  int nb = 0;
+  const hipError_t e =
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_persistent_mb_potts<false>, kPottsNT + 128, 0);
+  return e == hipSuccess ? nb : 0;
+}
+
+hipError_t launch_persistent_mb_potts(const HsArgs<float>& a, unsigned long long* mb, int grid, int iters,
+                                      int phi_in_lds, size_t dyn_lds, hipStream_t st) {
+  void* args[] = {(void*)&a, (void*)&mb, (void*)&iters};
+  const void* f = phi_in_lds ? (const void*)k_persistent_mb_potts<true> : (const void*)k_persistent_mb_potts<false>;
+  const hipError_t e = hipLaunchCooperativeKernel(f, dim3(grid), dim3(kPottsNT + 128), args, dyn_lds, st);
+  if (e != hipSuccess) (void)hipGetLastError();  // (see launch_mb_one)
+  return e;
 }
 
 hipError_t launch_mb_init(const float* U, const float* Ulo, unsigned long long* mb, size_t count, hipStream_t st) {

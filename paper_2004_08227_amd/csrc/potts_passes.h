@@ -1,0 +1,97 @@
+// The passes of (H) on an edge with Potts pairwise terms, in label order
+// (lane l holds label l): shared by the wave engine and the mailbox
+// engine's Potts instance.
+#pragma once
+#include "device_common.h"
+
+namespace mplpxx {
+
+// ---------------------------------------------------------------------------
+// Potts pairwise terms th(s,t) = w [s != t] (Sec. 4: the message-passing
+// minimization then takes O(L)).  Every pass of (H) has the form
+//   y(s) = min_t fl(th(s,t) + x(t)) = min( fl(0 + x(s)), fl(w + min_{t != s} x(t)) ),
+// exactly, because fl(w + .) is monotone: the minimum over t != s of the
+// rounded sums is the rounded sum with the minimum.  So the passes need,
+// per label s, the minimum of x over the other labels: the smallest value
+// when s is not where it is attained, else the second smallest.  Pass 3,
+// min_t fl(th(s,t) - q(t)), is the same with x = -q (exact negation).  The
+// results are bitwise the dense passes on the table w [s != t]: no
+// candidate of either is -0 (fl(+0 + x) and fl(w + x), w != -0, never
+// are), so the minima agree whatever a minimum makes of signed zeros.
+// The diagonal term is added as a +0 the compiler cannot see: a visible
+// constant lets it rewrite fl(0 - q) under a minimum as -q, which is -0
+// for q = +0.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float opaque_zero() {
+  float z = 0.0f;
+  asm volatile("" : "+v"(z));
+  return z;
+}
+// scalar load of read-only data through the constant address space
+__device__ __forceinline__ float ld_const_f(const float* p) {
+  return *(const __attribute__((address_space(4))) float*)p;
+}
+// (m1, m2) <- the two smallest of the multiset {m1, m2} + {o1, o2}, each
+// pair being the two smallest of a group of lanes (a repeated value counts
+// twice)
+__device__ __forceinline__ void min2_merge(float& m1, float& m2, float o1, float o2) {
+  const float hi = __builtin_fmaxf(m1, o1);
+  m1 = vmin(m1, o1);
+  m2 = vmin(hi, vmin(m2, o2));
+}
+template <int CTRL> __device__ __forceinline__ void min2_dpp(float& m1, float& m2) {
+  min2_merge(m1, m2, dpp_f<CTRL>(m1), dpp_f<CTRL>(m2));
+}
+// per lane (label) s: min over the real labels t != s of x(t) (+inf if
+// none).  The two smallest values of the wave, m1 <= m2, by a butterfly
+// over the lanes (DPP within rows of 16, then the row swaps); a label
+// holding m1 gets m2 (equal to m1 when the minimum is repeated), any other
+// label m1.  Which zero a minimum of +0 and -0 returns does not matter
+// here: the result only enters fl(w + .) with w != -0.  With L <= 16 every
+// label is in the first row of 16 lanes and the row swaps are skipped;
+// with L <= 32, the second one (L is the same on every lane).
+__device__ __forceinline__ float min_other(float x, bool real, int L) {
+  const float kInf = __builtin_inff();
+  float m1 = real ? x : kInf;
+  float m2;
+  {
+    const float o = dpp_f<0xB1>(m1);   // lane ^ 1 (m2 is +inf on both sides)
+    m2 = __builtin_fmaxf(m1, o);
+    m1 = vmin(m1, o);
+  }
+  min2_dpp<0x4E>(m1, m2);              // lane ^ 2
+  min2_dpp<0x141>(m1, m2);             // row_half_mirror: the other quad of the octet
+  min2_dpp<0x140>(m1, m2);             // row_mirror: the other octet of the row
+  if (L > 16) {
+    auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(m1), __float_as_uint(m1), false, false);
+    auto b = __builtin_amdgcn_permlane16_swap(__float_as_uint(m2), __float_as_uint(m2), false, false);
+    m1 = __uint_as_float(a[0]);
+    m2 = __uint_as_float(b[0]);
+    min2_merge(m1, m2, __uint_as_float(a[1]), __uint_as_float(b[1]));
+  }
+  if (L > 32) {
+    auto a = __builtin_amdgcn_permlane32_swap(__float_as_uint(m1), __float_as_uint(m1), false, false);
+    auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(m2), __float_as_uint(m2), false, false);
+    m1 = __uint_as_float(a[0]);
+    m2 = __uint_as_float(b[0]);
+    min2_merge(m1, m2, __uint_as_float(a[1]), __uint_as_float(b[1]));
+  }
+  return (real && x == m1) ? m2 : m1;
+}
+
+// New messages of one (H) update of a Potts edge, per lane (label): au, av
+// are the centred a'_u, a'_v of this label, w the edge's weight, delta the
+// shift between the centred passes and the messages.
+__device__ __forceinline__ void potts_passes(float au, float av, float w, bool lout, int L, float delta, float& phu,
+                                             float& phv) {
+  const float z = opaque_zero();   // th(s,s)
+  const float p = vmin(z + av, w + min_other(av, lout, L));
+  const float b = 0.5f * (au - p);
+  const float q = vmin(z + b, w + min_other(b, lout, L));
+  const float nq = -q;
+  const float r = vmin(z - q, w + min_other(nq, lout, L));
+  phu = r - delta;   // new message into u
+  phv = q + delta;   // new message into v
+}
+
+}  // namespace mplpxx

@@ -102,6 +102,7 @@ struct mplpxx_solver {
   int rule = MPLPXX_RULE_H;  // BCA-update (Sec. 4)
   int sched = MPLPXX_SCHED_AUTO;  // schedule kind of Alg. 1
   int threads_opt = 0;
+  bool potts = false;        // Potts pairwise terms: d_tables holds one weight per slot
   int grid_opt = 0;
   long long spin_limit = 1ll << 22;
   int num_cus = 0;
@@ -112,6 +113,7 @@ struct mplpxx_solver {
   hipStream_t stream() const { return user_stream ? user_stream : own_stream; }
   int LT() const { return next_tile(L); }
   int NT() const {
+    if (potts) return 64;  // one compute wave in label order (potts_mb.h)
     int nt = threads_opt ? threads_opt : 256;
     if (!valid_threads(LT(), nt)) nt = 256;
     // the FP32 persistent engine adds two sync waves: at most 512 + 128 threads
@@ -135,7 +137,8 @@ struct mplpxx_solver {
   int grid() const {
     int g = grid_opt > 0 ? grid_opt : num_cus;
     if (grid_opt == 0 && mb_engine() && max_step > num_cus)
-      g = std::max(num_cus, std::min(max_step, max_blocks_per_cu_mb(LT(), NT()) * num_cus));
+      g = std::max(num_cus, std::min(max_step, (potts ? max_blocks_per_cu_mb_potts() : max_blocks_per_cu_mb(LT(), NT())) *
+                                                     num_cus));
     if (g > m) g = m;
     if (g < 1) g = 1;
     return g;
@@ -192,7 +195,7 @@ int prepare_solver_graph(mplpxx_solver* h, const int32_t* edges) {
 
 int create_impl(int32_t n, int32_t L, int64_t m, const int32_t* edges, const void* unaries, const void* pairwise,
                 int32_t dtype, bool device_costs, hipStream_t copy_stream, mplpxx_solver** out,
-                int32_t sched = MPLPXX_SCHED_AUTO) {
+                int32_t sched = MPLPXX_SCHED_AUTO, bool potts = false) {
   if (!out) return fail(MPLPXX_EINVAL, "out is NULL");
   *out = nullptr;
   if (dtype != MPLPXX_F32 && dtype != MPLPXX_F64) return fail(MPLPXX_EINVAL, "unknown dtype %d", dtype);
@@ -204,8 +207,11 @@ int create_impl(int32_t n, int32_t L, int64_t m, const int32_t* edges, const voi
   if (sched != MPLPXX_SCHED_AUTO && sched != MPLPXX_SCHED_GREEDY && sched != MPLPXX_SCHED_COLOR)
     return fail(MPLPXX_EINVAL, "unknown schedule kind %d", sched);
   if (m > 0 && (!edges || !pairwise)) return fail(MPLPXX_EINVAL, "edges/pairwise is NULL");
+  if (potts && (dtype != MPLPXX_F32 || device_costs)) return fail(MPLPXX_EINVAL, "Potts models take FP32 host costs");
+  if (potts && L > 64) return fail(MPLPXX_EINVAL, "Potts models take L <= 64 (got %d)", L);
   const size_t esz = dtype == MPLPXX_F32 ? 4 : 8;
-  const size_t nL = (size_t)n * L, mLL = (size_t)m * L * L;
+  // (Potts models: one weight per edge instead of an L x L table)
+  const size_t nL = (size_t)n * L, mLL = potts ? (size_t)m : (size_t)m * L * L;
   if (!device_costs) {
     if (!finite_host(unaries, nL, dtype)) return fail(MPLPXX_EINVAL, "non-finite (or, in FP32, above 1e18) unary cost");
     if (m > 0 && !finite_host(pairwise, mLL, dtype)) return fail(MPLPXX_EINVAL, "non-finite (or, in FP32, above 1e18) pairwise cost");
@@ -218,10 +224,15 @@ int create_impl(int32_t n, int32_t L, int64_t m, const int32_t* edges, const voi
   h->dtype = dtype;
   h->esz = esz;
   h->sched = sched;
+  h->potts = potts;
   int rc = prepare_solver_graph(h, edges);
   if (rc != MPLPXX_OK) {
     delete h;
     return rc;
+  }
+  if (potts && h->max_deg >= 65536) {
+    delete h;
+    return fail(MPLPXX_EINVAL, "Potts models need degrees below 65536 (the mailbox engine's versions)");
   }
   auto bail = [&](int code) {
     free_all(h);
@@ -293,14 +304,19 @@ int create_impl(int32_t n, int32_t L, int64_t m, const int32_t* edges, const voi
     TRY(hipMemcpyAsync(h->d_unaries, unaries, nL * esz, hipMemcpyHostToDevice, st));
     if (m) {
       // pack tables in slot order, transposing edges given as (v, u)
+      // (Potts: the weights in slot order; a weight of -0 is stored as +0,
+      // which stands for the same table)
       std::vector<char> packed(mLL * esz);
-      const size_t tb = (size_t)L * L * esz;
+      const size_t tb = (potts ? 1 : (size_t)L * L) * esz;
       const char* src = static_cast<const char*>(pairwise);
       for (int i = 0; i < h->m; ++i) {
         const int e = h->order[i];
         char* dst = packed.data() + (size_t)i * tb;
         const char* s = src + (size_t)e * tb;
-        if (!h->flip[e]) {
+        if (potts) {
+          const float wv = *reinterpret_cast<const float*>(s) + 0.0f;
+          std::memcpy(dst, &wv, sizeof(float));
+        } else if (!h->flip[e]) {
           std::memcpy(dst, s, tb);
         } else {
           for (int r = 0; r < L; ++r)
@@ -460,7 +476,8 @@ template <typename T> int iterate_t(mplpxx_solver* h, int k, double* trace_host)
       // the workgroups' LDS never limits how many fit)
       const int in_lds = phi_bytes <= kPhiLdsBudget && G <= h->num_cus ? 1 : 0;
       HIP_TRY(launch_mb_init(static_cast<const float*>(h->d_U), h->d_Ulo, h->d_mb, (size_t)h->n * h->L, st));
-      HIP_TRY(launch_persistent_mb(a, h->d_mb, LT, NT, G, k, in_lds, in_lds ? phi_bytes : 0, st));
+      if (h->potts) HIP_TRY(launch_persistent_mb_potts(a, h->d_mb, G, k, in_lds, in_lds ? phi_bytes : 0, st));
+      else HIP_TRY(launch_persistent_mb(a, h->d_mb, LT, NT, G, k, in_lds, in_lds ? phi_bytes : 0, st));
       HIP_TRY(launch_mb_fini(static_cast<float*>(h->d_U), h->d_Ulo, h->d_mb, h->n, h->L,
                              trace_host ? h->d_trace_nodes + (size_t)(k - 1) * h->n : nullptr, st));
     } else {
@@ -668,6 +685,11 @@ int mplpxx_create(int32_t n, int32_t L, int64_t m, const int32_t* edges, const v
   return create_impl(n, L, m, edges, unaries, pairwise, dtype, false, nullptr, out);
 }
 
+int mplpxx_create_potts(int32_t n, int32_t L, int64_t m, const int32_t* edges, const float* unaries, const float* weights,
+                        mplpxx_solver** out) {
+  return create_impl(n, L, m, edges, unaries, weights, MPLPXX_F32, false, nullptr, out, MPLPXX_SCHED_AUTO, true);
+}
+
 int mplpxx_create_device(int32_t n, int32_t L, int64_t m, const int32_t* edges, const void* unaries_dev,
                          const void* pairwise_dev, int32_t dtype, void* hip_stream, mplpxx_solver** out) {
   return create_impl(n, L, m, edges, unaries_dev, pairwise_dev, dtype, true, static_cast<hipStream_t>(hip_stream), out);
@@ -686,6 +708,7 @@ int mplpxx_iterate(mplpxx_solver* h, int32_t k) {
 
 int mplpxx_iterate_trace(mplpxx_solver* h, int32_t k, double* trace) {
   if (!h) return fail(MPLPXX_EINVAL, "handle is NULL");
+  if (h->potts) return fail(MPLPXX_EINVAL, "per-iteration traces are not available for Potts models (use mplpxx_iterate_gap)");
   if (k < 0) return fail(MPLPXX_EINVAL, "k must be >= 0");
   if (k > 0 && !trace) return fail(MPLPXX_EINVAL, "trace is NULL");
   return h->dtype == MPLPXX_F32 ? iterate_t<float>(h, k, trace) : iterate_t<double>(h, k, trace);
@@ -693,6 +716,7 @@ int mplpxx_iterate_trace(mplpxx_solver* h, int32_t k, double* trace) {
 
 int mplpxx_adjoint_forward(mplpxx_solver* h, int32_t K, int32_t every, double* loss) {
   if (!h) return fail(MPLPXX_EINVAL, "handle is NULL");
+  if (h->potts) return fail(MPLPXX_EINVAL, "the adjoint takes dense tables");
   if (K < 1 || every < 1) return fail(MPLPXX_EINVAL, "K and every must be >= 1");
   if (h->rule != MPLPXX_RULE_H) return fail(MPLPXX_EINVAL, "the adjoint takes the (H) update only");
   h->adj_ready = false;
@@ -760,7 +784,8 @@ int mplpxx_dual_bound(mplpxx_solver* h, double* out) {
   hipStream_t st = h->stream();
   if (h->dtype == MPLPXX_F32)
     HIP_TRY(launch_dual<float>((const float*)h->d_unaries, (const float*)h->d_tables, (const float*)h->d_phi,
-                               h->d_node_ptr, h->d_inc, h->n, h->L, h->m, h->d_node_min, h->d_edge_min, h->d_scalar, st));
+                               h->d_node_ptr, h->d_inc, h->n, h->L, h->m, h->d_node_min, h->d_edge_min, h->d_scalar, st,
+                               h->potts));
   else
     HIP_TRY(launch_dual<double>((const double*)h->d_unaries, (const double*)h->d_tables, (const double*)h->d_phi,
                                 h->d_node_ptr, h->d_inc, h->n, h->L, h->m, h->d_node_min, h->d_edge_min, h->d_scalar, st));
@@ -775,7 +800,8 @@ int mplpxx_decode(mplpxx_solver* h, int32_t* labels, double* energy) {
   hipStream_t st = h->stream();
   if (h->dtype == MPLPXX_F32)
     HIP_TRY(launch_decode<float>((const float*)h->d_unaries, (const float*)h->d_tables, (const float*)h->d_phi,
-                                 h->d_slots, h->d_node_ptr, h->d_inc, h->n, h->L, h->m, h->d_labels, h->d_scalar + 1, st));
+                                 h->d_slots, h->d_node_ptr, h->d_inc, h->n, h->L, h->m, h->d_labels, h->d_scalar + 1, st,
+                                 h->potts));
   else
     HIP_TRY(launch_decode<double>((const double*)h->d_unaries, (const double*)h->d_tables, (const double*)h->d_phi,
                                   h->d_slots, h->d_node_ptr, h->d_inc, h->n, h->L, h->m, h->d_labels, h->d_scalar + 1, st));
@@ -812,11 +838,12 @@ int mplpxx_iterate_gap(mplpxx_solver* h, int32_t k, double* dual, double* energy
     hipError_t e;
     if (h->dtype == MPLPXX_F32) {
       e = launch_dual<float>((const float*)h->d_unaries, (const float*)h->d_tables, (const float*)h->d_phi,
-                             h->d_node_ptr, h->d_inc, h->n, h->L, h->m, h->d_node_min, h->d_edge_min, d_gap + it, st);
+                             h->d_node_ptr, h->d_inc, h->n, h->L, h->m, h->d_node_min, h->d_edge_min, d_gap + it, st,
+                             h->potts);
       if (e == hipSuccess)
         e = launch_decode<float>((const float*)h->d_unaries, (const float*)h->d_tables, (const float*)h->d_phi,
                                  h->d_slots, h->d_node_ptr, h->d_inc, h->n, h->L, h->m, d_lab + (size_t)it * h->n,
-                                 d_gap + k + it, st);
+                                 d_gap + k + it, st, h->potts);
     } else {
       e = launch_dual<double>((const double*)h->d_unaries, (const double*)h->d_tables, (const double*)h->d_phi,
                               h->d_node_ptr, h->d_inc, h->n, h->L, h->m, h->d_node_min, h->d_edge_min, d_gap + it, st);
@@ -971,16 +998,19 @@ int mplpxx_set_option(mplpxx_solver* h, int32_t key, int64_t value) {
   switch (key) {
     case MPLPXX_OPT_ENGINE:
       if (value < 0 || value > 2) return fail(MPLPXX_EINVAL, "engine must be 0, 1 or 2");
+      if (h->potts && value == ENGINE_STEP) return fail(MPLPXX_EINVAL, "Potts models run on the persistent engine only");
       h->engine_opt = (int)value;
       return MPLPXX_OK;
     case MPLPXX_OPT_THREADS:
+      if (h->potts && value != 0) return fail(MPLPXX_EINVAL, "Potts models run one compute wave per workgroup");
       if (value != 0 && !valid_threads(h->LT(), (int)value))
         return fail(MPLPXX_EINVAL, "threads %lld not valid for L=%d", (long long)value, h->L);
       h->threads_opt = (int)value;
       return MPLPXX_OK;
     case MPLPXX_OPT_GRID: {
       if (value < 0) return fail(MPLPXX_EINVAL, "grid must be >= 0");
-      const int nb = h->mb_engine() ? max_blocks_per_cu_mb(h->LT(), h->NT())
+      const int nb = h->potts ? max_blocks_per_cu_mb_potts()
+                     : h->mb_engine() ? max_blocks_per_cu_mb(h->LT(), h->NT())
                      : h->dtype == MPLPXX_F32 ? max_blocks_per_cu<float>(ENGINE_PERSISTENT, h->LT(), h->NT())
                                               : max_blocks_per_cu<double>(ENGINE_PERSISTENT, h->LT(), h->NT());
       if (value > (int64_t)nb * h->num_cus) return fail(MPLPXX_EINVAL, "grid %lld exceeds co-resident limit %d", (long long)value, nb * h->num_cus);
@@ -1001,6 +1031,7 @@ int mplpxx_set_option(mplpxx_solver* h, int32_t key, int64_t value) {
     case MPLPXX_OPT_RULE:
       if (value != MPLPXX_RULE_H && value != MPLPXX_RULE_M && value != MPLPXX_RULE_U)
         return fail(MPLPXX_EINVAL, "rule must be MPLPXX_RULE_H, _M or _U");
+      if (h->potts && value != MPLPXX_RULE_H) return fail(MPLPXX_EINVAL, "Potts models take the (H) update only");
       h->rule = (int)value;
       h->adj_ready = false;
       return MPLPXX_OK;

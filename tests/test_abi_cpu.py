@@ -191,3 +191,30 @@ def test_batch_inputs_rejected_without_device_work(case):
         M.Batch([good, bad], potts=potts)
     assert ei.value.code == M.EINVAL
     assert "model 1" in str(ei.value)
+
+
+@pytest.mark.parametrize("case", ["nan_w", "big_w", "L65", "self", "count"])
+def test_potts_solver_inputs_rejected_without_device_work(case):
+    """mplpxx_create_potts validates before any device work: non-finite or
+    oversized weights, L > 64, a bad edge, a weight array of the wrong size."""
+    w, _ = W.potts_pure(6, 5, 1.0, seed=3)
+    weights, un, edges, L = w.pairwise.copy(), w.unaries.copy(), w.edges.copy(), w.L
+    if case == "nan_w":
+        weights[2] = np.nan
+    elif case == "big_w":
+        weights[0] = -1e30
+    elif case == "L65":
+        L = 65
+        un = np.zeros((w.n, L), np.float32)
+    elif case == "self":
+        edges[1] = [2, 2]
+    elif case == "count":
+        weights = weights[:-1]
+    bad = W.Model(w.n, L, edges, un, weights, "bad")
+    if case == "count":
+        with pytest.raises(ValueError):
+            M.Solver.from_potts(bad)
+        return
+    with pytest.raises(M.MplpError) as ei:
+        M.Solver.from_potts(bad)
+    assert ei.value.code == M.EINVAL

@@ -176,3 +176,84 @@ def test_potts_reset_and_timeout(mode):
         b.reset()
         b.iterate(3)
         assert np.array_equal(b.dual_bounds(), d3)
+
+
+# ---------------------------------------------------------------------------
+# Single-model Potts handles (mplpxx_create_potts) on the mailbox engine
+# ---------------------------------------------------------------------------
+def _solver_run(make, iters):
+    with make() as s:
+        s.iterate(iters)
+        U, phi, c = s.get_state(comp=True)
+        d = s.dual_bound()
+        lab, e = s.decode()
+        info = (s.info("engine"), s.info("grid"), s.info("threads"))
+    return (U, phi, c), d, (lab, e), info
+
+
+SOLVER_CASES = [(2, 1, 1.0), (5, 2, 1.0), (9, 7, 0.6), (12, 16, 1.0), (8, 17, 1.0), (10, 32, 0.8), (30, 33, 0.3),
+                (16, 64, 1.0), (200, 64, 1.0), (120, 40, 0.5),
+                (600, 8, 1.0)]   # 300 edges per matching: more workgroups than CUs, messages in HBM
+
+
+@pytest.mark.parametrize("n,L,p", SOLVER_CASES, ids=[f"n{n}_L{L}_p{p}" for n, L, p in SOLVER_CASES])
+def test_potts_solver_is_bitwise_the_dense_solver(n, L, p):
+    _announce("potts solver", n, L, p)
+    w, d = W.potts_pure(n, L, p, seed=n + L)
+    iters = 4 if n >= 200 else 7
+    sp, dp, lp, ip = _solver_run(lambda: M.Solver.from_potts(w), iters)
+    sd, dd, ld, idn = _solver_run(lambda: M.Solver.from_model(d), iters)
+    assert ip[0] == M.ENGINE_PERSISTENT and ip[2] == 64
+    for a, b in zip(sp, sd):
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    assert dp == dd
+    assert np.array_equal(lp[0], ld[0]) and lp[1] == ld[1]
+    # the same model as a Potts batch: bitwise the same state
+    with M.Batch([w], potts=True) as bt:
+        bt.iterate(iters)
+        sb = bt.get_state(0, comp=True)
+    for a, b in zip(sp, sb):
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    if n <= 200:
+        st, ref = oracle.run_model(d, iters)
+        assert abs(dp - ref[-1]) <= 1e-5 * max(1.0, abs(ref[-1])), (dp, ref[-1])
+
+
+def test_potts_solver_gap_state_and_timeout():
+    _announce("potts solver gap/state/timeout")
+    w, d = W.potts_pure(40, 12, 0.5, seed=4)
+    with M.Solver.from_potts(w) as s, M.Solver.from_model(d) as t:
+        gp = s.iterate_gap(5)
+        gd = t.iterate_gap(5)
+        for a, b in zip(gp, gd):
+            assert np.array_equal(np.asarray(a), np.asarray(b))
+        U, phi, c = s.get_state(comp=True)
+        s.iterate(3)
+        ref = s.get_state(comp=True)
+        s.set_state(U, phi, c)
+        s.set_option(M.OPT_SPIN_LIMIT, 1)
+        with pytest.raises(M.MplpError) as ei:
+            s.iterate(3)
+        assert ei.value.code == M.ETIMEOUT
+        s.set_option(M.OPT_SPIN_LIMIT, 0)
+        s.set_state(U, phi, c)
+        s.iterate(3)
+        for a, b in zip(s.get_state(comp=True), ref):
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+def test_potts_solver_rejects_dense_only_calls():
+    _announce("potts solver errors")
+    w, _ = W.potts_pure(8, 6, 1.0, seed=5)
+    with M.Solver.from_potts(w) as s:
+        for key, val in ((M.OPT_ENGINE, M.ENGINE_STEP), (M.OPT_THREADS, 256), (M.OPT_RULE, M.RULE_M)):
+            with pytest.raises(M.MplpError) as ei:
+                s.set_option(key, val)
+            assert ei.value.code == M.EINVAL
+        with pytest.raises(M.MplpError) as ei:
+            s.iterate_trace(2)
+        assert ei.value.code == M.EINVAL
+        with pytest.raises(M.MplpError) as ei:
+            s.adjoint_forward(2, 1)
+        assert ei.value.code == M.EINVAL
+        s.iterate(1)
