@@ -260,7 +260,7 @@ __global__ void __launch_bounds__(NT + 128) k_persistent_mb(HsArgs<float> a, uns
   const int tid = threadIdx.x;
   const int L = FULL ? LT : a.L;
   const int G = gridDim.x;
-  if (blockIdx.x >= a.m) return;
+  if ((int)blockIdx.x >= a.m) return;
   if (tid == 0) sm.abort_flag = 0;
   if (PHI_LDS) {
     for (int slot = blockIdx.x, j = 0; slot < a.m; slot += G, ++j)
@@ -289,7 +289,7 @@ __global__ void __launch_bounds__(kPottsNT + 128) k_persistent_mb_potts(HsArgs<f
   const int tid = threadIdx.x;
   const int L = a.L;
   const int G = gridDim.x;
-  if (blockIdx.x >= a.m) return;
+  if ((int)blockIdx.x >= a.m) return;
   if (tid == 0) sm.abort_flag = 0;
   if (PHI_LDS) {
     for (int slot = blockIdx.x, j = 0; slot < a.m; slot += G, ++j)
