@@ -434,7 +434,7 @@ def main():
                     help="only a 3 x 1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "mplpxx runs on one GPU (the multi-GPU design is not implemented); --gpus must be 1"}))
         sys.exit(2)
 
     if args.copy_calibration:
