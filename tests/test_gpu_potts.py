@@ -257,3 +257,21 @@ def test_potts_solver_rejects_dense_only_calls():
             s.adjoint_forward(2, 1)
         assert ei.value.code == M.EINVAL
         s.iterate(1)
+
+
+@pytest.mark.parametrize("L", [1, 2, 5, 16, 17, 33, 64])
+def test_potts_single_edge_update_reaches_the_map(L):
+    """One (H) update of a single edge is block-optimal (Sec. 4): the dual
+    equals min_{s,t} theta_u(s) + theta_v(t) + w [s != t], brute force, for
+    positive, negative and zero weights (FP32 tolerance)."""
+    _announce("potts single edge", L)
+    rng = np.random.default_rng(L)
+    for w in (0.7, -0.3, 0.0, float(rng.uniform(0.1, 2.0))):
+        un = rng.random((2, L)).astype(np.float32)
+        model = W.Model(2, L, np.array([[0, 1]], np.int32), un, np.array([w], np.float32), "edge")
+        with M.Solver.from_potts(model) as s:
+            s.iterate(1)
+            d = s.dual_bound()
+        th = np.where(np.eye(L, dtype=bool), 0.0, np.float64(np.float32(w)))
+        g = un[0].astype(np.float64)[:, None] + un[1].astype(np.float64)[None, :] + th
+        assert abs(d - g.min()) <= 1e-5 * max(1.0, abs(g.min())), (L, w, d, g.min())
