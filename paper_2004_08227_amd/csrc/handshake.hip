@@ -32,6 +32,7 @@
 // then across waves through LDS).  Every entry of a pass is one IEEE add
 // followed by an exact minimum, so results do not depend on LT, NT, the
 // reduction tree or the engine.
+#include <algorithm>
 #include <type_traits>
 
 #include "step_common.h"
@@ -370,15 +371,32 @@ static hipError_t launch_mb_one(const HsArgs<float>& a, unsigned long long* mb, 
   return e;
 }
 
+// Workgroups of a persistent kernel that the dispatcher can always place on
+// one compute unit together.  The occupancy query assumes a workgroup's
+// waves spread evenly over the four SIMDs; a placement may put ceil(W/4) of
+// its W waves on one SIMD, so at most (waves one SIMD holds) / ceil(W/4)
+// workgroups are certain to be resident at once.  A cooperative launch
+// beyond that can leave workgroups waiting for a free slot that persistent
+// workgroups never release.
+static int placeable_per_cu(const void* f, int threads, int nb) {
+  int one_wave = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&one_wave, f, 64, 0) != hipSuccess || one_wave < 4) return nb;
+  const int per_simd = one_wave / 4;
+  const int per_wg = ((threads + 63) / 64 + 3) / 4;
+  return std::min(nb, std::max(1, per_simd / per_wg));
+}
+
 // workgroups of the FP32 mailbox kernel that fit on one compute unit (no
 // dynamic LDS)
 int max_blocks_per_cu_mb(int LT, int NT) {
   int nb = 0;
   hipError_t e = hipErrorInvalidValue;
 #define MPLPXX_CASE(lt, nt)                                                                                  \
-  if (LT == lt && NT == nt)                                                                                  \
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_persistent_mb<lt, nt, false, false, false, true>, \
-                                                     nt + 128, 0);
+  if (LT == lt && NT == nt) {                                                                                \
+    const void* f = (const void*)k_persistent_mb<lt, nt, false, false, false, true>;                         \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, nt + 128, 0);                                   \
+    if (e == hipSuccess) nb = placeable_per_cu(f, nt + 128, nb);                                             \
+  }
   MPLPXX_CASE(16, 256)
   MPLPXX_CASE(32, 256)
   MPLPXX_CASE(32, 512)
@@ -407,9 +425,9 @@ hipError_t launch_persistent_mb(const HsArgs<float>& a, unsigned long long* mb, 
 
 int max_blocks_per_cu_mb_potts() {
   int nb = 0;
-  const hipError_t e =
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_persistent_mb_potts<false>, kPottsNT + 128, 0);
-  return e == hipSuccess ? nb : 0;
+  const void* f = (const void*)k_persistent_mb_potts<false>;
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kPottsNT + 128, 0);
+  return e == hipSuccess ? placeable_per_cu(f, kPottsNT + 128, nb) : 0;
 }
 
 hipError_t launch_persistent_mb_potts(const HsArgs<float>& a, unsigned long long* mb, int grid, int iters,
@@ -458,9 +476,11 @@ int max_blocks_per_cu(int engine, int LT, int NT) {
   int nb = 0;
   hipError_t e = hipErrorInvalidValue;
 #define MPLPXX_CASE(lt, nt)                                                                           \
-  if (LT == lt && NT == nt)                                                                           \
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(                                                 \
-        &nb, engine == ENGINE_STEP ? (const void*)k_step<T, lt, nt> : (const void*)k_persistent<T, lt, nt>, nt, 0);
+  if (LT == lt && NT == nt) {                                                                         \
+    const void* f = engine == ENGINE_STEP ? (const void*)k_step<T, lt, nt> : (const void*)k_persistent<T, lt, nt>; \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, nt, 0);                                  \
+    if (e == hipSuccess && engine != ENGINE_STEP) nb = placeable_per_cu(f, nt, nb);                   \
+  }
   MPLPXX_CASE(16, 256)
   MPLPXX_CASE(32, 256)
   MPLPXX_CASE(32, 512)

@@ -381,3 +381,50 @@ def test_iterate_gap_is_dual_and_rounding_after_each_iteration(which):
     if which == "tiny_fp64":
         e_map, _ = oracle.bruteforce(model)
         assert d.max() <= e_map + 1e-12 and e.min() >= e_map - 1e-12
+
+
+def test_large_matchings_at_64_labels_stay_placeable():
+    """Matchings larger than the number of compute units at L = 64: the
+    mailbox kernel's six waves of 130 registers leave room for one workgroup
+    per compute unit that is certain to be placed, so the default grid stays
+    at one per CU (a second workgroup per CU could wait forever for a slot)
+    and the state is bitwise the per-matching engine's."""
+    _announce("large matchings L=64")
+    model = W.random_graph_model(1100, 64, 0.03, seed=5).astype(np.float32)
+    iters = 3
+    with M.Solver.from_model(model) as s:
+        s.set_option(M.OPT_SPIN_LIMIT, 1 << 20)
+        s.iterate(iters)
+        g = s.info("grid")
+        st0 = s.get_state(comp=True)
+        d0 = s.dual_bound()
+        with pytest.raises(M.MplpError) as ei:
+            s.set_option(M.OPT_GRID, 2 * s.info("grid") + 1)
+        assert ei.value.code == M.EINVAL
+    assert g <= 256, g
+    with M.Solver.from_model(model) as s:
+        s.set_option(M.OPT_ENGINE, M.ENGINE_STEP)
+        s.iterate(iters)
+        st1 = s.get_state(comp=True)
+        assert s.dual_bound() == d0
+    for a, b in zip(st0, st1):
+        assert np.array_equal(a, b)
+
+
+def test_more_workgroups_than_edges_per_matching():
+    """A grid larger than the largest matching (L = 16, where two workgroups
+    per compute unit are placeable): bitwise the default grid's state."""
+    _announce("grid beyond the matchings")
+    model = W.pose(200, 16, seed=2)
+    states = []
+    for grid in (0, 384):
+        with M.Solver.from_model(model) as s:
+            s.set_option(M.OPT_SPIN_LIMIT, 1 << 20)
+            if grid:
+                s.set_option(M.OPT_GRID, grid)
+            s.iterate(5)
+            states.append((s.info("grid"), s.get_state(comp=True), s.dual_bound()))
+    assert states[1][0] == 384
+    for a, b in zip(states[0][1], states[1][1]):
+        assert np.array_equal(a, b)
+    assert states[0][2] == states[1][2]
