@@ -158,6 +158,18 @@ def bench_batched(M, W, iters=100, per_problem=True):
         info["wg_busy_max_ms"] = b.info("wg_max_us") / 1e3
         info["wg_busy_mean_ms"] = b.info("wg_mean_us") / 1e3
         d_b = b.dual_bounds()
+        # the same launch with the autotuner's options for this batch (if the
+        # committed table has an entry): the same duals, bit for bit
+        from paper_2004_08227_amd import autotune as A
+        tuned = A.apply_batch(b, models)
+        if tuned:
+            b.reset()
+            b.iterate(2)
+            b.reset()
+            b.iterate(iters)
+            info["tuned_options"] = tuned
+            info["tuned_ms"] = b.info("last_ms")
+            info["tuned_duals_bitwise_equal"] = bool(np.array_equal(b.dual_bounds(), d_b))
     out = {"workload": "batched_mix: 256 pose models, n ~ U{20..300}, L ~ U{8..64}, seed 0", "iterations": iters,
            "edges": m_tot, "batched_ms": ms_b, "batched_wall_s": wall_b,
            "updates_per_s": m_tot * iters / (ms_b / 1e3),
