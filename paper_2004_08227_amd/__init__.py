@@ -404,3 +404,20 @@ class Batch:
         tm = np.zeros(g, np.int32)
         _check(lib().mplpxx_batch_wg_profile(self._h, se.ctypes.data, tm.ctypes.data))
         return se, tm
+
+
+def solve_batch(models, iters, potts=False, tuned=True, states=False):
+    """Solves `models` together for `iters` iterations in one persistent
+    launch (``Batch``), with the autotuner's options for such a batch when
+    ``tuned`` (the committed table; results are the same bits either way).
+    Returns the dual bounds [count] (FP64), and with ``states`` also the
+    list of (U, phi) per model."""
+    with Batch(models, potts=potts) as b:
+        if tuned:
+            from . import autotune
+            autotune.apply_batch(b, models)
+        b.iterate(iters)
+        d = b.dual_bounds()
+        if states:
+            return d, [b.get_state(i) for i in range(len(models))]
+        return d

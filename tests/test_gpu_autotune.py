@@ -37,3 +37,19 @@ def test_batch_tuner_candidates_agree():
     opts, ms, ms0 = A.tune_batch(models, iters=3, rounds=1)
     assert ms <= ms0
     assert set(opts) <= set(A.BATCH_CHOICES)
+
+
+def test_solve_batch_tuned_and_untuned_agree():
+    _announce("solve_batch")
+    models = [W.pose(30, 13, seed=1), W.pose(18, 40, seed=2), W.potts_er(50, 9, 0.3, seed=3)]
+    table = {A.batch_key(models): {"options": {"queue": 0, "wave_lat_mb_us": 4.0}, "workload": "test"}}
+    d0, s0 = M.solve_batch(models, 5, tuned=False, states=True)
+    with M.Batch(models) as b:
+        assert A.apply_batch(b, models, table) == {"queue": 0, "wave_lat_mb_us": 4.0}
+        b.iterate(5)
+        d1 = b.dual_bounds()
+        s1 = [b.get_state(i) for i in range(len(models))]
+    d2 = M.solve_batch(models, 5)
+    assert np.array_equal(d0, d1) and np.array_equal(d0, d2)
+    for (a, b), (c, e) in zip(s0, s1):
+        assert np.array_equal(a, c) and np.array_equal(b, e)
