@@ -25,6 +25,7 @@
 //    the colour of the next fan edge) and (u, w) gets d.
 #include <algorithm>
 #include <cstdint>
+#include <string>
 #include <vector>
 
 #include "host_util.h"
@@ -212,6 +213,43 @@ void build_schedule(int n, const std::vector<int>& eu, const std::vector<int>& e
   }
 }
 
+// A schedule is valid when its rounds list every edge exactly once and no
+// node twice within a round (Alg. 1: the rounds are matchings).  The
+// engines rely on both: the updates of a round run concurrently, and a
+// node's updates are counted in schedule order.
+static bool schedule_is_valid(int n, const std::vector<int>& eu, const std::vector<int>& ev,
+                              const std::vector<int>& step_ptr, const std::vector<int>& order, std::string* why) {
+  const int m = (int)eu.size();
+  if ((int)order.size() != m || step_ptr.empty() || step_ptr.front() != 0 || step_ptr.back() != m) {
+    *why = "the rounds do not cover the edges";
+    return false;
+  }
+  std::vector<char> seen(m, 0);
+  std::vector<int> round_of(n, -1);
+  for (int k = 0; k + 1 < (int)step_ptr.size(); ++k) {
+    if (step_ptr[k + 1] < step_ptr[k]) {
+      *why = "round boundaries out of order";
+      return false;
+    }
+    for (int i = step_ptr[k]; i < step_ptr[k + 1]; ++i) {
+      const int e = order[i];
+      if (e < 0 || e >= m || seen[e]) {
+        *why = "an edge is missing or listed twice";
+        return false;
+      }
+      seen[e] = 1;
+      for (int x : {eu[e], ev[e]}) {
+        if (round_of[x] == k) {
+          *why = "round " + std::to_string(k) + " is not a matching (node " + std::to_string(x) + ")";
+          return false;
+        }
+        round_of[x] = k;
+      }
+    }
+  }
+  return true;
+}
+
 int prepare_graph(int n, int m, const int32_t* edges, GraphPrep& g, int kind) {
   std::vector<int> eu(m), ev(m);
   g.flip.assign(m, 0);
@@ -233,7 +271,11 @@ int prepare_graph(int n, int m, const int32_t* edges, GraphPrep& g, int kind) {
   }
   build_schedule(n, eu, ev, g.step_ptr, g.order, kind);
   g.S = (int)g.step_ptr.size() - 1;
-  if ((int)g.order.size() != m) return fail(MPLPXX_EINVAL, "internal: schedule does not cover the edges");
+  {
+    std::string why;
+    if (!schedule_is_valid(n, eu, ev, g.step_ptr, g.order, &why))
+      return fail(MPLPXX_EINVAL, "internal: invalid schedule (%s)", why.c_str());
+  }
   g.slot_of_edge.assign(m, -1);
   g.slots.resize(m);
   g.deg.assign(n, 0);
