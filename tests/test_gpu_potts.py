@@ -275,3 +275,25 @@ def test_potts_single_edge_update_reaches_the_map(L):
         th = np.where(np.eye(L, dtype=bool), 0.0, np.float64(np.float32(w)))
         g = un[0].astype(np.float64)[:, None] + un[1].astype(np.float64)[None, :] + th
         assert abs(d - g.min()) <= 1e-5 * max(1.0, abs(g.min())), (L, w, d, g.min())
+
+
+def test_potts_edgeless_models():
+    """No edges (single handle and inside a batch) and a single node: the
+    dual bound is the sum of the unary minima, before and after iterating."""
+    _announce("potts edgeless")
+    rng = np.random.default_rng(9)
+    for n, L in ((1, 5), (4, 64), (7, 3)):
+        un = rng.random((n, L)).astype(np.float32)
+        model = W.Model(n, L, np.zeros((0, 2), np.int32), un, np.zeros(0, np.float32), "edgeless")
+        want = float(np.sum(un.astype(np.float64).min(axis=1)))
+        with M.Solver.from_potts(model) as s:
+            assert s.dual_bound() == pytest.approx(want, rel=1e-12)
+            s.iterate(3)
+            assert s.dual_bound() == pytest.approx(want, rel=1e-12)
+            lab, e = s.decode()
+            assert np.array_equal(lab, un.argmin(axis=1))
+        w, _ = W.potts_pure(9, L, 1.0, seed=n)
+        with M.Batch([model, w], potts=True) as b:
+            b.iterate(3)
+            d = b.dual_bounds()
+        assert d[0] == pytest.approx(want, rel=1e-12)
