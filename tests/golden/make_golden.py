@@ -4,10 +4,11 @@ Everything here is computed by the FP64 CPU oracle (``oracle/``) on inputs
 from the seeded generators (``paper_2004_08227_amd/workloads.py``); nothing
 comes from the HIP path.  Run from the repository root:
 
-    python tests/golden/make_golden.py [all|pose|potts|potts_sched|batch|adjoint]
+    python tests/golden/make_golden.py [all|pose|pose_rules|potts|potts_sched|batch|adjoint]
 
 Outputs (JSON, one file per workload):
   pose_k200_l64.json        dual trace of 200 iterations, final node minima
+  pose_k200_l64_rules.json  200-iteration dual traces of the (M) and (U) updates
   potts_er_n1000_l16.json   dual traces (30 iterations) at 5/25/50/100 % density
   potts_er_n1000_l16_sched.json  the same workload under both schedules of
                             the oracle (greedy matchings, Delta + 1 edge
@@ -50,6 +51,16 @@ def make_pose():
     tr = st.run(200, trace=True, nthreads=THREADS)
     dump("pose_k200_l64.json", {"workload": "pose n=200 L=64 seed=0", "iters": 200, "trace": tr.tolist(),
                                 "node_min": st.Tu.min(axis=1).tolist(), "seconds": time.time() - t})
+
+
+def make_pose_rules():
+    model = W.pose(200, 64, seed=0)
+    out = {"workload": "pose n=200 L=64 seed=0", "iters": 200, "traces": {}}
+    for rule in ("M", "U"):
+        st = oracle.State(model)
+        out["traces"][rule] = st.run(200, rule=rule, trace=True, nthreads=THREADS).tolist()
+        print("pose rule", rule, flush=True)
+    dump("pose_k200_l64_rules.json", out)
 
 
 def make_potts():
@@ -178,6 +189,8 @@ if __name__ == "__main__":
     W.build_generator()
     if what in ("all", "pose"):
         make_pose()
+    if what in ("all", "pose_rules"):
+        make_pose_rules()
     if what in ("all", "potts"):
         make_potts()
     if what in ("all", "potts_sched"):

@@ -126,3 +126,22 @@ def test_rule_option_errors():
         assert ei.value.code == M.EINVAL
         s.set_option(M.OPT_RULE, M.RULE_H)
         s.adjoint_forward(2, 1)
+
+
+@pytest.mark.parametrize("rule", ["M", "U"])
+def test_rule_full_size_pose_matches_stored_oracle_trace(rule):
+    """The pose workload at full size (n = 200, L = 64, 200 iterations from
+    phi = 0) under (M) and (U): every iteration's dual within 1e-5 of the
+    oracle's stored trace (tests/golden/make_golden.py, oracle only)."""
+    import json
+    import os
+    _announce("full size rule", rule)
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "pose_k200_l64_rules.json")))
+    assert g["workload"] == "pose n=200 L=64 seed=0"
+    ref = np.asarray(g["traces"][rule])
+    model = W.pose(200, 64, seed=0)
+    with M.Solver.from_model(model) as s:
+        s.set_option(M.OPT_RULE, M.RULE_M if rule == "M" else M.RULE_U)
+        tr = s.iterate_trace(200)
+    rel = np.abs(tr - ref) / np.maximum(1.0, np.abs(ref))
+    assert rel.max() <= 1e-5, (rel.max(), int(rel.argmax()))
