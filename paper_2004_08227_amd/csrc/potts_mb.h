@@ -8,11 +8,13 @@
 // operations as in the dense engines, so the results are bitwise those of
 // the dense engine on the expanded table.
 //
-// Per step both kinds of waves meet at the same two barriers as in mb_run:
-// the first (the step's nodes are in LDS), then the mid-step barrier, after
-// which the sync waves go on to the next step's nodes (double-buffered by
-// slot parity).  The compute wave reads everything it needs from LDS before
-// the mid-step barrier, so the next gathers overlap its passes.
+// Per step both kinds of waves meet at one barrier (the step's nodes are in
+// LDS); there is no mid-step barrier as in mb_run, since the compute wave
+// exchanges nothing with other waves.  The sync waves then go on to the next
+// step's nodes, which go to the other half of the double buffer (slot
+// parity); they come back to this half only after the compute wave has
+// reached the next step's barrier, i.e. after it has read this step's
+// values, so the next gathers overlap its passes.
 #pragma once
 #include "potts_passes.h"
 
@@ -66,7 +68,6 @@ __device__ __forceinline__ bool mb_run_potts(const MbView& v_in, int first_in, i
       if (v.stamps && last_iter && lane == 0) v.stamps[(size_t)slot * kStampStride + (is_sync_u ? 1 : 2)] = wall_clock64();
       __syncthreads();
       if (sm.abort_flag) return false;
-      __syncthreads();  // the compute wave's mid-step barrier
       si = si_next;
       parity ^= 1;
       if (++j == owned) { j = 0; ++it; }
@@ -102,7 +103,6 @@ __device__ __forceinline__ bool mb_run_potts(const MbView& v_in, int first_in, i
     const float hu = sm.uh[parity][li], lu = sm.ul[parity][li];
     const float hv = sm.vh[parity][li], lv = sm.vl[parity][li];
     const float delta = 0.5f * (sm.cc[parity][0] - sm.cc[parity][1]);
-    __syncthreads();  // mid-step barrier: the sync waves move on to the next step
     float phu, phv;
     potts_passes(au, av, w, lout, L, delta, phu, phv);
     float nhu, nlu, nhv, nlv;
