@@ -90,6 +90,39 @@ def test_fp32_dual_matches_oracle(name, make, iters, engine):
     assert np.max(np.abs(U - st.Tu)) <= 1e-4 * max(1.0, np.abs(st.Tu).max())
 
 
+FP64_CASES = [
+    ("pose_L64", lambda: W.pose(24, 64, seed=11), 10),
+    ("pose_L100", lambda: W.pose(12, 100, seed=12), 6),
+    ("uniform_L128", lambda: W.uniform(8, 128, seed=13), 4),
+    ("uniform_ragged13", lambda: W.uniform(21, 13, seed=14), 20),
+    ("potts_er_L33", lambda: W.potts_er(40, 33, 0.4, seed=15), 10),
+]
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+@pytest.mark.parametrize("name,make,iters", FP64_CASES, ids=[c[0] for c in FP64_CASES])
+def test_fp64_matches_oracle_at_large_and_ragged_labels(name, make, iters, engine):
+    """The FP64 instantiation (three-minimization form of (H)) against the
+    oracle's four-line form at L up to the library maximum, full and ragged
+    tiles, on both engines: the two forms are equal in exact arithmetic, so
+    they may differ only by FP64 roundings."""
+    _announce("fp64", name, engine)
+    base = make()
+    model = W.Model(base.n, base.L, base.edges, base.unaries.astype(np.float64),
+                    base.pairwise.astype(np.float64), base.name + "_f64")
+    st, ref = oracle.run_model(model, iters)
+    with M.Solver.from_model(model) as s:
+        s.set_option(M.OPT_ENGINE, engine)
+        tr = s.iterate_trace(iters)
+        d = s.dual_bound()
+        U, phi = s.get_state()
+    assert np.max(np.abs(tr - ref) / np.maximum(1.0, np.abs(ref))) <= 1e-12
+    assert _rel(d, st.dual()) <= 1e-12
+    assert np.max(np.abs(U - st.Tu)) <= 1e-12 * max(1.0, np.abs(st.Tu).max())
+    Te = st.pairwise - phi[:, 0, :, None] - phi[:, 1, None, :]
+    assert np.max(np.abs(Te - st.Te)) <= 1e-12 * max(1.0, np.abs(st.Te).max())
+
+
 def test_engines_and_tunings_are_bitwise_identical():
     model = W.pose(50, 64, seed=11)
     states = []
