@@ -213,3 +213,33 @@ def test_adjoint_memory_is_reported():
         s.adjoint_forward(K, every)
         twin = own64 + nL * 8 * 2 + m * L * L * 8 + mp * 8
         assert s.info("adjoint_bytes") == twin
+
+
+@pytest.mark.parametrize("n,L,K", [(10, 64, 4), (8, 100, 3), (6, 128, 3)])
+def test_fp64_adjoint_at_large_labels(n, L, K):
+    """At L up to the library maximum (full and ragged tiles): adding c to
+    every label of one node's unary, or to every entry of one edge's table,
+    raises D_K by exactly c (the update (H) passes a uniform shift through
+    and no argmin moves), so the gradient sums to 1 over each node's L
+    entries and over each edge's L x L entries; and seeded coordinates match
+    central differences of the oracle (a step may cross a kink of the
+    piecewise-linear D_K for at most one of them)."""
+    _announce("fp64 adjoint large L", n, L, K)
+    model = W.uniform(n, L, seed=40 + L, dtype=np.float64)
+    loss, gu, gp = _grad(model, K, 1)
+    st, _ = oracle.run_model(model, K)
+    assert abs(loss - st.dual()) <= 1e-12 * max(1, abs(loss))
+    assert np.max(np.abs(gu.sum(axis=1) - 1.0)) <= 1e-9
+    assert np.max(np.abs(gp.sum(axis=(1, 2)) - 1.0)) <= 1e-9
+    rng = np.random.default_rng(L)
+    bad = []
+    for arr, g, count in ((model.unaries, gu, 8), (model.pairwise, gp, 8)):
+        for _ in range(count):
+            idx = tuple(int(rng.integers(0, d)) for d in arr.shape)
+            du = np.zeros(model.unaries.shape)
+            dp = np.zeros(model.pairwise.shape)
+            (du if arr is model.unaries else dp)[idx] = 1.0
+            fd = _fd(model, K, du, dp, 1e-7)
+            if abs(g[idx] - fd) > 1e-6 * max(1.0, abs(fd)):
+                bad.append((idx, float(g[idx]), fd))
+    assert len(bad) <= 1, bad

@@ -301,6 +301,28 @@ def test_edges_of_a_matching_commute():
     assert np.array_equal(a.Tu, b.Tu) and np.array_equal(a.Te, b.Te)
 
 
+@pytest.mark.parametrize("rule", ["H", "M", "U"])
+def test_dual_moves_by_a_constant_added_to_one_node_or_edge(rule):
+    """Adding c to every label of one node's unary, or to every entry of one
+    edge's table, adds c to the energy of every labelling; every update
+    (Sec. 4) passes such a uniform shift through without moving an argmin,
+    so the dual after K iterations moves by exactly c (up to the rounding of
+    the sums).  A dropped or doubled half in an update breaks this."""
+    m = W.uniform(7, 5, seed=11, dtype=np.float64)
+    c = 0.375
+    d0 = oracle.dual_after(m, 3, rule=rule)
+    for u in range(m.n):
+        du = np.zeros_like(m.unaries)
+        du[u] = c
+        mu = W.Model(m.n, m.L, m.edges, m.unaries + du, m.pairwise)
+        assert abs(oracle.dual_after(mu, 3, rule=rule) - (d0 + c)) <= 1e-12 * max(1.0, abs(d0))
+    for e in range(0, m.m, 4):
+        dp = np.zeros_like(m.pairwise)
+        dp[e] = c
+        me = W.Model(m.n, m.L, m.edges, m.unaries, m.pairwise + dp)
+        assert abs(oracle.dual_after(me, 3, rule=rule) - (d0 + c)) <= 1e-12 * max(1.0, abs(d0))
+
+
 def test_threads_do_not_change_results():
     m = W.uniform(24, 5, seed=2, dtype=np.float64)
     a = oracle.State(m)
