@@ -186,7 +186,7 @@ def test_autograd_function():
     loss = mplp_dual(un, pw, model.edges, K=6, every=3)
     (2.0 * loss).backward()
     l2, gu, gp = _grad(model, 6, 3)
-    assert float(loss) == np.float32(l2)
+    assert float(loss.detach()) == np.float32(l2)
     assert np.array_equal(un.grad.cpu().numpy(), 2.0 * gu)
     assert np.array_equal(pw.grad.cpu().numpy(), 2.0 * gp)
 
