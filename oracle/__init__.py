@@ -18,7 +18,11 @@ ECCV 2018):
 * ``energy``        the energy of Eq. (1);
 * ``bruteforce``    exhaustive MAP (the argmin of Eq. (1));
 * ``dual_after``    D after K iterations as a function of the input costs,
-                    for finite differences.
+                    for finite differences;
+* ``dual_derivative`` the directional derivative of that function, by
+                    forward-mode differentiation of the (H) iterations
+                    (minima take the derivative of their lowest-index
+                    minimizer).
 """
 from __future__ import annotations
 
@@ -79,6 +83,10 @@ def _load():
         lib.orc_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, _i32p, ctypes.c_int, _i32p, _i32p,
                                 _f64p, _f64p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int]
         lib.orc_run.restype = ctypes.c_int
+        lib.orc_run_tangent.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, _i32p, ctypes.c_int, _i32p,
+                                        _i32p, _f64p, _f64p, _f64p, _f64p, ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_double), ctypes.c_int]
+        lib.orc_run_tangent.restype = ctypes.c_int
         lib.orc_decode.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, _i32p, _f64p, _f64p, _i32p]
         lib.orc_decode.restype = ctypes.c_int
         lib.orc_energy.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, _i32p, _f64p, _f64p, _i32p]
@@ -167,6 +175,7 @@ class State:
     def __init__(self, model, step_ptr=None, order=None, schedule_kind="greedy"):
         self.n = int(model.n)
         self.L = int(model.L)
+        self._edges_in = _i32(model.edges).reshape(-1, 2)
         self.edges, self.pairwise = canonicalize(self.n, self.L, model.edges, model.unaries, model.pairwise)
         self.unaries = _f64(model.unaries).reshape(self.n, self.L).copy()
         self.m = int(self.edges.shape[0])
@@ -194,6 +203,22 @@ class State:
 
     def dual(self):
         return dual(self.Tu, self.Te)
+
+    def run_tangent(self, iters, du, dp, nthreads=1):
+        """Runs ``iters`` (H) iterations (bitwise as ``run``) carrying the
+        derivative of the state along the direction (du [n][L], dp [m][L][L]
+        in the model's edge order and orientation); returns the derivative
+        of D (Eq. 3) after them."""
+        lib = _load()
+        _, dTe = canonicalize(self.n, self.L, self._edges_in, _f64(du), _f64(dp))
+        dTu = _f64(du).reshape(self.n, self.L).copy()
+        out = ctypes.c_double(0.0)
+        rc = lib.orc_run_tangent(self.n, self.L, self.m, self.edges, self.n_steps, self.step_ptr, self.order,
+                                 self.Tu, self.Te, dTu, dTe, int(iters), ctypes.byref(out), int(nthreads))
+        if rc != 0:
+            raise OracleError(f"tangent run failed (code {rc})")
+        self.iterations += iters
+        return float(out.value)
 
     def decode(self):
         lib = _load()
@@ -241,6 +266,15 @@ def dual_after(model, iters, rule="H", nthreads=1):
     st = State(model)
     st.run(iters, rule=rule, nthreads=nthreads)
     return st.dual()
+
+
+def dual_derivative(model, iters, du, dp, nthreads=1):
+    """Directional derivative of ``dual_after(model, iters)`` (rule (H))
+    along (du, dp) (arrays shaped like the model's unaries and pairwise
+    costs), exact for the linear piece that the run's minimizers select
+    (lowest index on ties)."""
+    st = State(model)
+    return st.run_tangent(iters, du, dp, nthreads=nthreads)
 
 
 def max_threads():

@@ -471,6 +471,128 @@ int orc_run(int n, int L, int64_t m, const int32_t* edges, int S, const int32_t*
 }
 
 /* ------------------------------------------------------------------ */
+/* Directional derivative of the dual after K iterations (not in the    */
+/* paper; the reference for the adjoint).  D_K is piecewise linear in   */
+/* the input costs: every quantity of (H) is a sum, a difference, a     */
+/* half or a minimum of earlier ones.  Forward-mode differentiation     */
+/* carries, next to each value x of the run, its derivative dx along a  */
+/* direction (du on the unaries, dp on the tables): sums and halves     */
+/* pass derivatives through, and a minimum takes the derivative of the  */
+/* entry that attains it, the lowest index on ties.  The values are     */
+/* computed by the same operations as update_edge, so the run is        */
+/* bitwise the plain one.                                               */
+/* ------------------------------------------------------------------ */
+
+/* (H) on one edge with derivatives: g and dg are the aggregated cost and
+ * its derivative; hu, hv, dhu, dhv the new unaries and their derivatives. */
+static void update_edge_tangent(int L, double* Te, double* Tu_u, double* Tu_v, double* dTe, double* dTu_u,
+                                double* dTu_v, double* g, double* dg, double* hu, double* hv, double* dhu,
+                                double* dhv) {
+    aggregate(L, Te, Tu_u, Tu_v, g);
+    aggregate(L, dTe, dTu_u, dTu_v, dg);
+    /* MPLP halves: hu(s) = min_t g(s,t) / 2, hv(t) = min_s g(s,t) / 2 */
+    for (int s = 0; s < L; ++s) {
+        double mn = INFINITY, best = INFINITY;
+        int at = 0;
+        for (int t = 0; t < L; ++t) {
+            double x = g[(size_t)s * L + t];
+            mn = fmin(mn, x);
+            if (x < best) { best = x; at = t; }
+        }
+        hu[s] = 0.5 * mn;
+        dhu[s] = 0.5 * dg[(size_t)s * L + at];
+    }
+    for (int t = 0; t < L; ++t) {
+        double mn = INFINITY, best = INFINITY;
+        int at = 0;
+        for (int s = 0; s < L; ++s) {
+            double x = g[(size_t)s * L + t];
+            mn = fmin(mn, x);
+            if (x < best) { best = x; at = s; }
+        }
+        hv[t] = 0.5 * mn;
+        dhv[t] = 0.5 * dg[(size_t)at * L + t];
+    }
+    /* second line of (H): hv(t) += min_s [g(s,t) - hv(t) - hu(s)]; the
+     * derivative of the sum is dg(s*,t) - dhu(s*), the old dhv cancels */
+    for (int t = 0; t < L; ++t) {
+        double mn = INFINITY, best = INFINITY;
+        int at = 0;
+        for (int s = 0; s < L; ++s) {
+            double x = g[(size_t)s * L + t] - hv[t] - hu[s];
+            mn = fmin(mn, x);
+            if (x < best) { best = x; at = s; }
+        }
+        dhv[t] = dhv[t] + (dg[(size_t)at * L + t] - dhv[t] - dhu[at]);
+        hv[t] = hv[t] + mn;
+    }
+    /* third line: hu(s) += min_t [g(s,t) - hv(t) - hu(s)] with the new hv */
+    for (int s = 0; s < L; ++s) {
+        double mn = INFINITY, best = INFINITY;
+        int at = 0;
+        for (int t = 0; t < L; ++t) {
+            double x = g[(size_t)s * L + t] - hv[t] - hu[s];
+            mn = fmin(mn, x);
+            if (x < best) { best = x; at = t; }
+        }
+        dhu[s] = dhu[s] + (dg[(size_t)s * L + at] - dhv[at] - dhu[s]);
+        hu[s] = hu[s] + mn;
+    }
+    write_back(L, Te, Tu_u, Tu_v, g, hu, hv);
+    write_back(L, dTe, dTu_u, dTu_v, dg, dhu, dhv);
+}
+
+/* Runs `iters` (H) iterations like orc_run, carrying the derivatives dTu
+ * [n][L] and dTe [m][L][L] (on entry: the direction, tables oriented as Te),
+ * and writes to *dD the derivative of D_K = sum_u min_s Tu(u, s) + sum_e
+ * min Te(e): each node term contributes dTu at its minimizing label (lowest
+ * on ties).  The edge terms contribute nothing: after an edge's (H) update
+ * every row minimum of its reparametrized table is zero (Sec. 4, after (H)),
+ * for any input, so for iters >= 1 each edge term is identically zero as a
+ * function of the costs. */
+int orc_run_tangent(int n, int L, int64_t m, const int32_t* edges, int S, const int32_t* step_ptr,
+                    const int32_t* order, double* Tu, double* Te, double* dTu, double* dTe, int iters,
+                    double* dD, int nthreads) {
+    if (n < 1 || L < 1 || m < 0 || iters < 0 || !dD) return ORC_EINVAL;
+    if (nthreads < 1) nthreads = 1;
+    size_t per = 2 * (size_t)L * L + 4 * (size_t)L;
+    double* scratch = (double*)malloc(sizeof(double) * per * (size_t)nthreads);
+    if (!scratch) return ORC_ENOMEM;
+    for (int it = 0; it < iters; ++it) {
+        for (int k = 0; k < S; ++k) {
+            int64_t lo = step_ptr[k], hi = step_ptr[k + 1];
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+#endif
+            for (int64_t i = lo; i < hi; ++i) {
+                int tid = 0;
+#ifdef _OPENMP
+                tid = omp_get_thread_num();
+#endif
+                double* g = scratch + per * (size_t)tid;
+                double* dg = g + (size_t)L * L;
+                double* h = dg + (size_t)L * L;
+                int32_t e = order[i];
+                int u = edges[2 * e], v = edges[2 * e + 1];
+                update_edge_tangent(L, Te + (size_t)e * L * L, Tu + (size_t)u * L, Tu + (size_t)v * L,
+                                    dTe + (size_t)e * L * L, dTu + (size_t)u * L, dTu + (size_t)v * L, g, dg, h,
+                                    h + L, h + 2 * L, h + 3 * L);
+            }
+        }
+    }
+    double d = 0.0;
+    for (int u = 0; u < n; ++u) {
+        int at = 0;
+        for (int s = 1; s < L; ++s)
+            if (Tu[(size_t)u * L + s] < Tu[(size_t)u * L + at]) at = s;
+        d += dTu[(size_t)u * L + at];
+    }
+    *dD = d;
+    free(scratch);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
 /* Primal rounding, Eq. (5), and energy, Eq. (1).                       */
 /* ------------------------------------------------------------------ */
 

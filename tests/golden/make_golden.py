@@ -15,9 +15,10 @@ Outputs (JSON, one file per workload):
                             colouring) at 1/5/25/50 % density: schedule
                             sizes and 30-iteration dual traces
   batched_mix_samples.json  100-iteration traces of 8 models of the 256-model mix
-  adjoint_uniform_k100_l32.json  central and one-sided differences of D_50
-                            along seeded dense and sparse directions and
-                            coordinates, three step sizes each
+  adjoint_uniform_k100_l32.json  the oracle's derivative of D_50 along seeded
+                            dense and sparse directions and coordinates,
+                            and finite differences (four step sizes) along
+                            the sparse directions and coordinates
 """
 import json
 import os
@@ -131,29 +132,63 @@ def adjoint_sparse_directions(model, count, seed, support=32):
     return out
 
 
-def adjoint_coords(model, count, seed):
-    """Coordinates: a third unary entries, the rest pairwise entries."""
+def adjoint_coords(model, final_Tu, final_Te, count, seed):
+    """Coordinates (flat indices into unaries then pairwise; edges u < v):
+    the gradient of D_K is sparse, so three quarters sit where it is likely
+    nonzero and one quarter anywhere.  Half unary: a node's final minimizing
+    label s*_u.  Half pairwise: the zero of row s*_u of an edge's final
+    reparametrized table, or the zero of its column s*_v (the entries the
+    last passes through that table selected)."""
     rng = np.random.default_rng(seed)
+    n, L = model.n, model.L
     nu = model.unaries.size
-    cu = rng.choice(nu, size=count // 3, replace=False)
-    cp = nu + rng.choice(model.pairwise.size, size=count - count // 3, replace=False)
-    return [int(c) for c in np.concatenate([cu, cp])]
+    best = np.argmin(final_Tu, axis=1)
+    q = count // 4
+    half = count // 2
+    nodes = rng.choice(n, size=min(n, half - q // 2), replace=False)
+    cu = [int(u * L + best[u]) for u in nodes] + [int(c) for c in rng.choice(nu, size=q // 2, replace=False)]
+    cp = []
+    for k, e in enumerate(rng.choice(model.m, size=min(model.m, half - q // 2), replace=False)):
+        u, v = model.edges[e]
+        if k % 2 == 0:
+            s, t = best[u], int(np.argmin(final_Te[e, best[u], :]))
+        else:
+            s, t = int(np.argmin(final_Te[e, :, best[v]])), best[v]
+        cp.append(int(nu + (e * L + s) * L + t))
+    cp += [int(nu + c) for c in rng.choice(model.pairwise.size, size=q // 2, replace=False)]
+    return cu + cp
+
+
+def coord_direction(model, c):
+    du = np.zeros_like(model.unaries)
+    dp = np.zeros_like(model.pairwise)
+    if c < model.unaries.size:
+        du.flat[c] = 1.0
+    else:
+        dp.flat[c - model.unaries.size] = 1.0
+    return du, dp
 
 
 def make_adjoint():
-    """D_K is piecewise linear in the costs with kinks at every scale along a
-    generic direction, so each check stores, for several step sizes h, the
-    central difference and both one-sided differences."""
+    """Reference derivatives of D_50 on the differentiation workload: the
+    oracle's forward-mode derivative along 16 dense and 16 sparse seeded
+    directions and 64 coordinates.  For the sparse directions and the
+    coordinates also central and one-sided differences of the oracle's D_50
+    at four step sizes (D_K is piecewise linear: where the one-sided
+    differences agree the step stayed inside one linear piece)."""
     K, every = 50, 10
     model = W.uniform(100, 32, seed=0)
     base = model.astype(np.float64)
-    nu = base.unaries.size
+    st = oracle.State(base)
+    st.run(K, nthreads=THREADS)
+    D0 = st.dual()
 
     def D(du, dp):
         mo = W.Model(base.n, base.L, base.edges, base.unaries + du, base.pairwise + dp)
         return oracle.dual_after(mo, K, nthreads=THREADS)
 
-    D0 = D(0.0, 0.0)
+    def tangent(du, dp):
+        return oracle.dual_derivative(base, K, du, dp, nthreads=THREADS)
 
     def diffs(du, dp, hs):
         rows = []
@@ -162,24 +197,23 @@ def make_adjoint():
             rows.append({"h": h, "central": (p - m) / (2 * h), "right": (p - D0) / h, "left": (D0 - m) / h})
         return rows
 
+    hs = (1e-5, 1e-6, 1e-7, 1e-8)
     out = {"workload": "uniform n=100 L=32 seed=0 (FP32 inputs promoted to FP64)", "K": K, "every": every, "D": D0,
-           "dense": {"seed": 7, "count": 8, "fd": []}, "sparse": {"seed": 9, "count": 8, "support": 32, "fd": []},
-           "coords": {"seed": 11, "count": 24, "index": [], "fd": []}}
-    for du, dp in adjoint_directions(base, 8, 7):
-        out["dense"]["fd"].append(diffs(du, dp, (1e-7, 1e-8, 1e-9)))
+           "dense": {"seed": 7, "count": 16, "tangent": []},
+           "sparse": {"seed": 9, "count": 16, "support": 32, "tangent": [], "fd": []},
+           "coords": {"seed": 11, "count": 64, "index": [], "tangent": [], "fd": []}}
+    for du, dp in adjoint_directions(base, 16, 7):
+        out["dense"]["tangent"].append(tangent(du, dp))
     print("dense directions", flush=True)
-    for du, dp in adjoint_sparse_directions(base, 8, 9):
-        out["sparse"]["fd"].append(diffs(du, dp, (1e-6, 1e-7, 1e-8)))
+    for du, dp in adjoint_sparse_directions(base, 16, 9):
+        out["sparse"]["tangent"].append(tangent(du, dp))
+        out["sparse"]["fd"].append(diffs(du, dp, hs))
     print("sparse directions", flush=True)
-    for c in adjoint_coords(base, 24, 11):
-        du = np.zeros_like(base.unaries)
-        dp = np.zeros_like(base.pairwise)
-        if c < nu:
-            du.flat[c] = 1.0
-        else:
-            dp.flat[c - nu] = 1.0
+    for c in adjoint_coords(base, st.Tu, st.Te, 64, 11):
+        du, dp = coord_direction(base, c)
         out["coords"]["index"].append(c)
-        out["coords"]["fd"].append(diffs(du, dp, (1e-6, 1e-7, 1e-8)))
+        out["coords"]["tangent"].append(tangent(du, dp))
+        out["coords"]["fd"].append(diffs(du, dp, hs))
     print("coordinates", flush=True)
     dump("adjoint_uniform_k100_l32.json", out)
 

@@ -21,8 +21,8 @@ MUTANTS = [
     ("mplp half dropped on v", "hv[t] = 0.5 * mn;\n    }\n}", "hv[t] = mn;\n    }\n}"),
     ("row min instead of column min", "for (int s = 0; s < L; ++s) mn = fmin(mn, g[(size_t)s * L + t]);\n        hv[t] = 0.5",
      "for (int s = 0; s < L; ++s) mn = fmin(mn, g[(size_t)t * L + s]);\n        hv[t] = 0.5"),
-    ("v correction drops its base", "hv[t] = hv[t] + mn;", "hv[t] = mn;"),
-    ("u correction drops its base", "hu[s] = hu[s] + mn;", "hu[s] = mn;"),
+    ("v correction drops its base", "                hv[t] = hv[t] + mn;", "                hv[t] = mn;"),
+    ("u correction drops its base", "                hu[s] = hu[s] + mn;", "                hu[s] = mn;"),
     ("u corrected before v", "/* (H), second line", "/* (H), second line */ for (int s = 0; s < L; ++s) { double mn = INFINITY; for (int t = 0; t < L; ++t) mn = fmin(mn, g[(size_t)s * L + t] - hv[t] - hu[s]); hu[s] = hu[s] + mn; } /*"),
     ("wrong sign in write back", "- hu[s] - hv[t];", "- hu[s] + hv[t];"),
     ("wrong index in aggregate", "+ Tu_u[s] + Tu_v[t];", "+ Tu_u[s] + Tu_v[s];"),
@@ -48,6 +48,14 @@ MUTANTS = [
     ("colouring: no path swap", "for (int i = 0; i + 1 < np; ++i) paint(k, path[i], path[i + 1], was[i] == c ? d : c);",
      "for (int i = 0; i + 1 < np; ++i) paint(k, path[i], path[i + 1], was[i]);"),
     ("colouring: fan not rotated", "        paint(k, u, fan[i], cn);\n", "        paint(k, u, fan[i + 1], cn);\n"),
+    ("tangent: MPLP half of u not halved", "dhu[s] = 0.5 * dg[(size_t)s * L + at];", "dhu[s] = dg[(size_t)s * L + at];"),
+    ("tangent: second line drops u's half", "- dhv[t] - dhu[at]);", "- dhv[t]);"),
+    ("tangent: third line reads v at the wrong label", "dg[(size_t)s * L + at] - dhv[at] - dhu[s]",
+     "dg[(size_t)s * L + at] - dhv[s] - dhu[s]"),
+    ("tangent: aggregate misses v", "aggregate(L, dTe, dTu_u, dTu_v, dg);", "aggregate(L, dTe, dTu_u, dTu_u, dg);"),
+    ("tangent: tables not carried", "    write_back(L, dTe, dTu_u, dTu_v, dg, dhu, dhv);\n",
+     "    for (int s = 0; s < L; ++s) { dTu_u[s] = dhu[s]; dTu_v[s] = dhv[s]; }\n"),
+    ("tangent: node term at label 0", "d += dTu[(size_t)u * L + at];", "d += dTu[(size_t)u * L];"),
     ("colouring: largest colour first", "for (int c = 0; c < k->C && !grown; ++c) {", "for (int c = k->C - 1; c >= 0 && !grown; --c) {"),
 ]
 
@@ -65,6 +73,7 @@ def test_pins_catch_mutant(tmp_path, name, old, new):
                     str(c), "-lm"], check=True)
     env = dict(os.environ, MPLP_ORACLE_LIB=str(so))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        "tests/test_oracle_pins.py", "tests/test_oracle_schedule.py"],
+                        "tests/test_oracle_pins.py", "tests/test_oracle_schedule.py",
+                        "tests/test_oracle_derivative.py"],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
     assert r.returncode != 0, f"mutant '{name}' survived every pin:\n{r.stdout[-2000:]}"
