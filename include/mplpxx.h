@@ -132,7 +132,10 @@ int mplpxx_create_potts(int32_t n, int32_t L, int64_t m, const int32_t* edges, c
  * example torch tensor storage) in the same layout; edges stay on the host.
  * The library copies the costs into its own layout before returning, so the
  * device buffers may be reused afterwards.  The copy runs on the stream
- * given (NULL = the default stream). */
+ * given (NULL = the default stream).  Errors: those of mplpxx_create, and
+ * MPLPXX_EINVAL when unaries_dev or pairwise_dev is not device memory of the
+ * current device (checked with hipPointerGetAttributes before any kernel
+ * reads it). */
 int mplpxx_create_device(int32_t n, int32_t L, int64_t m, const int32_t* edges, const void* unaries_dev,
                          const void* pairwise_dev, int32_t dtype, void* hip_stream, mplpxx_solver** out);
 

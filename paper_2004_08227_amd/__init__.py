@@ -136,6 +136,29 @@ def schedule(n, edges, kind=0):
     return sp[:S.value + 1].copy(), order[:m].copy()
 
 
+def _check_device_costs(torch, n, L, m, unaries, pairwise):
+    """Argument checks of Solver.from_torch (ValueError, never assert)."""
+    for name, t in (("unaries", unaries), ("pairwise", pairwise)):
+        if not isinstance(t, torch.Tensor):
+            raise ValueError(f"{name} must be a torch tensor")
+        if not t.is_cuda:
+            raise ValueError(f"{name} must be on the GPU (got {t.device})")
+        if t.dtype not in (torch.float32, torch.float64):
+            raise ValueError(f"{name} must be float32 or float64 (got {t.dtype})")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+    if pairwise.dtype != unaries.dtype:
+        raise ValueError(f"unaries and pairwise must share a dtype (got {unaries.dtype}, {pairwise.dtype})")
+    if pairwise.device != unaries.device:
+        raise ValueError(f"unaries and pairwise must be on one device (got {unaries.device}, {pairwise.device})")
+    if unaries.device.index is not None and unaries.device.index != torch.cuda.current_device():
+        raise ValueError(f"the tensors must be on the current device cuda:{torch.cuda.current_device()}")
+    if tuple(unaries.shape) != (n, L):
+        raise ValueError(f"unaries must have shape ({n}, {L}), got {tuple(unaries.shape)}")
+    if tuple(pairwise.shape) != (m, L, L):
+        raise ValueError(f"pairwise must have shape ({m}, {L}, {L}), got {tuple(pairwise.shape)}")
+
+
 class Solver:
     """One model: ``Solver(n, L, edges, unaries, pairwise)`` with host numpy
     arrays (float32 or float64), or ``Solver.from_torch`` with device tensors."""
@@ -188,13 +211,14 @@ class Solver:
     @classmethod
     def from_torch(cls, n, L, edges, unaries, pairwise, stream=None):
         """unaries [n, L] and pairwise [m, L, L]: contiguous float32/float64
-        torch tensors on the GPU; edges: host int32 [m, 2]."""
-        import torch  # noqa: F401  (device memory and streams only)
+        torch tensors of one dtype on the current GPU; edges: host int32
+        [m, 2].  Raises ValueError before any library call otherwise (a
+        host pointer handed to the device copy would fault the GPU)."""
+        import torch  # (device memory and streams only)
         edges = np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
         m = edges.shape[0]
-        assert unaries.is_cuda and unaries.is_contiguous() and pairwise.is_contiguous()
-        assert unaries.numel() == n * L and pairwise.numel() == m * L * L
-        dt = F32 if str(unaries.dtype) == "torch.float32" else F64
+        _check_device_costs(torch, int(n), int(L), m, unaries, pairwise)
+        dt = F32 if unaries.dtype == torch.float32 else F64
         h = ctypes.c_void_p()
         st = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
         _check(lib().mplpxx_create_device(int(n), int(L), int(m), _ptr(edges) if m else None,

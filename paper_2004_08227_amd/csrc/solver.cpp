@@ -193,6 +193,17 @@ int prepare_solver_graph(mplpxx_solver* h, const int32_t* edges) {
   return MPLPXX_OK;
 }
 
+// True when p is device memory of device dev (a host or foreign pointer
+// handed to a kernel would fault the GPU instead of failing the call).
+bool is_device_memory(const void* p, int dev) {
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return (a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged) && a.device == dev;
+}
+
 int create_impl(int32_t n, int32_t L, int64_t m, const int32_t* edges, const void* unaries, const void* pairwise,
                 int32_t dtype, bool device_costs, hipStream_t copy_stream, mplpxx_solver** out,
                 int32_t sched = MPLPXX_SCHED_AUTO, bool potts = false) {
@@ -250,6 +261,10 @@ int create_impl(int32_t n, int32_t L, int64_t m, const int32_t* edges, const voi
   } while (0)
   int dev = 0;
   TRY(hipGetDevice(&dev));
+  if (device_costs && (!is_device_memory(unaries, dev) || (m > 0 && !is_device_memory(pairwise, dev)))) {
+    fail(MPLPXX_EINVAL, "unaries/pairwise must be device memory of the current device %d", dev);
+    return bail(MPLPXX_EINVAL);
+  }
   TRY(hipDeviceGetAttribute(&h->num_cus, hipDeviceAttributeMultiprocessorCount, dev));
   TRY(hipDeviceGetAttribute(&h->wallclock_khz, hipDeviceAttributeWallClockRate, dev));
   TRY(hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking));

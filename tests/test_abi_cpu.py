@@ -218,3 +218,20 @@ def test_potts_solver_inputs_rejected_without_device_work(case):
     with pytest.raises(M.MplpError) as ei:
         M.Solver.from_potts(bad)
     assert ei.value.code == M.EINVAL
+
+
+def test_from_torch_rejects_host_tensors_before_any_library_call(monkeypatch):
+    """Solver.from_torch hands raw tensor pointers to the device copy, so it
+    raises ValueError (not an assert) for tensors that are not CUDA tensors,
+    and the library is never reached."""
+    import torch
+    called = []
+    monkeypatch.setattr(M, "lib", lambda: called.append(1))
+    model = W.uniform(4, 3, seed=0)
+    un = torch.from_numpy(model.unaries)
+    pw = torch.from_numpy(model.pairwise)
+    with pytest.raises(ValueError):
+        M.Solver.from_torch(model.n, model.L, model.edges, un, pw)
+    with pytest.raises(ValueError):
+        M.Solver.from_torch(model.n, model.L, model.edges, model.unaries, model.pairwise)
+    assert not called

@@ -183,6 +183,31 @@ def test_reversed_edges_and_device_create():
     assert np.array_equal(Ua, Uc) and np.array_equal(pa, pc)
 
 
+def test_device_create_rejects_bad_tensors_and_host_pointers():
+    """from_torch raises ValueError for a host pairwise next to GPU unaries,
+    mixed dtypes and wrong shapes; mplpxx_create_device itself returns
+    MPLPXX_EINVAL for a host pointer (hipPointerGetAttributes), before any
+    kernel could read it."""
+    import ctypes
+    import torch
+    _announce("device create checks")
+    model = W.pose(8, 5, seed=3)
+    un = torch.from_numpy(model.unaries).cuda()
+    pw = torch.from_numpy(model.pairwise).cuda()
+    for bad_un, bad_pw in ((un, pw.cpu()), (un, pw.double()), (un.double(), pw), (un[:, :4].contiguous(), pw),
+                           (un, pw.transpose(1, 2))):
+        with pytest.raises(ValueError):
+            M.Solver.from_torch(model.n, model.L, model.edges, bad_un, bad_pw)
+    h = ctypes.c_void_p()
+    host_pw = np.ascontiguousarray(model.pairwise)
+    rc = M.lib().mplpxx_create_device(model.n, model.L, model.m, model.edges.ctypes.data_as(ctypes.c_void_p),
+                                      ctypes.c_void_p(un.data_ptr()), host_pw.ctypes.data_as(ctypes.c_void_p),
+                                      M.F32, None, ctypes.byref(h))
+    assert rc == M.EINVAL and not h.value
+    with M.Solver.from_torch(model.n, model.L, model.edges, un, pw) as s:
+        s.iterate(2)
+
+
 def test_degenerate_models():
     _announce("degenerate")
     # single node, no edges
