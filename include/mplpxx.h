@@ -324,6 +324,46 @@ int mplpxx_adjoint_forward(mplpxx_solver* h, int32_t K, int32_t every, double* l
 int mplpxx_adjoint_backward(mplpxx_solver* h, void* grad_unaries, void* grad_pairwise);
 
 /* ------------------------------------------------------------------------
+ * Solving without device allocation.
+ * --------------------------------------------------------------------- */
+
+/* Working memory of mplpxx_solve_noalloc, in MiB: one static device array
+ * per GPU, held by each GPU the library runs on until the process ends. */
+#define MPLPXX_NOALLOC_SCRATCH_MB 64
+
+/* For callers that cannot allocate device memory (code under stream or graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the work of
+ * mplpxx_create_device + mplpxx_iterate(iters) + mplpxx_dual_bound + reading
+ * the state, in one call that allocates nothing on the device.  Its working
+ * memory (tables packed in schedule order, messages, mailboxes, schedule
+ * metadata, reduction buffers) lives in a static device array of
+ * MPLPXX_NOALLOC_SCRATCH_MB MiB per GPU; the results are bitwise those of the
+ * allocating calls on the same FP32 model (default schedule, engine and
+ * launch shape).
+ *   edges        HOST int32 [m][2], as for mplpxx_create (any orientation);
+ *   unaries_dev  DEVICE float [n][L], pairwise_dev DEVICE float [m][L][L]
+ *                (read only; layouts of mplpxx_create);
+ *   U_dev        DEVICE float [n][L], out: the reparametrized unaries U after
+ *                `iters` >= 0 iterations (as mplpxx_get_state's U);
+ *   phi_dev      DEVICE float [m][2][L], out: the messages in edge order (as
+ *                mplpxx_get_state's phi);
+ *   dual         HOST double, out (may be NULL): Eq. (3) of that state, as
+ *                mplpxx_dual_bound;
+ *   hip_stream   the stream the work is queued on (NULL = the default
+ *                stream); the call returns after it is done.
+ * All device buffers must be memory of the current device.  Errors:
+ * MPLPXX_EINVAL for the model errors of mplpxx_create, non-device buffers,
+ * a node degree >= 65536, or a model whose working memory exceeds the array
+ * (the message names the size needed; the pose workload n = 200, L = 64 does
+ * not fit, n = 100, L = 32 does); MPLPXX_ETIMEOUT, MPLPXX_EDEVICE.  Calls on
+ * one GPU share its array and must not overlap (one at a time per GPU, from
+ * any thread or stream); the array keeps the last call's contents and every
+ * call clears what it needs cleared. */
+int mplpxx_solve_noalloc(int32_t n, int32_t L, int64_t m, const int32_t* edges, const float* unaries_dev,
+                         const float* pairwise_dev, int32_t iters, float* U_dev, float* phi_dev, double* dual,
+                         void* hip_stream);
+
+/* ------------------------------------------------------------------------
  * Batched solving: many independent FP32 models in one persistent launch.
  * --------------------------------------------------------------------- */
 

@@ -105,6 +105,7 @@ def lib():
         "mplpxx_batch_get_info": (ctypes.c_int, [vp, i32, ctypes.POINTER(dbl)]),
         "mplpxx_batch_wg_profile": (ctypes.c_int, [vp, vp, vp]),
         "mplpxx_batch_destroy": (None, [vp]),
+        "mplpxx_solve_noalloc": (ctypes.c_int, [i32, i32, i64, vp, vp, vp, i32, vp, vp, ctypes.POINTER(dbl), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -342,6 +343,32 @@ class Solver:
         d = ctypes.c_double()
         _check(lib().mplpxx_last_iterate_ms(self._h, ctypes.byref(d)))
         return d.value
+
+
+def solve_noalloc(edges, unaries, pairwise, iters, U_out, phi_out, stream=None):
+    """``mplpxx_solve_noalloc``: `iters` iterations from phi = 0 of the FP32
+    model (unaries [n, L], pairwise [m, L, L] float32 CUDA tensors; edges host
+    int32 [m, 2]) with no device allocation; writes U [n, L] and phi
+    [m, 2, L] into the float32 CUDA tensors U_out, phi_out and returns the
+    dual bound of Eq. (3)."""
+    import torch  # (device memory and streams only)
+    edges = np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
+    m = edges.shape[0]
+    n, L = (int(x) for x in unaries.shape)
+    _check_device_costs(torch, n, L, m, unaries, pairwise)
+    for name, t, shape in (("U_out", U_out, (n, L)), ("phi_out", phi_out, (m, 2, L))):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+                and tuple(t.shape) == shape and t.device == unaries.device):
+            raise ValueError(f"{name} must be a contiguous float32 tensor of shape {shape} on {unaries.device}")
+    if unaries.dtype != torch.float32:
+        raise ValueError("solve_noalloc takes float32 costs")
+    d = ctypes.c_double()
+    st = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
+    _check(lib().mplpxx_solve_noalloc(n, L, m, _ptr(edges) if m else None, ctypes.c_void_p(unaries.data_ptr()),
+                                      ctypes.c_void_p(pairwise.data_ptr()) if m else None, int(iters),
+                                      ctypes.c_void_p(U_out.data_ptr()), ctypes.c_void_p(phi_out.data_ptr()) if m else None,
+                                      ctypes.byref(d), st))
+    return d.value
 
 
 class Batch:

@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmplpxx.so")
 
 SOURCES = ["solver.cpp", "batch.cpp", "schedule.cpp", "handshake.hip", "dual.hip", "batch.hip", "adjoint.hip",
-           "rules.hip"]
+           "rules.hip", "noalloc.hip"]
 ARCH = os.environ.get("MPLPXX_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
