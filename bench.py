@@ -422,6 +422,42 @@ def bench_adjoint(M, W, K=50, every=10):
     return out
 
 
+def loaded_runtimes():
+    """Paths of the HIP and HSA runtime libraries mapped into this process."""
+    out = set()
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                path = line.split()[-1] if len(line.split()) >= 6 else ""
+                if "libamdhip64" in path or "libhsa-runtime64" in path:
+                    out.add(path)
+    except OSError:
+        pass
+    return sorted(out)
+
+
+def kernel_only(steps, warmup):
+    """The C1 launch alone, without PyTorch, on the library build linked
+    against /opt/rocm's HIP runtime: the process for rocprofv3 runs (whose
+    tool library loads /opt/rocm's HSA runtime; PyTorch's bundled HIP
+    runtime next to it would add a second HSA runtime to the process)."""
+    os.environ["MPLPXX_RUNTIME"] = "rocm"
+    import paper_2004_08227_amd as M
+    from paper_2004_08227_amd import workloads as W
+    model = W.pose(200, 64, seed=0)
+    with M.Solver.from_model(model) as s:
+        U0, phi0 = s.get_state()
+        if warmup:
+            s.iterate(warmup)
+        s.set_state(U0, phi0)
+        s.iterate(steps)
+        ms = s.last_iterate_ms()
+        d = s.dual_bound()
+        print(json.dumps({"kernel_only": "pose_k200_l64", "steps": steps, "ms_per_step": ms / steps, "dual_bound": d,
+                          "hbm_frac": model.m * steps * algorithmic_bytes_per_update(64) / (ms / 1e3) / 1e9 /
+                          HBM_PEAK_GBS, "runtimes": loaded_runtimes()}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -442,6 +478,8 @@ def main():
     ap.add_argument("--only-batch", action="store_true", help="run only the batched-mix section")
     ap.add_argument("--no-per-problem", action="store_true",
                     help="batched section without the per-problem comparison runs")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="only the timed pose n=200/L=64 launch, without PyTorch (for rocprofv3 runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only a 3 x 1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -451,6 +489,9 @@ def main():
 
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.kernel_only:
+        kernel_only(args.steps, args.warmup)
         return
 
     import torch

@@ -11,14 +11,19 @@ for Dense Graphical Models", ECCV 2018.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 import re
+import weakref
 
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmplpxx.so")
+# MPLPXX_RUNTIME=rocm: the build linked against /opt/rocm's HIP runtime, and
+# no PyTorch (for profiling under rocprofv3: one HIP/HSA runtime per process)
+ROCM_ONLY = os.environ.get("MPLPXX_RUNTIME") == "rocm"
+LIB_PATH = os.path.join(_HERE, "libmplpxx_rocm.so" if ROCM_ONLY else "libmplpxx.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "mplpxx.h")
 
 F32, F64 = 0, 1
@@ -39,6 +44,19 @@ INFO = {"n": 1, "L": 2, "m": 3, "steps": 4, "dtype": 5, "engine": 6, "grid": 7, 
         "wallclock_khz": 10, "adjoint_bytes": 11}
 
 _lib = None
+# open handles; closed by an exit hook before the interpreter shuts down, so
+# that no handle is freed by a finalizer after the HIP runtime has begun its
+# own teardown
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_handles():
+    for obj in list(_LIVE):
+        try:
+            obj.close()
+        except Exception:
+            pass
 
 
 class MplpError(RuntimeError):
@@ -61,12 +79,14 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build() "
                            "or python paper_2004_08227_amd/build.py")
-    try:
-        # load PyTorch's HIP runtime first: the library then binds to the same
-        # runtime (same soname), so device pointers and streams can be shared
-        import torch  # noqa: F401
-    except ImportError:
-        pass
+    if not ROCM_ONLY:
+        try:
+            # load PyTorch's HIP runtime first: the library then binds to the
+            # same runtime (same soname), so device pointers and streams can
+            # be shared
+            import torch  # noqa: F401
+        except ImportError:
+            pass
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     pp = ctypes.POINTER(ctypes.c_void_p)
@@ -185,6 +205,7 @@ class Solver:
                                              _ptr(pw) if m else None, F32 if dt == np.float32 else F64,
                                              int(schedule), ctypes.byref(h)))
             self._h = h
+        _LIVE.add(self)
         self.n = self.info("n")
         self.L = self.info("L")
         self.m = self.info("m")
@@ -400,6 +421,7 @@ class Batch:
         create = lib().mplpxx_batch_create_potts if potts else lib().mplpxx_batch_create
         _check(create(count, _ptr(self.n), _ptr(self.L), _ptr(self.m), e_ptrs, u_ptrs, p_ptrs, ctypes.byref(h)))
         self._h = h
+        _LIVE.add(self)
         self.count = count
 
     def close(self):

@@ -16,6 +16,11 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmplpxx.so")
+# The same objects linked against /opt/rocm's HIP runtime only, for processes
+# that do not load PyTorch (profiling under rocprofv3, whose tool library
+# brings /opt/rocm's HSA runtime: with PyTorch's bundled HIP runtime next to
+# it the process would hold two HSA runtimes).
+LIB_ROCM = os.path.join(HERE, "libmplpxx_rocm.so")
 
 SOURCES = ["solver.cpp", "batch.cpp", "schedule.cpp", "handshake.hip", "dual.hip", "batch.hip", "adjoint.hip",
            "rules.hip", "noalloc.hip"]
@@ -67,17 +72,22 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     os.makedirs(build_dir, exist_ok=True)
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(lambda src: _compile(src, build_dir, defines), SOURCES))
+    _link(objs, out, hip_runtime_dir())
+    if out == LIB:
+        _link(objs, LIB_ROCM, "/opt/rocm/lib")
+    if verbose:
+        print(f"built {out}")
+    return out
+
+
+def _link(objs, out, rt):
     tmp = out + ".tmp"
-    rt = hip_runtime_dir()
-    cmd = ["g++", "-shared", "-fPIC", "-o", tmp, *objs, f"-L{rt}", "-lamdhip64", f"-Wl,-rpath,{rt}",
-           "-Wl,-rpath,/opt/rocm/lib", "-Wl,--no-undefined"]
+    rpath = [f"-Wl,-rpath,{rt}"] + (["-Wl,-rpath,/opt/rocm/lib"] if rt != "/opt/rocm/lib" else [])
+    cmd = ["g++", "-shared", "-fPIC", "-o", tmp, *objs, f"-L{rt}", "-lamdhip64", *rpath, "-Wl,--no-undefined"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, out)
-    if verbose:
-        print(f"built {out}")
-    return out
 
 
 if __name__ == "__main__":
