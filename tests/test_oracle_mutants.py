@@ -74,6 +74,6 @@ def test_pins_catch_mutant(tmp_path, name, old, new):
     env = dict(os.environ, MPLP_ORACLE_LIB=str(so))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         "tests/test_oracle_pins.py", "tests/test_oracle_schedule.py",
-                        "tests/test_oracle_derivative.py"],
+                        "tests/test_oracle_derivative.py", "tests/test_oracle_plateau.py"],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
     assert r.returncode != 0, f"mutant '{name}' survived every pin:\n{r.stdout[-2000:]}"
