@@ -254,7 +254,7 @@ template <int LT, int NT> struct SmemMB {
   float ul[2][LT];   // lo of U_u
   float vl[2][LT];
   float cc[2][2];    // references c_u, c_v
-  float red[TileShape<float, LT, NT>::W][LT];
+  alignas(16) float red[TileShape<float, LT, NT>::W][LT];
   int abort_flag;
 };
 
@@ -532,13 +532,15 @@ __device__ __forceinline__ bool mb_run(const MbView& v_in, int first_in, int str
         if (lane == 0) {
           // a wait may also end because another workgroup reported first
           if (ld_dev(err) == 0 || seen != (want & 0xFFFFu)) report_timeout(err, slot, node, want & 0xFFFFu, seen);
-          sm.abort_flag = 1;
+          sm.abort_flag = q + 1;  // tagged with the step, so a later step's flag is not taken for this one's
         }
       }
       if (v.stamps && last_iter && lane == 0) v.stamps[(size_t)slot * kStampStride + (is_sync_u ? 1 : 2)] = wall_clock64();
       __syncthreads();
-      if (sm.abort_flag) return false;
       __syncthreads();  // the compute waves' mid-step barrier
+      // (a timed-out wait of this step is seen by every wave after the
+      // mid-step barrier)
+      if (sm.abort_flag == q + 1) return false;
       // per-iteration trace: the first update of a node in iteration it
       // sees the node's value at the end of iteration it-1
       if (TRACE && it > 0) {
@@ -635,7 +637,6 @@ __device__ __forceinline__ bool mb_run(const MbView& v_in, int first_in, int str
     if (v.stamps && last_iter && tid == 0) v.stamps[(size_t)slot * kStampStride + 4] = wall_clock64();
 #endif
     __syncthreads();
-    if (sm.abort_flag) return false;
     if (!PHI_FAR) load_phiset(fc, j);
     pad_tile<LT, NT, FULL>(L, xc);
 #if MPLPXX_FINE_STAMPS
@@ -700,20 +701,31 @@ __device__ __forceinline__ bool mb_run(const MbView& v_in, int first_in, int str
 #if MPLPXX_FINE_STAMPS
     if (v.stamps && last_iter && tid == 0) v.stamps[(size_t)slot * kStampStride + 7] = wall_clock64();
 #endif
+    // The waves' partial column minima, every read issued before the first
+    // use (one LDS round trip), and the abort flag with them.
+    float part[S::W][S::BC], opart[S::W];
+#pragma unroll
+    for (int w = 0; w < S::W; ++w) {
+#pragma unroll
+      for (int jj = 0; jj < S::BC; ++jj) part[w][jj] = sm.red[w][cb * S::BC + jj];
+      opart[w] = sm.red[w][out_ic];
+    }
+    const int aborted = sm.abort_flag;
+    __builtin_amdgcn_sched_barrier(0);
+    if (aborted == q + 1) return false;
 #pragma unroll
     for (int jj = 0; jj < S::BC; ++jj) {
-      const int t = cb * S::BC + jj;
-      float mn = sm.red[0][t];
+      float mn = part[0][jj];
 #pragma unroll
-      for (int w = 1; w < S::W; ++w) mn = vmin(mn, sm.red[w][t]);
+      for (int w = 1; w < S::W; ++w) mn = vmin(mn, part[w][jj]);
       qv[jj] = mn;
     }
     // the output column's message q' + delta, q' reduced the same way
     float omsg;
     {
-      float mn = sm.red[0][out_ic];
+      float mn = opart[0];
 #pragma unroll
-      for (int w = 1; w < S::W; ++w) mn = vmin(mn, sm.red[w][out_ic]);
+      for (int w = 1; w < S::W; ++w) mn = vmin(mn, opart[w]);
       omsg = mn + delta;
     }
     // pass 3: r(s) = min_t [th(s,t) - q(t)]
