@@ -128,6 +128,39 @@ int mplpxx_create_sched(int32_t n, int32_t L, int64_t m, const int32_t* edges, c
 int mplpxx_create_potts(int32_t n, int32_t L, int64_t m, const int32_t* edges, const float* unaries,
                         const float* weights, mplpxx_solver** out);
 
+/* Structured pairwise costs (Sec. 4 notes that for Potts, absolute
+ * difference and similar costs the message-passing minimization takes
+ * O(|Y|) instead of O(|Y|^2)), given by parameters per edge instead of
+ * tables:
+ *   MPLPXX_COST_POTTS         theta_uv(s, t) = w [s != t]; 1 parameter: w
+ *                             (any sign; -0 counts as +0);
+ *   MPLPXX_COST_TRUNC_LINEAR  theta_uv(s, t) = fl(w * min(|s - t|, tau)),
+ *                             the FP32 product; 2 parameters: w >= 0 and
+ *                             tau >= 0 (tau >= L - 1: absolute difference
+ *                             w |s - t|; tau <= 1: Potts with weight
+ *                             fl(w * tau)); symmetric, so the orientation of
+ *                             an edge does not matter. */
+#define MPLPXX_COST_POTTS 1
+#define MPLPXX_COST_TRUNC_LINEAR 2
+
+/* A model with structured pairwise costs of one kind (above): params = HOST
+ * float [m][P] in the order of edges, P = 1 (Potts) or 2 (truncated
+ * linear); unaries as for mplpxx_create (FP32).  Runs on the persistent
+ * mailbox engine with one compute wave per workgroup in label order.  Potts:
+ * as mplpxx_create_potts (bitwise the dense handle on the expanded tables).
+ * Truncated linear: each pass is a min-plus distance transform in O(L) work
+ * and O(log L) steps (prefix and suffix minima of x(t) + w |s - t| by
+ * doubling distances within rows of 16 lanes, carried across rows, then the
+ * truncation at min_t x(t) + fl(w tau)); the sums are formed in a different
+ * order than x(t) + fl(w |s - t|), so results agree with the expanded
+ * tables up to FP32 rounding, not bitwise.  dual_bound, decode,
+ * iterate_gap, get/set_state and the schedule work as for dense handles
+ * (on the expanded costs).  Errors: those of mplpxx_create_potts, and
+ * MPLPXX_EINVAL for an unknown kind or, for truncated linear, w < 0,
+ * tau < 0, a non-finite parameter or fl(w * tau) above MPLPXX_F32_MAX_COST. */
+int mplpxx_create_structured(int32_t n, int32_t L, int64_t m, const int32_t* edges, const float* unaries,
+                             int32_t kind, const float* params, mplpxx_solver** out);
+
 /* Same as mplpxx_create, but unaries and pairwise are DEVICE pointers (for
  * example torch tensor storage) in the same layout; edges stay on the host.
  * The library copies the costs into its own layout before returning, so the
@@ -396,6 +429,15 @@ int mplpxx_batch_create(int32_t count, const int32_t* n, const int32_t* L, const
 int mplpxx_batch_create_potts(int32_t count, const int32_t* n, const int32_t* L, const int64_t* m,
                               const int32_t* const* edges, const float* const* unaries, const float* const* weights,
                               mplpxx_batch** out);
+
+/* A batch of models with structured pairwise costs of one kind
+ * (MPLPXX_COST_*, see mplpxx_create_structured): params[i] = HOST float
+ * [m[i]][P]; everything else as mplpxx_batch_create_potts (wave engine,
+ * L[i] <= 64).  Errors: those of mplpxx_batch_create_potts and the
+ * parameter errors of mplpxx_create_structured, with the model index. */
+int mplpxx_batch_create_structured(int32_t count, const int32_t* n, const int32_t* L, const int64_t* m,
+                                   const int32_t* const* edges, const float* const* unaries, int32_t kind,
+                                   const float* const* params, mplpxx_batch** out);
 
 /* Runs k >= 0 BCA-iterations (Sec. 5) of every model of the batch in one
  * persistent launch (by default replayed from a hipGraph captured for this

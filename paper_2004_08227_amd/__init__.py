@@ -32,6 +32,8 @@ MAX_LABELS = 128
 OPT_ENGINE, OPT_THREADS, OPT_GRID, OPT_SPIN_LIMIT, OPT_PROFILE, OPT_ADJOINT_F64, OPT_RULE = 1, 2, 3, 4, 5, 6, 7
 RULE_H, RULE_M, RULE_U = 0, 1, 2
 SCHED_AUTO, SCHED_GREEDY, SCHED_COLOR = 0, 1, 2
+COST_POTTS, COST_TRUNC_LINEAR = 1, 2
+COST_PARAMS = {COST_POTTS: 1, COST_TRUNC_LINEAR: 2}
 ENGINE_AUTO, ENGINE_STEP, ENGINE_PERSISTENT = 0, 1, 2
 BOPT = {"grid": 1, "graph": 2, "spin_limit": 3, "one_per_model": 4, "handoff_us": 5, "edge16_us": 6,
         "edge32_us": 7, "edge64_us": 8, "edge128_us": 9, "lds": 10, "engine": 11, "wave_edge16_us": 12,
@@ -117,6 +119,8 @@ def lib():
         "mplpxx_batch_create": (ctypes.c_int, [i32, vp, vp, vp, vp, vp, vp, pp]),
         "mplpxx_batch_create_potts": (ctypes.c_int, [i32, vp, vp, vp, vp, vp, vp, pp]),
         "mplpxx_create_potts": (ctypes.c_int, [i32, i32, i64, vp, vp, vp, pp]),
+        "mplpxx_create_structured": (ctypes.c_int, [i32, i32, i64, vp, vp, i32, vp, pp]),
+        "mplpxx_batch_create_structured": (ctypes.c_int, [i32, vp, vp, vp, vp, vp, i32, vp, pp]),
         "mplpxx_batch_iterate": (ctypes.c_int, [vp, i32]),
         "mplpxx_batch_dual_bounds": (ctypes.c_int, [vp, vp]),
         "mplpxx_batch_get_state": (ctypes.c_int, [vp, i32, vp, vp, vp]),
@@ -228,6 +232,22 @@ class Solver:
         h = ctypes.c_void_p()
         _check(lib().mplpxx_create_potts(int(model.n), int(model.L), int(m), _ptr(edges) if m else None, _ptr(un),
                                          _ptr(w) if m else None, ctypes.byref(h)))
+        return cls(model.n, model.L, None, None, None, _handle=h)
+
+    @classmethod
+    def from_structured(cls, model, kind):
+        """A model with structured pairwise costs (``mplpxx_create_structured``):
+        ``model.pairwise`` holds the parameters per edge [m, P] (Potts: w;
+        truncated linear: w, tau); FP32."""
+        edges = np.ascontiguousarray(model.edges, dtype=np.int32).reshape(-1, 2)
+        m = edges.shape[0]
+        un = np.ascontiguousarray(model.unaries, dtype=np.float32)
+        prm = np.ascontiguousarray(model.pairwise, dtype=np.float32)
+        if un.size != model.n * model.L or prm.size != m * COST_PARAMS.get(kind, 0):
+            raise ValueError("unaries must hold n*L values and params m*P (P parameters of the cost kind)")
+        h = ctypes.c_void_p()
+        _check(lib().mplpxx_create_structured(int(model.n), int(model.L), int(m), _ptr(edges) if m else None, _ptr(un),
+                                              int(kind), _ptr(prm) if m else None, ctypes.byref(h)))
         return cls(model.n, model.L, None, None, None, _handle=h)
 
     @classmethod
@@ -394,11 +414,13 @@ def solve_noalloc(edges, unaries, pairwise, iters, U_out, phi_out, stream=None):
 
 class Batch:
     """Many independent FP32 models solved together (``mplpxx_batch_*``).
-    ``potts=True``: every model's ``pairwise`` is a weight per edge [m]
-    (pairwise term w_e [s != t], ``mplpxx_batch_create_potts``)."""
+    ``kind`` (COST_POTTS, COST_TRUNC_LINEAR; ``potts=True`` means COST_POTTS):
+    every model's ``pairwise`` holds the cost's parameters per edge [m, P]
+    (``mplpxx_batch_create_structured``)."""
 
-    def __init__(self, models, potts=False):
+    def __init__(self, models, potts=False, kind=0):
         count = len(models)
+        kind = COST_POTTS if potts and not kind else int(kind)
         self.models = models
         self.n = np.array([mo.n for mo in models], dtype=np.int32)
         self.L = np.array([mo.L for mo in models], dtype=np.int32)
@@ -411,15 +433,19 @@ class Batch:
             e = np.ascontiguousarray(mo.edges, dtype=np.int32)
             u = np.ascontiguousarray(mo.unaries, dtype=np.float32)
             pw = np.ascontiguousarray(mo.pairwise, dtype=np.float32)
-            if potts and pw.size != mo.m:
-                raise ValueError("Potts models take one weight per edge")
+            if kind and pw.size != mo.m * COST_PARAMS.get(kind, 0):
+                raise ValueError("structured models take the cost's parameters per edge")
             keep += [e, u, pw]
             e_ptrs[i] = e.ctypes.data if mo.m else None
             u_ptrs[i] = u.ctypes.data
             p_ptrs[i] = pw.ctypes.data if mo.m else None
         h = ctypes.c_void_p()
-        create = lib().mplpxx_batch_create_potts if potts else lib().mplpxx_batch_create
-        _check(create(count, _ptr(self.n), _ptr(self.L), _ptr(self.m), e_ptrs, u_ptrs, p_ptrs, ctypes.byref(h)))
+        if kind:
+            _check(lib().mplpxx_batch_create_structured(count, _ptr(self.n), _ptr(self.L), _ptr(self.m), e_ptrs, u_ptrs,
+                                                        kind, p_ptrs, ctypes.byref(h)))
+        else:
+            _check(lib().mplpxx_batch_create(count, _ptr(self.n), _ptr(self.L), _ptr(self.m), e_ptrs, u_ptrs, p_ptrs,
+                                             ctypes.byref(h)))
         self._h = h
         _LIVE.add(self)
         self.count = count

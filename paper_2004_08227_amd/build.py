@@ -32,8 +32,10 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wno-unused-comman
           "-I", os.path.join(ROOT, "include")]
 
 
-# The handshake kernels see no NaN: inputs are validated finite, pads are
-# +inf and no pass can form inf - inf.  Telling the compiler so lets min
+# The handshake kernels see no NaN: inputs are validated finite (FP32:
+# |cost| <= 1e18), padded tile entries are +inf (per-matching engine) or
+# 2^126 (mailbox and wave engines), padded labels of the structured passes
+# +inf, and no pass can form inf - inf.  Telling the compiler so lets min
 # reductions skip the quieting of their operands and fold into DPP forms;
 # on non-NaN operands the results are bitwise the same.
 EXTRA = {"handshake.hip": ["-fno-honor-nans"], "batch.hip": ["-fno-honor-nans"], "rules.hip": ["-fno-honor-nans"]}

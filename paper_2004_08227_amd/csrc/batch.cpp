@@ -43,7 +43,7 @@ using namespace mplpxx;
 
 struct ModelHost {
   int n, L, m, S, lt;
-  int potts = 0;                   // Potts pairwise terms (one weight per edge)
+  int potts = 0;                   // structured cost kind (MPLPXX_COST_*; parameters per edge), 0 dense
   int max_step;                    // edges of the largest matching
   std::vector<int> slot_of_edge;   // for state export
 };
@@ -104,7 +104,7 @@ struct mplpxx_batch {
   size_t wv_lds_limit = 0;     // dynamic LDS a workgroup of the wave kernel can have
   size_t wv_lds_cap = 0;       // dynamic LDS that keeps the kernel's register-limited occupancy
   int wv_waves = 8;
-  bool potts = false;          // a batch of Potts models (one weight per edge)
+  int potts = 0;               // a batch of structured-cost models (MPLPXX_COST_*), 0 dense
   bool plan_dirty = true;
   // execution
   hipStream_t stream = nullptr;
@@ -138,7 +138,7 @@ double wave_model_time(const mplpxx_batch* b, int i, int T, double bw_per_wg_byt
   const double lat = (T == 1 && lds_fits(b, i)) ? b->wv_lat_lds_us : b->wv_lat_mb_us;
   const double workers = (double)T * b->wv_waves;
   const double chain = h.S * std::ceil(h.max_step / workers) * lat;
-  const double bytes = (h.potts ? 4.0 : 4.0 * h.L * h.L) + 16.0 * h.L;
+  const double bytes = (h.potts ? 4.0 * cost_params(h.potts) : 4.0 * h.L * h.L) + 16.0 * h.L;
   const double work = (double)h.m / T * (tw + bytes / (0.75 * bw_per_wg_bytes_us));
   return std::max(chain, work);
 }
@@ -222,7 +222,7 @@ int plan(mplpxx_batch* b) {
   if (b->engine_opt == 2 && b->max_lt > 64) return fail(MPLPXX_EINVAL, "the wave engine takes models with L <= 64");
   bool any_potts = false;
   for (const ModelHost& h : b->mh) any_potts = any_potts || h.potts;
-  if (any_potts && b->engine_opt == 1) return fail(MPLPXX_EINVAL, "Potts models run on the wave engine only");
+  if (any_potts && b->engine_opt == 1) return fail(MPLPXX_EINVAL, "structured costs run on the wave engine only");
   b->wave = b->engine_opt == 2 || (b->engine_opt == 0 && b->max_lt <= 64);
   if (b->wave) {
     // LDS-resident models only as large as keeps the register-limited
@@ -379,7 +379,7 @@ extern "C" {
 
 static int create_batch(int32_t count, const int32_t* n, const int32_t* L, const int64_t* m,
                         const int32_t* const* edges, const float* const* unaries, const float* const* pairwise,
-                        bool potts, mplpxx_batch** out) {
+                        int potts, mplpxx_batch** out) {
   if (!out) return fail(MPLPXX_EINVAL, "out is NULL");
   *out = nullptr;
   if (count < 1) return fail(MPLPXX_EINVAL, "count must be >= 1");
@@ -403,13 +403,17 @@ static int create_batch(int32_t count, const int32_t* n, const int32_t* L, const
     if (m[i] > 0 && (!edges || !pairwise || !edges[i] || !pairwise[i]))
       return bail(fail(MPLPXX_EINVAL, "model %d: NULL edges or pairwise", i));
     if (!unaries[i]) return bail(fail(MPLPXX_EINVAL, "model %d: NULL unaries", i));
-    if (potts && L[i] > 64) return bail(fail(MPLPXX_EINVAL, "model %d: Potts models take L <= 64", i));
+    if (potts && L[i] > 64) return bail(fail(MPLPXX_EINVAL, "model %d: structured costs take L <= 64", i));
     for (size_t k = 0; k < (size_t)n[i] * L[i]; ++k)
       if (!(std::fabs(unaries[i][k]) <= (float)MPLPXX_F32_MAX_COST))
         return bail(fail(MPLPXX_EINVAL, "model %d: non-finite or too large unary", i));
-    for (size_t k = 0; k < (size_t)m[i] * (potts ? 1 : (size_t)L[i] * L[i]); ++k)
+    for (size_t k = 0; k < (size_t)m[i] * (potts ? (size_t)cost_params(potts) : (size_t)L[i] * L[i]); ++k)
       if (!(std::fabs(pairwise[i][k]) <= (float)MPLPXX_F32_MAX_COST))
         return bail(fail(MPLPXX_EINVAL, "model %d: non-finite or too large pairwise", i));
+    if (potts == MPLPXX_COST_TRUNC_LINEAR && m[i] > 0 && check_trunc_linear_params(pairwise[i], m[i]) != MPLPXX_OK) {
+      const std::string msg = g_last_error;
+      return bail(fail(MPLPXX_EINVAL, "model %d: %s", i, msg.c_str()));
+    }
     const int rc = prepare_graph(n[i], (int)m[i], m[i] ? edges[i] : nullptr, preps[i]);
     if (rc != MPLPXX_OK) {
       const std::string msg = g_last_error;
@@ -419,7 +423,7 @@ static int create_batch(int32_t count, const int32_t* n, const int32_t* L, const
     h.n = n[i];
     h.L = L[i];
     h.m = (int)m[i];
-    h.potts = potts ? 1 : 0;
+    h.potts = potts;
     h.S = preps[i].S;
     h.lt = next_tile(L[i]);
     h.max_step = 1;
@@ -441,7 +445,7 @@ static int create_batch(int32_t count, const int32_t* n, const int32_t* L, const
     d.csr_off = b->total_csr;
     d.inc_off = b->total_inc;
     d.potts = h.potts;
-    b->total_tables += (long long)h.m * (potts ? 1 : (long long)h.L * h.L);
+    b->total_tables += (long long)h.m * (potts ? (long long)cost_params(potts) : (long long)h.L * h.L);
     b->total_phi += (long long)h.m * 2 * h.L;
     b->total_u += (long long)h.n * h.L;
     b->total_slots += h.m;
@@ -497,15 +501,15 @@ static int create_batch(int32_t count, const int32_t* n, const int32_t* L, const
     const ModelHost& h = b->mh[i];
     const BatchModel& d = b->md[i];
     const GraphPrep& g = preps[i];
-    const size_t tl = potts ? 1 : (size_t)h.L * h.L;
+    const size_t tl = potts ? (size_t)cost_params(potts) : (size_t)h.L * h.L;
     packed.resize((size_t)h.m * tl);
     for (int s = 0; s < h.m; ++s) {
       const int e = g.order[s];
       const float* src = pairwise[i] + (size_t)e * tl;
       float* dst = packed.data() + (size_t)s * tl;
-      if (potts) {
+      if (potts == MPLPXX_COST_POTTS) {
         *dst = src[0] + 0.0f;  // (a weight of -0 is stored as +0: the table it stands for is the same)
-      } else if (!g.flip[e]) {
+      } else if (potts || !g.flip[e]) {   // (structured costs are symmetric in s, t)
         std::memcpy(dst, src, tl * sizeof(float));
       } else {
         for (int r = 0; r < h.L; ++r)
@@ -553,13 +557,21 @@ static int create_batch(int32_t count, const int32_t* n, const int32_t* L, const
 int mplpxx_batch_create(int32_t count, const int32_t* n, const int32_t* L, const int64_t* m,
                         const int32_t* const* edges, const float* const* unaries, const float* const* pairwise,
                         mplpxx_batch** out) {
-  return create_batch(count, n, L, m, edges, unaries, pairwise, false, out);
+  return create_batch(count, n, L, m, edges, unaries, pairwise, 0, out);
 }
 
 int mplpxx_batch_create_potts(int32_t count, const int32_t* n, const int32_t* L, const int64_t* m,
                               const int32_t* const* edges, const float* const* unaries, const float* const* weights,
                               mplpxx_batch** out) {
-  return create_batch(count, n, L, m, edges, unaries, weights, true, out);
+  return create_batch(count, n, L, m, edges, unaries, weights, MPLPXX_COST_POTTS, out);
+}
+
+int mplpxx_batch_create_structured(int32_t count, const int32_t* n, const int32_t* L, const int64_t* m,
+                                   const int32_t* const* edges, const float* const* unaries, int32_t kind,
+                                   const float* const* params, mplpxx_batch** out) {
+  if (out) *out = nullptr;
+  if (kind != MPLPXX_COST_POTTS && kind != MPLPXX_COST_TRUNC_LINEAR) return fail(MPLPXX_EINVAL, "unknown cost kind %d", kind);
+  return create_batch(count, n, L, m, edges, unaries, params, kind, out);
 }
 
 int mplpxx_batch_iterate(mplpxx_batch* b, int32_t k) {

@@ -168,7 +168,7 @@ size_t batch_lds_limit(int max_lt) {
 constexpr int kWvWaves = MPLPXX_WV_WAVES;
 constexpr int kWvSink = 192;  // scratch words per wave
 
-template <int LT, bool POTTS = false>
+template <int LT, int KIND = kCostDense>
 __device__ __forceinline__ void wv_task(const BatchArgs& b, const BatchModel& md, const BatchTask& task,
                                         WvScratch& scr, int iters, unsigned char* dyn, int* abort) {
   const int wave = threadIdx.x >> 6;
@@ -180,8 +180,8 @@ __device__ __forceinline__ void wv_task(const BatchArgs& b, const BatchModel& md
   const int owned = first < md.m ? (md.m - first + stride - 1) / stride : 0;
   const bool far = owned >= 2;
   if (!task.lds) {
-    if (far) (void)wv_run<LT, false, true, POTTS>(v, first, stride, iters, scr, b.spin_limit, b.err, abort);
-    else (void)wv_run<LT, false, false, POTTS>(v, first, stride, iters, scr, b.spin_limit, b.err, abort);
+    if (far) (void)wv_run<LT, false, true, KIND>(v, first, stride, iters, scr, b.spin_limit, b.err, abort);
+    else (void)wv_run<LT, false, false, KIND>(v, first, stride, iters, scr, b.spin_limit, b.err, abort);
     return;
   }
   // the model's unaries and update counters into LDS, run, and back
@@ -196,16 +196,17 @@ __device__ __forceinline__ void wv_task(const BatchArgs& b, const BatchModel& md
   }
   for (int i = threadIdx.x; i < md.n; i += blockDim.x) v.lds_ver[i] = 0;
   __syncthreads();
-  if (far) (void)wv_run<LT, true, true, POTTS>(v, first, stride, iters, scr, b.spin_limit, b.err, abort);
-  else (void)wv_run<LT, true, false, POTTS>(v, first, stride, iters, scr, b.spin_limit, b.err, abort);
+  if (far) (void)wv_run<LT, true, true, KIND>(v, first, stride, iters, scr, b.spin_limit, b.err, abort);
+  else (void)wv_run<LT, true, false, KIND>(v, first, stride, iters, scr, b.spin_limit, b.err, abort);
   __syncthreads();
   for (int i = threadIdx.x; i < nl; i += blockDim.x)
     v.mb[i] = mb_pack(v.lds_hi[i], __uint_as_float((unsigned)v.lds_lo[i] << 16), 0u);
 }
 
-// POTTS: a batch of Potts models (mplpxx_batch_create_potts); a separate
-// instance, so that the dense kernel keeps its own register allocation
-template <bool POTTS>
+// KIND: a batch of models with structured costs (mplpxx_batch_create_potts,
+// mplpxx_batch_create_structured); separate instances, so that the dense
+// kernel keeps its own register allocation
+template <int KIND>
 __global__ void __launch_bounds__(kWvWaves * 64, MPLPXX_WV_WPE) k_wbatch(BatchArgs b, int iters) {
   __shared__ WvScratch scr[kWvWaves];
   __shared__ int s_wg, s_abort, s_q;
@@ -223,8 +224,8 @@ __global__ void __launch_bounds__(kWvWaves * 64, MPLPXX_WV_WPE) k_wbatch(BatchAr
     if (t == end && !next_queued(b, s_q, t, end)) break;
     const BatchTask task = b.tasks[t];
     const BatchModel& md = b.models[task.model];
-    if constexpr (POTTS) {
-      wv_task<64, true>(b, md, task, my, iters, dyn_lds, &s_abort);
+    if constexpr (KIND != kCostDense) {
+      wv_task<64, KIND>(b, md, task, my, iters, dyn_lds, &s_abort);
     } else {
       if (md.lt == 16) wv_task<16>(b, md, task, my, iters, dyn_lds, &s_abort);
       else if (md.lt == 32) wv_task<32>(b, md, task, my, iters, dyn_lds, &s_abort);
@@ -240,35 +241,40 @@ __global__ void __launch_bounds__(kWvWaves * 64, MPLPXX_WV_WPE) k_wbatch(BatchAr
 int wbatch_waves() { return kWvWaves; }
 size_t wbatch_sink_words() { return (size_t)kWvWaves * kWvSink; }
 
-static const void* wbatch_kernel(bool potts) {
-  return potts ? (const void*)k_wbatch<true> : (const void*)k_wbatch<false>;
+static const void* wbatch_kernel(int kind) {
+  return kind == MPLPXX_COST_TRUNC_LINEAR ? (const void*)k_wbatch<MPLPXX_COST_TRUNC_LINEAR>
+         : kind == MPLPXX_COST_POTTS      ? (const void*)k_wbatch<MPLPXX_COST_POTTS>
+                                          : (const void*)k_wbatch<kCostDense>;
 }
 
-hipError_t launch_wbatch(const BatchArgs& b, int grid, int iters, size_t dyn_lds, bool potts, hipStream_t st) {
-  if (potts) hipLaunchKernelGGL(k_wbatch<true>, dim3(grid), dim3(kWvWaves * 64), dyn_lds, st, b, iters);
-  else hipLaunchKernelGGL(k_wbatch<false>, dim3(grid), dim3(kWvWaves * 64), dyn_lds, st, b, iters);
+hipError_t launch_wbatch(const BatchArgs& b, int grid, int iters, size_t dyn_lds, int kind, hipStream_t st) {
+  if (kind == MPLPXX_COST_TRUNC_LINEAR)
+    hipLaunchKernelGGL(k_wbatch<MPLPXX_COST_TRUNC_LINEAR>, dim3(grid), dim3(kWvWaves * 64), dyn_lds, st, b, iters);
+  else if (kind == MPLPXX_COST_POTTS)
+    hipLaunchKernelGGL(k_wbatch<MPLPXX_COST_POTTS>, dim3(grid), dim3(kWvWaves * 64), dyn_lds, st, b, iters);
+  else hipLaunchKernelGGL(k_wbatch<kCostDense>, dim3(grid), dim3(kWvWaves * 64), dyn_lds, st, b, iters);
   return hipGetLastError();
 }
 
-int wbatch_blocks_per_cu(size_t dyn_lds, bool potts) {
+int wbatch_blocks_per_cu(size_t dyn_lds, int kind) {
   int nb = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, wbatch_kernel(potts), kWvWaves * 64, dyn_lds);
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, wbatch_kernel(kind), kWvWaves * 64, dyn_lds);
   return e == hipSuccess ? nb : 0;
 }
 
 // static LDS of the wave kernel, and the largest dynamic LDS it can have
 // (raises the kernel's limit to it)
-size_t wbatch_lds_limit(size_t* static_bytes, bool potts) {
+size_t wbatch_lds_limit(size_t* static_bytes, int kind) {
   int dev = 0, per_block = 0;
   if (static_bytes) *static_bytes = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 0;
   hipFuncAttributes fa{};
-  if (hipFuncGetAttributes(&fa, wbatch_kernel(potts)) != hipSuccess) return 0;
+  if (hipFuncGetAttributes(&fa, wbatch_kernel(kind)) != hipSuccess) return 0;
   if (static_bytes) *static_bytes = fa.sharedSizeBytes;
   if ((size_t)per_block <= fa.sharedSizeBytes) return 0;
   const size_t limit = (size_t)per_block - fa.sharedSizeBytes;
-  if (hipFuncSetAttribute(wbatch_kernel(potts), hipFuncAttributeMaxDynamicSharedMemorySize, (int)limit) != hipSuccess)
+  if (hipFuncSetAttribute(wbatch_kernel(kind), hipFuncAttributeMaxDynamicSharedMemorySize, (int)limit) != hipSuccess)
     return 0;
   return limit;
 }
@@ -351,14 +357,14 @@ __global__ void __launch_bounds__(256) k_batch_edge_terms(const float* __restric
   const BatchModel md = models[slot_model[g]];
   const int slot = g - md.slot_off;
   const int L = md.L;
-  // (Potts models: the table w [s != t] from the slot's weight)
-  const float* tab = tables + md.table_off + (md.potts ? (size_t)slot : (size_t)slot * L * L);
+  // (structured costs: the expanded table from the slot's parameters)
+  const float* tab = tables + md.table_off + (md.potts ? (size_t)slot * cost_params(md.potts) : (size_t)slot * L * L);
   const float* p0 = phi + md.phi_off + (size_t)slot * 2 * L;
   const float* p1 = p0 + L;
   double mn = __builtin_inf();
   for (int i = threadIdx.x; i < L * L; i += 256) {
     const int s = i / L, t = i - s * L;
-    const float th = md.potts ? (s == t ? 0.0f : tab[0]) : tab[i];
+    const float th = md.potts ? structured_cost(md.potts, tab, s, t) : tab[i];
     mn = __builtin_fmin(mn, (double)th - (double)p0[s] - (double)p1[t]);
   }
   mn = breduce<256, true>(mn, sh);

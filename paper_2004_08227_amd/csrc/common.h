@@ -9,6 +9,23 @@ namespace mplpxx {
 
 enum { ENGINE_AUTO = 0, ENGINE_STEP = 1, ENGINE_PERSISTENT = 2 };
 
+// Pairwise cost of a model: a dense L x L table per edge, or a structured
+// cost given by a few parameters per edge (MPLPXX_COST_* of the header):
+// Potts w [s != t] (1 parameter: w), truncated linear w min(|s - t|, tau)
+// (2 parameters: w, tau).  The parameters of slot i sit at
+// tables[i * cost_params(kind)].
+constexpr int kCostDense = 0;
+__host__ __device__ constexpr int cost_params(int kind) { return kind == MPLPXX_COST_TRUNC_LINEAR ? 2 : 1; }
+// th(s, t) of a structured cost from its parameters (the expanded table:
+// for truncated linear the FP32 product w * min(|s - t|, tau))
+__host__ __device__ inline float structured_cost(int kind, const float* prm, int s, int t) {
+  if (kind == MPLPXX_COST_TRUNC_LINEAR) {
+    const float d = (float)(s > t ? s - t : t - s);
+    return prm[0] * (d < prm[1] ? d : prm[1]);
+  }
+  return s == t ? 0.0f : prm[0];
+}
+
 // timestamps per slot: 4 in normal builds; a diagnostics build
 // (-DMPLPXX_FINE_STAMPS=1) records 4 more points inside the edge update
 #ifndef MPLPXX_FINE_STAMPS
@@ -62,7 +79,7 @@ struct BatchModel {
   int n, L, m, lt;      // sizes and register tile (16, 32, 64 or 128)
   int csr_off;          // first node_ptr entry (n+1 per model)
   int inc_off;          // first incidence entry (2m per model)
-  int potts;            // 1: pairwise terms w_e [s != t], one weight per slot at table_off + slot
+  int potts;            // cost kind (0 dense; MPLPXX_COST_*: parameters per slot at table_off + slot * cost_params)
 };
 struct BatchTask {
   int model;   // which model
@@ -124,7 +141,7 @@ hipError_t launch_persistent_mb(const HsArgs<float>& a, unsigned long long* mb, 
 // the same for Potts models (one weight per slot, L <= 64; potts_mb.h)
 int max_blocks_per_cu_mb_potts();
 hipError_t launch_persistent_mb_potts(const HsArgs<float>& a, unsigned long long* mb, int grid, int iters,
-                                      int phi_in_lds, size_t dyn_lds, hipStream_t st);
+                                      int phi_in_lds, size_t dyn_lds, hipStream_t st, int kind = MPLPXX_COST_POTTS);
 hipError_t launch_mb_init(const float* U, const float* Ulo, unsigned long long* mb, size_t count, hipStream_t st);
 hipError_t launch_mb_fini(float* U, float* Ulo, const unsigned long long* mb, int n, int L, double* trace_row,
                           hipStream_t st);

@@ -51,11 +51,14 @@ __global__ void __launch_bounds__(128) k_node_terms(const T* __restrict__ unarie
   if (s == 0) node_min[u] = mn;
 }
 
-// th(s, t) of the edge in `slot`: its table, or, for Potts models (one
-// weight per slot), w [s != t]
+// th(s, t) of the edge in `slot`: its table, or, for structured costs (their
+// parameters per slot), the expanded table entry
 template <typename T>
 __device__ __forceinline__ T table_at(const T* tables, int slot, int L, int s, int t, int potts) {
-  return potts ? (s == t ? T(0) : tables[slot]) : tables[(size_t)slot * L * L + (size_t)s * L + t];
+  if constexpr (sizeof(T) == 4) {
+    if (potts) return structured_cost(potts, tables + (size_t)slot * cost_params(potts), s, t);
+  }
+  return tables[(size_t)slot * L * L + (size_t)s * L + t];
 }
 
 // edge terms: one workgroup per slot

@@ -282,7 +282,7 @@ __global__ void __launch_bounds__(NT + 128) k_persistent_mb(HsArgs<float> a, uns
 
 // Potts models (one weight per slot, L <= 64): one compute wave in label
 // order plus the two sync waves (potts_mb.h)
-template <bool PHI_LDS>
+template <bool PHI_LDS, int KIND>
 __global__ void __launch_bounds__(kPottsNT + 128) k_persistent_mb_potts(HsArgs<float> a, unsigned long long* __restrict__ mb,
                                                                        int iters) {
   __shared__ SmemMB<64, kPottsNT> sm;
@@ -299,7 +299,7 @@ __global__ void __launch_bounds__(kPottsNT + 128) k_persistent_mb_potts(HsArgs<f
   __syncthreads();
   MbView v{a.tables, a.phi, mb, a.slots, a.deg, nullptr, nullptr, a.stamps, L, a.m, a.n, nullptr, nullptr,
            a.sink + (size_t)blockIdx.x * (kPottsNT + 128)};
-  if (!mb_run_potts<PHI_LDS>(v, blockIdx.x, G, iters, sm, phi_lds, a.spin_limit, a.err)) return;
+  if (!mb_run_potts<PHI_LDS, KIND>(v, blockIdx.x, G, iters, sm, phi_lds, a.spin_limit, a.err)) return;
   __syncthreads();
   if (PHI_LDS) {
     for (int slot = blockIdx.x, j = 0; slot < a.m; slot += G, ++j)
@@ -425,15 +425,19 @@ hipError_t launch_persistent_mb(const HsArgs<float>& a, unsigned long long* mb, 
 
 int max_blocks_per_cu_mb_potts() {
   int nb = 0;
-  const void* f = (const void*)k_persistent_mb_potts<false>;
+  const void* f = (const void*)k_persistent_mb_potts<false, MPLPXX_COST_POTTS>;
   const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kPottsNT + 128, 0);
   return e == hipSuccess ? placeable_per_cu(f, kPottsNT + 128, nb) : 0;
 }
 
 hipError_t launch_persistent_mb_potts(const HsArgs<float>& a, unsigned long long* mb, int grid, int iters,
-                                      int phi_in_lds, size_t dyn_lds, hipStream_t st) {
+                                      int phi_in_lds, size_t dyn_lds, hipStream_t st, int kind) {
   void* args[] = {(void*)&a, (void*)&mb, (void*)&iters};
-  const void* f = phi_in_lds ? (const void*)k_persistent_mb_potts<true> : (const void*)k_persistent_mb_potts<false>;
+  const void* f = kind == MPLPXX_COST_TRUNC_LINEAR
+                      ? (phi_in_lds ? (const void*)k_persistent_mb_potts<true, MPLPXX_COST_TRUNC_LINEAR>
+                                    : (const void*)k_persistent_mb_potts<false, MPLPXX_COST_TRUNC_LINEAR>)
+                      : (phi_in_lds ? (const void*)k_persistent_mb_potts<true, MPLPXX_COST_POTTS>
+                                    : (const void*)k_persistent_mb_potts<false, MPLPXX_COST_POTTS>);
   const hipError_t e = hipLaunchCooperativeKernel(f, dim3(grid), dim3(kPottsNT + 128), args, dyn_lds, st);
   if (e != hipSuccess) (void)hipGetLastError();  // (see launch_mb_one)
   return e;

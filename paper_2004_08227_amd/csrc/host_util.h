@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <string>
@@ -31,6 +32,19 @@ inline int fail(int code, const char* fmt, ...) {
       return ::mplpxx::fail(MPLPXX_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));                       \
     }                                                                                                       \
   } while (0)
+
+// Truncated linear parameters (w, tau) per edge: finite, w >= 0, tau >= 0,
+// and the costs fl(w * tau), fl(w * d) within the FP32 cost bound.
+inline int check_trunc_linear_params(const float* prm, int64_t m) {
+  for (int64_t e = 0; e < m; ++e) {
+    const float w = prm[2 * e], tau = prm[2 * e + 1];
+    if (!(w >= 0.0f && tau >= 0.0f && std::isfinite(w) && std::isfinite(tau)))
+      return fail(MPLPXX_EINVAL, "edge %lld: truncated linear costs need finite w >= 0 and tau >= 0", (long long)e);
+    if (!(w * tau <= (float)MPLPXX_F32_MAX_COST) || !(w * (float)MPLPXX_MAX_LABELS <= (float)MPLPXX_F32_MAX_COST))
+      return fail(MPLPXX_EINVAL, "edge %lld: truncated linear cost above %g", (long long)e, MPLPXX_F32_MAX_COST);
+  }
+  return MPLPXX_OK;
+}
 
 // smallest register tile (16, 32, 64, 128) holding L labels
 inline int next_tile(int L) {

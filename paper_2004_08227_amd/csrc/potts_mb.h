@@ -1,12 +1,13 @@
-// Mailbox engine (persistent, FP32) for models with Potts pairwise terms
-// th(s,t) = w [s != t] and L <= 64: the single-model counterpart of the wave
-// engine's Potts instance.  A workgroup is one compute wave (label l on lane
-// l, the three passes by the minimum / second-minimum butterfly of
-// potts_passes.h) plus the two sync waves of the dense engine, which poll
-// the mailboxes of the next step's two nodes and deliver them to LDS.  The
-// tables hold one weight per slot.  Every value is formed by the same IEEE
-// operations as in the dense engines, so the results are bitwise those of
-// the dense engine on the expanded table.
+// Mailbox engine (persistent, FP32) for models with structured pairwise
+// costs (Potts th(s,t) = w [s != t], truncated linear w min(|s - t|, tau))
+// and L <= 64: the single-model counterpart of the wave engine's structured
+// instances.  A workgroup is one compute wave (label l on lane l, the three
+// passes of potts_passes.h) plus the two sync waves of the dense engine,
+// which poll the mailboxes of the next step's two nodes and deliver them to
+// LDS.  The tables hold the cost's parameters per slot.  For Potts costs
+// every value is formed by the same IEEE operations as in the dense
+// engines, so the results are bitwise those of the dense engine on the
+// expanded table.
 //
 // Per step both kinds of waves meet at one barrier (the step's nodes are in
 // LDS); there is no mid-step barrier as in mb_run, since the compute wave
@@ -22,7 +23,7 @@ namespace mplpxx {
 
 constexpr int kPottsNT = 64;  // compute threads of the Potts instance
 
-template <bool PHI_LDS>
+template <bool PHI_LDS, int KIND = MPLPXX_COST_POTTS>
 __device__ __forceinline__ bool mb_run_potts(const MbView& v_in, int first_in, int stride_in, int iters_in,
                                              SmemMB<64, kPottsNT>& sm, float* phi_lds, long long spin_limit,
                                              int* err) {
@@ -91,9 +92,9 @@ __device__ __forceinline__ bool mb_run_potts(const MbView& v_in, int first_in, i
     nxt = uni(nxt);
     const bool last_iter = it == iters - 1;
     const SlotInfo si_next = ld_const(v.slots + nxt);
-    // the slot's weight and old messages (each label's message is written
-    // and read only by this lane, so program order suffices)
-    const float w = ld_const_f(v.tables + slot);
+    // the slot's cost parameters and old messages (each label's message is
+    // written and read only by this lane, so program order suffices)
+    const float* prm = v.tables + (size_t)slot * cost_params(KIND);
     float* ph = PHI_LDS ? phi_lds + (size_t)j * 2 * L : v.phi + (size_t)slot * 2 * L;
     const float fu = ph[li], fv = ph[L + li];
     __syncthreads();  // the step's nodes are in LDS
@@ -104,7 +105,7 @@ __device__ __forceinline__ bool mb_run_potts(const MbView& v_in, int first_in, i
     const float hv = sm.vh[parity][li], lv = sm.vl[parity][li];
     const float delta = 0.5f * (sm.cc[parity][0] - sm.cc[parity][1]);
     float phu, phv;
-    potts_passes(au, av, w, lout, L, delta, phu, phv);
+    structured_passes<KIND>(au, av, prm, lout, L, delta, phu, phv);
     float nhu, nlu, nhv, nlv;
     comp_update(hu, lu, fu, phu, nhu, nlu);
     comp_update(hv, lv, fv, phv, nhv, nlv);

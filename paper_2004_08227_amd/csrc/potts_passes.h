@@ -1,6 +1,6 @@
-// The passes of (H) on an edge with Potts pairwise terms, in label order
-// (lane l holds label l): shared by the wave engine and the mailbox
-// engine's Potts instance.
+// The passes of (H) on an edge with a structured pairwise cost (Potts,
+// truncated linear), in label order (lane l holds label l): shared by the
+// wave engine and the mailbox engine's structured instance.
 #pragma once
 #include "device_common.h"
 
@@ -92,6 +92,83 @@ __device__ __forceinline__ void potts_passes(float au, float av, float w, bool l
   const float r = vmin(z - q, w + min_other(nq, lout, L));
   phu = r - delta;   // new message into u
   phv = q + delta;   // new message into v
+}
+
+// ---------------------------------------------------------------------------
+// Truncated linear terms th(s,t) = fl(w min(|s - t|, tau)), w, tau >= 0 (Sec.
+// 4 names absolute-difference costs among those whose message passing takes
+// O(|Y|)).  A pass y(s) = min_t [x(t) + th(s,t)] is the distance transform
+//   y(s) = min( min_t [x(t) + w |s - t|],  min_t x(t) + fl(w tau) ):
+// a label farther than tau costs x(t) + w tau >= min x + w tau, and a nearer
+// one x(t) + w |s - t| <= x(t) + w tau.  The first term is a prefix minimum
+// (labels t <= s) and a suffix minimum (t >= s) of x(t) + w |s - t|, formed
+// by doubling distances: after the steps d = 1, 2, 4, 8 (DPP row shifts,
+// adding w d, exact for these powers of two) each label holds the minimum
+// over the labels of its row of 16 lanes; the rows are then joined by the
+// carry of the earlier (later) rows' ends, through at most three rows.  The
+// sums are rounded in a different order than fl(x(t) + fl(w |s - t|)), so
+// the pass agrees with the expanded table up to a few FP32 roundings.
+// ---------------------------------------------------------------------------
+template <int CTRL> __device__ __forceinline__ float dpp_shift_inf(float x) {
+  // lanes whose source is outside the row keep +inf
+  return __int_as_float(__builtin_amdgcn_update_dpp((int)0x7f800000, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float lane_value(float x, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+__device__ __forceinline__ float tl_pass(float x, bool real, float w, float wt, int L) {
+  const float kInf = __builtin_inff();
+  const float xs = real ? x : kInf;
+  float f = xs, g = xs;   // from labels below / above
+  f = vmin(f, dpp_shift_inf<0x111>(f) + w);   // row_shr:1
+  g = vmin(g, dpp_shift_inf<0x101>(g) + w);   // row_shl:1
+  const float w2 = 2.0f * w, w4 = 4.0f * w, w8 = 8.0f * w;
+  f = vmin(f, dpp_shift_inf<0x112>(f) + w2);
+  g = vmin(g, dpp_shift_inf<0x102>(g) + w2);
+  f = vmin(f, dpp_shift_inf<0x114>(f) + w4);
+  g = vmin(g, dpp_shift_inf<0x104>(g) + w4);
+  f = vmin(f, dpp_shift_inf<0x118>(f) + w8);
+  g = vmin(g, dpp_shift_inf<0x108>(g) + w8);
+  float xm = row16_min(xs);
+  if (L > 16) {
+    const int lane = threadIdx.x & 63, row = lane >> 4, k = lane & 15;
+    const float w16 = 16.0f * w;
+    // c_r: min over the labels of the rows below r of x(t) + w (16 r - 1 - t)
+    const float c1 = lane_value(f, 15);
+    const float c2 = vmin(lane_value(f, 31), c1 + w16);
+    const float c3 = vmin(lane_value(f, 47), c2 + w16);
+    const float c = row == 0 ? kInf : row == 1 ? c1 : row == 2 ? c2 : c3;
+    // d_r: min over the labels of the rows above r of x(t) + w (t - 16 (r + 1))
+    const float d2 = lane_value(g, 48);
+    const float d1 = vmin(lane_value(g, 32), d2 + w16);
+    const float d0 = vmin(lane_value(g, 16), d1 + w16);
+    const float d = row == 3 ? kInf : row == 2 ? d2 : row == 1 ? d1 : d0;
+    f = vmin(f, c + w * (float)(k + 1));
+    g = vmin(g, d + w * (float)(16 - k));
+    xm = col4_min(xm);
+  }
+  return vmin(vmin(f, g), xm + wt);
+}
+
+// New messages of one (H) update of a structured edge, per lane (label): au,
+// av are the centred a'_u, a'_v of this label, prm the edge's parameters
+// (Potts: w; truncated linear: w, tau), delta the shift between the centred
+// passes and the messages.
+template <int KIND>
+__device__ __forceinline__ void structured_passes(float au, float av, const float* prm, bool lout, int L, float delta,
+                                                  float& phu, float& phv) {
+  if constexpr (KIND == MPLPXX_COST_TRUNC_LINEAR) {
+    const float w = ld_const_f(prm), tau = ld_const_f(prm + 1);
+    const float wt = w * tau;   // the table's value beyond the truncation
+    const float p = tl_pass(av, lout, w, wt, L);
+    const float b = 0.5f * (au - p);
+    const float q = tl_pass(b, lout, w, wt, L);
+    const float r = tl_pass(-q, lout, w, wt, L);
+    phu = r - delta;
+    phv = q + delta;
+  } else {
+    potts_passes(au, av, ld_const_f(prm), lout, L, delta, phu, phv);
+  }
 }
 
 }  // namespace mplpxx

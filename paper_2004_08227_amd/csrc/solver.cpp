@@ -102,7 +102,7 @@ struct mplpxx_solver {
   int rule = MPLPXX_RULE_H;  // BCA-update (Sec. 4)
   int sched = MPLPXX_SCHED_AUTO;  // schedule kind of Alg. 1
   int threads_opt = 0;
-  bool potts = false;        // Potts pairwise terms: d_tables holds one weight per slot
+  int potts = 0;             // structured cost kind (MPLPXX_COST_*): d_tables holds its parameters per slot
   int grid_opt = 0;
   long long spin_limit = 1ll << 22;
   int num_cus = 0;
@@ -206,7 +206,7 @@ bool is_device_memory(const void* p, int dev) {
 
 int create_impl(int32_t n, int32_t L, int64_t m, const int32_t* edges, const void* unaries, const void* pairwise,
                 int32_t dtype, bool device_costs, hipStream_t copy_stream, mplpxx_solver** out,
-                int32_t sched = MPLPXX_SCHED_AUTO, bool potts = false) {
+                int32_t sched = MPLPXX_SCHED_AUTO, int potts = 0) {
   if (!out) return fail(MPLPXX_EINVAL, "out is NULL");
   *out = nullptr;
   if (dtype != MPLPXX_F32 && dtype != MPLPXX_F64) return fail(MPLPXX_EINVAL, "unknown dtype %d", dtype);
@@ -218,11 +218,13 @@ int create_impl(int32_t n, int32_t L, int64_t m, const int32_t* edges, const voi
   if (sched != MPLPXX_SCHED_AUTO && sched != MPLPXX_SCHED_GREEDY && sched != MPLPXX_SCHED_COLOR)
     return fail(MPLPXX_EINVAL, "unknown schedule kind %d", sched);
   if (m > 0 && (!edges || !pairwise)) return fail(MPLPXX_EINVAL, "edges/pairwise is NULL");
-  if (potts && (dtype != MPLPXX_F32 || device_costs)) return fail(MPLPXX_EINVAL, "Potts models take FP32 host costs");
-  if (potts && L > 64) return fail(MPLPXX_EINVAL, "Potts models take L <= 64 (got %d)", L);
+  if (potts && potts != MPLPXX_COST_POTTS && potts != MPLPXX_COST_TRUNC_LINEAR)
+    return fail(MPLPXX_EINVAL, "unknown cost kind %d", potts);
+  if (potts && (dtype != MPLPXX_F32 || device_costs)) return fail(MPLPXX_EINVAL, "structured costs take FP32 host costs");
+  if (potts && L > 64) return fail(MPLPXX_EINVAL, "structured costs take L <= 64 (got %d)", L);
   const size_t esz = dtype == MPLPXX_F32 ? 4 : 8;
   // (Potts models: one weight per edge instead of an L x L table)
-  const size_t nL = (size_t)n * L, mLL = potts ? (size_t)m : (size_t)m * L * L;
+  const size_t nL = (size_t)n * L, mLL = potts ? (size_t)m * cost_params(potts) : (size_t)m * L * L;
   if (!device_costs) {
     if (!finite_host(unaries, nL, dtype)) return fail(MPLPXX_EINVAL, "non-finite (or, in FP32, above 1e18) unary cost");
     if (m > 0 && !finite_host(pairwise, mLL, dtype)) return fail(MPLPXX_EINVAL, "non-finite (or, in FP32, above 1e18) pairwise cost");
@@ -319,19 +321,20 @@ int create_impl(int32_t n, int32_t L, int64_t m, const int32_t* edges, const voi
     TRY(hipMemcpyAsync(h->d_unaries, unaries, nL * esz, hipMemcpyHostToDevice, st));
     if (m) {
       // pack tables in slot order, transposing edges given as (v, u)
-      // (Potts: the weights in slot order; a weight of -0 is stored as +0,
-      // which stands for the same table)
+      // (structured costs: the parameters in slot order, symmetric in s, t;
+      // a Potts weight of -0 is stored as +0, which stands for the same
+      // table)
       std::vector<char> packed(mLL * esz);
-      const size_t tb = (potts ? 1 : (size_t)L * L) * esz;
+      const size_t tb = (potts ? (size_t)cost_params(potts) : (size_t)L * L) * esz;
       const char* src = static_cast<const char*>(pairwise);
       for (int i = 0; i < h->m; ++i) {
         const int e = h->order[i];
         char* dst = packed.data() + (size_t)i * tb;
         const char* s = src + (size_t)e * tb;
-        if (potts) {
+        if (potts == MPLPXX_COST_POTTS) {
           const float wv = *reinterpret_cast<const float*>(s) + 0.0f;
           std::memcpy(dst, &wv, sizeof(float));
-        } else if (!h->flip[e]) {
+        } else if (potts || !h->flip[e]) {
           std::memcpy(dst, s, tb);
         } else {
           for (int r = 0; r < L; ++r)
@@ -491,7 +494,7 @@ template <typename T> int iterate_t(mplpxx_solver* h, int k, double* trace_host)
       // the workgroups' LDS never limits how many fit)
       const int in_lds = phi_bytes <= kPhiLdsBudget && G <= h->num_cus ? 1 : 0;
       HIP_TRY(launch_mb_init(static_cast<const float*>(h->d_U), h->d_Ulo, h->d_mb, (size_t)h->n * h->L, st));
-      if (h->potts) HIP_TRY(launch_persistent_mb_potts(a, h->d_mb, G, k, in_lds, in_lds ? phi_bytes : 0, st));
+      if (h->potts) HIP_TRY(launch_persistent_mb_potts(a, h->d_mb, G, k, in_lds, in_lds ? phi_bytes : 0, st, h->potts));
       else HIP_TRY(launch_persistent_mb(a, h->d_mb, LT, NT, G, k, in_lds, in_lds ? phi_bytes : 0, st));
       HIP_TRY(launch_mb_fini(static_cast<float*>(h->d_U), h->d_Ulo, h->d_mb, h->n, h->L,
                              trace_host ? h->d_trace_nodes + (size_t)(k - 1) * h->n : nullptr, st));
@@ -702,7 +705,20 @@ int mplpxx_create(int32_t n, int32_t L, int64_t m, const int32_t* edges, const v
 
 int mplpxx_create_potts(int32_t n, int32_t L, int64_t m, const int32_t* edges, const float* unaries, const float* weights,
                         mplpxx_solver** out) {
-  return create_impl(n, L, m, edges, unaries, weights, MPLPXX_F32, false, nullptr, out, MPLPXX_SCHED_AUTO, true);
+  return create_impl(n, L, m, edges, unaries, weights, MPLPXX_F32, false, nullptr, out, MPLPXX_SCHED_AUTO,
+                     MPLPXX_COST_POTTS);
+}
+
+int mplpxx_create_structured(int32_t n, int32_t L, int64_t m, const int32_t* edges, const float* unaries, int32_t kind,
+                             const float* params, mplpxx_solver** out) {
+  if (out) *out = nullptr;
+  if (kind != MPLPXX_COST_POTTS && kind != MPLPXX_COST_TRUNC_LINEAR) return fail(MPLPXX_EINVAL, "unknown cost kind %d", kind);
+  if (m > 0 && !params) return fail(MPLPXX_EINVAL, "params is NULL");
+  if (kind == MPLPXX_COST_TRUNC_LINEAR && m > 0 && m <= 0x3fffffff) {
+    const int rc = check_trunc_linear_params(params, m);
+    if (rc != MPLPXX_OK) return rc;
+  }
+  return create_impl(n, L, m, edges, unaries, params, MPLPXX_F32, false, nullptr, out, MPLPXX_SCHED_AUTO, kind);
 }
 
 int mplpxx_create_device(int32_t n, int32_t L, int64_t m, const int32_t* edges, const void* unaries_dev,
@@ -723,7 +739,7 @@ int mplpxx_iterate(mplpxx_solver* h, int32_t k) {
 
 int mplpxx_iterate_trace(mplpxx_solver* h, int32_t k, double* trace) {
   if (!h) return fail(MPLPXX_EINVAL, "handle is NULL");
-  if (h->potts) return fail(MPLPXX_EINVAL, "per-iteration traces are not available for Potts models (use mplpxx_iterate_gap)");
+  if (h->potts) return fail(MPLPXX_EINVAL, "per-iteration traces are not available for structured costs (use mplpxx_iterate_gap)");
   if (k < 0) return fail(MPLPXX_EINVAL, "k must be >= 0");
   if (k > 0 && !trace) return fail(MPLPXX_EINVAL, "trace is NULL");
   return h->dtype == MPLPXX_F32 ? iterate_t<float>(h, k, trace) : iterate_t<double>(h, k, trace);

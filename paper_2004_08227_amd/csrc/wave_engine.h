@@ -143,12 +143,14 @@ __device__ __forceinline__ int opaque(int x) {
 // the start of its own update, and other waves of the compute unit cover the
 // latency.
 //
-// POTTS: the model's pairwise terms are w_e [s != t] with one weight per
-// slot in v.tables (see above); the passes run in label order, no tile.
-template <int LT, bool LDSU, bool PHI_FAR, bool POTTS = false>
+// KIND: 0 dense tables; MPLPXX_COST_POTTS / _TRUNC_LINEAR: structured costs
+// with their parameters per slot in v.tables (cost_params floats each); the
+// passes then run in label order, no tile.
+template <int LT, bool LDSU, bool PHI_FAR, int KIND = kCostDense>
 __device__ __forceinline__ bool wv_run(const WvView& v_in, int first_in, int stride_in, int iters_in,
                                        WvScratch& scr, long long spin_limit, int* err, int* abort) {
   constexpr int B = WvShape<LT>::B;
+  constexpr bool POTTS = KIND != kCostDense;   // (any structured cost)
   constexpr bool PRE = LT <= 32 && !POTTS;
   WvView v = v_in;
   v.L = uni(v.L);
@@ -197,7 +199,7 @@ __device__ __forceinline__ bool wv_run(const WvView& v_in, int first_in, int str
       }
     };
     if (!PRE && !POTTS) wv_load_tile<LT>(v.tables + (size_t)slot * L * L, L, rbl, cbl, xc);
-    const float w = POTTS ? ld_const_f(v.tables + slot) : 0.f;
+    const float* prm = v.tables + (size_t)slot * cost_params(KIND);
     if (!PHI_FAR) {
       const float* p = v.phi + (size_t)slot * 2 * L;
       fu = p[li];
@@ -267,7 +269,7 @@ __device__ __forceinline__ bool wv_run(const WvView& v_in, int first_in, int str
       // centred a' in label order; the three passes by min_other
       const float au = ((hu - c_u) + lu) - fu;
       const float av = ((hv - c_v) + lv) - fv;
-      potts_passes(au, av, w, lout, L, delta, phu, phv);
+      structured_passes<KIND>(au, av, prm, lout, L, delta, phu, phv);
     } else {
       // ---- centred a' in label order, then into the grid ----
       scr.au[lane] = lout ? ((hu - c_u) + lu) - fu : 0x1p127f;

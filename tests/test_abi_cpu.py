@@ -235,3 +235,51 @@ def test_from_torch_rejects_host_tensors_before_any_library_call(monkeypatch):
     with pytest.raises(ValueError):
         M.Solver.from_torch(model.n, model.L, model.edges, model.unaries, model.pairwise)
     assert not called
+
+
+@pytest.mark.parametrize("case", ["neg_w", "neg_tau", "nan_tau", "inf_w", "kind", "null"])
+def test_structured_costs_rejected_without_device_work(case):
+    """Truncated linear parameters need finite w >= 0 and tau >= 0; an
+    unknown cost kind or missing parameters are rejected before any device
+    work (single model and batch)."""
+    params, _ = W.trunc_linear(6, 5, 1.0, seed=0, tau=2.0)
+    prm = params.pairwise.copy()
+    kind = M.COST_TRUNC_LINEAR
+    if case == "neg_w":
+        prm[3, 0] = -0.5
+    elif case == "neg_tau":
+        prm[2, 1] = -1.0
+    elif case == "nan_tau":
+        prm[1, 1] = np.nan
+    elif case == "inf_w":
+        prm[0, 0] = np.inf
+    elif case == "kind":
+        kind = 7
+    edges = np.ascontiguousarray(params.edges)
+    un = np.ascontiguousarray(params.unaries)
+    h = ctypes.c_void_p()
+    pp = None if case == "null" else ctypes.c_void_p(prm.ctypes.data)
+    rc = M.lib().mplpxx_create_structured(params.n, params.L, params.m, ctypes.c_void_p(edges.ctypes.data),
+                                          ctypes.c_void_p(un.ctypes.data), kind, pp, ctypes.byref(h))
+    assert rc == M.EINVAL and not h.value
+    n = np.array([params.n], np.int32)
+    L = np.array([params.L], np.int32)
+    m = np.array([params.m], np.int64)
+    e_p = (ctypes.c_void_p * 1)(edges.ctypes.data)
+    u_p = (ctypes.c_void_p * 1)(un.ctypes.data)
+    p_p = (ctypes.c_void_p * 1)(None if case == "null" else prm.ctypes.data)
+    rc = M.lib().mplpxx_batch_create_structured(1, ctypes.c_void_p(n.ctypes.data), ctypes.c_void_p(L.ctypes.data),
+                                                ctypes.c_void_p(m.ctypes.data), e_p, u_p, kind, p_p, ctypes.byref(h))
+    assert rc == M.EINVAL and not h.value
+
+
+def test_trunc_linear_expansion_is_the_fp32_product():
+    """The dense twin of a truncated linear model holds fl(w * min(|s - t|,
+    tau)) in FP32, the same product the device forms for the dual bound."""
+    params, dense = W.trunc_linear(5, 9, 1.0, seed=3, tau=3.5)
+    for e in range(params.m):
+        w, tau = params.pairwise[e]
+        for s in range(9):
+            for t in range(9):
+                want = np.float32(w) * np.float32(min(abs(s - t), tau))
+                assert dense.pairwise[e, s, t].view(np.uint32) == np.float32(want).view(np.uint32)
