@@ -7,14 +7,18 @@ comes from the HIP path.  Run from the repository root:
     python tests/golden/make_golden.py [all|pose|pose_rules|potts|potts_sched|batch|adjoint]
 
 Outputs (JSON, one file per workload):
-  pose_k200_l64.json        dual trace of 200 iterations, final node minima
+  pose_k200_l64.json        dual trace of 200 iterations, final node minima,
+                            sampled entries of the final reparametrized
+                            unaries and pairwise costs
   pose_k200_l64_rules.json  200-iteration dual traces of the (M) and (U) updates
   potts_er_n1000_l16.json   dual traces (30 iterations) at 5/25/50/100 % density
+                            and sampled final state entries
   potts_er_n1000_l16_sched.json  the same workload under both schedules of
                             the oracle (greedy matchings, Delta + 1 edge
                             colouring) at 1/5/25/50 % density: schedule
                             sizes and 30-iteration dual traces
-  batched_mix_samples.json  100-iteration traces of 8 models of the 256-model mix
+  batched_mix_samples.json  100-iteration traces and sampled final state
+                            entries of 8 models of the 256-model mix
   adjoint_uniform_k100_l32.json  the oracle's derivative of D_50 along seeded
                             dense and sparse directions and coordinates,
                             and finite differences (four step sizes) along
@@ -45,13 +49,25 @@ def dump(name, obj):
     print("wrote", name, flush=True)
 
 
+def state_sample(st, seed, n_unary, n_pair):
+    """Seeded entries of the oracle's state after its run: reparametrized
+    unaries Tu[u][s] and reparametrized pairwise costs Te[e][s][t] (edges in
+    the model's order, u < v), as index lists and values."""
+    rng = np.random.default_rng(seed)
+    iu = rng.choice(st.Tu.size, size=min(n_unary, st.Tu.size), replace=False)
+    ie = rng.choice(st.Te.size, size=min(n_pair, st.Te.size), replace=False) if st.m else np.zeros(0, int)
+    return {"seed": seed, "unary_index": [int(i) for i in iu], "unary": st.Tu.ravel()[iu].tolist(),
+            "pair_index": [int(i) for i in ie], "pair": st.Te.ravel()[ie].tolist()}
+
+
 def make_pose():
     model = W.pose(200, 64, seed=0)
     st = oracle.State(model)
     t = time.time()
     tr = st.run(200, trace=True, nthreads=THREADS)
     dump("pose_k200_l64.json", {"workload": "pose n=200 L=64 seed=0", "iters": 200, "trace": tr.tolist(),
-                                "node_min": st.Tu.min(axis=1).tolist(), "seconds": time.time() - t})
+                                "node_min": st.Tu.min(axis=1).tolist(), "seconds": time.time() - t,
+                                "state": state_sample(st, 5, 4096, 8192)})
 
 
 def make_pose_rules():
@@ -70,7 +86,8 @@ def make_potts():
         model = W.potts_er(1000, 16, p, seed=0)
         st = oracle.State(model)
         out["traces"][str(p)] = {"m": model.m, "steps": st.n_steps,
-                                 "trace": st.run(30, trace=True, nthreads=THREADS).tolist()}
+                                 "trace": st.run(30, trace=True, nthreads=THREADS).tolist(),
+                                 "state": state_sample(st, 6, 2048, 4096)}
         print("potts", p, flush=True)
     dump("potts_er_n1000_l16.json", out)
 
@@ -108,7 +125,7 @@ def make_batch():
         model = W.pose(n, L, seed=1_000_003 * 0 + i)
         st = oracle.State(model)
         tr = st.run(100, trace=True, nthreads=THREADS)
-        out["models"][str(i)] = {"n": n, "L": L, "trace": tr.tolist()}
+        out["models"][str(i)] = {"n": n, "L": L, "trace": tr.tolist(), "state": state_sample(st, 7, 512, 1024)}
         print("batch model", i, n, L, flush=True)
     dump("batched_mix_samples.json", out)
 

@@ -12,6 +12,7 @@ import pytest
 
 import oracle
 from paper_2004_08227_amd import workloads as W
+from tests import state_parity as SP
 
 pytestmark = pytest.mark.gpu
 M = pytest.importorskip("paper_2004_08227_amd")
@@ -138,7 +139,8 @@ def test_single_and_batched_match_oracle_where_workgroups_own_one_or_two_slots(n
 def test_batched_mix_samples_match_stored_oracle_traces():
     """The 256-model pose mix (n in 20..300, L in 8..64), 100 iterations in one
     launch; 8 sampled models (two smallest, two largest, four random) against
-    the oracle's stored duals."""
+    the oracle's stored duals and sampled entries of its final reparametrized
+    unaries and pairwise costs, each within 1e-5."""
     import json
     import os
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batched_mix_samples.json")
@@ -147,14 +149,21 @@ def test_batched_mix_samples_match_stored_oracle_traces():
     g = json.load(open(path))
     _announce("batched mix 256 x 100 iterations")
     models = W.batched_mix(256, seed=0)
+    states = {}
     with M.Batch(models) as b:
         b.iterate(g["iters"])
         duals = b.dual_bounds()
-    del models
+        for key in g["models"]:
+            states[key] = b.get_state(int(key), comp=True)
     for key, rec in g["models"].items():
         i = int(key)
         ref = rec["trace"][-1]
         assert abs(duals[i] - ref) <= 1e-5 * max(1.0, abs(ref)), (i, rec["n"], rec["L"], duals[i], ref)
+        U, phi, Uc = states[key]
+        eu, ep = SP.sampled_errors(models[i], U, Uc, phi, rec["state"])
+        print(f"model {i} (n={rec['n']}, L={rec['L']}): worst relative error unaries {eu:.2e}, pairwise {ep:.2e}",
+              flush=True)
+        assert eu <= SP.TOL and ep <= SP.TOL
 
 
 def test_wave_engine_rejects_more_than_64_labels():

@@ -10,6 +10,7 @@ import pytest
 
 import oracle
 from paper_2004_08227_amd import workloads as W
+from tests import state_parity as SP
 
 pytestmark = pytest.mark.gpu
 
@@ -84,10 +85,14 @@ def test_fp32_dual_matches_oracle(name, make, iters, engine):
         s.set_option(M.OPT_ENGINE, engine)
         tr = s.iterate_trace(iters)
         d = s.dual_bound()
-        U, _ = s.get_state()
+        U, phi, Uc = s.get_state(comp=True)
     assert _rel(d, ref[-1]) <= 1e-5, (d, ref[-1])
     assert np.max(np.abs(tr - ref) / np.maximum(1.0, np.abs(ref))) <= 1e-5
-    assert np.max(np.abs(U - st.Tu)) <= 1e-4 * max(1.0, np.abs(st.Tu).max())
+    # every reparametrized unary and pairwise cost, element by element
+    eu = SP.worst(SP.gpu_unaries(U, Uc), st.Tu)
+    ep = SP.worst(SP.gpu_pairwise(model.pairwise, phi), st.Te)
+    print(f"{name}: worst relative error unaries {eu:.2e}, pairwise {ep:.2e}", flush=True)
+    assert eu <= SP.TOL and ep <= SP.TOL
 
 
 FP64_CASES = [
@@ -293,7 +298,9 @@ def test_step_profile_timestamps_are_ordered():
 def test_pose_k200_l64_full_size_200_iterations_matches_stored_oracle():
     """The measured workload in the measured launch configuration (default
     engine, grid and tile): FP32 dual trace and certified dual within 1e-5 of
-    the FP64 oracle after the same schedule and 200 iterations."""
+    the FP64 oracle after the same schedule and 200 iterations, and 4096
+    reparametrized unaries and 8192 reparametrized pairwise costs of the
+    final state, sampled by the oracle's golden writer, each within 1e-5."""
     import json
     import os
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "pose_k200_l64.json")
@@ -303,7 +310,7 @@ def test_pose_k200_l64_full_size_200_iterations_matches_stored_oracle():
     with M.Solver.from_model(model) as s:
         tr = s.iterate_trace(g["iters"])
         d = s.dual_bound()
-        U, _ = s.get_state()
+        U, phi, Uc = s.get_state(comp=True)
     ref = np.array(g["trace"])
     print("max rel trace error", np.max(np.abs(tr - ref) / np.abs(ref)), "final", (d - ref[-1]) / ref[-1], flush=True)
     assert np.max(np.abs(tr - ref) / np.abs(ref)) <= 1e-5
@@ -311,14 +318,18 @@ def test_pose_k200_l64_full_size_200_iterations_matches_stored_oracle():
     # the trace (compensated node minima + exact edge terms) is the certified
     # bound of the same state up to FP64 summation
     assert abs(tr[-1] - d) <= 1e-9 * abs(d)
-    assert np.max(np.abs(U.min(axis=1) - np.array(g["node_min"]))) <= 1e-4
+    eu, ep = SP.sampled_errors(model, U, Uc, phi, g["state"])
+    en = SP.worst(SP.gpu_unaries(U, Uc).min(axis=1), g["node_min"])
+    print(f"state: worst relative error unaries {eu:.2e}, pairwise {ep:.2e}, node minima {en:.2e}", flush=True)
+    assert eu <= SP.TOL and ep <= SP.TOL and en <= SP.TOL
 
 
 @pytest.mark.parametrize("density", [0.05, 0.25, 0.5, 1.0])
 def test_potts_er_n1000_l16_full_size_matches_stored_oracle(density):
     """The sparsification workload at full size (n = 1000, L = 16, 30
     iterations): the per-iteration dual trace against the oracle's stored
-    trace, to 1e-5 relative, at each density."""
+    trace, and sampled entries of the final reparametrized unaries and
+    pairwise costs, to 1e-5 relative, at each density."""
     import json
     import os
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "potts_er_n1000_l16.json")
@@ -332,8 +343,12 @@ def test_potts_er_n1000_l16_full_size_matches_stored_oracle(density):
         assert s.info("steps") == rec["steps"]
         tr = s.iterate_trace(g["iters"])
         d = s.dual_bound()
+        U, phi, Uc = s.get_state(comp=True)
     assert np.max(np.abs(tr - ref) / np.maximum(1.0, np.abs(ref))) <= 1e-5
     assert _rel(d, ref[-1]) <= 1e-5, (d, ref[-1])
+    eu, ep = SP.sampled_errors(model, U, Uc, phi, rec["state"])
+    print(f"density {density}: worst relative error unaries {eu:.2e}, pairwise {ep:.2e}", flush=True)
+    assert eu <= SP.TOL and ep <= SP.TOL
 
 
 def test_large_matchings_default_grid_is_bitwise_identical():
