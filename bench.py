@@ -384,6 +384,86 @@ def bench_potts(M, W, iters=50, mix_count=64):
     return out
 
 
+def bench_trunc_linear(M, W, iters=50, mix_count=64, tau=8.0):
+    """Truncated linear costs w min(|s - t|, tau) by their O(L) distance
+    transform (mplpxx_*_create_structured, 8 bytes of pairwise data per edge)
+    against the dense engines on the expanded tables (4 L^2 bytes): one
+    complete pose-size model (n = 200, L = 64) on the batched wave engine as
+    a batch of one and on the single-model mailbox engine, and the first
+    `mix_count` sizes of the batched mix (complete graphs) as one batch.  Same
+    iterations from phi = 0, device times from HIP events.  The structured
+    passes round in another order than the dense ones: the largest relative
+    difference of the final duals is reported (the parity tests hold both to
+    the oracle at 1e-5)."""
+    def run_batch(models, kind):
+        with M.Batch(models, kind=kind) as b:
+            b.iterate(2)
+            b.reset()
+            b.iterate(iters)
+            return b.info("last_ms"), np.asarray(b.dual_bounds())
+
+    def run_single(make):
+        with make() as s1:
+            U0, phi0 = s1.get_state()
+            s1.iterate(2)
+            s1.set_state(U0, phi0)
+            s1.iterate(iters)
+            return s1.last_iterate_ms(), np.asarray([s1.dual_bound()])
+
+    out = {"iterations": iters, "tau": tau}
+    sizes = W.batched_mix(mix_count, seed=0, models=False)
+    for name, sz in (("complete_n200_l64", [(200, 64)]), (f"mix_{mix_count}_complete", sizes)):
+        pairs = [W.trunc_linear(n, L, 1.0, seed=40 + i, tau=tau) for i, (n, L) in enumerate(sz)]
+        m_tot = sum(p[0].m for p in pairs)
+        b_tl = sum(p[0].m * (8 + 16 * p[0].L) for p in pairs)
+        b_d = sum(p[0].m * algorithmic_bytes_per_update(p[0].L) for p in pairs)
+        params, dense = [p[0] for p in pairs], [p[1] for p in pairs]
+        del pairs
+        ms_t, d_t = run_batch(params, M.COST_TRUNC_LINEAR)
+        ms_d, d_d = run_batch(dense, 0)
+        rec = {"models": len(sz), "edges": m_tot, "structured_ms_per_iter": ms_t / iters,
+               "dense_ms_per_iter": ms_d / iters, "speedup": ms_d / ms_t,
+               "structured_updates_per_s": m_tot * iters / (ms_t / 1e3),
+               "structured_bytes_per_update": b_tl / m_tot, "dense_bytes_per_update": b_d / m_tot,
+               "max_rel_dual_difference": float(np.max(np.abs(d_t - d_d) / np.maximum(1.0, np.abs(d_d))))}
+        if len(sz) == 1:
+            ms_s, d_s = run_single(lambda: M.Solver.from_model(dense[0]))
+            ms_st, d_st = run_single(lambda: M.Solver.from_structured(params[0], M.COST_TRUNC_LINEAR))
+            rec.update({"single_model_dense_ms_per_iter": ms_s / iters,
+                        "single_model_structured_ms_per_iter": ms_st / iters,
+                        "single_model_speedup": ms_s / ms_st,
+                        "single_model_rel_dual_difference": float(abs(d_st[0] - d_s[0]) / max(1.0, abs(d_s[0])))})
+        out[name] = rec
+        del params, dense
+    return out
+
+
+def summary(result):
+    """The headline numbers of every section, short enough to survive the
+    end of a long line."""
+    sm = {"c1_ms_per_iter": result.get("ms_per_step"), "c1_hbm_frac": result.get("hbm_frac")}
+    b = result.get("batched")
+    if b:
+        sm.update({"c3_batched_ms": b.get("batched_ms"), "c3_speedup_vs_per_problem": b.get("speedup"),
+                   "c3_hbm_frac": b.get("hbm_frac")})
+    c2 = result.get("c2")
+    if c2 and isinstance(c2.get("densities"), dict):
+        sm["c2_hbm_frac"] = {k: v.get("hbm_frac") for k, v in c2["densities"].items() if isinstance(v, dict)}
+    a = result.get("adjoint")
+    if a:
+        tw = a.get("fp64_twin", {})
+        sm["c4_forward_s"] = tw.get("forward_s")
+        sm["c4_backward_s"] = tw.get("backward_s")
+    r = result.get("rules")
+    if r and isinstance(r.get("pose_k200_l64"), dict):
+        sm["c1_final_dual_by_rule"] = {k: v.get("final_dual") for k, v in r["pose_k200_l64"].items()
+                                       if isinstance(v, dict) and "final_dual" in v}
+    t = result.get("trunc_linear")
+    if t:
+        sm["trunc_linear_speedup"] = {k: v.get("speedup") for k, v in t.items() if isinstance(v, dict)}
+    return sm
+
+
 def copy_calibration():
     """A plain 1 GiB device copy, three times: the reference for the HBM
     byte counters (run under rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)."""
@@ -476,6 +556,9 @@ def main():
     ap.add_argument("--no-stream", action="store_true", help="skip the measured streaming-rate reference")
     ap.add_argument("--only-potts", action="store_true", help="run only the structured Potts section")
     ap.add_argument("--only-batch", action="store_true", help="run only the batched-mix section")
+    ap.add_argument("--no-trunc-linear", action="store_true", help="skip the truncated linear vs dense section")
+    ap.add_argument("--only-adjoint", action="store_true", help="run only the adjoint (differentiation) section")
+    ap.add_argument("--only-trunc-linear", action="store_true", help="run only the truncated linear section")
     ap.add_argument("--no-per-problem", action="store_true",
                     help="batched section without the per-problem comparison runs")
     ap.add_argument("--kernel-only", action="store_true",
@@ -503,6 +586,12 @@ def main():
         return
     if args.only_batch:
         print(json.dumps({"batched": bench_batched(M, W, per_problem=not args.no_per_problem)}))
+        return
+    if args.only_trunc_linear:
+        print(json.dumps({"trunc_linear": bench_trunc_linear(M, W)}))
+        return
+    if args.only_adjoint:
+        print(json.dumps({"adjoint": bench_adjoint(M, W)}))
         return
 
     assert torch.cuda.is_available(), "bench needs a GPU"
@@ -610,6 +699,9 @@ def main():
         result["gap"] = bench_gap(M, W)
     if not args.no_potts:
         result["potts"] = bench_potts(M, W)
+    if not args.no_trunc_linear:
+        result["trunc_linear"] = bench_trunc_linear(M, W)
+    result["summary"] = summary(result)
     print(json.dumps(result))
 
 
