@@ -152,12 +152,6 @@ template <typename T> __device__ __forceinline__ T ldv_dev(const T* p) {
 template <typename T> __device__ __forceinline__ void stv_dev(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-// wait until this wave's memory operations have completed
-__device__ __forceinline__ void wait_vmem() {
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
 
 template <typename T, int LT, int NT> struct TileShape {
   static constexpr int RB = NT / 16;   // row blocks

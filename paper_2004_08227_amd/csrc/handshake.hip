@@ -147,7 +147,6 @@ __device__ __forceinline__ void handshake_passes(const T (&x)[TileShape<T, LT, N
       }
     }
   }
-  if (kCoherent) wait_vmem();
   __syncthreads();
 }
 
@@ -192,7 +191,12 @@ __global__ void __launch_bounds__(NT) k_step(HsArgs<T> a, int slot_begin) {
 // waits until u and v have seen exactly the updates that precede this one in
 // the schedule (per-node version counters); afterwards it publishes the new
 // unaries and bumps both versions.  This is the paper's barrier between
-// matchings reduced to the two nodes an edge depends on.
+// matchings reduced to the two nodes an edge depends on.  The versions carry
+// the ordering: thread 0 stores them after the workgroup barrier that ends
+// the passes (so every thread's unary stores happen before it) and a
+// device-scope release; a waiter reads one with relaxed polls followed by a
+// device-scope acquire, before the barrier that lets its workgroup read the
+// unaries.
 // ---------------------------------------------------------------------------
 template <typename T, int LT, int NT>
 __global__ void __launch_bounds__(NT) k_persistent(HsArgs<T> a, int iters) {
@@ -225,6 +229,10 @@ __global__ void __launch_bounds__(NT) k_persistent(HsArgs<T> a, int iters) {
             break;
           }
         }
+        // acquire at device scope: the unaries published before the
+        // version this wait saw are read after it (the barrier below
+        // orders every other thread's reads after this fence)
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
       __syncthreads();
       if (sm.abort_flag) return;
@@ -238,6 +246,10 @@ __global__ void __launch_bounds__(NT) k_persistent(HsArgs<T> a, int iters) {
       const bool last_v = a.trace && si.pos_v == a.deg[si.v] - 1;
       handshake_passes<T, LT, NT, true>(x, sm, L, phi_slot, Uu, Uv, Lu, Lv, last_u || last_v);
       if (tid == 0) {
+        // release at device scope, then the two versions: a waiter that
+        // reads either one and acquires sees every unary this workgroup
+        // wrote before the barrier at the end of the passes
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         st_dev(a.ver + si.u, (int)((unsigned)it * (unsigned)a.deg[si.u] + (unsigned)si.pos_u + 1u));
         st_dev(a.ver + si.v, (int)((unsigned)it * (unsigned)a.deg[si.v] + (unsigned)si.pos_v + 1u));
       }

@@ -58,12 +58,6 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
-// wait until this wave's LDS (and scalar) operations have completed
-__device__ __forceinline__ void wait_lgkm() {
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
 
 // minimum over the 8 lanes of an octet (lane bits 0..2), N values at once
 template <int N> __device__ __forceinline__ void oct_min_n(float (&x)[N]) {
@@ -215,8 +209,8 @@ __device__ __forceinline__ bool wv_run(const WvView& v_in, int first_in, int str
       long long spins = 0;
       if (LDSU) {
         for (;;) {
-          const unsigned cu = (unsigned)__hip_atomic_load(v.lds_ver + si.u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-          const unsigned cv = (unsigned)__hip_atomic_load(v.lds_ver + si.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          const unsigned cu = (unsigned)__hip_atomic_load(v.lds_ver + si.u, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+          const unsigned cv = (unsigned)__hip_atomic_load(v.lds_ver + si.v, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
           if (cu == want_u && cv == want_v) break;
           if (++spins > spin_limit || ((spins & 63) == 0 && (*(volatile int*)abort != 0 || ld_dev(err) != 0))) {
             if (lane == 0) {
@@ -355,10 +349,11 @@ __device__ __forceinline__ bool wv_run(const WvView& v_in, int first_in, int str
         v.lds_hi[(size_t)si.v * L + lane] = nhv;
         v.lds_lo[(size_t)si.v * L + lane] = (unsigned short)(__float_as_uint(nlv) >> 16);
       }
-      wait_lgkm();
+      // (release stores at workgroup scope: a wave whose acquire poll reads
+      // these versions reads the unaries above)
       if (lane == 0) {
-        __hip_atomic_store(v.lds_ver + si.u, (int)(want_u + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        __hip_atomic_store(v.lds_ver + si.v, (int)(want_v + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_store(v.lds_ver + si.u, (int)(want_u + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_store(v.lds_ver + si.v, (int)(want_v + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
       }
     } else {
       mb_store(lout ? v.mb + (size_t)si.u * L + lane : v.sink + lane, mb_pack(nhu, nlu, want_u + 1));
