@@ -384,7 +384,7 @@ def bench_potts(M, W, iters=50, mix_count=64):
     return out
 
 
-def bench_trunc_linear(M, W, iters=50, mix_count=64, tau=8.0):
+def bench_trunc_linear(M, W, iters=50, mix_count=64, tau=8.0, kind=None):
     """Truncated linear costs w min(|s - t|, tau) by their O(L) distance
     transform (mplpxx_*_create_structured, 8 bytes of pairwise data per edge)
     against the dense engines on the expanded tables (4 L^2 bytes): one
@@ -394,7 +394,11 @@ def bench_trunc_linear(M, W, iters=50, mix_count=64, tau=8.0):
     iterations from phi = 0, device times from HIP events.  The structured
     passes round in another order than the dense ones: the largest relative
     difference of the final duals is reported (the parity tests hold both to
-    the oracle at 1e-5)."""
+    the oracle at 1e-5).  kind = COST_TRUNC_QUAD: the same for truncated
+    quadratic costs w min((s - t)^2, tau) (every candidate formed from the two
+    parameters, bitwise the dense engines: the difference is 0)."""
+    kind = M.COST_TRUNC_LINEAR if kind is None else kind
+    make = W.trunc_linear if kind == M.COST_TRUNC_LINEAR else W.trunc_quad
     def run_batch(models, kind):
         with M.Batch(models, kind=kind) as b:
             b.iterate(2)
@@ -413,13 +417,13 @@ def bench_trunc_linear(M, W, iters=50, mix_count=64, tau=8.0):
     out = {"iterations": iters, "tau": tau}
     sizes = W.batched_mix(mix_count, seed=0, models=False)
     for name, sz in (("complete_n200_l64", [(200, 64)]), (f"mix_{mix_count}_complete", sizes)):
-        pairs = [W.trunc_linear(n, L, 1.0, seed=40 + i, tau=tau) for i, (n, L) in enumerate(sz)]
+        pairs = [make(n, L, 1.0, seed=40 + i, tau=tau) for i, (n, L) in enumerate(sz)]
         m_tot = sum(p[0].m for p in pairs)
         b_tl = sum(p[0].m * (8 + 16 * p[0].L) for p in pairs)
         b_d = sum(p[0].m * algorithmic_bytes_per_update(p[0].L) for p in pairs)
         params, dense = [p[0] for p in pairs], [p[1] for p in pairs]
         del pairs
-        ms_t, d_t = run_batch(params, M.COST_TRUNC_LINEAR)
+        ms_t, d_t = run_batch(params, kind)
         ms_d, d_d = run_batch(dense, 0)
         rec = {"models": len(sz), "edges": m_tot, "structured_ms_per_iter": ms_t / iters,
                "dense_ms_per_iter": ms_d / iters, "speedup": ms_d / ms_t,
@@ -428,7 +432,7 @@ def bench_trunc_linear(M, W, iters=50, mix_count=64, tau=8.0):
                "max_rel_dual_difference": float(np.max(np.abs(d_t - d_d) / np.maximum(1.0, np.abs(d_d))))}
         if len(sz) == 1:
             ms_s, d_s = run_single(lambda: M.Solver.from_model(dense[0]))
-            ms_st, d_st = run_single(lambda: M.Solver.from_structured(params[0], M.COST_TRUNC_LINEAR))
+            ms_st, d_st = run_single(lambda: M.Solver.from_structured(params[0], kind))
             rec.update({"single_model_dense_ms_per_iter": ms_s / iters,
                         "single_model_structured_ms_per_iter": ms_st / iters,
                         "single_model_speedup": ms_s / ms_st,
@@ -458,9 +462,10 @@ def summary(result):
     if r and isinstance(r.get("pose_k200_l64"), dict):
         sm["c1_final_dual_by_rule"] = {k: v.get("final_dual") for k, v in r["pose_k200_l64"].items()
                                        if isinstance(v, dict) and "final_dual" in v}
-    t = result.get("trunc_linear")
-    if t:
-        sm["trunc_linear_speedup"] = {k: v.get("speedup") for k, v in t.items() if isinstance(v, dict)}
+    for sec in ("trunc_linear", "trunc_quad"):
+        t = result.get(sec)
+        if t:
+            sm[sec + "_speedup"] = {k: v.get("speedup") for k, v in t.items() if isinstance(v, dict)}
     return sm
 
 
@@ -558,7 +563,9 @@ def main():
     ap.add_argument("--only-batch", action="store_true", help="run only the batched-mix section")
     ap.add_argument("--no-trunc-linear", action="store_true", help="skip the truncated linear vs dense section")
     ap.add_argument("--only-adjoint", action="store_true", help="run only the adjoint (differentiation) section")
-    ap.add_argument("--only-trunc-linear", action="store_true", help="run only the truncated linear section")
+    ap.add_argument("--only-trunc-linear", action="store_true",
+                    help="run only the truncated linear and truncated quadratic sections")
+    ap.add_argument("--no-trunc-quad", action="store_true", help="skip the truncated quadratic vs dense section")
     ap.add_argument("--no-per-problem", action="store_true",
                     help="batched section without the per-problem comparison runs")
     ap.add_argument("--kernel-only", action="store_true",
@@ -588,7 +595,8 @@ def main():
         print(json.dumps({"batched": bench_batched(M, W, per_problem=not args.no_per_problem)}))
         return
     if args.only_trunc_linear:
-        print(json.dumps({"trunc_linear": bench_trunc_linear(M, W)}))
+        print(json.dumps({"trunc_linear": bench_trunc_linear(M, W),
+                          "trunc_quad": bench_trunc_linear(M, W, kind=M.COST_TRUNC_QUAD, tau=64.0)}))
         return
     if args.only_adjoint:
         print(json.dumps({"adjoint": bench_adjoint(M, W)}))
@@ -701,6 +709,8 @@ def main():
         result["potts"] = bench_potts(M, W)
     if not args.no_trunc_linear:
         result["trunc_linear"] = bench_trunc_linear(M, W)
+    if not args.no_trunc_quad:
+        result["trunc_quad"] = bench_trunc_linear(M, W, kind=M.COST_TRUNC_QUAD, tau=64.0)
     result["summary"] = summary(result)
     print(json.dumps(result))
 

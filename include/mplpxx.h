@@ -139,13 +139,19 @@ int mplpxx_create_potts(int32_t n, int32_t L, int64_t m, const int32_t* edges, c
  *                             tau >= 0 (tau >= L - 1: absolute difference
  *                             w |s - t|; tau <= 1: Potts with weight
  *                             fl(w * tau)); symmetric, so the orientation of
- *                             an edge does not matter. */
+ *                             an edge does not matter;
+ *   MPLPXX_COST_TRUNC_QUAD    theta_uv(s, t) = fl(w * min((s - t)^2, tau)),
+ *                             the FP32 product (the square is exact); 2
+ *                             parameters: w >= 0 and tau >= 0 (tau >=
+ *                             (L - 1)^2: quadratic w (s - t)^2; tau <= 1:
+ *                             Potts with weight fl(w * tau)); symmetric. */
 #define MPLPXX_COST_POTTS 1
 #define MPLPXX_COST_TRUNC_LINEAR 2
+#define MPLPXX_COST_TRUNC_QUAD 3
 
 /* A model with structured pairwise costs of one kind (above): params = HOST
  * float [m][P] in the order of edges, P = 1 (Potts) or 2 (truncated
- * linear); unaries as for mplpxx_create (FP32).  Runs on the persistent
+ * linear, truncated quadratic); unaries as for mplpxx_create (FP32).  Runs on the persistent
  * mailbox engine with one compute wave per workgroup in label order.  Potts:
  * as mplpxx_create_potts (bitwise the dense handle on the expanded tables).
  * Truncated linear: each pass is a min-plus distance transform in O(L) work
@@ -153,11 +159,16 @@ int mplpxx_create_potts(int32_t n, int32_t L, int64_t m, const int32_t* edges, c
  * doubling distances within rows of 16 lanes, carried across rows, then the
  * truncation at min_t x(t) + fl(w tau)); the sums are formed in a different
  * order than x(t) + fl(w |s - t|), so results agree with the expanded
- * tables up to FP32 rounding, not bitwise.  dual_bound, decode,
+ * tables up to FP32 rounding, not bitwise.  Truncated quadratic: no table
+ * is stored or read; lane s of the pass evaluates every candidate
+ * fl(x(t) + fl(w min((s - t)^2, tau))) from the two parameters (O(L) steps
+ * with L lanes), so the results are bitwise those of the dense engine on
+ * the expanded table.  dual_bound, decode,
  * iterate_gap, get/set_state and the schedule work as for dense handles
  * (on the expanded costs).  Errors: those of mplpxx_create_potts, and
- * MPLPXX_EINVAL for an unknown kind or, for truncated linear, w < 0,
- * tau < 0, a non-finite parameter or fl(w * tau) above MPLPXX_F32_MAX_COST. */
+ * MPLPXX_EINVAL for an unknown kind or, for truncated linear and
+ * quadratic, w < 0, tau < 0, a non-finite parameter or a cost above
+ * MPLPXX_F32_MAX_COST. */
 int mplpxx_create_structured(int32_t n, int32_t L, int64_t m, const int32_t* edges, const float* unaries,
                              int32_t kind, const float* params, mplpxx_solver** out);
 

@@ -32,8 +32,8 @@ MAX_LABELS = 128
 OPT_ENGINE, OPT_THREADS, OPT_GRID, OPT_SPIN_LIMIT, OPT_PROFILE, OPT_ADJOINT_F64, OPT_RULE = 1, 2, 3, 4, 5, 6, 7
 RULE_H, RULE_M, RULE_U = 0, 1, 2
 SCHED_AUTO, SCHED_GREEDY, SCHED_COLOR = 0, 1, 2
-COST_POTTS, COST_TRUNC_LINEAR = 1, 2
-COST_PARAMS = {COST_POTTS: 1, COST_TRUNC_LINEAR: 2}
+COST_POTTS, COST_TRUNC_LINEAR, COST_TRUNC_QUAD = 1, 2, 3
+COST_PARAMS = {COST_POTTS: 1, COST_TRUNC_LINEAR: 2, COST_TRUNC_QUAD: 2}
 ENGINE_AUTO, ENGINE_STEP, ENGINE_PERSISTENT = 0, 1, 2
 BOPT = {"grid": 1, "graph": 2, "spin_limit": 3, "one_per_model": 4, "handoff_us": 5, "edge16_us": 6,
         "edge32_us": 7, "edge64_us": 8, "edge128_us": 9, "lds": 10, "engine": 11, "wave_edge16_us": 12,
@@ -414,7 +414,7 @@ def solve_noalloc(edges, unaries, pairwise, iters, U_out, phi_out, stream=None):
 
 class Batch:
     """Many independent FP32 models solved together (``mplpxx_batch_*``).
-    ``kind`` (COST_POTTS, COST_TRUNC_LINEAR; ``potts=True`` means COST_POTTS):
+    ``kind`` (COST_POTTS, COST_TRUNC_LINEAR, COST_TRUNC_QUAD; ``potts=True`` means COST_POTTS):
     every model's ``pairwise`` holds the cost's parameters per edge [m, P]
     (``mplpxx_batch_create_structured``)."""
 

@@ -410,7 +410,7 @@ static int create_batch(int32_t count, const int32_t* n, const int32_t* L, const
     for (size_t k = 0; k < (size_t)m[i] * (potts ? (size_t)cost_params(potts) : (size_t)L[i] * L[i]); ++k)
       if (!(std::fabs(pairwise[i][k]) <= (float)MPLPXX_F32_MAX_COST))
         return bail(fail(MPLPXX_EINVAL, "model %d: non-finite or too large pairwise", i));
-    if (potts == MPLPXX_COST_TRUNC_LINEAR && m[i] > 0 && check_trunc_linear_params(pairwise[i], m[i]) != MPLPXX_OK) {
+    if (potts && m[i] > 0 && check_structured_params(potts, pairwise[i], m[i]) != MPLPXX_OK) {
       const std::string msg = g_last_error;
       return bail(fail(MPLPXX_EINVAL, "model %d: %s", i, msg.c_str()));
     }
@@ -509,6 +509,9 @@ static int create_batch(int32_t count, const int32_t* n, const int32_t* L, const
       float* dst = packed.data() + (size_t)s * tl;
       if (potts == MPLPXX_COST_POTTS) {
         *dst = src[0] + 0.0f;  // (a weight of -0 is stored as +0: the table it stands for is the same)
+      } else if (potts == MPLPXX_COST_TRUNC_QUAD) {
+        dst[0] = src[0] + 0.0f;  // (w and tau of -0 as +0: every cost is then +0 or positive)
+        dst[1] = src[1] + 0.0f;
       } else if (potts || !g.flip[e]) {   // (structured costs are symmetric in s, t)
         std::memcpy(dst, src, tl * sizeof(float));
       } else {
@@ -570,7 +573,7 @@ int mplpxx_batch_create_structured(int32_t count, const int32_t* n, const int32_
                                    const int32_t* const* edges, const float* const* unaries, int32_t kind,
                                    const float* const* params, mplpxx_batch** out) {
   if (out) *out = nullptr;
-  if (kind != MPLPXX_COST_POTTS && kind != MPLPXX_COST_TRUNC_LINEAR) return fail(MPLPXX_EINVAL, "unknown cost kind %d", kind);
+  if (!known_cost_kind(kind)) return fail(MPLPXX_EINVAL, "unknown cost kind %d", kind);
   return create_batch(count, n, L, m, edges, unaries, params, kind, out);
 }
 

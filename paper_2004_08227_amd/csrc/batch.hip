@@ -242,13 +242,16 @@ int wbatch_waves() { return kWvWaves; }
 size_t wbatch_sink_words() { return (size_t)kWvWaves * kWvSink; }
 
 static const void* wbatch_kernel(int kind) {
-  return kind == MPLPXX_COST_TRUNC_LINEAR ? (const void*)k_wbatch<MPLPXX_COST_TRUNC_LINEAR>
+  return kind == MPLPXX_COST_TRUNC_QUAD     ? (const void*)k_wbatch<MPLPXX_COST_TRUNC_QUAD>
+         : kind == MPLPXX_COST_TRUNC_LINEAR ? (const void*)k_wbatch<MPLPXX_COST_TRUNC_LINEAR>
          : kind == MPLPXX_COST_POTTS      ? (const void*)k_wbatch<MPLPXX_COST_POTTS>
                                           : (const void*)k_wbatch<kCostDense>;
 }
 
 hipError_t launch_wbatch(const BatchArgs& b, int grid, int iters, size_t dyn_lds, int kind, hipStream_t st) {
-  if (kind == MPLPXX_COST_TRUNC_LINEAR)
+  if (kind == MPLPXX_COST_TRUNC_QUAD)
+    hipLaunchKernelGGL(k_wbatch<MPLPXX_COST_TRUNC_QUAD>, dim3(grid), dim3(kWvWaves * 64), dyn_lds, st, b, iters);
+  else if (kind == MPLPXX_COST_TRUNC_LINEAR)
     hipLaunchKernelGGL(k_wbatch<MPLPXX_COST_TRUNC_LINEAR>, dim3(grid), dim3(kWvWaves * 64), dyn_lds, st, b, iters);
   else if (kind == MPLPXX_COST_POTTS)
     hipLaunchKernelGGL(k_wbatch<MPLPXX_COST_POTTS>, dim3(grid), dim3(kWvWaves * 64), dyn_lds, st, b, iters);

@@ -12,16 +12,20 @@ enum { ENGINE_AUTO = 0, ENGINE_STEP = 1, ENGINE_PERSISTENT = 2 };
 // Pairwise cost of a model: a dense L x L table per edge, or a structured
 // cost given by a few parameters per edge (MPLPXX_COST_* of the header):
 // Potts w [s != t] (1 parameter: w), truncated linear w min(|s - t|, tau)
-// (2 parameters: w, tau).  The parameters of slot i sit at
-// tables[i * cost_params(kind)].
+// and truncated quadratic w min((s - t)^2, tau) (2 parameters: w, tau).  The
+// parameters of slot i sit at tables[i * cost_params(kind)].
 constexpr int kCostDense = 0;
-__host__ __device__ constexpr int cost_params(int kind) { return kind == MPLPXX_COST_TRUNC_LINEAR ? 2 : 1; }
-// th(s, t) of a structured cost from its parameters (the expanded table:
-// for truncated linear the FP32 product w * min(|s - t|, tau))
+__host__ __device__ constexpr int cost_params(int kind) {
+  return kind == MPLPXX_COST_TRUNC_LINEAR || kind == MPLPXX_COST_TRUNC_QUAD ? 2 : 1;
+}
+// fl(w * min(d, tau)) for a distance term d that is exact in FP32: the
+// entry of the expanded table of the truncated kinds
+__host__ __device__ inline float truncated_cost(float w, float tau, float d) { return w * (d < tau ? d : tau); }
+// th(s, t) of a structured cost from its parameters (the expanded table)
 __host__ __device__ inline float structured_cost(int kind, const float* prm, int s, int t) {
-  if (kind == MPLPXX_COST_TRUNC_LINEAR) {
+  if (kind == MPLPXX_COST_TRUNC_LINEAR || kind == MPLPXX_COST_TRUNC_QUAD) {
     const float d = (float)(s > t ? s - t : t - s);
-    return prm[0] * (d < prm[1] ? d : prm[1]);
+    return truncated_cost(prm[0], prm[1], kind == MPLPXX_COST_TRUNC_QUAD ? d * d : d);
   }
   return s == t ? 0.0f : prm[0];
 }

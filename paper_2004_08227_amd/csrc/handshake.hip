@@ -445,7 +445,10 @@ int max_blocks_per_cu_mb_potts() {
 hipError_t launch_persistent_mb_potts(const HsArgs<float>& a, unsigned long long* mb, int grid, int iters,
                                       int phi_in_lds, size_t dyn_lds, hipStream_t st, int kind) {
   void* args[] = {(void*)&a, (void*)&mb, (void*)&iters};
-  const void* f = kind == MPLPXX_COST_TRUNC_LINEAR
+  const void* f = kind == MPLPXX_COST_TRUNC_QUAD
+                      ? (phi_in_lds ? (const void*)k_persistent_mb_potts<true, MPLPXX_COST_TRUNC_QUAD>
+                                    : (const void*)k_persistent_mb_potts<false, MPLPXX_COST_TRUNC_QUAD>)
+                  : kind == MPLPXX_COST_TRUNC_LINEAR
                       ? (phi_in_lds ? (const void*)k_persistent_mb_potts<true, MPLPXX_COST_TRUNC_LINEAR>
                                     : (const void*)k_persistent_mb_potts<false, MPLPXX_COST_TRUNC_LINEAR>)
                       : (phi_in_lds ? (const void*)k_persistent_mb_potts<true, MPLPXX_COST_POTTS>

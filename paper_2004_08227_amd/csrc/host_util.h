@@ -46,6 +46,31 @@ inline int check_trunc_linear_params(const float* prm, int64_t m) {
   return MPLPXX_OK;
 }
 
+// Truncated quadratic parameters (w, tau) per edge: finite, w >= 0, tau >= 0,
+// and every entry fl(w * min(d^2, tau)) within the FP32 cost bound.
+inline int check_trunc_quad_params(const float* prm, int64_t m) {
+  const float dmax = (float)((MPLPXX_MAX_LABELS - 1) * (MPLPXX_MAX_LABELS - 1));
+  for (int64_t e = 0; e < m; ++e) {
+    const float w = prm[2 * e], tau = prm[2 * e + 1];
+    if (!(w >= 0.0f && tau >= 0.0f && std::isfinite(w) && std::isfinite(tau)))
+      return fail(MPLPXX_EINVAL, "edge %lld: truncated quadratic costs need finite w >= 0 and tau >= 0", (long long)e);
+    if (!(w * (tau < dmax ? tau : dmax) <= (float)MPLPXX_F32_MAX_COST))
+      return fail(MPLPXX_EINVAL, "edge %lld: truncated quadratic cost above %g", (long long)e, MPLPXX_F32_MAX_COST);
+  }
+  return MPLPXX_OK;
+}
+
+// parameter check of a structured cost kind (Potts weights are checked as
+// costs by the caller)
+inline int check_structured_params(int kind, const float* prm, int64_t m) {
+  if (kind == MPLPXX_COST_TRUNC_LINEAR) return check_trunc_linear_params(prm, m);
+  if (kind == MPLPXX_COST_TRUNC_QUAD) return check_trunc_quad_params(prm, m);
+  return MPLPXX_OK;
+}
+inline bool known_cost_kind(int kind) {
+  return kind == MPLPXX_COST_POTTS || kind == MPLPXX_COST_TRUNC_LINEAR || kind == MPLPXX_COST_TRUNC_QUAD;
+}
+
 // smallest register tile (16, 32, 64, 128) holding L labels
 inline int next_tile(int L) {
   int lt = 16;

@@ -1,5 +1,5 @@
 // The passes of (H) on an edge with a structured pairwise cost (Potts,
-// truncated linear), in label order (lane l holds label l): shared by the
+// truncated linear, truncated quadratic), in label order (lane l holds label l): shared by the
 // wave engine and the mailbox engine's structured instance.
 #pragma once
 #include "device_common.h"
@@ -150,14 +150,109 @@ __device__ __forceinline__ float tl_pass(float x, bool real, float w, float wt, 
   return vmin(vmin(f, g), xm + wt);
 }
 
+// ---------------------------------------------------------------------------
+// Truncated quadratic terms th(s,t) = fl(w min((s - t)^2, tau)), w, tau >= 0
+// (Sec. 4 names quadratic costs among those whose message passing needs no
+// L x L table).  No table is read: lane s holds the L costs of its row, each
+// formed from the two parameters exactly as the expanded table's entry
+// ((s - t)^2 is exact in FP32, then one rounded product), and a pass takes
+// y(s) = min_t fl(x(t) + th(s,t)) over every candidate t, x(t) coming from
+// lane t as a wave-uniform value.  Each candidate is the same single IEEE
+// add as in the dense passes, and no candidate is -0 (the costs are >= +0
+// and a sum is -0 only when both terms are), so the minimum, and with it
+// every update, is bitwise that of the dense engine on the expanded table.
+// The pass takes L steps with L lanes; the table's 4 L^2 bytes become 8.
+// ---------------------------------------------------------------------------
+// costs of this lane's row s = lane: c[t] = fl(w min((s - t)^2, tau))
+__device__ __forceinline__ void tq_costs(float w, float tau, float (&c)[64]) {
+  const float fs = (float)(threadIdx.x & 63);
+#pragma unroll
+  for (int t = 0; t < 64; ++t) {
+    const float d = fs - (float)t;
+    c[t] = truncated_cost(w, tau, d * d);
+  }
+}
+// y(s) = min over the real labels t of fl(x(t) + c[t]); labels t >= L are
+// visited in whole groups of 8 at most, with x = +inf
+__device__ __forceinline__ float tq_pass(float x, bool real, const float (&c)[64], int L) {
+  const float xs = real ? x : __builtin_inff();
+  float y0 = __builtin_inff(), y1 = __builtin_inff();
+#pragma unroll
+  for (int g = 0; g < 8; ++g) {
+    if (8 * g < L) {
+#pragma unroll
+      for (int k = 0; k < 8; k += 2) {
+        const int t = 8 * g + k;
+        y0 = vmin(y0, lane_value(xs, t) + c[t]);
+        y1 = vmin(y1, lane_value(xs, t + 1) + c[t + 1]);
+      }
+    }
+  }
+  return vmin(y0, y1);
+}
+
+// The same minimum over a window of distances.  Every label t with (s -
+// t)^2 >= tau has th(s,t) = fl(w tau), so
+//   y(s) = min( min_{|s - t| <= D} fl(x(t) + th(s,t)),  fl(min_t x(t) + fl(w tau)) )
+// exactly for any D whose square reaches tau (the second term equals the
+// smallest of the omitted candidates, and is no smaller than a candidate of
+// the table when tau exceeds every (s - t)^2: fl(w .) is monotone).  The
+// labels at distance d come from lanes s - d and s + d by one-lane wave
+// shifts (DPP wave_shr:1, wave_shl:1; lanes shifted in from outside the
+// wave hold +inf); distances are taken in groups of 4 up to D, and the
+// extra ones of the last group are candidates of the table too.
+__device__ __forceinline__ float tq_pass_window(float x, bool real, float w, float tau, int D) {
+  const float kInf = __builtin_inff();
+  const float xs = real ? x : kInf;
+  float y = xs + truncated_cost(w, tau, opaque_zero());   // d = 0
+  float xl = xs, xr = xs;
+#pragma unroll
+  for (int g = 0; g < 16; ++g) {
+    if (4 * g + 1 <= D) {
+#pragma unroll
+      for (int k = 1; k <= 4; ++k) {
+        const float d = (float)(4 * g + k);
+        xl = dpp_shift_inf<0x138>(xl);   // wave_shr:1, from lane s - d
+        xr = dpp_shift_inf<0x130>(xr);   // wave_shl:1, from lane s + d
+        const float c = truncated_cost(w, tau, d * d);
+        y = vmin(y, vmin(xl + c, xr + c));
+      }
+    }
+  }
+  return vmin(y, col4_min(row16_min(xs)) + w * tau);
+}
+
 // New messages of one (H) update of a structured edge, per lane (label): au,
 // av are the centred a'_u, a'_v of this label, prm the edge's parameters
-// (Potts: w; truncated linear: w, tau), delta the shift between the centred
-// passes and the messages.
+// (Potts: w; truncated linear and quadratic: w, tau), delta the shift
+// between the centred passes and the messages.
 template <int KIND>
 __device__ __forceinline__ void structured_passes(float au, float av, const float* prm, bool lout, int L, float delta,
                                                   float& phu, float& phv) {
-  if constexpr (KIND == MPLPXX_COST_TRUNC_LINEAR) {
+  if constexpr (KIND == MPLPXX_COST_TRUNC_QUAD) {
+    const float w = ld_const_f(prm), tau = ld_const_f(prm + 1);
+    // window of distances whose square reaches tau (one more than the
+    // rounded square root, so its rounding cannot matter); the whole row
+    // when that is most of it.  Both forms give the same bits.
+    const int D = uni(min(L - 1, (int)__builtin_sqrtf(tau) + 1));
+    if (2 * D < L) {
+      const float p = tq_pass_window(av, lout, w, tau, D);
+      const float b = 0.5f * (au - p);
+      const float q = tq_pass_window(b, lout, w, tau, D);
+      const float r = tq_pass_window(-q, lout, w, tau, D);
+      phu = r - delta;
+      phv = q + delta;
+    } else {
+      float c[64];
+      tq_costs(w, tau, c);
+      const float p = tq_pass(av, lout, c, L);
+      const float b = 0.5f * (au - p);
+      const float q = tq_pass(b, lout, c, L);
+      const float r = tq_pass(-q, lout, c, L);
+      phu = r - delta;
+      phv = q + delta;
+    }
+  } else if constexpr (KIND == MPLPXX_COST_TRUNC_LINEAR) {
     const float w = ld_const_f(prm), tau = ld_const_f(prm + 1);
     const float wt = w * tau;   // the table's value beyond the truncation
     const float p = tl_pass(av, lout, w, wt, L);

@@ -218,8 +218,7 @@ int create_impl(int32_t n, int32_t L, int64_t m, const int32_t* edges, const voi
   if (sched != MPLPXX_SCHED_AUTO && sched != MPLPXX_SCHED_GREEDY && sched != MPLPXX_SCHED_COLOR)
     return fail(MPLPXX_EINVAL, "unknown schedule kind %d", sched);
   if (m > 0 && (!edges || !pairwise)) return fail(MPLPXX_EINVAL, "edges/pairwise is NULL");
-  if (potts && potts != MPLPXX_COST_POTTS && potts != MPLPXX_COST_TRUNC_LINEAR)
-    return fail(MPLPXX_EINVAL, "unknown cost kind %d", potts);
+  if (potts && !known_cost_kind(potts)) return fail(MPLPXX_EINVAL, "unknown cost kind %d", potts);
   if (potts && (dtype != MPLPXX_F32 || device_costs)) return fail(MPLPXX_EINVAL, "structured costs take FP32 host costs");
   if (potts && L > 64) return fail(MPLPXX_EINVAL, "structured costs take L <= 64 (got %d)", L);
   const size_t esz = dtype == MPLPXX_F32 ? 4 : 8;
@@ -334,6 +333,10 @@ int create_impl(int32_t n, int32_t L, int64_t m, const int32_t* edges, const voi
         if (potts == MPLPXX_COST_POTTS) {
           const float wv = *reinterpret_cast<const float*>(s) + 0.0f;
           std::memcpy(dst, &wv, sizeof(float));
+        } else if (potts == MPLPXX_COST_TRUNC_QUAD) {
+          // (w and tau of -0 as +0: every cost is then +0 or positive)
+          const float wt[2] = {reinterpret_cast<const float*>(s)[0] + 0.0f, reinterpret_cast<const float*>(s)[1] + 0.0f};
+          std::memcpy(dst, wt, sizeof wt);
         } else if (potts || !h->flip[e]) {
           std::memcpy(dst, s, tb);
         } else {
@@ -712,10 +715,10 @@ int mplpxx_create_potts(int32_t n, int32_t L, int64_t m, const int32_t* edges, c
 int mplpxx_create_structured(int32_t n, int32_t L, int64_t m, const int32_t* edges, const float* unaries, int32_t kind,
                              const float* params, mplpxx_solver** out) {
   if (out) *out = nullptr;
-  if (kind != MPLPXX_COST_POTTS && kind != MPLPXX_COST_TRUNC_LINEAR) return fail(MPLPXX_EINVAL, "unknown cost kind %d", kind);
+  if (!known_cost_kind(kind)) return fail(MPLPXX_EINVAL, "unknown cost kind %d", kind);
   if (m > 0 && !params) return fail(MPLPXX_EINVAL, "params is NULL");
-  if (kind == MPLPXX_COST_TRUNC_LINEAR && m > 0 && m <= 0x3fffffff) {
-    const int rc = check_trunc_linear_params(params, m);
+  if (m > 0 && m <= 0x3fffffff) {
+    const int rc = check_structured_params(kind, params, m);
     if (rc != MPLPXX_OK) return rc;
   }
   return create_impl(n, L, m, edges, unaries, params, MPLPXX_F32, false, nullptr, out, MPLPXX_SCHED_AUTO, kind);

@@ -217,6 +217,43 @@ def trunc_linear(n: int, L: int, density: float, seed: int = 0, tau=4.0, w_range
     return params, dense
 
 
+def trunc_quad(n: int, L: int, density: float, seed: int = 0, tau=16.0, w_range=(0.005, 0.05),
+               integer: bool = False):
+    """Truncated quadratic model w_uv min((s - t)^2, tau) on G(n, density)
+    (complete for density >= 1), w_uv ~ U[w_range] (``integer``: w and the
+    unaries small integers, so that many sums tie), unaries U[0,1): (params
+    model with pairwise [m, 2] = (w, tau) per edge, dense model) with the same
+    edges and unaries.  The dense tables are the expansion in FP32:
+    th(s, t) = fl(w * min((s - t)^2, tau)) ((s - t)^2 is exact).  ``tau`` may
+    be a number or an array of m values; tau >= (L - 1)^2 gives the plain
+    quadratic cost.  Stands in for the smoothness costs of the paper's
+    stereo-type datasets (Sec. 7)."""
+    rng = np.random.default_rng(seed)
+    if integer:
+        unaries = rng.integers(0, 4, size=(n, L)).astype(np.float32)
+    else:
+        unaries = rng.random((n, L)).astype(np.float32)
+    if density >= 1.0:
+        edges = complete_edges(n)
+    else:
+        iu = np.triu_indices(n, 1)
+        keep = rng.random(iu[0].shape[0]) < density
+        edges = np.stack([iu[0][keep], iu[1][keep]], axis=1).astype(np.int32)
+    m = edges.shape[0]
+    if integer:
+        w = rng.integers(0, 3, size=m).astype(np.float32)
+    else:
+        w = rng.uniform(w_range[0], w_range[1], size=m).astype(np.float32)
+    t = np.broadcast_to(np.asarray(tau, dtype=np.float32), (m,)).astype(np.float32)
+    name = f"trunc_quad_n{n}_L{L}_p{density}_s{seed}"
+    params = Model(n, L, edges, unaries, np.stack([w, t], axis=1).astype(np.float32), name + "_params")
+    d = (np.arange(L)[:, None] - np.arange(L)[None, :]).astype(np.float32)
+    d2 = d * d
+    dense = Model(n, L, edges, unaries, (w[:, None, None] * np.minimum(d2[None], t[:, None, None])).astype(np.float32),
+                  name)
+    return params, dense
+
+
 def batched_mix(count: int = 256, seed: int = 0, n_range=(20, 300), L_range=(8, 64),
                 dtype=np.float32, models: bool = True):
     """Sizes (and, if ``models``, the models) of the batched pose-shaped mix.

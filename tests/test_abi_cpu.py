@@ -237,15 +237,21 @@ def test_from_torch_rejects_host_tensors_before_any_library_call(monkeypatch):
     assert not called
 
 
-@pytest.mark.parametrize("case", ["neg_w", "neg_tau", "nan_tau", "inf_w", "kind", "null"])
-def test_structured_costs_rejected_without_device_work(case):
-    """Truncated linear parameters need finite w >= 0 and tau >= 0; an
-    unknown cost kind or missing parameters are rejected before any device
-    work (single model and batch)."""
-    params, _ = W.trunc_linear(6, 5, 1.0, seed=0, tau=2.0)
+@pytest.mark.parametrize("case", ["neg_w", "neg_tau", "nan_tau", "inf_w", "kind", "null", "too_large"])
+@pytest.mark.parametrize("cost", ["trunc_linear", "trunc_quad"])
+def test_structured_costs_rejected_without_device_work(case, cost):
+    """Truncated linear and quadratic parameters need finite w >= 0 and tau
+    >= 0 and costs within the FP32 bound; an unknown cost kind or missing
+    parameters are rejected before any device work (single model and
+    batch)."""
+    make = W.trunc_linear if cost == "trunc_linear" else W.trunc_quad
+    params, _ = make(6, 5, 1.0, seed=0, tau=2.0)
     prm = params.pairwise.copy()
-    kind = M.COST_TRUNC_LINEAR
-    if case == "neg_w":
+    kind = M.COST_TRUNC_LINEAR if cost == "trunc_linear" else M.COST_TRUNC_QUAD
+    if case == "too_large":
+        # fl(w tau) above 1e18 (for the quadratic kind also beyond (L_max - 1)^2)
+        prm[2] = (1e15, 1e4)
+    elif case == "neg_w":
         prm[3, 0] = -0.5
     elif case == "neg_tau":
         prm[2, 1] = -1.0
@@ -282,4 +288,17 @@ def test_trunc_linear_expansion_is_the_fp32_product():
         for s in range(9):
             for t in range(9):
                 want = np.float32(w) * np.float32(min(abs(s - t), tau))
+                assert dense.pairwise[e, s, t].view(np.uint32) == np.float32(want).view(np.uint32)
+
+
+def test_trunc_quad_expansion_is_the_fp32_product():
+    """The dense twin of a truncated quadratic model holds fl(w * min((s -
+    t)^2, tau)) in FP32 (the square exact), the same product the device
+    forms for the passes and the dual bound."""
+    params, dense = W.trunc_quad(5, 11, 1.0, seed=3, tau=20.5)
+    for e in range(params.m):
+        w, tau = params.pairwise[e]
+        for s in range(11):
+            for t in range(11):
+                want = np.float32(w) * np.float32(min((s - t) ** 2, tau))
                 assert dense.pairwise[e, s, t].view(np.uint32) == np.float32(want).view(np.uint32)
