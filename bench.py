@@ -458,6 +458,8 @@ def summary(result):
         tw = a.get("fp64_twin", {})
         sm["c4_forward_s"] = tw.get("forward_s")
         sm["c4_backward_s"] = tw.get("backward_s")
+        sm["c4_fp32_forward_s"] = a.get("fp32_forward_s")
+        sm["c4_backward_vs_fp32_forward"] = tw.get("backward_vs_fp32_forward")
     r = result.get("rules")
     if r and isinstance(r.get("pose_k200_l64"), dict):
         sm["c1_final_dual_by_rule"] = {k: v.get("final_dual") for k, v in r["pose_k200_l64"].items()
@@ -485,25 +487,40 @@ def copy_calibration():
 
 def bench_adjoint(M, W, K=50, every=10):
     """Forward (K iterations with checkpoints) and backward of the
-    differentiation workload on an FP32 handle."""
+    differentiation workload on an FP32 handle: by default on its FP64 twin
+    (persistent kernels: one launch per segment and direction), the same
+    with one launch per matching (MPLPXX_OPT_ENGINE = 1, bitwise the same
+    gradients), and the FP32 run's own adjoint; next to the plain FP32
+    forward (K iterations from phi = 0 on the mailbox engine)."""
     import torch
     model = W.uniform(100, 32, seed=0)
     out = {"workload": "uniform n=100 L=32 seed 0, FP32 costs", "K": K, "every": every}
-    for f64 in (1, 0):
+    with M.Solver.from_model(model) as s:
+        U0, phi0 = s.get_state()
+        s.iterate(K)
+        s.set_state(U0, phi0)
+        s.iterate(K)
+        out["fp32_forward_s"] = s.last_iterate_ms() / 1e3
+    grads = {}
+    for key, f64, engine in (("fp64_twin", 1, 0), ("fp64_twin_per_matching", 1, 1), ("fp32_run", 0, 0)):
         with M.Solver.from_model(model) as s:
             s.set_option(M.OPT_ADJOINT_F64, f64)
+            s.set_option(M.OPT_ENGINE, engine)
             s.adjoint_forward(K, every)
             s.adjoint_backward()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             loss = s.adjoint_forward(K, every)
             t1 = time.perf_counter()
-            s.adjoint_backward()
+            gu, gp = s.adjoint_backward()
             t2 = time.perf_counter()
             mem = s.info("adjoint_bytes")
-        key = "fp64_twin" if f64 else "fp32_run"
-        out[key] = {"loss": loss, "forward_s": t1 - t0, "backward_s": t2 - t1, "adjoint_device_bytes": mem,
+        grads[key] = (gu, gp)
+        out[key] = {"loss": loss, "forward_s": t1 - t0, "backward_s": t2 - t1,
+                    "backward_vs_fp32_forward": (t2 - t1) / out["fp32_forward_s"], "adjoint_device_bytes": mem,
                     "model_device_bytes": model.m * (4 * model.L * model.L + 8 * model.L) + model.n * model.L * 12}
+    a, b = grads["fp64_twin"], grads["fp64_twin_per_matching"]
+    out["persistent_equals_per_matching"] = bool(np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]))
     return out
 
 

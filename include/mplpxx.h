@@ -357,7 +357,13 @@ int mplpxx_last_iterate_ms(mplpxx_solver* h, double* ms);
 int mplpxx_adjoint_forward(mplpxx_solver* h, int32_t K, int32_t every, double* loss);
 
 /* Gradient of D_K with respect to the input costs, by reverse sweeps over
- * the recorded minimizers (recomputing each segment from its checkpoint):
+ * the recorded minimizers (recomputing each segment from its checkpoint).
+ * FP64 runs with L <= 64 (an FP64 handle, or the FP64 run of an FP32
+ * handle) use persistent kernels unless MPLPXX_OPT_ENGINE = 1: one launch
+ * reverses a segment while it recomputes the previous one, the node values
+ * and their adjoints passing between workgroups through tagged mailbox
+ * words; otherwise one launch per matching.  Both give the same bits.
+ * Output:
  * DEVICE buffers grad_unaries [n][L] and grad_pairwise [m][L][L] in the
  * handle's dtype and in the caller's layout (edge order and orientation of
  * mplpxx_create).  D_K is piecewise linear in the costs; the gradient is the

@@ -130,6 +130,18 @@ hipError_t launch_adj_step(const SlotInfo* slots, int L, int slot_begin, int cou
                            T* pb, T* thb, hipStream_t st);
 template <typename T>
 hipError_t launch_adj_seed(const T* U, const T* Ulo, int n, int L, T* Ub, double* node_min, hipStream_t st);
+// persistent FP64 adjoint, L <= 64 (adjoint.hip): values in mailboxes of two
+// tagged 64-bit words per label (mb[n][L][2]); rec = nullptr: plain forward
+hipError_t launch_mb64_init(const double* x, unsigned long long* mb, size_t count, hipStream_t st);
+hipError_t launch_mb64_fini(double* x, const unsigned long long* mb, size_t count, hipStream_t st);
+// one launch: the reverse of `seg` recorded iterations (rev_grid workgroups,
+// 0 for none) beside the forward of `iters` iterations (fwd_grid
+// workgroups; fwd_rec: argmin records, or null), then the reverse
+// segment's table adjoints
+hipError_t launch_adj64(const double* tables, double* phi, unsigned long long* mb_fwd, int iters, unsigned char* fwd_rec,
+                        int fwd_grid, const unsigned char* rev_rec, unsigned long long* mb_rev, double* pb,
+                        double* contrib, double* thb, int seg, int rev_grid, const SlotInfo* slots, int L, int m,
+                        int* err, long long spin_limit, hipStream_t st);
 
 int max_blocks_per_cu_mb(int LT, int NT);
 // the (M) and (U) updates on the per-matching engine (rules.hip); rule 1 = M, 2 = U

@@ -89,6 +89,11 @@ struct mplpxx_solver {
   void* d_Ub = nullptr;                   // [n][L]
   void* d_pb = nullptr;                   // [m][2][L]
   void* d_thb = nullptr;                  // [m][L][L]
+  // persistent FP64 adjoint (L <= 64): mailboxes [2][n][L][2] (unaries of
+  // the forward, then their adjoints), and the reverse steps' scatter
+  // vectors [every][m][3][L]; d_rec then holds two segments of records
+  unsigned long long* d_mb64 = nullptr;
+  double* d_contrib = nullptr;
   size_t adj_bytes = 0;                   // device bytes of the adjoint buffers above
   int* d_slot_of_edge = nullptr;          // [m]
   int* d_edge_flip = nullptr;             // [m]
@@ -151,7 +156,7 @@ void free_all(mplpxx_solver* h) {
   void* ptrs[] = {h->d_tables, h->d_phi, h->d_U, h->d_Ulo, h->d_ck_Ulo, h->d_unaries, h->d_slots, h->d_deg, h->d_ver, h->d_err,
                   h->d_node_ptr, h->d_inc, h->d_node_min, h->d_edge_min, h->d_scalar, h->d_labels,
                   h->d_trace_nodes, h->d_trace_out, h->d_trace_e, h->d_mb, h->d_sink, h->d_stamps, h->d_ck_U, h->d_ck_phi,
-                  h->d_rec, h->d_Ub, h->d_pb, h->d_thb, h->d_slot_of_edge, h->d_edge_flip};
+                  h->d_rec, h->d_Ub, h->d_pb, h->d_thb, h->d_slot_of_edge, h->d_edge_flip, h->d_mb64, h->d_contrib};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h->ev0) (void)hipEventDestroy(h->ev0);
@@ -534,23 +539,59 @@ template <typename T> int iterate_t(mplpxx_solver* h, int k, double* trace_host)
 // ---------------------------------------------------------------------------
 namespace {
 
+// FP64 handles with tiles up to 64 labels differentiate on the persistent
+// mailbox kernels (one launch per segment and direction); the per-matching
+// engine option keeps one launch per matching.  Both give the same bits.
+template <typename T> bool adjoint_persistent(const mplpxx_solver* h) {
+  return sizeof(T) == 8 && h->L <= 64 && h->m > 0 && h->engine() != ENGINE_STEP;
+}
+// workgroups of one role of the persistent adjoint launch: one per compute
+// unit for a launch with one role, half of them each when the reverse of
+// one segment runs beside the recomputation of the previous one (a
+// workgroup of either role fits beside one of the other on a unit); at most
+// one per slot
+int adjoint_grid(const mplpxx_solver* h, bool two_roles) {
+  return std::max(1, std::min(h->m, two_roles ? h->num_cus / 2 : h->num_cus));
+}
+
+// `seg` iterations of an FP64 handle on the persistent forward, the
+// unaries through the mailboxes
+int fwd64_segment(mplpxx_solver* h, int seg) {
+  hipStream_t st = h->stream();
+  const size_t nL = (size_t)h->n * h->L;
+  HIP_TRY(launch_mb64_init(static_cast<const double*>(h->d_U), h->d_mb64, nL, st));
+  HIP_TRY(launch_adj64(static_cast<const double*>(h->d_tables), static_cast<double*>(h->d_phi), h->d_mb64, seg, nullptr,
+                       adjoint_grid(h, false), nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0, h->d_slots, h->L,
+                       h->m, h->d_err, h->spin_limit, st));
+  HIP_TRY(launch_mb64_fini(static_cast<double*>(h->d_U), h->d_mb64, nL, st));
+  const int rc = sync_and_check(h);
+  if (rc == MPLPXX_OK) h->iterations += seg;
+  return rc;
+}
+
 template <typename T> int adjoint_forward_t(mplpxx_solver* h, int K, int every, double* loss) {
   hipStream_t st = h->stream();
   const size_t nL = (size_t)h->n * h->L, mp = (size_t)h->m * 2 * h->L, esz = sizeof(T);
   const int nck = (K + every - 1) / every;
+  const bool pers = adjoint_persistent<T>(h);
   // (re)allocate checkpoint and record storage
-  for (void** p : {&h->d_ck_U, &h->d_ck_phi, (void**)&h->d_rec, (void**)&h->d_ck_Ulo})
+  for (void** p : {&h->d_ck_U, &h->d_ck_phi, (void**)&h->d_rec, (void**)&h->d_ck_Ulo, (void**)&h->d_contrib})
     if (*p) { (void)hipFree(*p); *p = nullptr; }
+  if (pers) {
+    if (!h->d_mb64) HIP_TRY(hipMalloc(&h->d_mb64, 2 * nL * 2 * sizeof(unsigned long long)));
+    HIP_TRY(hipMalloc(&h->d_contrib, (size_t)every * h->m * 3 * h->L * sizeof(double)));
+  }
+  const size_t rec_bytes = (pers ? 2 : 1) * (size_t)every * h->m * 3 * h->L;
   HIP_TRY(hipMalloc(&h->d_ck_U, (nck + 1) * nL * esz));
   if (h->d_Ulo) HIP_TRY(hipMalloc((void**)&h->d_ck_Ulo, (nck + 1) * nL * sizeof(float)));
   HIP_TRY(hipMalloc(&h->d_ck_phi, std::max<size_t>(1, (nck + 1) * mp * esz)));
-  HIP_TRY(hipMalloc(&h->d_rec, std::max<size_t>(1, (size_t)every * h->m * 3 * h->L)));
+  HIP_TRY(hipMalloc(&h->d_rec, std::max<size_t>(1, rec_bytes)));
   if (!h->d_Ub) HIP_TRY(hipMalloc(&h->d_Ub, nL * esz));
   if (!h->d_pb) HIP_TRY(hipMalloc(&h->d_pb, std::max<size_t>(1, mp * esz)));
   if (!h->d_thb) HIP_TRY(hipMalloc(&h->d_thb, std::max<size_t>(1, (size_t)h->m * h->L * h->L * esz)));
   h->adj_bytes = (nck + 1) * nL * esz + (h->d_Ulo ? (nck + 1) * nL * sizeof(float) : 0) + (nck + 1) * mp * esz +
-                 (size_t)every * h->m * 3 * h->L + nL * esz + mp * esz + (size_t)h->m * h->L * h->L * esz +
-                 (size_t)h->m * 2 * sizeof(int);
+                 rec_bytes + nL * esz + mp * esz + (size_t)h->m * h->L * h->L * esz + (size_t)h->m * 2 * sizeof(int) +
+                 (pers ? 2 * nL * 2 * sizeof(unsigned long long) + (size_t)every * h->m * 3 * h->L * sizeof(double) : 0);
   if (!h->d_slot_of_edge && h->m) {
     HIP_TRY(hipMalloc(&h->d_slot_of_edge, h->m * sizeof(int)));
     HIP_TRY(hipMalloc(&h->d_edge_flip, h->m * sizeof(int)));
@@ -569,7 +610,7 @@ template <typename T> int adjoint_forward_t(mplpxx_solver* h, int K, int every, 
       HIP_TRY(hipMemcpyAsync(h->d_ck_Ulo + c * nL, h->d_Ulo, nL * sizeof(float), hipMemcpyDeviceToDevice, st));
     if (h->m) HIP_TRY(hipMemcpyAsync((char*)h->d_ck_phi + c * mp * esz, h->d_phi, mp * esz, hipMemcpyDeviceToDevice, st));
     const int seg = std::min(every, K - c * every);
-    const int rc = iterate_t<T>(h, seg, nullptr);
+    const int rc = pers ? fwd64_segment(h, seg) : iterate_t<T>(h, seg, nullptr);
     if (rc != MPLPXX_OK) return rc;
   }
   HIP_TRY(hipMemcpyAsync((char*)h->d_ck_U + nck * nL * esz, h->d_U, nL * esz, hipMemcpyDeviceToDevice, st));
@@ -615,7 +656,41 @@ template <typename T> int adjoint_backward_t(mplpxx_solver* h, void* grad_u, voi
     HIP_TRY(hipMemsetAsync(h->d_pb, 0, mp * esz, st));
     HIP_TRY(hipMemsetAsync(h->d_thb, 0, (size_t)h->m * h->L * h->L * esz, st));
   }
-  for (int c = nck - 1; c >= 0 && h->m > 0; --c) {
+  const bool pers = adjoint_persistent<T>(h) && h->d_mb64 && h->d_contrib;
+  if (pers) {
+    // Persistent pipeline: launch c runs the reverse of segment c beside
+    // the recomputation (with argmin records) of segment c - 1, which needs
+    // only its checkpoint; records alternate between two buffers.  The
+    // first launch recomputes the last segment alone, the last reverses
+    // segment 0 alone.
+    unsigned long long* mb_fwd = h->d_mb64;
+    unsigned long long* mb_rev = h->d_mb64 + 2 * nL;
+    auto rec_of = [&](int c) { return h->d_rec + (size_t)(c & 1) * every * rec_it; };
+    auto seg_of = [&](int c) { return std::min(every, K - c * every); };
+    auto restore = [&](int c) -> hipError_t {
+      hipError_t e = hipMemcpyAsync(h->d_U, (char*)h->d_ck_U + c * nL * esz, nL * esz, hipMemcpyDeviceToDevice, st);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(h->d_phi, (char*)h->d_ck_phi + c * mp * esz, mp * esz, hipMemcpyDeviceToDevice, st);
+      if (e == hipSuccess) e = launch_mb64_init(static_cast<const double*>(h->d_U), mb_fwd, nL, st);
+      return e;
+    };
+    for (int c = nck; c >= 0; --c) {
+      // reverse of segment c (c < nck), recomputation of segment c - 1 (c >= 1)
+      const bool rev = c < nck, fwd = c >= 1;
+      if (fwd) HIP_TRY(restore(c - 1));
+      if (rev) HIP_TRY(launch_mb64_init(static_cast<const double*>(h->d_Ub), mb_rev, nL, st));
+      const bool both = rev && fwd;
+      HIP_TRY(launch_adj64(static_cast<const double*>(h->d_tables), static_cast<double*>(h->d_phi), mb_fwd,
+                           fwd ? seg_of(c - 1) : 0, fwd ? rec_of(c - 1) : nullptr, adjoint_grid(h, both),
+                           rev ? rec_of(c) : nullptr, mb_rev, static_cast<double*>(h->d_pb), h->d_contrib,
+                           static_cast<double*>(h->d_thb), rev ? seg_of(c) : 0, adjoint_grid(h, both), h->d_slots,
+                           h->L, h->m, h->d_err, h->spin_limit, st));
+      if (rev) HIP_TRY(launch_mb64_fini(static_cast<double*>(h->d_Ub), mb_rev, nL, st));
+      const int rc = sync_and_check(h);
+      if (rc != MPLPXX_OK) return rc;
+    }
+  }
+  for (int c = nck - 1; c >= 0 && h->m > 0 && !pers; --c) {
     const int seg = std::min(every, K - c * every);
     HIP_TRY(hipMemcpyAsync(h->d_U, (char*)h->d_ck_U + c * nL * esz, nL * esz, hipMemcpyDeviceToDevice, st));
     if (lo) HIP_TRY(hipMemcpyAsync(lo, ck_lo + c * nL, nL * esz, hipMemcpyDeviceToDevice, st));
@@ -759,6 +834,8 @@ int mplpxx_adjoint_forward(mplpxx_solver* h, int32_t K, int32_t every, double* l
       const int rc = make_shadow(h);
       if (rc != MPLPXX_OK) return rc;
     }
+    h->shadow->engine_opt = h->engine_opt;  // (one launch per matching, or persistent)
+    h->shadow->spin_limit = h->spin_limit;
     int rc = adjoint_forward_t<double>(h->shadow, K, every, loss);
     if (rc != MPLPXX_OK) return rc;
     // the handle's own FP32 run of K iterations from phi = 0

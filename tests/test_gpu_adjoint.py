@@ -184,19 +184,27 @@ def test_autograd_function():
 def test_adjoint_memory_is_reported():
     """MPLPXX_INFO_ADJOINT_BYTES after a forward: checkpoints (K/every + 1
     copies of U and phi), one segment of argmin records (3 L bytes per edge
-    and iteration), the adjoint buffers; an FP32 handle differentiating its
-    FP64 twin adds the twin's costs and state."""
+    and iteration), the adjoint buffers, and on the persistent path (FP64,
+    L <= 64) a second segment of records, two sets of two-word mailboxes of
+    the nodes (16 bytes per label each) and one segment of the reverse
+    steps' scatter vectors (3 L doubles per edge and iteration); an FP32 handle differentiating its FP64 twin adds the twin's
+    costs and state."""
     _announce("adjoint bytes")
     n, L, K, every = 12, 5, 9, 4
     m64 = W.uniform(n, L, seed=3, dtype=np.float64)
     m = m64.m
     nck = (K + every - 1) // every
     nL, mp = n * L, m * 2 * L
-    own64 = (nck + 1) * nL * 8 + (nck + 1) * mp * 8 + every * m * 3 * L + nL * 8 + mp * 8 + m * L * L * 8 + m * 8
+    per_matching = (nck + 1) * nL * 8 + (nck + 1) * mp * 8 + every * m * 3 * L + nL * 8 + mp * 8 + m * L * L * 8 + m * 8
+    own64 = per_matching + every * m * 3 * L + 2 * nL * 16 + every * m * 3 * L * 8
     with M.Solver.from_model(m64) as s:
         assert s.info("adjoint_bytes") == 0
         s.adjoint_forward(K, every)
         assert s.info("adjoint_bytes") == own64
+    with M.Solver.from_model(m64) as s:
+        s.set_option(M.OPT_ENGINE, 1)
+        s.adjoint_forward(K, every)
+        assert s.info("adjoint_bytes") == per_matching
     m32 = W.uniform(n, L, seed=3, dtype=np.float32)
     with M.Solver.from_model(m32) as s:
         s.set_option(M.OPT_ADJOINT_F64, 1)
@@ -232,3 +240,36 @@ def test_fp64_adjoint_at_large_labels(n, L, K):
         worst = max(worst, abs(float(flat[c]) - ref))
     print(f"L={L}: {len(flat) and nonzero} nonzero references, worst error {worst:.2e}", flush=True)
     assert worst <= 1e-10
+
+
+@pytest.mark.parametrize("name,make,K,every", [
+    ("uniform_n9_L4_fp64", lambda: W.uniform(9, 4, seed=41, dtype=np.float64), 6, 4),
+    ("pose_n24_L13_ragged", lambda: W.pose(24, 13, seed=42), 7, 3),
+    ("uniform_n30_L32", lambda: W.uniform(30, 32, seed=43), 9, 10),
+    ("pose_n20_L33_ragged", lambda: W.pose(20, 33, seed=44), 5, 2),
+    ("uniform_n16_L64", lambda: W.uniform(16, 64, seed=45), 4, 3),
+    ("er_n40_L16_greedy", lambda: W.potts_er(40, 16, 0.3, seed=46), 6, 4),
+    ("single_label_n6", lambda: W.uniform(6, 1, seed=47), 3, 2),
+])
+def test_persistent_adjoint_equals_per_matching_adjoint(name, make, K, every):
+    """The persistent FP64 adjoint (forward, recorded recomputation and
+    reverse in one launch per segment, values through tagged mailboxes,
+    table adjoints added per slot) gives bitwise the loss and gradients of
+    the per-matching kernels (MPLPXX_OPT_ENGINE = 1), for FP64 handles and
+    for the FP64 twin of FP32 handles, with ragged tiles, a partial last
+    segment, a greedy schedule and a single label."""
+    _announce("persistent adjoint vs per-matching", name)
+    model = make()
+    out = {}
+    for engine in (1, 0):
+        with M.Solver.from_model(model) as s:
+            s.set_option(M.OPT_ENGINE, engine)
+            loss = s.adjoint_forward(K, every)
+            gu, gp = s.adjoint_backward()
+            U, phi = s.get_state()
+        out[engine] = (loss, gu, gp, U, phi)
+    a, b = out[1], out[0]
+    assert a[0] == b[0], (a[0], b[0])
+    for x, y in zip(a[1:], b[1:]):
+        assert np.array_equal(x.view(np.uint8), y.view(np.uint8))
+    print(f"{name}: loss {b[0]:.12g}, |grad_u|_1 {np.abs(b[1]).sum():.6g}, bitwise equal", flush=True)
