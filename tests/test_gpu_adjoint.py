@@ -221,7 +221,10 @@ def test_fp64_adjoint_at_large_labels(n, L, K):
     and no argmin moves), so the gradient sums to 1 over each node's L
     entries and over each edge's L x L entries; and up to 32 coordinates, three
     quarters of them where the oracle's final state says the gradient is
-    likely nonzero, match the oracle's derivative with no misses."""
+    likely nonzero, plus 16 pairwise coordinates where the GPU gradient
+    itself is nonzero (a gradient placed at a wrong (s, t) would meet an
+    oracle derivative of 0 there), match the oracle's exact derivative with
+    no misses, at least 16 of them nonzero."""
     import sys
     sys.path.insert(0, GOLD)
     import make_golden as MG
@@ -233,13 +236,18 @@ def test_fp64_adjoint_at_large_labels(n, L, K):
     assert np.max(np.abs(gu.sum(axis=1) - 1.0)) <= 1e-9
     assert np.max(np.abs(gp.sum(axis=(1, 2)) - 1.0)) <= 1e-9
     flat = np.concatenate([gu.ravel(), gp.ravel()])
+    coords = list(MG.adjoint_coords(model, st.Tu, st.Te, 32, L))
+    support = np.flatnonzero(gp.ravel()) + gu.size
+    rng = np.random.default_rng(L)
+    coords += [int(c) for c in rng.choice(support, size=min(16, support.size), replace=False)]
     worst, nonzero = 0.0, 0
-    for c in MG.adjoint_coords(model, st.Tu, st.Te, 32, L):
+    for c in coords:
         ref = oracle.dual_derivative(model, K, *MG.coord_direction(model, c))
         nonzero += ref != 0.0
         worst = max(worst, abs(float(flat[c]) - ref))
-    print(f"L={L}: {len(flat) and nonzero} nonzero references, worst error {worst:.2e}", flush=True)
+    print(f"L={L}: {len(coords)} coordinates, {nonzero} nonzero references, worst error {worst:.2e}", flush=True)
     assert worst <= 1e-10
+    assert nonzero >= 16
 
 
 @pytest.mark.parametrize("name,make,K,every", [
