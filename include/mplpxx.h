@@ -292,6 +292,12 @@ int mplpxx_iterate_trace(mplpxx_solver* h, int32_t k, double* trace);
 #define MPLPXX_OPT_PROFILE 5     /* 1: record per-slot timestamps (persistent FP32 engine) */
 #define MPLPXX_OPT_ADJOINT_F64 6 /* FP32 handles: 1 (default) differentiate an FP64 run on the same costs
                                     (exactly widened); 0: differentiate the FP32 run itself */
+#define MPLPXX_OPT_PHI 8         /* FP32 persistent engine, where a workgroup keeps the messages of its
+                                    slots: 0 auto (LDS when they fit 96 KB and one workgroup runs per
+                                    compute unit), 1 the same, 2 global memory */
+#define MPLPXX_OPT_PREFETCH 9    /* FP32 persistent engine, dense tables up to 64 labels: steps ahead the
+                                    tables are loaded into the register ring, 0 auto (2), 1 or 2
+                                    (per-iteration traces always use 2) */
 /* The BCA-update applied to every edge (Sec. 4), unlike the options above a
  * change of the method: MPLPXX_RULE_H (default) the MPLP++ handshake (H);
  * MPLPXX_RULE_M the MPLP update (M), both nodes get half of the row and

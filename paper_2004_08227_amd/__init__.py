@@ -30,6 +30,7 @@ F32, F64 = 0, 1
 OK, EINVAL, ENOMEM, EDEVICE, ETIMEOUT, ESTATE = 0, -1, -2, -3, -4, -5
 MAX_LABELS = 128
 OPT_ENGINE, OPT_THREADS, OPT_GRID, OPT_SPIN_LIMIT, OPT_PROFILE, OPT_ADJOINT_F64, OPT_RULE = 1, 2, 3, 4, 5, 6, 7
+OPT_PHI, OPT_PREFETCH = 8, 9
 RULE_H, RULE_M, RULE_U = 0, 1, 2
 SCHED_AUTO, SCHED_GREEDY, SCHED_COLOR = 0, 1, 2
 COST_POTTS, COST_TRUNC_LINEAR, COST_TRUNC_QUAD = 1, 2, 3

@@ -92,7 +92,11 @@ def apply_batch(batch, models, table=None):
 # ---------------------------------------------------------------------------
 def solver_candidates(M, solver):
     """Options worth timing for this handle: the persistent engine at each
-    valid thread count and a few grids, and the per-matching engine."""
+    valid thread count and a few grids, and the per-matching engine; for
+    FP32 handles also where a workgroup keeps its messages (LDS or global
+    memory) and how far ahead the tables are prefetched (one step or two),
+    at the default threads and grid and at the grid of one workgroup per
+    edge of a matching when that differs."""
     L = solver.info("L")
     lt = next_tile(L)
     f32 = solver.info("dtype") == M.F32
@@ -106,6 +110,15 @@ def solver_candidates(M, solver):
             if c != {"OPT_ENGINE": M.ENGINE_PERSISTENT, "OPT_THREADS": 256}:
                 cands.append(c)
     cands.append({"OPT_ENGINE": M.ENGINE_STEP})
+    if f32:
+        for phi, pre in ((2, 0), (0, 1), (2, 1)):
+            c = {"OPT_ENGINE": M.ENGINE_PERSISTENT}
+            if phi:
+                c["OPT_PHI"] = phi
+            if pre and lt <= 64:
+                c["OPT_PREFETCH"] = pre
+            if len(c) > 1:
+                cands.append(c)
     return cands
 
 
@@ -242,7 +255,8 @@ def tune_batch(models, iters=10, rounds=2, log=None, gain=0.97, repeats=2):
 # ---------------------------------------------------------------------------
 def build_table(log=print, quick=False):
     table = {}
-    solver_models = [W.pose(200, 64, seed=0), W.potts_er(1000, 16, 0.25, seed=0), W.uniform(100, 32, seed=0).astype(np.float32)]
+    solver_models = [W.pose(200, 64, seed=0), W.potts_er(1000, 16, 0.05, seed=0), W.potts_er(1000, 16, 0.25, seed=0),
+                     W.potts_er(1000, 16, 1.0, seed=0), W.uniform(100, 32, seed=0).astype(np.float32)]
     if quick:
         solver_models = solver_models[:1]
     for mo in solver_models:

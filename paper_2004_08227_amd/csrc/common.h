@@ -152,8 +152,10 @@ hipError_t launch_handshake(const HsArgs<T>& a, int engine, int LT, int NT, int 
                             int iters, hipStream_t st);
 template <typename T> int max_blocks_per_cu(int engine, int LT, int NT);
 // FP32 persistent engine with tagged mailboxes
+// prefetch: steps the tables are loaded ahead (0 the default: 2 for tiles up
+// to 64, 1 for 128; 1: one step, for tiles up to 64 without a trace)
 hipError_t launch_persistent_mb(const HsArgs<float>& a, unsigned long long* mb, int LT, int NT, int grid, int iters,
-                                int phi_in_lds, size_t dyn_lds, hipStream_t st);
+                                int phi_in_lds, size_t dyn_lds, hipStream_t st, int prefetch = 0);
 // the same for Potts models (one weight per slot, L <= 64; potts_mb.h)
 int max_blocks_per_cu_mb_potts();
 hipError_t launch_persistent_mb_potts(const HsArgs<float>& a, unsigned long long* mb, int grid, int iters,

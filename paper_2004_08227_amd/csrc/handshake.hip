@@ -265,7 +265,7 @@ __global__ void __launch_bounds__(NT) k_persistent(HsArgs<T> a, int iters) {
   }
 }
 
-template <int LT, int NT, bool PHI_LDS, bool FULL, bool TRACE, bool PHI_FAR>
+template <int LT, int NT, bool PHI_LDS, bool FULL, bool TRACE, bool PHI_FAR, int DEPTH = (LT <= 64 ? 2 : 1)>
 __global__ void __launch_bounds__(NT + 128) k_persistent_mb(HsArgs<float> a, unsigned long long* __restrict__ mb,
                                                             int iters) {
   __shared__ SmemMB<LT, NT> sm;
@@ -282,8 +282,8 @@ __global__ void __launch_bounds__(NT + 128) k_persistent_mb(HsArgs<float> a, uns
   __syncthreads();
   MbView v{a.tables, a.phi, mb, a.slots, a.deg, a.trace, a.trace_e, a.stamps, L, a.m, a.n, nullptr, nullptr,
            a.sink + (size_t)blockIdx.x * (NT + 128)};
-  if (!mb_run<LT, NT, PHI_LDS, FULL, TRACE, false, PHI_FAR>(v, blockIdx.x, G, iters, sm, phi_lds, a.spin_limit,
-                                                            a.err))
+  if (!mb_run<LT, NT, PHI_LDS, FULL, TRACE, false, PHI_FAR, DEPTH>(v, blockIdx.x, G, iters, sm, phi_lds, a.spin_limit,
+                                                                   a.err))
     return;
   __syncthreads();
   if (PHI_LDS) {
@@ -361,20 +361,23 @@ static hipError_t launch_one(const HsArgs<T>& a, int engine, int slot_begin, int
 
 template <int LT, int NT>
 static hipError_t launch_mb_one(const HsArgs<float>& a, unsigned long long* mb, int grid, int iters, int phi_in_lds,
-                                size_t dyn_lds, hipStream_t st) {
+                                size_t dyn_lds, hipStream_t st, int prefetch) {
   void* args[] = {(void*)&a, (void*)&mb, (void*)&iters};
   const bool full = a.L == LT;
-  // messages prefetched with the tables when every workgroup owns at least
-  // DEPTH + 2 slots (the engine's rule; DEPTH is 2 for tiles up to 64)
-  const int depth = LT <= 64 ? 2 : 1;
+  // tables prefetched DEPTH steps ahead (2 for tiles up to 64 unless one
+  // step is asked for; 1 for 128 and for traces); messages prefetched with
+  // them when every workgroup owns at least DEPTH + 2 slots
+  const int depth = (LT <= 64 && !a.trace && prefetch != 1) || (LT <= 64 && a.trace) ? 2 : 1;
   const bool far = (a.m / grid) >= depth + 2;
-#define MPLPXX_PICK(TR, FA)                                                                          \
-  (phi_in_lds ? (full ? (const void*)k_persistent_mb<LT, NT, true, true, TR, FA>                     \
-                      : (const void*)k_persistent_mb<LT, NT, true, false, TR, FA>)                   \
-              : (full ? (const void*)k_persistent_mb<LT, NT, false, true, TR, FA>                    \
-                      : (const void*)k_persistent_mb<LT, NT, false, false, TR, FA>))
-  const void* f = a.trace ? (far ? MPLPXX_PICK(true, true) : MPLPXX_PICK(true, false))
-                          : (far ? MPLPXX_PICK(false, true) : MPLPXX_PICK(false, false));
+#define MPLPXX_PICK(TR, FA, D)                                                                       \
+  (phi_in_lds ? (full ? (const void*)k_persistent_mb<LT, NT, true, true, TR, FA, D>                  \
+                      : (const void*)k_persistent_mb<LT, NT, true, false, TR, FA, D>)                \
+              : (full ? (const void*)k_persistent_mb<LT, NT, false, true, TR, FA, D>                 \
+                      : (const void*)k_persistent_mb<LT, NT, false, false, TR, FA, D>))
+  constexpr int D0 = LT <= 64 ? 2 : 1;
+  const void* f = a.trace ? (far ? MPLPXX_PICK(true, true, D0) : MPLPXX_PICK(true, false, D0))
+                  : depth == D0 ? (far ? MPLPXX_PICK(false, true, D0) : MPLPXX_PICK(false, false, D0))
+                                : (far ? MPLPXX_PICK(false, true, 1) : MPLPXX_PICK(false, false, 1));
 #undef MPLPXX_PICK
   const hipError_t e = hipLaunchCooperativeKernel(f, dim3(grid), dim3(NT + 128), args, dyn_lds, st);
   // a refused launch returns its error here; clear the runtime's copy so
@@ -421,9 +424,9 @@ int max_blocks_per_cu_mb(int LT, int NT) {
 }
 
 hipError_t launch_persistent_mb(const HsArgs<float>& a, unsigned long long* mb, int LT, int NT, int grid, int iters,
-                                int phi_in_lds, size_t dyn_lds, hipStream_t st) {
+                                int phi_in_lds, size_t dyn_lds, hipStream_t st, int prefetch) {
 #define MPLPXX_CASE(lt, nt) \
-  if (LT == lt && NT == nt) return launch_mb_one<lt, nt>(a, mb, grid, iters, phi_in_lds, dyn_lds, st);
+  if (LT == lt && NT == nt) return launch_mb_one<lt, nt>(a, mb, grid, iters, phi_in_lds, dyn_lds, st, prefetch);
   MPLPXX_CASE(16, 256)
   MPLPXX_CASE(32, 256)
   MPLPXX_CASE(32, 512)

@@ -109,6 +109,8 @@ struct mplpxx_solver {
   int threads_opt = 0;
   int potts = 0;             // structured cost kind (MPLPXX_COST_*): d_tables holds its parameters per slot
   int grid_opt = 0;
+  int phi_opt = 0;       // FP32 persistent engine: 0 auto, 1 messages in LDS when they fit, 2 in global memory
+  int prefetch_opt = 0;  // FP32 persistent engine: tables loaded 1 or 2 steps ahead (0 auto)
   long long spin_limit = 1ll << 22;
   int num_cus = 0;
   long long iterations = 0;
@@ -500,10 +502,10 @@ template <typename T> int iterate_t(mplpxx_solver* h, int k, double* trace_host)
       const size_t phi_bytes = owned * 2 * h->L * sizeof(float);
       // (more than one workgroup per compute unit: messages in HBM, so that
       // the workgroups' LDS never limits how many fit)
-      const int in_lds = phi_bytes <= kPhiLdsBudget && G <= h->num_cus ? 1 : 0;
+      const int in_lds = phi_bytes <= kPhiLdsBudget && G <= h->num_cus && h->phi_opt != 2 ? 1 : 0;
       HIP_TRY(launch_mb_init(static_cast<const float*>(h->d_U), h->d_Ulo, h->d_mb, (size_t)h->n * h->L, st));
       if (h->potts) HIP_TRY(launch_persistent_mb_potts(a, h->d_mb, G, k, in_lds, in_lds ? phi_bytes : 0, st, h->potts));
-      else HIP_TRY(launch_persistent_mb(a, h->d_mb, LT, NT, G, k, in_lds, in_lds ? phi_bytes : 0, st));
+      else HIP_TRY(launch_persistent_mb(a, h->d_mb, LT, NT, G, k, in_lds, in_lds ? phi_bytes : 0, st, h->prefetch_opt));
       HIP_TRY(launch_mb_fini(static_cast<float*>(h->d_U), h->d_Ulo, h->d_mb, h->n, h->L,
                              trace_host ? h->d_trace_nodes + (size_t)(k - 1) * h->n : nullptr, st));
     } else {
@@ -1134,6 +1136,14 @@ int mplpxx_set_option(mplpxx_solver* h, int32_t key, int64_t value) {
       return MPLPXX_OK;
     case MPLPXX_OPT_PROFILE:
       h->profile = value != 0;
+      return MPLPXX_OK;
+    case MPLPXX_OPT_PHI:
+      if (value < 0 || value > 2) return fail(MPLPXX_EINVAL, "phi placement must be 0, 1 or 2");
+      h->phi_opt = (int)value;
+      return MPLPXX_OK;
+    case MPLPXX_OPT_PREFETCH:
+      if (value < 0 || value > 2) return fail(MPLPXX_EINVAL, "prefetch must be 0, 1 or 2");
+      h->prefetch_opt = (int)value;
       return MPLPXX_OK;
     case MPLPXX_OPT_ADJOINT_F64:
       h->adjoint_f64 = value != 0;
