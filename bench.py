@@ -538,6 +538,21 @@ def loaded_runtimes():
     return sorted(out)
 
 
+def code_mappings():
+    """Executable mappings of this process (address range, path), for
+    reading addresses in a crash report."""
+    out = []
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                parts = line.split()
+                if len(parts) >= 6 and "x" in parts[1]:
+                    out.append(f"{parts[0]} {parts[5]}")
+    except OSError:
+        pass
+    return out
+
+
 def kernel_only(steps, warmup):
     """The C1 launch alone, without PyTorch, on the library build linked
     against /opt/rocm's HIP runtime: the process for rocprofv3 runs (whose
@@ -558,6 +573,9 @@ def kernel_only(steps, warmup):
         print(json.dumps({"kernel_only": "pose_k200_l64", "steps": steps, "ms_per_step": ms / steps, "dual_bound": d,
                           "hbm_frac": model.m * steps * algorithmic_bytes_per_update(64) / (ms / 1e3) / 1e9 /
                           HBM_PEAK_GBS, "runtimes": loaded_runtimes()}), flush=True)
+    # (on stderr: the process's code mappings, to place the frames of a
+    # report from exit handlers that run after this line)
+    print("\n".join(code_mappings()), file=sys.stderr, flush=True)
 
 
 def main():

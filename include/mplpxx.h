@@ -116,15 +116,19 @@ int mplpxx_create_sched(int32_t n, int32_t L, int64_t m, const int32_t* edges, c
  * notes that message passing then takes O(L)): weights = HOST float [m],
  * one weight per edge in the order of edges (any sign; -0 counts as +0);
  * unaries as for mplpxx_create (FP32).  The handle runs on the persistent
- * mailbox engine with one compute wave per workgroup in label order (three
- * passes of a minimum / second-minimum reduction over the lanes instead of
- * the L x L tile); its results are bitwise those of an FP32 handle created
- * with the expanded tables.  dual_bound, decode, iterate_gap, get/set_state,
+ * mailbox engine, either with one compute wave per workgroup in label order
+ * (three passes of a minimum / second-minimum reduction over the lanes
+ * instead of the L x L tile; MPLPXX_OPT_THREADS = 64, the default above 32
+ * labels) or with the dense engine's four compute waves, each tile formed
+ * in registers from the edge's weight instead of loaded
+ * (MPLPXX_OPT_THREADS = 256, the default up to 32 labels); either way its
+ * results are bitwise those of an FP32 handle created with the expanded
+ * tables.  dual_bound, decode, iterate_gap, get/set_state,
  * schedule and step profile work as for dense handles.  Errors: those of
  * mplpxx_create, and MPLPXX_EINVAL for L > 64 or a node degree >= 65536;
  * later, MPLPXX_EINVAL from mplpxx_iterate_trace, mplpxx_adjoint_forward,
- * MPLPXX_OPT_ENGINE = per-matching, MPLPXX_OPT_THREADS != 0 and
- * MPLPXX_OPT_RULE other than (H). */
+ * MPLPXX_OPT_ENGINE = per-matching, MPLPXX_OPT_THREADS other than 0, 64
+ * and 256, and MPLPXX_OPT_RULE other than (H). */
 int mplpxx_create_potts(int32_t n, int32_t L, int64_t m, const int32_t* edges, const float* unaries,
                         const float* weights, mplpxx_solver** out);
 
@@ -152,8 +156,12 @@ int mplpxx_create_potts(int32_t n, int32_t L, int64_t m, const int32_t* edges, c
 /* A model with structured pairwise costs of one kind (above): params = HOST
  * float [m][P] in the order of edges, P = 1 (Potts) or 2 (truncated
  * linear, truncated quadratic); unaries as for mplpxx_create (FP32).  Runs on the persistent
- * mailbox engine with one compute wave per workgroup in label order.  Potts:
- * as mplpxx_create_potts (bitwise the dense handle on the expanded tables).
+ * mailbox engine with one compute wave per workgroup in label order, or,
+ * for Potts and truncated quadratic costs, on its four compute waves with
+ * each tile formed from the edge's parameters (MPLPXX_OPT_THREADS 64 or
+ * 256; the default: 256 for truncated quadratic costs, for Potts costs up to
+ * 32 labels).  Potts: as mplpxx_create_potts (bitwise the dense handle on
+ * the expanded tables).
  * Truncated linear: each pass is a min-plus distance transform in O(L) work
  * and O(log L) steps (prefix and suffix minima of x(t) + w |s - t| by
  * doubling distances within rows of 16 lanes, carried across rows, then the

@@ -154,8 +154,10 @@ template <typename T> int max_blocks_per_cu(int engine, int LT, int NT);
 // FP32 persistent engine with tagged mailboxes
 // prefetch: steps the tables are loaded ahead (0 the default: 2 for tiles up
 // to 64, 1 for 128; 1: one step, for tiles up to 64 without a trace)
+// kind: a structured cost (Potts or truncated quadratic, NT = 256, LT <= 64)
+// whose tiles are formed from the slots' parameters
 hipError_t launch_persistent_mb(const HsArgs<float>& a, unsigned long long* mb, int LT, int NT, int grid, int iters,
-                                int phi_in_lds, size_t dyn_lds, hipStream_t st, int prefetch = 0);
+                                int phi_in_lds, size_t dyn_lds, hipStream_t st, int prefetch = 0, int kind = 0);
 // the same for Potts models (one weight per slot, L <= 64; potts_mb.h)
 int max_blocks_per_cu_mb_potts();
 hipError_t launch_persistent_mb_potts(const HsArgs<float>& a, unsigned long long* mb, int grid, int iters,

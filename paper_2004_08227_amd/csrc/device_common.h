@@ -423,6 +423,47 @@ __device__ __forceinline__ void pad_tile(int L, float (&x)[TileShape<float, LT, 
   }
 }
 
+// A +0 the compiler cannot see (a visible constant would let it rewrite
+// fl(0 - q) under a minimum as -q, which is -0 for q = +0).
+__device__ __forceinline__ float opaque_zero() {
+  float z = 0.0f;
+  asm volatile("" : "+v"(z));
+  return z;
+}
+// scalar load of read-only data through the constant address space
+__device__ __forceinline__ float ld_const_f(const float* p) {
+  return *(const __attribute__((address_space(4))) float*)p;
+}
+
+// The register tile of a structured cost, formed from the slot's
+// parameters instead of loaded: entry (s, t) is exactly the expanded
+// table's value (Potts: +0 on the diagonal, w off it; truncated quadratic:
+// fl(w min((s - t)^2, tau))), so the passes give the dense engine's bits.
+// Entries outside L x L are replaced by the pad at use (pad_tile).
+template <int LT, int NT, int KIND>
+__device__ __forceinline__ void gen_tile(const float* prm, float (&x)[TileShape<float, LT, NT>::BR][TileShape<float, LT, NT>::BC]) {
+  using S = TileShape<float, LT, NT>;
+  const int rb = threadIdx.x >> 4, cb = threadIdx.x & 15;
+  const float w = ld_const_f(prm);
+  if constexpr (KIND == MPLPXX_COST_POTTS) {
+    const float z = opaque_zero();
+#pragma unroll
+    for (int i = 0; i < S::BR; ++i)
+#pragma unroll
+      for (int j = 0; j < S::BC; ++j) x[i][j] = (rb * S::BR + i == cb * S::BC + j) ? z : w;
+  } else {
+    static_assert(KIND == MPLPXX_COST_TRUNC_QUAD, "tiles are formed for Potts and truncated quadratic costs");
+    const float tau = ld_const_f(prm + 1);
+#pragma unroll
+    for (int i = 0; i < S::BR; ++i)
+#pragma unroll
+      for (int j = 0; j < S::BC; ++j) {
+        const float d = (float)(rb * S::BR + i - cb * S::BC - j);
+        x[i][j] = truncated_cost(w, tau, d * d);
+      }
+  }
+}
+
 // Messages of one slot for this thread's rows (into u) and columns (into v).
 template <int LT, int NT, bool PHI_LDS, bool FULL>
 __device__ __forceinline__ void load_phi(const float* src, int L, float (&pu)[TileShape<float, LT, NT>::BR],
@@ -472,7 +513,11 @@ __device__ __forceinline__ void load_phi(const float* src, int L, float (&pu)[Ti
 // computes; that is safe inside a matching (its edges share no node), and
 // before the first slot of every matching all threads meet at one more
 // barrier, after the previous slot's results are written.
-template <int LT, int NT, bool PHI_LDS, bool FULL, bool TRACE, bool LDSU, bool PHI_FAR, int DEPTH = (LT <= 64 ? 2 : 1)>
+// KIND: 0 dense tables; MPLPXX_COST_POTTS or _TRUNC_QUAD: the tile of each
+// slot is formed from its parameters (v.tables holds cost_params(KIND)
+// floats per slot) by gen_tile, the rest is the dense engine.
+template <int LT, int NT, bool PHI_LDS, bool FULL, bool TRACE, bool LDSU, bool PHI_FAR, int DEPTH = (LT <= 64 ? 2 : 1),
+          int KIND = kCostDense>
 __device__ __forceinline__ bool mb_run(const MbView& v_in, int first_in, int stride_in, int iters_in,
                                        SmemMB<LT, NT>& sm, float* phi_lds, long long spin_limit, int* err) {
   using S = TileShape<float, LT, NT>;
@@ -595,8 +640,13 @@ __device__ __forceinline__ bool mb_run(const MbView& v_in, int first_in, int str
   int it = 0, j = 0, jp = 0;
   {
     const int j1 = owned > 1 ? 1 : 0;
-    load_tile_raw<LT, NT, FULL>(v.tables + (size_t)first * L * L, L, t0);
-    if (DEPTH == 2) load_tile_raw<LT, NT, FULL>(v.tables + (size_t)(first + j1 * stride) * L * L, L, t1);
+    if constexpr (KIND == kCostDense) {
+      load_tile_raw<LT, NT, FULL>(v.tables + (size_t)first * L * L, L, t0);
+      if (DEPTH == 2) load_tile_raw<LT, NT, FULL>(v.tables + (size_t)(first + j1 * stride) * L * L, L, t1);
+    } else {
+      gen_tile<LT, NT, KIND>(v.tables + (size_t)first * cost_params(KIND), t0);
+      if (DEPTH == 2) gen_tile<LT, NT, KIND>(v.tables + (size_t)(first + j1 * stride) * cost_params(KIND), t1);
+    }
     if (PHI_FAR) {
       load_phiset(f0, 0);
       if (DEPTH == 2) load_phiset(f1, j1);
@@ -624,7 +674,8 @@ __device__ __forceinline__ bool mb_run(const MbView& v_in, int first_in, int str
     {
       // (past the end: a harmless reload of the last step's table)
       const int jq = q + DEPTH < total ? jp : owned - 1;
-      load_tile_raw<LT, NT, FULL>(v.tables + (size_t)(first + jq * stride) * L * L, L, xp);
+      if constexpr (KIND == kCostDense) load_tile_raw<LT, NT, FULL>(v.tables + (size_t)(first + jq * stride) * L * L, L, xp);
+      else gen_tile<LT, NT, KIND>(v.tables + (size_t)(first + jq * stride) * cost_params(KIND), xp);
       if (PHI_FAR) load_phiset(fp, jq);
     }
 #if MPLPXX_FINE_STAMPS

@@ -265,7 +265,8 @@ __global__ void __launch_bounds__(NT) k_persistent(HsArgs<T> a, int iters) {
   }
 }
 
-template <int LT, int NT, bool PHI_LDS, bool FULL, bool TRACE, bool PHI_FAR, int DEPTH = (LT <= 64 ? 2 : 1)>
+template <int LT, int NT, bool PHI_LDS, bool FULL, bool TRACE, bool PHI_FAR, int DEPTH = (LT <= 64 ? 2 : 1),
+          int KIND = kCostDense>
 __global__ void __launch_bounds__(NT + 128) k_persistent_mb(HsArgs<float> a, unsigned long long* __restrict__ mb,
                                                             int iters) {
   __shared__ SmemMB<LT, NT> sm;
@@ -282,8 +283,8 @@ __global__ void __launch_bounds__(NT + 128) k_persistent_mb(HsArgs<float> a, uns
   __syncthreads();
   MbView v{a.tables, a.phi, mb, a.slots, a.deg, a.trace, a.trace_e, a.stamps, L, a.m, a.n, nullptr, nullptr,
            a.sink + (size_t)blockIdx.x * (NT + 128)};
-  if (!mb_run<LT, NT, PHI_LDS, FULL, TRACE, false, PHI_FAR, DEPTH>(v, blockIdx.x, G, iters, sm, phi_lds, a.spin_limit,
-                                                                   a.err))
+  if (!mb_run<LT, NT, PHI_LDS, FULL, TRACE, false, PHI_FAR, DEPTH, KIND>(v, blockIdx.x, G, iters, sm, phi_lds,
+                                                                         a.spin_limit, a.err))
     return;
   __syncthreads();
   if (PHI_LDS) {
@@ -359,10 +360,33 @@ static hipError_t launch_one(const HsArgs<T>& a, int engine, int slot_begin, int
   return e;
 }
 
+// structured costs on the dense mailbox engine, the tiles formed from the
+// slots' parameters (TRACE off, default prefetch)
+template <int LT, int KIND>
+static const void* mb_gen_kernel(bool phi_in_lds, bool full, bool far) {
+#define MPLPXX_G(P, F, A) (const void*)k_persistent_mb<LT, 256, P, F, false, A, (LT <= 64 ? 2 : 1), KIND>
+  return phi_in_lds ? (full ? (far ? MPLPXX_G(true, true, true) : MPLPXX_G(true, true, false))
+                            : (far ? MPLPXX_G(true, false, true) : MPLPXX_G(true, false, false)))
+                    : (full ? (far ? MPLPXX_G(false, true, true) : MPLPXX_G(false, true, false))
+                            : (far ? MPLPXX_G(false, false, true) : MPLPXX_G(false, false, false)));
+#undef MPLPXX_G
+}
+
 template <int LT, int NT>
 static hipError_t launch_mb_one(const HsArgs<float>& a, unsigned long long* mb, int grid, int iters, int phi_in_lds,
-                                size_t dyn_lds, hipStream_t st, int prefetch) {
+                                size_t dyn_lds, hipStream_t st, int prefetch, int kind) {
   void* args[] = {(void*)&a, (void*)&mb, (void*)&iters};
+  if (kind != kCostDense) {
+    if constexpr (NT == 256 && LT <= 64) {
+      const bool far = (a.m / grid) >= 4;
+      const void* f = kind == MPLPXX_COST_POTTS ? mb_gen_kernel<LT, MPLPXX_COST_POTTS>(phi_in_lds, a.L == LT, far)
+                                                : mb_gen_kernel<LT, MPLPXX_COST_TRUNC_QUAD>(phi_in_lds, a.L == LT, far);
+      const hipError_t e = hipLaunchCooperativeKernel(f, dim3(grid), dim3(NT + 128), args, dyn_lds, st);
+      if (e != hipSuccess) (void)hipGetLastError();
+      return e;
+    }
+    return hipErrorInvalidValue;
+  }
   const bool full = a.L == LT;
   // tables prefetched DEPTH steps ahead (2 for tiles up to 64 unless one
   // step is asked for; 1 for 128 and for traces); messages prefetched with
@@ -424,9 +448,9 @@ int max_blocks_per_cu_mb(int LT, int NT) {
 }
 
 hipError_t launch_persistent_mb(const HsArgs<float>& a, unsigned long long* mb, int LT, int NT, int grid, int iters,
-                                int phi_in_lds, size_t dyn_lds, hipStream_t st, int prefetch) {
+                                int phi_in_lds, size_t dyn_lds, hipStream_t st, int prefetch, int kind) {
 #define MPLPXX_CASE(lt, nt) \
-  if (LT == lt && NT == nt) return launch_mb_one<lt, nt>(a, mb, grid, iters, phi_in_lds, dyn_lds, st, prefetch);
+  if (LT == lt && NT == nt) return launch_mb_one<lt, nt>(a, mb, grid, iters, phi_in_lds, dyn_lds, st, prefetch, kind);
   MPLPXX_CASE(16, 256)
   MPLPXX_CASE(32, 256)
   MPLPXX_CASE(32, 512)

@@ -22,15 +22,7 @@ namespace mplpxx {
 // constant lets it rewrite fl(0 - q) under a minimum as -q, which is -0
 // for q = +0.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float opaque_zero() {
-  float z = 0.0f;
-  asm volatile("" : "+v"(z));
-  return z;
-}
-// scalar load of read-only data through the constant address space
-__device__ __forceinline__ float ld_const_f(const float* p) {
-  return *(const __attribute__((address_space(4))) float*)p;
-}
+// (opaque_zero and ld_const_f: device_common.h)
 // (m1, m2) <- the two smallest of the multiset {m1, m2} + {o1, o2}, each
 // pair being the two smallest of a group of lanes (a repeated value counts
 // twice)

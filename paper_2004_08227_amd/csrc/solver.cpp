@@ -119,8 +119,18 @@ struct mplpxx_solver {
 
   hipStream_t stream() const { return user_stream ? user_stream : own_stream; }
   int LT() const { return next_tile(L); }
+  // Structured costs run either one compute wave in label order (potts_mb.h;
+  // threads 64) or, for Potts and truncated quadratic costs, the dense
+  // engine's four compute waves with each tile formed from the slot's
+  // parameters (threads 256).  Default: the formed tiles for truncated
+  // quadratic costs and for Potts costs up to 32 labels.
+  bool gen_tiles() const {
+    if (potts != MPLPXX_COST_POTTS && potts != MPLPXX_COST_TRUNC_QUAD) return false;
+    if (threads_opt) return threads_opt == 256;
+    return potts == MPLPXX_COST_TRUNC_QUAD || L <= 32;
+  }
   int NT() const {
-    if (potts) return 64;  // one compute wave in label order (potts_mb.h)
+    if (potts) return gen_tiles() ? 256 : 64;
     int nt = threads_opt ? threads_opt : 256;
     if (!valid_threads(LT(), nt)) nt = 256;
     // the FP32 persistent engine adds two sync waves: at most 512 + 128 threads
@@ -144,7 +154,8 @@ struct mplpxx_solver {
   int grid() const {
     int g = grid_opt > 0 ? grid_opt : num_cus;
     if (grid_opt == 0 && mb_engine() && max_step > num_cus)
-      g = std::max(num_cus, std::min(max_step, (potts ? max_blocks_per_cu_mb_potts() : max_blocks_per_cu_mb(LT(), NT())) *
+      g = std::max(num_cus, std::min(max_step, (potts && !gen_tiles() ? max_blocks_per_cu_mb_potts()
+                                                                       : max_blocks_per_cu_mb(LT(), NT())) *
                                                      num_cus));
     if (g > m) g = m;
     if (g < 1) g = 1;
@@ -504,10 +515,23 @@ template <typename T> int iterate_t(mplpxx_solver* h, int k, double* trace_host)
       // the workgroups' LDS never limits how many fit)
       const int in_lds = phi_bytes <= kPhiLdsBudget && G <= h->num_cus && h->phi_opt != 2 ? 1 : 0;
       HIP_TRY(launch_mb_init(static_cast<const float*>(h->d_U), h->d_Ulo, h->d_mb, (size_t)h->n * h->L, st));
-      if (h->potts) HIP_TRY(launch_persistent_mb_potts(a, h->d_mb, G, k, in_lds, in_lds ? phi_bytes : 0, st, h->potts));
-      else HIP_TRY(launch_persistent_mb(a, h->d_mb, LT, NT, G, k, in_lds, in_lds ? phi_bytes : 0, st, h->prefetch_opt));
+      if (h->potts && !h->gen_tiles())
+        HIP_TRY(launch_persistent_mb_potts(a, h->d_mb, G, k, in_lds, in_lds ? phi_bytes : 0, st, h->potts));
+      else
+        HIP_TRY(launch_persistent_mb(a, h->d_mb, LT, NT, G, k, in_lds, in_lds ? phi_bytes : 0, st, h->prefetch_opt,
+                                     h->gen_tiles() ? h->potts : 0));
       HIP_TRY(launch_mb_fini(static_cast<float*>(h->d_U), h->d_Ulo, h->d_mb, h->n, h->L,
                              trace_host ? h->d_trace_nodes + (size_t)(k - 1) * h->n : nullptr, st));
+    } else if (!trace_host && h->L <= 64) {
+      // FP64 without a trace: the mailbox forward (two tagged words per
+      // label, no fences; bitwise the version-counter engine below)
+      const size_t nL = (size_t)h->n * h->L;
+      if (!h->d_mb64) HIP_TRY(hipMalloc(&h->d_mb64, 2 * nL * 2 * sizeof(unsigned long long)));
+      HIP_TRY(launch_mb64_init(static_cast<const double*>(h->d_U), h->d_mb64, nL, st));
+      HIP_TRY(launch_adj64(static_cast<const double*>(h->d_tables), static_cast<double*>(h->d_phi), h->d_mb64, k,
+                           nullptr, std::max(1, std::min(h->m, h->num_cus)), nullptr, nullptr, nullptr, nullptr, nullptr,
+                           0, 0, h->d_slots, h->L, h->m, h->d_err, h->spin_limit, st));
+      HIP_TRY(launch_mb64_fini(static_cast<double*>(h->d_U), h->d_mb64, nL, st));
     } else {
       HsArgs<T> a = hs_args<T>(h, trace_host ? h->d_trace_nodes : nullptr);
       HIP_TRY(launch_fill_int(h->d_ver, 0, h->n, st));
@@ -1115,14 +1139,21 @@ int mplpxx_set_option(mplpxx_solver* h, int32_t key, int64_t value) {
       h->engine_opt = (int)value;
       return MPLPXX_OK;
     case MPLPXX_OPT_THREADS:
-      if (h->potts && value != 0) return fail(MPLPXX_EINVAL, "Potts models run one compute wave per workgroup");
+      if (h->potts) {
+        const bool gen = h->potts == MPLPXX_COST_POTTS || h->potts == MPLPXX_COST_TRUNC_QUAD;
+        if (value != 0 && value != 64 && !(gen && value == 256))
+          return fail(MPLPXX_EINVAL, "structured costs run 64 threads (label order) or, for Potts and truncated "
+                                     "quadratic costs, 256 (tiles formed from the parameters)");
+        h->threads_opt = (int)value;
+        return MPLPXX_OK;
+      }
       if (value != 0 && !valid_threads(h->LT(), (int)value))
         return fail(MPLPXX_EINVAL, "threads %lld not valid for L=%d", (long long)value, h->L);
       h->threads_opt = (int)value;
       return MPLPXX_OK;
     case MPLPXX_OPT_GRID: {
       if (value < 0) return fail(MPLPXX_EINVAL, "grid must be >= 0");
-      const int nb = h->potts ? max_blocks_per_cu_mb_potts()
+      const int nb = h->potts && !h->gen_tiles() ? max_blocks_per_cu_mb_potts()
                      : h->mb_engine() ? max_blocks_per_cu_mb(h->LT(), h->NT())
                      : h->dtype == MPLPXX_F32 ? max_blocks_per_cu<float>(ENGINE_PERSISTENT, h->LT(), h->NT())
                                               : max_blocks_per_cu<double>(ENGINE_PERSISTENT, h->LT(), h->NT());

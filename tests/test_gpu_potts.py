@@ -203,11 +203,23 @@ def test_potts_solver_is_bitwise_the_dense_solver(n, L, p):
     iters = 4 if n >= 200 else 7
     sp, dp, lp, ip = _solver_run(lambda: M.Solver.from_potts(w), iters)
     sd, dd, ld, idn = _solver_run(lambda: M.Solver.from_model(d), iters)
-    assert ip[0] == M.ENGINE_PERSISTENT and ip[2] == 64
+    # default engine: tiles formed from the weights on four compute waves up
+    # to 32 labels, one wave in label order above
+    assert ip[0] == M.ENGINE_PERSISTENT and ip[2] == (256 if L <= 32 else 64)
     for a, b in zip(sp, sd):
         assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
     assert dp == dd
     assert np.array_equal(lp[0], ld[0]) and lp[1] == ld[1]
+    # the other single-model Potts engine
+    def other():
+        s = M.Solver.from_potts(w)
+        s.set_option(M.OPT_THREADS, 64 if L <= 32 else 256)
+        return s
+    so, do, lo, io = _solver_run(other, iters)
+    assert io[2] == (64 if L <= 32 else 256)
+    for a, b in zip(so, sd):
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    assert do == dd
     # the same model as a Potts batch: bitwise the same state
     with M.Batch([w], potts=True) as bt:
         bt.iterate(iters)
@@ -246,7 +258,7 @@ def test_potts_solver_rejects_dense_only_calls():
     _announce("potts solver errors")
     w, _ = W.potts_pure(8, 6, 1.0, seed=5)
     with M.Solver.from_potts(w) as s:
-        for key, val in ((M.OPT_ENGINE, M.ENGINE_STEP), (M.OPT_THREADS, 256), (M.OPT_RULE, M.RULE_M)):
+        for key, val in ((M.OPT_ENGINE, M.ENGINE_STEP), (M.OPT_THREADS, 512), (M.OPT_RULE, M.RULE_M)):
             with pytest.raises(M.MplpError) as ei:
                 s.set_option(key, val)
             assert ei.value.code == M.EINVAL

@@ -157,3 +157,24 @@ def test_batched_and_single_model_engines_agree_bitwise():
         b.iterate(6)
         Ub, pb = b.get_state(0)
     assert np.array_equal(Ua, Ub) and np.array_equal(pa, pb)
+
+
+@pytest.mark.parametrize("L,tau", [(7, 9.0), (16, 30.0), (33, 5000.0), (64, 64.0)])
+def test_formed_tiles_and_label_order_engines_agree_bitwise(L, tau):
+    """The single-model engine with four compute waves whose tiles are formed
+    from (w, tau) (threads 256, the default) and the one-wave label-order
+    engine (threads 64) give the same bits, and both the dense engine's."""
+    _announce("trunc quad formed tiles", L, tau)
+    params, dense = W.trunc_quad(30, L, 1.0, seed=50 + L, tau=tau)
+    out = []
+    for nt in (256, 64):
+        with M.Solver.from_structured(params, M.COST_TRUNC_QUAD) as s:
+            s.set_option(M.OPT_THREADS, nt)
+            assert s.info("threads") == nt
+            s.iterate(8)
+            out.append((s.dual_bound(), s.get_state(comp=True)))
+    dd, st_d, _ = _run_dense(dense, 8)
+    for d, st in out:
+        assert d == dd
+        for a, b in zip(st, st_d):
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
