@@ -33,7 +33,7 @@ METRIC = "edge-block updates/s + HBM GB/s fraction; time-to-dual-bound vs plain,
 # iteration of the pose n=200/L=64 launch, and the factors that map each
 # counter to bytes, from the same counters on a 1 GiB copy.  Valid only for
 # the kernel sources they were taken on (hash below); otherwise null.
-TRAFFIC = {"src_sha": "a49c6ef09a1ddb6b", "fetch_kib_per_iter": 3762763.375 / 20, "fetch_scale": 2.0,
+TRAFFIC = {"src_sha": "88167fd28787d85e", "fetch_kib_per_iter": 3760053.8125 / 20, "fetch_scale": 2.0,
            "write_kib_per_iter": 457708.0 / 20, "write_scale": 1.0}
 TRAFFIC_SRCS = ("paper_2004_08227_amd/csrc/common.h", "paper_2004_08227_amd/csrc/device_common.h",
                 "paper_2004_08227_amd/csrc/step_common.h", "paper_2004_08227_amd/csrc/potts_passes.h",
@@ -385,18 +385,22 @@ def bench_potts(M, W, iters=50, mix_count=64):
 
 
 def bench_trunc_linear(M, W, iters=50, mix_count=64, tau=8.0, kind=None):
-    """Truncated linear costs w min(|s - t|, tau) by their O(L) distance
-    transform (mplpxx_*_create_structured, 8 bytes of pairwise data per edge)
-    against the dense engines on the expanded tables (4 L^2 bytes): one
-    complete pose-size model (n = 200, L = 64) on the batched wave engine as
-    a batch of one and on the single-model mailbox engine, and the first
-    `mix_count` sizes of the batched mix (complete graphs) as one batch.  Same
-    iterations from phi = 0, device times from HIP events.  The structured
-    passes round in another order than the dense ones: the largest relative
-    difference of the final duals is reported (the parity tests hold both to
-    the oracle at 1e-5).  kind = COST_TRUNC_QUAD: the same for truncated
-    quadratic costs w min((s - t)^2, tau) (every candidate formed from the two
-    parameters, bitwise the dense engines: the difference is 0)."""
+    """Truncated linear costs w min(|s - t|, tau) (mplpxx_*_create_structured,
+    8 bytes of pairwise data per edge) against the dense engines on the
+    expanded tables (4 L^2 bytes): one complete pose-size model (n = 200,
+    L = 64) on the batched wave engine as a batch of one and on the
+    single-model mailbox engine, and the first `mix_count` sizes of the
+    batched mix (complete graphs) as one batch.  Same iterations from phi =
+    0, device times from HIP events.  The wave engine runs the O(L)
+    distance transform, whose sums round in another order than the dense
+    passes: the largest relative difference of the final duals is reported
+    (the parity tests hold both to the oracle at 1e-5).  The single-model
+    engine forms each tile from (w, tau) by default (bitwise the dense
+    engine) and is also timed in label order (the distance transform,
+    threads 64).  kind = COST_TRUNC_QUAD: the same for truncated quadratic
+    costs w min((s - t)^2, tau) (every candidate formed from the two
+    parameters, bitwise the dense engines on either path: the differences
+    are 0)."""
     kind = M.COST_TRUNC_LINEAR if kind is None else kind
     make = W.trunc_linear if kind == M.COST_TRUNC_LINEAR else W.trunc_quad
     def run_batch(models, kind):
@@ -406,8 +410,10 @@ def bench_trunc_linear(M, W, iters=50, mix_count=64, tau=8.0, kind=None):
             b.iterate(iters)
             return b.info("last_ms"), np.asarray(b.dual_bounds())
 
-    def run_single(make):
+    def run_single(make, threads=0):
         with make() as s1:
+            if threads:
+                s1.set_option(M.OPT_THREADS, threads)
             U0, phi0 = s1.get_state()
             s1.iterate(2)
             s1.set_state(U0, phi0)
@@ -433,10 +439,14 @@ def bench_trunc_linear(M, W, iters=50, mix_count=64, tau=8.0, kind=None):
         if len(sz) == 1:
             ms_s, d_s = run_single(lambda: M.Solver.from_model(dense[0]))
             ms_st, d_st = run_single(lambda: M.Solver.from_structured(params[0], kind))
+            ms_lo, d_lo = run_single(lambda: M.Solver.from_structured(params[0], kind), threads=64)
             rec.update({"single_model_dense_ms_per_iter": ms_s / iters,
                         "single_model_structured_ms_per_iter": ms_st / iters,
                         "single_model_speedup": ms_s / ms_st,
-                        "single_model_rel_dual_difference": float(abs(d_st[0] - d_s[0]) / max(1.0, abs(d_s[0])))})
+                        "single_model_rel_dual_difference": float(abs(d_st[0] - d_s[0]) / max(1.0, abs(d_s[0]))),
+                        "single_model_label_order_ms_per_iter": ms_lo / iters,
+                        "single_model_label_order_rel_dual_difference":
+                            float(abs(d_lo[0] - d_s[0]) / max(1.0, abs(d_s[0])))})
         out[name] = rec
         del params, dense
     return out
@@ -468,6 +478,8 @@ def summary(result):
         t = result.get(sec)
         if t:
             sm[sec + "_speedup"] = {k: v.get("speedup") for k, v in t.items() if isinstance(v, dict)}
+            sm[sec + "_speedup"].update({k + "_single_model": v["single_model_speedup"] for k, v in t.items()
+                                         if isinstance(v, dict) and "single_model_speedup" in v})
     return sm
 
 
@@ -578,6 +590,34 @@ def kernel_only(steps, warmup):
     print("\n".join(code_mappings()), file=sys.stderr, flush=True)
 
 
+def adjoint_only(steps, warmup):
+    """The differentiation workload alone (uniform n=100, L=32, FP32 costs;
+    50 iterations with a checkpoint every 10, then the backward on the FP64
+    twin), without PyTorch, on the library build linked against /opt/rocm's
+    HIP runtime: the process for rocprofv3 runs of the adjoint kernels.  The
+    gradients stay on the device (the backward is called with no output)."""
+    os.environ["MPLPXX_RUNTIME"] = "rocm"
+    import paper_2004_08227_amd as M
+    from paper_2004_08227_amd import workloads as W
+    model = W.uniform(100, 32, seed=0)
+    fwd, bwd = [], []
+    with M.Solver.from_model(model) as s:
+        for rep in range(warmup + steps):
+            t0 = time.perf_counter()
+            loss = s.adjoint_forward(50, 10)
+            t1 = time.perf_counter()
+            M._check(M.lib().mplpxx_adjoint_backward(s._h, None, None))
+            t2 = time.perf_counter()
+            if rep >= warmup:
+                fwd.append(t1 - t0)
+                bwd.append(t2 - t1)
+            print(f"adjoint rep {rep}: forward {1e3 * (t1 - t0):.2f} ms, backward {1e3 * (t2 - t1):.2f} ms",
+                  file=sys.stderr, flush=True)
+    print(json.dumps({"adjoint_only": "uniform_n100_l32_k50_every10", "reps": steps, "loss": loss,
+                      "forward_ms": 1e3 * float(np.median(fwd)), "backward_ms": 1e3 * float(np.median(bwd)),
+                      "runtimes": loaded_runtimes()}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -605,6 +645,8 @@ def main():
                     help="batched section without the per-problem comparison runs")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only the timed pose n=200/L=64 launch, without PyTorch (for rocprofv3 runs)")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="the differentiation workload alone, without PyTorch (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only a 3 x 1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -617,6 +659,9 @@ def main():
         return
     if args.kernel_only:
         kernel_only(args.steps, args.warmup)
+        return
+    if args.adjoint_only:
+        adjoint_only(args.steps, args.warmup)
         return
 
     import torch

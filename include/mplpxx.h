@@ -140,7 +140,8 @@ int mplpxx_create_potts(int32_t n, int32_t L, int64_t m, const int32_t* edges, c
  *                             (any sign; -0 counts as +0);
  *   MPLPXX_COST_TRUNC_LINEAR  theta_uv(s, t) = fl(w * min(|s - t|, tau)),
  *                             the FP32 product; 2 parameters: w >= 0 and
- *                             tau >= 0 (tau >= L - 1: absolute difference
+ *                             tau >= 0, -0 counting as +0 for both (as for
+ *                             the next kind; tau >= L - 1: absolute difference
  *                             w |s - t|; tau <= 1: Potts with weight
  *                             fl(w * tau)); symmetric, so the orientation of
  *                             an edge does not matter;
@@ -156,11 +157,13 @@ int mplpxx_create_potts(int32_t n, int32_t L, int64_t m, const int32_t* edges, c
 /* A model with structured pairwise costs of one kind (above): params = HOST
  * float [m][P] in the order of edges, P = 1 (Potts) or 2 (truncated
  * linear, truncated quadratic); unaries as for mplpxx_create (FP32).  Runs on the persistent
- * mailbox engine with one compute wave per workgroup in label order, or,
- * for Potts and truncated quadratic costs, on its four compute waves with
- * each tile formed from the edge's parameters (MPLPXX_OPT_THREADS 64 or
- * 256; the default: 256 for truncated quadratic costs, for Potts costs up to
- * 32 labels).  Potts: as mplpxx_create_potts (bitwise the dense handle on
+ * mailbox engine with one compute wave per workgroup in label order, or on
+ * its four compute waves with each tile formed from the edge's parameters
+ * (MPLPXX_OPT_THREADS 64 or 256; the default: 256 for the truncated kinds,
+ * for Potts costs up to 32 labels).  Formed tiles hold exactly the expanded
+ * table's entries, so that engine gives the dense handle's bits for every
+ * kind.  In label order:
+ * Potts: as mplpxx_create_potts (bitwise the dense handle on
  * the expanded tables).
  * Truncated linear: each pass is a min-plus distance transform in O(L) work
  * and O(log L) steps (prefix and suffix minima of x(t) + w |s - t| by

@@ -509,7 +509,7 @@ static int create_batch(int32_t count, const int32_t* n, const int32_t* L, const
       float* dst = packed.data() + (size_t)s * tl;
       if (potts == MPLPXX_COST_POTTS) {
         *dst = src[0] + 0.0f;  // (a weight of -0 is stored as +0: the table it stands for is the same)
-      } else if (potts == MPLPXX_COST_TRUNC_QUAD) {
+      } else if (potts == MPLPXX_COST_TRUNC_QUAD || potts == MPLPXX_COST_TRUNC_LINEAR) {
         dst[0] = src[0] + 0.0f;  // (w and tau of -0 as +0: every cost is then +0 or positive)
         dst[1] = src[1] + 0.0f;
       } else if (potts || !g.flip[e]) {   // (structured costs are symmetric in s, t)

@@ -437,8 +437,9 @@ __device__ __forceinline__ float ld_const_f(const float* p) {
 
 // The register tile of a structured cost, formed from the slot's
 // parameters instead of loaded: entry (s, t) is exactly the expanded
-// table's value (Potts: +0 on the diagonal, w off it; truncated quadratic:
-// fl(w min((s - t)^2, tau))), so the passes give the dense engine's bits.
+// table's value (Potts: +0 on the diagonal, w off it; truncated linear:
+// fl(w min(|s - t|, tau)); truncated quadratic: fl(w min((s - t)^2, tau))),
+// so the passes give the dense engine's bits.
 // Entries outside L x L are replaced by the pad at use (pad_tile).
 template <int LT, int NT, int KIND>
 __device__ __forceinline__ void gen_tile(const float* prm, float (&x)[TileShape<float, LT, NT>::BR][TileShape<float, LT, NT>::BC]) {
@@ -452,14 +453,15 @@ __device__ __forceinline__ void gen_tile(const float* prm, float (&x)[TileShape<
 #pragma unroll
       for (int j = 0; j < S::BC; ++j) x[i][j] = (rb * S::BR + i == cb * S::BC + j) ? z : w;
   } else {
-    static_assert(KIND == MPLPXX_COST_TRUNC_QUAD, "tiles are formed for Potts and truncated quadratic costs");
+    static_assert(KIND == MPLPXX_COST_TRUNC_LINEAR || KIND == MPLPXX_COST_TRUNC_QUAD, "structured cost kind");
     const float tau = ld_const_f(prm + 1);
 #pragma unroll
     for (int i = 0; i < S::BR; ++i)
 #pragma unroll
       for (int j = 0; j < S::BC; ++j) {
-        const float d = (float)(rb * S::BR + i - cb * S::BC - j);
-        x[i][j] = truncated_cost(w, tau, d * d);
+        const int dd = rb * S::BR + i - cb * S::BC - j;
+        const float d = (float)(dd < 0 ? -dd : dd);
+        x[i][j] = truncated_cost(w, tau, KIND == MPLPXX_COST_TRUNC_QUAD ? d * d : d);
       }
   }
 }

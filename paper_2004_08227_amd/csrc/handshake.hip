@@ -380,7 +380,9 @@ static hipError_t launch_mb_one(const HsArgs<float>& a, unsigned long long* mb, 
     if constexpr (NT == 256 && LT <= 64) {
       const bool far = (a.m / grid) >= 4;
       const void* f = kind == MPLPXX_COST_POTTS ? mb_gen_kernel<LT, MPLPXX_COST_POTTS>(phi_in_lds, a.L == LT, far)
-                                                : mb_gen_kernel<LT, MPLPXX_COST_TRUNC_QUAD>(phi_in_lds, a.L == LT, far);
+                      : kind == MPLPXX_COST_TRUNC_LINEAR
+                          ? mb_gen_kernel<LT, MPLPXX_COST_TRUNC_LINEAR>(phi_in_lds, a.L == LT, far)
+                          : mb_gen_kernel<LT, MPLPXX_COST_TRUNC_QUAD>(phi_in_lds, a.L == LT, far);
       const hipError_t e = hipLaunchCooperativeKernel(f, dim3(grid), dim3(NT + 128), args, dyn_lds, st);
       if (e != hipSuccess) (void)hipGetLastError();
       return e;

@@ -120,14 +120,13 @@ struct mplpxx_solver {
   hipStream_t stream() const { return user_stream ? user_stream : own_stream; }
   int LT() const { return next_tile(L); }
   // Structured costs run either one compute wave in label order (potts_mb.h;
-  // threads 64) or, for Potts and truncated quadratic costs, the dense
-  // engine's four compute waves with each tile formed from the slot's
-  // parameters (threads 256).  Default: the formed tiles for truncated
-  // quadratic costs and for Potts costs up to 32 labels.
+  // threads 64) or the dense engine's four compute waves with each tile
+  // formed from the slot's parameters (threads 256).  Default: the formed
+  // tiles for the truncated kinds and for Potts costs up to 32 labels.
   bool gen_tiles() const {
-    if (potts != MPLPXX_COST_POTTS && potts != MPLPXX_COST_TRUNC_QUAD) return false;
+    if (!potts) return false;
     if (threads_opt) return threads_opt == 256;
-    return potts == MPLPXX_COST_TRUNC_QUAD || L <= 32;
+    return potts != MPLPXX_COST_POTTS || L <= 32;
   }
   int NT() const {
     if (potts) return gen_tiles() ? 256 : 64;
@@ -351,7 +350,7 @@ int create_impl(int32_t n, int32_t L, int64_t m, const int32_t* edges, const voi
         if (potts == MPLPXX_COST_POTTS) {
           const float wv = *reinterpret_cast<const float*>(s) + 0.0f;
           std::memcpy(dst, &wv, sizeof(float));
-        } else if (potts == MPLPXX_COST_TRUNC_QUAD) {
+        } else if (potts == MPLPXX_COST_TRUNC_QUAD || potts == MPLPXX_COST_TRUNC_LINEAR) {
           // (w and tau of -0 as +0: every cost is then +0 or positive)
           const float wt[2] = {reinterpret_cast<const float*>(s)[0] + 0.0f, reinterpret_cast<const float*>(s)[1] + 0.0f};
           std::memcpy(dst, wt, sizeof wt);
@@ -1140,10 +1139,9 @@ int mplpxx_set_option(mplpxx_solver* h, int32_t key, int64_t value) {
       return MPLPXX_OK;
     case MPLPXX_OPT_THREADS:
       if (h->potts) {
-        const bool gen = h->potts == MPLPXX_COST_POTTS || h->potts == MPLPXX_COST_TRUNC_QUAD;
-        if (value != 0 && value != 64 && !(gen && value == 256))
-          return fail(MPLPXX_EINVAL, "structured costs run 64 threads (label order) or, for Potts and truncated "
-                                     "quadratic costs, 256 (tiles formed from the parameters)");
+        if (value != 0 && value != 64 && value != 256)
+          return fail(MPLPXX_EINVAL, "structured costs run 64 threads (label order) or 256 (tiles formed from "
+                                     "the parameters)");
         h->threads_opt = (int)value;
         return MPLPXX_OK;
       }

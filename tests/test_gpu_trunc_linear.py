@@ -1,14 +1,17 @@
 """GPU tests of truncated linear pairwise costs w min(|s - t|, tau) (Sec. 4:
 absolute-difference costs are among those whose message passing takes O(L)).
 
-The structured passes (a min-plus distance transform per pass, O(L) work and
-O(log L) steps) form their sums in another order than the dense passes, so
-the reference is the FP64 oracle on the expanded FP32 tables, at the FP32
-parity bar: the certified dual and every reparametrized unary and pairwise
-cost within 1e-5 (relative to max(1, |value|)), on the single-model engine
-and on the batched wave engine (models in LDS and split over teams), with
-ragged label counts, ties, zero weights, truncation at 0, below 1 (a Potts
-cost) and beyond the label range (plain absolute difference)."""
+The structured passes in label order (a min-plus distance transform per
+pass, O(L) work and O(log L) steps) form their sums in another order than
+the dense passes, so their reference is the FP64 oracle on the expanded FP32
+tables, at the FP32 parity bar: the certified dual and every reparametrized
+unary and pairwise cost within 1e-5 (relative to max(1, |value|)), on the
+single-model engine and on the batched wave engine (models in LDS and split
+over teams), with ragged label counts, ties, zero weights, truncation at 0,
+below 1 (a Potts cost) and beyond the label range (plain absolute
+difference).  The single-model engine with tiles formed from (w, tau) (the
+default) gives the dense engine's bits on the expanded tables, and the
+oracle's bar as well."""
 import numpy as np
 import pytest
 
@@ -44,20 +47,37 @@ def _check_state(dense, iters, d, U, phi, Uc):
     return eu, ep
 
 
+@pytest.mark.parametrize("threads", [64, 256], ids=["label_order", "formed_tiles"])
 @pytest.mark.parametrize("name,make,iters", CASES, ids=[c[0] for c in CASES])
-def test_single_model_engine_matches_oracle_on_expanded_tables(name, make, iters):
-    _announce("trunc linear single", name)
+def test_single_model_engine_matches_oracle_on_expanded_tables(name, make, iters, threads):
+    _announce("trunc linear single", name, "threads", threads)
     params, dense = make()
     with M.Solver.from_structured(params, M.COST_TRUNC_LINEAR) as s:
+        s.set_option(M.OPT_THREADS, threads)
+        assert s.info("threads") == threads
         s.iterate(iters)
         d = s.dual_bound()
         U, phi, Uc = s.get_state(comp=True)
         labels, energy = s.decode()
     eu, ep = _check_state(dense, iters, d, U, phi, Uc)
-    print(f"{name}: unaries {eu:.2e}, pairwise {ep:.2e}", flush=True)
+    print(f"{name} threads {threads}: unaries {eu:.2e}, pairwise {ep:.2e}", flush=True)
     assert eu <= SP.TOL and ep <= SP.TOL
     # the rounding's energy is Eq. (1) on the expanded costs
     assert abs(energy - oracle.energy(dense, labels)) <= 1e-5 * max(1.0, abs(energy))
+    if threads == 256:
+        # formed tiles: the dense engine's bits on the expanded tables
+        with M.Solver.from_model(dense) as sd:
+            sd.iterate(iters)
+            assert sd.dual_bound() == d
+            for a, b in zip(sd.get_state(comp=True), (U, phi, Uc)):
+                assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+            assert np.array_equal(sd.decode()[0], labels)
+
+
+def test_formed_tiles_are_the_default():
+    params, _ = W.trunc_linear(12, 9, 1.0, seed=40, tau=2.0)
+    with M.Solver.from_structured(params, M.COST_TRUNC_LINEAR) as s:
+        assert s.info("threads") == 256
 
 
 def test_per_edge_truncation_and_zero_weights():
@@ -122,10 +142,12 @@ def test_batched_wave_engine_matches_oracle(mode):
 
 
 def test_batched_and_single_model_engines_agree_bitwise():
-    """The two engines run the same passes in the same order per label."""
+    """The two engines in label order run the same passes in the same order
+    per label."""
     _announce("trunc linear batch vs single")
     params, _ = W.trunc_linear(40, 29, 0.6, seed=30, tau=3.0)
     with M.Solver.from_structured(params, M.COST_TRUNC_LINEAR) as s:
+        s.set_option(M.OPT_THREADS, 64)
         s.iterate(6)
         Ua, pa = s.get_state()
     with M.Batch([params], kind=M.COST_TRUNC_LINEAR) as b:
