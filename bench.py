@@ -460,6 +460,12 @@ def summary(result):
     if b:
         sm.update({"c3_batched_ms": b.get("batched_ms"), "c3_speedup_vs_per_problem": b.get("speedup"),
                    "c3_hbm_frac": b.get("hbm_frac")})
+    ms = result.get("measured_stream")
+    if ms:
+        sm["measured_read_gbs"] = max(ms.get("read_gbs", 0.0), ms.get("hip_read_gbs", 0.0))
+        sm["c1_frac_of_measured_read"] = ms.get("frac_of_measured_read")
+        if b and b.get("hbm_frac") is not None:
+            sm["c3_frac_of_measured_read"] = b["hbm_frac"] * HBM_PEAK_GBS / sm["measured_read_gbs"]
     c2 = result.get("c2")
     if c2 and isinstance(c2.get("densities"), dict):
         sm["c2_hbm_frac"] = {k: v.get("hbm_frac") for k, v in c2["densities"].items() if isinstance(v, dict)}
@@ -647,6 +653,8 @@ def main():
                     help="only the timed pose n=200/L=64 launch, without PyTorch (for rocprofv3 runs)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="the differentiation workload alone, without PyTorch (for profiler runs)")
+    ap.add_argument("--stream-probe", action="store_true",
+                    help="only the library's streaming-read probe at 1, 2, 4 and 8 GiB, without PyTorch")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only a 3 x 1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -662,6 +670,15 @@ def main():
         return
     if args.adjoint_only:
         adjoint_only(args.steps, args.warmup)
+        return
+    if args.stream_probe:
+        os.environ["MPLPXX_RUNTIME"] = "rocm"
+        import paper_2004_08227_amd as M
+        out = {}
+        for gib in (1, 2, 4, 8):
+            med, best = M.stream_read_probe(gib << 30, 5)
+            out[f"{gib}GiB"] = {"median_gbs": med, "best_gbs": best}
+        print(json.dumps({"stream_read_probe": out}), flush=True)
         return
 
     import torch
@@ -772,9 +789,14 @@ def main():
     s.close()
     if not args.no_stream:
         sp = measured_stream_peak()
-        result["measured_stream"] = dict(sp, frac_of_measured_read=gbs / sp["read_gbs"],
-                                         note="torch sum (read) and copy_ (read + write) over 4 GiB; the roofline "
-                                              "peak stays the published 8 TB/s")
+        med, best = M.stream_read_probe(4 << 30, 5)
+        sp.update(hip_read_gbs=med, hip_read_best_gbs=best)
+        ceiling = max(sp["read_gbs"], med)
+        result["measured_stream"] = dict(sp, frac_of_measured_read=gbs / ceiling,
+                                         note="torch sum (read) and copy_ (read + write) over 4 GiB, and the "
+                                              "library's plain HIP read kernel over 4 GiB (median and best of 5); "
+                                              "frac_of_measured_read uses the larger median read rate; the "
+                                              "roofline peak stays the published 8 TB/s")
     if not args.no_batch:
         result["batched"] = bench_batched(M, W, per_problem=not args.no_per_problem)
     if not args.no_c2:

@@ -238,6 +238,21 @@ const char* mplpxx_error_string(int code);
 /* Text of the last failure on the calling thread ("" if none). */
 const char* mplpxx_last_error(void);
 
+/* Measured streaming-read rate of the current device, the ceiling reported
+ * beside the published HBM bandwidth for the kernels' bandwidth fractions
+ * (each of the three passes of Sec. 4 reads every entry of the edge's
+ * read-only table once, so the dense kernels are bounded by read
+ * streaming).  Allocates a buffer of `bytes` (a multiple of 16, at least 1
+ * MiB), fills it with zeros, and times `reps` (1..1000) launches of a plain
+ * read kernel (16-byte nontemporal loads at a grid stride, eight in flight
+ * per thread, sixteen 256-thread workgroups per compute unit) after one
+ * warm-up launch, each with HIP events on its
+ * own stream; writes the median and (if gbs_best is not NULL) the best rate
+ * in GB/s (1e9 bytes per second) to the HOST pointers.  Frees everything
+ * before returning.  Errors: MPLPXX_EINVAL for a bad size, count or NULL
+ * gbs_median; MPLPXX_ENOMEM; MPLPXX_EDEVICE. */
+int mplpxx_stream_read_probe(int64_t bytes, int32_t reps, double* gbs_median, double* gbs_best);
+
 /* ------------------------------------------------------------------------
  * Extensions (streams, schedule, state, traces, tuning).
  * --------------------------------------------------------------------- */

@@ -131,6 +131,7 @@ def lib():
         "mplpxx_batch_wg_profile": (ctypes.c_int, [vp, vp, vp]),
         "mplpxx_batch_destroy": (None, [vp]),
         "mplpxx_solve_noalloc": (ctypes.c_int, [i32, i32, i64, vp, vp, vp, i32, vp, vp, ctypes.POINTER(dbl), vp]),
+        "mplpxx_stream_read_probe": (ctypes.c_int, [i64, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -147,6 +148,15 @@ def _check(rc):
 
 def _ptr(a):
     return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+def stream_read_probe(nbytes=4 << 30, reps=5):
+    """(median, best) streaming-read rate of the current device in GB/s
+    from the library's plain read kernel over `nbytes` bytes (the measured
+    ceiling beside the published HBM bandwidth)."""
+    med, best = ctypes.c_double(), ctypes.c_double()
+    _check(lib().mplpxx_stream_read_probe(int(nbytes), int(reps), ctypes.byref(med), ctypes.byref(best)))
+    return med.value, best.value
 
 
 def schedule(n, edges, kind=0):

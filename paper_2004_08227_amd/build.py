@@ -23,7 +23,7 @@ LIB = os.path.join(HERE, "libmplpxx.so")
 LIB_ROCM = os.path.join(HERE, "libmplpxx_rocm.so")
 
 SOURCES = ["solver.cpp", "batch.cpp", "schedule.cpp", "handshake.hip", "dual.hip", "batch.hip", "adjoint.hip",
-           "rules.hip", "noalloc.hip"]
+           "rules.hip", "noalloc.hip", "probe.hip"]
 ARCH = os.environ.get("MPLPXX_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

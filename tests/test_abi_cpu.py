@@ -97,6 +97,15 @@ def test_null_out_and_null_handle():
     lib.mplpxx_destroy(None)
 
 
+def test_stream_read_probe_rejects_bad_arguments_before_device_work():
+    lib = M.lib()
+    med, best = ctypes.c_double(), ctypes.c_double()
+    for nbytes, reps, out in (((1 << 20) - 16, 3, ctypes.byref(med)), ((1 << 20) + 8, 3, ctypes.byref(med)),
+                              (1 << 20, 0, ctypes.byref(med)), (1 << 20, 1001, ctypes.byref(med)), (1 << 20, 3, None)):
+        assert lib.mplpxx_stream_read_probe(nbytes, reps, out, ctypes.byref(best)) == M.EINVAL
+        assert M.lib().mplpxx_last_error()
+
+
 @pytest.mark.parametrize("kind,args", [("complete", (2,)), ("complete", (3,)), ("complete", (8,)), ("complete", (57,)),
                                        ("complete", (200,)), ("er", (100, 0.05, 1)), ("er", (60, 0.5, 2)),
                                        ("er", (1000, 0.01, 3)), ("chain", (12,))])
