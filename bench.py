@@ -231,8 +231,9 @@ def bench_c2(M, W, iters=30, with_cpu=True):
             tr = s.iterate_trace(iters)
             steps = s.info("steps")
             eng = s.info("engine")
+            nt = s.info("threads")
         t = ms / 1e3
-        rec = {"m": model.m, "matchings": steps, "engine": eng, "ms_per_iter": ms / iters,
+        rec = {"m": model.m, "matchings": steps, "engine": eng, "threads": nt, "ms_per_iter": ms / iters,
                "updates_per_s": model.m * iters / t, "hbm_gbs": model.m * iters * B / t / 1e9,
                "hbm_frac": model.m * iters * B / t / 1e9 / HBM_PEAK_GBS, "dual": float(tr[-1])}
         ref = None

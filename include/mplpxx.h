@@ -312,7 +312,8 @@ int mplpxx_iterate_trace(mplpxx_solver* h, int32_t k, double* trace);
 #define MPLPXX_OPT_ENGINE 1      /* 0 auto, 1 one launch per matching, 2 persistent
                                     (FP32 handles with a node of degree >= 65536
                                     always run one launch per matching) */
-#define MPLPXX_OPT_THREADS 2     /* threads per workgroup: 0 auto, 256, 512, 1024 */
+#define MPLPXX_OPT_THREADS 2     /* threads per workgroup: 0 auto, 256, 512, 1024; 64 (one compute
+                                    wave, FP32 persistent engine) up to 32 labels */
 #define MPLPXX_OPT_GRID 3        /* workgroups of the persistent engine (0 auto) */
 #define MPLPXX_OPT_SPIN_LIMIT 4  /* device wait bound in polls (0 default) */
 #define MPLPXX_OPT_PROFILE 5     /* 1: record per-slot timestamps (persistent FP32 engine) */

@@ -92,7 +92,8 @@ def apply_batch(batch, models, table=None):
 # ---------------------------------------------------------------------------
 def solver_candidates(M, solver):
     """Options worth timing for this handle: the persistent engine at each
-    valid thread count and a few grids, and the per-matching engine; for
+    valid thread count (FP32 up to 32 labels: also one compute wave, 64) and
+    a few grids, and the per-matching engine; for
     FP32 handles also where a workgroup keeps its messages (LDS or global
     memory) and how far ahead the tables are prefetched (one step or two),
     at the default threads and grid and at the grid of one workgroup per
@@ -102,13 +103,14 @@ def solver_candidates(M, solver):
     f32 = solver.info("dtype") == M.F32
     cands = [{}]
     threads = [nt for nt in (256, 512, 1024) if nt <= 16 * lt and (not f32 or nt <= 512)]
+    if f32 and lt <= 32:
+        threads = [64] + threads   # one compute wave (the mailbox engine)
     for nt in threads:
         for grid in (0, 128, 192):
             c = {"OPT_ENGINE": M.ENGINE_PERSISTENT, "OPT_THREADS": nt}
             if grid:
                 c["OPT_GRID"] = grid
-            if c != {"OPT_ENGINE": M.ENGINE_PERSISTENT, "OPT_THREADS": 256}:
-                cands.append(c)
+            cands.append(c)
     cands.append({"OPT_ENGINE": M.ENGINE_STEP})
     if f32:
         for phi, pre in ((2, 0), (0, 1), (2, 1)):

@@ -438,7 +438,9 @@ int max_blocks_per_cu_mb(int LT, int NT) {
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, nt + 128, 0);                                   \
     if (e == hipSuccess) nb = placeable_per_cu(f, nt + 128, nb);                                             \
   }
+  MPLPXX_CASE(16, 64)
   MPLPXX_CASE(16, 256)
+  MPLPXX_CASE(32, 64)
   MPLPXX_CASE(32, 256)
   MPLPXX_CASE(32, 512)
   MPLPXX_CASE(64, 256)
@@ -453,7 +455,9 @@ hipError_t launch_persistent_mb(const HsArgs<float>& a, unsigned long long* mb, 
                                 int phi_in_lds, size_t dyn_lds, hipStream_t st, int prefetch, int kind) {
 #define MPLPXX_CASE(lt, nt) \
   if (LT == lt && NT == nt) return launch_mb_one<lt, nt>(a, mb, grid, iters, phi_in_lds, dyn_lds, st, prefetch, kind);
+  MPLPXX_CASE(16, 64)
   MPLPXX_CASE(16, 256)
+  MPLPXX_CASE(32, 64)
   MPLPXX_CASE(32, 256)
   MPLPXX_CASE(32, 512)
   MPLPXX_CASE(64, 256)

@@ -146,6 +146,46 @@ def test_engines_and_tunings_are_bitwise_identical():
         assert np.array_equal(c, states[0][2])
 
 
+@pytest.mark.parametrize("n,L,density", [(40, 16, 1.0), (60, 13, 0.3), (30, 32, 1.0), (50, 29, 0.5), (12, 1, 1.0)])
+def test_one_wave_mailbox_engine_is_bitwise_the_four_wave_one(n, L, density):
+    """Up to 32 labels the FP32 mailbox engine also runs one compute wave
+    per workgroup (threads 64): the same bits as four waves, with and without
+    a trace, and the same rounding."""
+    _announce("one-wave engine", n, L, density)
+    model = W.uniform(n, L, seed=100 + L) if density >= 1.0 else W.potts_er(n, L, density, seed=100 + L)
+    out = []
+    for threads in (256, 64):
+        with M.Solver.from_model(model) as s:
+            s.set_option(M.OPT_THREADS, threads)
+            assert s.info("threads") == threads
+            s.iterate(7)
+            tr = s.iterate_trace(3)
+            out.append((s.get_state(comp=True), tr, s.dual_bound(), s.decode()))
+    (a, tra, da, deca), (b, trb, db, decb) = out
+    for x, y in zip(a, b):
+        assert np.array_equal(x.view(np.uint32), y.view(np.uint32))
+    assert np.array_equal(tra, trb) and da == db
+    assert np.array_equal(deca[0], decb[0]) and deca[1] == decb[1]
+
+
+def test_one_wave_option_falls_back_where_it_does_not_apply():
+    """Threads 64 is refused above 32 labels, and FP64 handles (or the
+    per-matching engine) keep 256 threads."""
+    with M.Solver.from_model(W.uniform(10, 40, seed=1)) as s:
+        with pytest.raises(M.MplpError) as ei:
+            s.set_option(M.OPT_THREADS, 64)
+        assert ei.value.code == M.EINVAL
+    with M.Solver.from_model(W.uniform(10, 16, seed=1, dtype=np.float64)) as s:
+        s.set_option(M.OPT_THREADS, 64)
+        assert s.info("threads") == 256
+        s.iterate(2)
+    with M.Solver.from_model(W.uniform(10, 16, seed=1)) as s:
+        s.set_option(M.OPT_THREADS, 64)
+        s.set_option(M.OPT_ENGINE, M.ENGINE_STEP)
+        assert s.info("threads") == 256
+        s.iterate(2)
+
+
 @pytest.mark.parametrize("engine", [1, 2])
 def test_checkpoint_resume_is_bitwise(engine):
     """State = (U, U_comp, phi): handing all three back resumes bit for bit,
