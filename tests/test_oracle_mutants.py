@@ -77,3 +77,35 @@ def test_pins_catch_mutant(tmp_path, name, old, new):
                         "tests/test_oracle_derivative.py", "tests/test_oracle_plateau.py"],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
     assert r.returncode != 0, f"mutant '{name}' survived every pin:\n{r.stdout[-2000:]}"
+
+
+# The mutants of the update, the dual, the energy, brute force and the
+# schedule's matching property that the randomized property tests
+# (test_oracle_properties.py) catch on their own, with hypothesis's search
+# fixed by its seed; the others (orientation, rounding details, the exact
+# schedule rule, the derivative) are pinned by the tests above only.
+PROPERTY_CATCHES = [
+    "mplp half dropped on u", "mplp half dropped on v", "row min instead of column min",
+    "v correction drops its base", "u correction drops its base", "wrong sign in write back",
+    "wrong index in aggregate", "transposed table in aggregate", "dual drops edge terms", "dual uses max",
+    "energy transposed lookup", "energy drops unaries", "greedy ignores the second node", "duplicates accepted",
+    "brute force skips labellings", "colouring: d free on the fan's first node", "colouring: no path swap",
+    "colouring: fan not rotated",
+]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", PROPERTY_CATCHES)
+def test_properties_catch_mutant(tmp_path, name):
+    old, new = next((o, n) for m, o, n in MUTANTS if m == name)
+    src = open(SRC).read()
+    c = tmp_path / "mut.c"
+    c.write_text(src.replace(old, new))
+    so = tmp_path / "libmut.so"
+    subprocess.run(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-o", str(so),
+                    str(c), "-lm"], check=True)
+    env = dict(os.environ, MPLP_ORACLE_LIB=str(so))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "--hypothesis-seed=0",
+                        "tests/test_oracle_properties.py"],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0, f"mutant '{name}' survived the property tests:\n{r.stdout[-2000:]}"
