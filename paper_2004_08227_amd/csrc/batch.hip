@@ -139,11 +139,16 @@ size_t batch_lds_limit(int max_lt) {
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 0;
   hipFuncAttributes fa{};
-  if (hipFuncGetAttributes(&fa, batch_kernel(max_lt)) != hipSuccess) return 0;
+  if (hipFuncGetAttributes(&fa, batch_kernel(max_lt)) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
   if ((size_t)per_block <= fa.sharedSizeBytes) return 0;
   const size_t limit = (size_t)per_block - fa.sharedSizeBytes;
-  if (hipFuncSetAttribute(batch_kernel(max_lt), hipFuncAttributeMaxDynamicSharedMemorySize, (int)limit) != hipSuccess)
+  if (hipFuncSetAttribute(batch_kernel(max_lt), hipFuncAttributeMaxDynamicSharedMemorySize, (int)limit) != hipSuccess) {
+    (void)hipGetLastError();  // (not left for a later launch check)
     return 0;
+  }
   return limit;
 }
 
@@ -273,12 +278,17 @@ size_t wbatch_lds_limit(size_t* static_bytes, int kind) {
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 0;
   hipFuncAttributes fa{};
-  if (hipFuncGetAttributes(&fa, wbatch_kernel(kind)) != hipSuccess) return 0;
+  if (hipFuncGetAttributes(&fa, wbatch_kernel(kind)) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
   if (static_bytes) *static_bytes = fa.sharedSizeBytes;
   if ((size_t)per_block <= fa.sharedSizeBytes) return 0;
   const size_t limit = (size_t)per_block - fa.sharedSizeBytes;
-  if (hipFuncSetAttribute(wbatch_kernel(kind), hipFuncAttributeMaxDynamicSharedMemorySize, (int)limit) != hipSuccess)
+  if (hipFuncSetAttribute(wbatch_kernel(kind), hipFuncAttributeMaxDynamicSharedMemorySize, (int)limit) != hipSuccess) {
+    (void)hipGetLastError();  // (not left for a later launch check)
     return 0;
+  }
   return limit;
 }
 

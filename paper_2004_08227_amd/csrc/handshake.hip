@@ -421,7 +421,11 @@ static hipError_t launch_mb_one(const HsArgs<float>& a, unsigned long long* mb, 
 // workgroups never release.
 static int placeable_per_cu(const void* f, int threads, int nb) {
   int one_wave = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&one_wave, f, 64, 0) != hipSuccess || one_wave < 4) return nb;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&one_wave, f, 64, 0) != hipSuccess) {
+    (void)hipGetLastError();  // (not left for a later launch check)
+    return nb;
+  }
+  if (one_wave < 4) return nb;
   const int per_simd = one_wave / 4;
   const int per_wg = ((threads + 63) / 64 + 3) / 4;
   return std::min(nb, std::max(1, per_simd / per_wg));

@@ -14,6 +14,9 @@ namespace mplpxx {
 // text of the last failure on the calling thread (mplpxx_last_error)
 inline thread_local std::string g_last_error;
 
+// Records the failure's text.  It also takes the HIP runtime's last error,
+// which a failed runtime call leaves set: left there, the next launch check
+// of a later call (hipGetLastError after a launch) would report it again.
 inline int fail(int code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -21,6 +24,7 @@ inline int fail(int code, const char* fmt, ...) {
   vsnprintf(buf, sizeof(buf), fmt, ap);
   va_end(ap);
   g_last_error = buf;
+  (void)hipGetLastError();
   return code;
 }
 
