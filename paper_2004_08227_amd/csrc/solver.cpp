@@ -606,7 +606,7 @@ int fwd64_segment(mplpxx_solver* h, int seg) {
 template <typename T> int adjoint_forward_t(mplpxx_solver* h, int K, int every, double* loss) {
   hipStream_t st = h->stream();
   const size_t nL = (size_t)h->n * h->L, mp = (size_t)h->m * 2 * h->L, esz = sizeof(T);
-  const int nck = (K + every - 1) / every;
+  const int nck = (int)(((long long)K + every - 1) / every);  // (64-bit: K + every can pass 2^31)
   const bool pers = adjoint_persistent<T>(h);
   // (re)allocate checkpoint and record storage
   for (void** p : {&h->d_ck_U, &h->d_ck_phi, (void**)&h->d_rec, (void**)&h->d_ck_Ulo, (void**)&h->d_contrib})

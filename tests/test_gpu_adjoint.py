@@ -166,6 +166,33 @@ def test_backward_requires_a_forward():
         assert ei.value.code == M.ESTATE
 
 
+@pytest.mark.parametrize("dtype,f64", [(np.float64, 1), (np.float32, 1), (np.float32, 0)])
+def test_adjoint_allocation_failure_is_reported(dtype, f64):
+    """Records for 2^31 - 1 iterations per segment need terabytes: the
+    forward fails in hipMalloc before any kernel runs (MPLPXX_ENOMEM), the
+    backward then refuses (no forward to differentiate), and a forward of a
+    normal size afterwards gives the gradient of a fresh handle, bit for
+    bit."""
+    _announce("adjoint allocation failure", dtype.__name__, f64)
+    model = W.tiny(5).astype(dtype)
+    big = 2**31 - 1
+    with M.Solver.from_model(model) as s:
+        s.set_option(M.OPT_ADJOINT_F64, f64)
+        with pytest.raises(M.MplpError) as ei:
+            s.adjoint_forward(big, big)
+        assert ei.value.code == M.ENOMEM
+        with pytest.raises(M.MplpError) as ei:
+            s.adjoint_backward()
+        assert ei.value.code == M.ESTATE
+        loss = s.adjoint_forward(6, 2)
+        gu, gp = s.adjoint_backward()
+    with M.Solver.from_model(model) as s2:
+        s2.set_option(M.OPT_ADJOINT_F64, f64)
+        loss2 = s2.adjoint_forward(6, 2)
+        gu2, gp2 = s2.adjoint_backward()
+    assert loss == loss2 and np.array_equal(gu, gu2) and np.array_equal(gp, gp2)
+
+
 def test_autograd_function():
     import torch
     from paper_2004_08227_amd.autograd import mplp_dual
