@@ -264,15 +264,19 @@ def bench_c2(M, W, iters=30, with_cpu=True):
 def bench_rules(M, W, iters=200):
     """MPLP (M) and uniform (U) against MPLP++ (H) from the same start (phi =
     0): dual traces of `iters` iterations, each rule on the per-matching
-    engine (same kernel structure, one launch per matching), and (H) also on
-    the persistent engine; seconds to reach D* - eps|D*|, D* the best final
+    engine (same kernel structure, one launch per matching), and (H) and (M)
+    also on the persistent mailbox engine (timed there; the trace of (M) comes
+    from the per-matching engine, and the two engines' final states are
+    compared bit for bit); seconds to reach D* - eps|D*|, D* the best final
     dual of all runs, from each run's own time per iteration."""
     out = {}
     for key, model in (("pose_k200_l64", W.pose(200, 64, seed=0)),
                        ("potts_er_n1000_l16_p0.25", W.potts_er(1000, 16, 0.25, seed=0))):
         runs = {}
+        same = {}
         for name, rule, engine in (("H_persistent", M.RULE_H, M.ENGINE_PERSISTENT), ("H", M.RULE_H, M.ENGINE_STEP),
-                                   ("M", M.RULE_M, M.ENGINE_STEP), ("U", M.RULE_U, M.ENGINE_STEP)):
+                                   ("M_persistent", M.RULE_M, M.ENGINE_PERSISTENT), ("M", M.RULE_M, M.ENGINE_STEP),
+                                   ("U", M.RULE_U, M.ENGINE_STEP)):
             with M.Solver.from_model(model) as s:
                 s.set_option(M.OPT_ENGINE, engine)
                 s.set_option(M.OPT_RULE, rule)
@@ -281,12 +285,17 @@ def bench_rules(M, W, iters=200):
                 s.set_state(U0, phi0)
                 s.iterate(iters)
                 t_it = s.last_iterate_ms() / 1e3 / iters
+                st_it = s.get_state(comp=True)
                 s.set_state(U0, phi0)
                 tr = s.iterate_trace(iters)
+                st_tr = s.get_state(comp=True)
+            if name == "M_persistent":
+                same[name] = all(np.array_equal(x, y) for x, y in zip(st_it, st_tr))
             runs[name] = (tr, t_it)
         d_star = float(max(tr.max() for tr, _ in runs.values()))
         eps = [1e-1, 1e-2, 1e-3, 1e-4, 1e-5]
-        rec = {"m": model.m, "iterations": iters, "d_star": d_star, "eps_rel": eps}
+        rec = {"m": model.m, "iterations": iters, "d_star": d_star, "eps_rel": eps,
+               "M_persistent_state_equals_per_matching": same.get("M_persistent")}
         for name, (tr, t_it) in runs.items():
             rec[name] = {"s_per_iter": t_it, "final_dual": float(tr[-1]), "time_to_bound_s": time_to_bound(tr, t_it, d_star, eps),
                          "iterations_to_bound": {f"{e:g}": (None if not np.any(tr >= d_star - e * abs(d_star))
@@ -481,6 +490,9 @@ def summary(result):
     if r and isinstance(r.get("pose_k200_l64"), dict):
         sm["c1_final_dual_by_rule"] = {k: v.get("final_dual") for k, v in r["pose_k200_l64"].items()
                                        if isinstance(v, dict) and "final_dual" in v}
+        sm["c1_s_to_10pct_of_dstar_by_rule"] = {k: v["time_to_bound_s"].get("0.1")
+                                                for k, v in r["pose_k200_l64"].items()
+                                                if isinstance(v, dict) and "time_to_bound_s" in v}
     for sec in ("trunc_linear", "trunc_quad"):
         t = result.get(sec)
         if t:

@@ -154,10 +154,12 @@ template <typename T> int max_blocks_per_cu(int engine, int LT, int NT);
 // FP32 persistent engine with tagged mailboxes
 // prefetch: steps the tables are loaded ahead (0 the default: 2 for tiles up
 // to 64, 1 for 128; 1: one step, for tiles up to 64 without a trace)
-// kind: a structured cost (Potts or truncated quadratic, NT = 256, LT <= 64)
-// whose tiles are formed from the slots' parameters
+// kind: a structured cost (MPLPXX_COST_*, NT = 256, LT <= 64) whose tiles
+// are formed from the slots' parameters
+// rule: MPLPXX_RULE_H, or MPLPXX_RULE_M (dense tables, NT = 256, no trace)
 hipError_t launch_persistent_mb(const HsArgs<float>& a, unsigned long long* mb, int LT, int NT, int grid, int iters,
-                                int phi_in_lds, size_t dyn_lds, hipStream_t st, int prefetch = 0, int kind = 0);
+                                int phi_in_lds, size_t dyn_lds, hipStream_t st, int prefetch = 0, int kind = 0,
+                                int rule = 0);
 // the same for Potts models (one weight per slot, L <= 64; potts_mb.h)
 int max_blocks_per_cu_mb_potts();
 hipError_t launch_persistent_mb_potts(const HsArgs<float>& a, unsigned long long* mb, int grid, int iters,

@@ -519,7 +519,7 @@ __device__ __forceinline__ void load_phi(const float* src, int L, float (&pu)[Ti
 // slot is formed from its parameters (v.tables holds cost_params(KIND)
 // floats per slot) by gen_tile, the rest is the dense engine.
 template <int LT, int NT, bool PHI_LDS, bool FULL, bool TRACE, bool LDSU, bool PHI_FAR, int DEPTH = (LT <= 64 ? 2 : 1),
-          int KIND = kCostDense>
+          int KIND = kCostDense, int RULE = MPLPXX_RULE_H>
 __device__ __forceinline__ bool mb_run(const MbView& v_in, int first_in, int stride_in, int iters_in,
                                        SmemMB<LT, NT>& sm, float* phi_lds, long long spin_limit, int* err) {
   using S = TileShape<float, LT, NT>;
@@ -714,9 +714,10 @@ __device__ __forceinline__ bool mb_run(const MbView& v_in, int first_in, int str
         if (cb == i) ophi = pu[i];
     }
     // pass 1: p(s) = min_t [th(s,t) + a_v(t)], b = (a_u - p) / 2
-    float b[S::BR];
+    // ((M), Sec. 4: the column pass takes a_u itself, b = a_u)
+    static_assert(RULE == MPLPXX_RULE_H || (RULE == MPLPXX_RULE_M && !TRACE), "update rule");
+    float b[S::BR], pm[S::BR];
     {
-      float pm[S::BR];
 #pragma unroll
       for (int i = 0; i < S::BR; ++i) {
         float mn = xc[i][0] + av[0];
@@ -726,9 +727,9 @@ __device__ __forceinline__ bool mb_run(const MbView& v_in, int first_in, int str
       }
       row16_min_n<S::BR>(pm);
 #pragma unroll
-      for (int i = 0; i < S::BR; ++i) b[i] = 0.5f * (au[i] - pm[i]);
+      for (int i = 0; i < S::BR; ++i) b[i] = RULE == MPLPXX_RULE_M ? au[i] : 0.5f * (au[i] - pm[i]);
     }
-    // pass 2: q(t) = min_s [th(s,t) + b(s)]
+    // pass 2: q(t) = min_s [th(s,t) + b(s)]  ((M): p'(t) = min_s [th(s,t) + a_u(s)])
     float qv[S::BC];
 #pragma unroll
     for (int jj = 0; jj < S::BC; ++jj) {
@@ -768,23 +769,31 @@ __device__ __forceinline__ bool mb_run(const MbView& v_in, int first_in, int str
       qv[jj] = mn;
     }
     // the output column's message q' + delta, q' reduced the same way
+    // ((M): (p' - a'_v)/2 + delta)
     float omsg;
     {
       float mn = opart[0];
 #pragma unroll
       for (int w = 1; w < S::W; ++w) mn = vmin(mn, opart[w]);
-      omsg = mn + delta;
+      if constexpr (RULE == MPLPXX_RULE_M) omsg = 0.5f * (mn - (sm.uv[parity][out_ic] - fc.pvo)) + delta;
+      else omsg = mn + delta;
     }
-    // pass 3: r(s) = min_t [th(s,t) - q(t)]
+    // pass 3: r(s) = min_t [th(s,t) - q(t)]  ((M): none; the row message is
+    // (p - a'_u)/2 - delta)
     float r[S::BR];
+    if constexpr (RULE == MPLPXX_RULE_M) {
 #pragma unroll
-    for (int i = 0; i < S::BR; ++i) {
-      float mn = xc[i][0] - qv[0];
+      for (int i = 0; i < S::BR; ++i) r[i] = 0.5f * (pm[i] - au[i]);
+    } else {
 #pragma unroll
-      for (int jj = 1; jj < S::BC; ++jj) mn = vmin(mn, xc[i][jj] - qv[jj]);
-      r[i] = mn;
+      for (int i = 0; i < S::BR; ++i) {
+        float mn = xc[i][0] - qv[0];
+#pragma unroll
+        for (int jj = 1; jj < S::BC; ++jj) mn = vmin(mn, xc[i][jj] - qv[jj]);
+        r[i] = mn;
+      }
+      row16_min_n<S::BR>(r);
     }
-    row16_min_n<S::BR>(r);
     if (TRACE) {
       // edge term of Eq. (3) after this update from the stored messages
       // rs = r' - delta, qs = q' + delta: min over real rows of

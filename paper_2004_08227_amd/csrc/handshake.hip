@@ -266,7 +266,7 @@ __global__ void __launch_bounds__(NT) k_persistent(HsArgs<T> a, int iters) {
 }
 
 template <int LT, int NT, bool PHI_LDS, bool FULL, bool TRACE, bool PHI_FAR, int DEPTH = (LT <= 64 ? 2 : 1),
-          int KIND = kCostDense>
+          int KIND = kCostDense, int RULE = MPLPXX_RULE_H>
 __global__ void __launch_bounds__(NT + 128) k_persistent_mb(HsArgs<float> a, unsigned long long* __restrict__ mb,
                                                             int iters) {
   __shared__ SmemMB<LT, NT> sm;
@@ -283,7 +283,7 @@ __global__ void __launch_bounds__(NT + 128) k_persistent_mb(HsArgs<float> a, uns
   __syncthreads();
   MbView v{a.tables, a.phi, mb, a.slots, a.deg, a.trace, a.trace_e, a.stamps, L, a.m, a.n, nullptr, nullptr,
            a.sink + (size_t)blockIdx.x * (NT + 128)};
-  if (!mb_run<LT, NT, PHI_LDS, FULL, TRACE, false, PHI_FAR, DEPTH, KIND>(v, blockIdx.x, G, iters, sm, phi_lds,
+  if (!mb_run<LT, NT, PHI_LDS, FULL, TRACE, false, PHI_FAR, DEPTH, KIND, RULE>(v, blockIdx.x, G, iters, sm, phi_lds,
                                                                          a.spin_limit, a.err))
     return;
   __syncthreads();
@@ -372,10 +372,32 @@ static const void* mb_gen_kernel(bool phi_in_lds, bool full, bool far) {
 #undef MPLPXX_G
 }
 
+// the (M) update on the dense engine (four compute waves, no trace)
+template <int LT>
+static const void* mb_rule_m_kernel(bool phi_in_lds, bool full, bool far) {
+#define MPLPXX_G(P, F, A) (const void*)k_persistent_mb<LT, 256, P, F, false, A, (LT <= 64 ? 2 : 1), kCostDense, MPLPXX_RULE_M>
+  return phi_in_lds ? (full ? (far ? MPLPXX_G(true, true, true) : MPLPXX_G(true, true, false))
+                            : (far ? MPLPXX_G(true, false, true) : MPLPXX_G(true, false, false)))
+                    : (full ? (far ? MPLPXX_G(false, true, true) : MPLPXX_G(false, true, false))
+                            : (far ? MPLPXX_G(false, false, true) : MPLPXX_G(false, false, false)));
+#undef MPLPXX_G
+}
+
 template <int LT, int NT>
 static hipError_t launch_mb_one(const HsArgs<float>& a, unsigned long long* mb, int grid, int iters, int phi_in_lds,
-                                size_t dyn_lds, hipStream_t st, int prefetch, int kind) {
+                                size_t dyn_lds, hipStream_t st, int prefetch, int kind, int rule) {
   void* args[] = {(void*)&a, (void*)&mb, (void*)&iters};
+  if (rule != MPLPXX_RULE_H) {
+    if constexpr (NT == 256) {
+      if (rule != MPLPXX_RULE_M || kind != kCostDense || a.trace) return hipErrorInvalidValue;
+      const bool far = (a.m / grid) >= (LT <= 64 ? 2 : 1) + 2;
+      const void* f = mb_rule_m_kernel<LT>(phi_in_lds, a.L == LT, far);
+      const hipError_t e = hipLaunchCooperativeKernel(f, dim3(grid), dim3(NT + 128), args, dyn_lds, st);
+      if (e != hipSuccess) (void)hipGetLastError();
+      return e;
+    }
+    return hipErrorInvalidValue;
+  }
   if (kind != kCostDense) {
     if constexpr (NT == 256 && LT <= 64) {
       const bool far = (a.m / grid) >= 4;
@@ -456,9 +478,9 @@ int max_blocks_per_cu_mb(int LT, int NT) {
 }
 
 hipError_t launch_persistent_mb(const HsArgs<float>& a, unsigned long long* mb, int LT, int NT, int grid, int iters,
-                                int phi_in_lds, size_t dyn_lds, hipStream_t st, int prefetch, int kind) {
+                                int phi_in_lds, size_t dyn_lds, hipStream_t st, int prefetch, int kind, int rule) {
 #define MPLPXX_CASE(lt, nt) \
-  if (LT == lt && NT == nt) return launch_mb_one<lt, nt>(a, mb, grid, iters, phi_in_lds, dyn_lds, st, prefetch, kind);
+  if (LT == lt && NT == nt) return launch_mb_one<lt, nt>(a, mb, grid, iters, phi_in_lds, dyn_lds, st, prefetch, kind, rule);
   MPLPXX_CASE(16, 64)
   MPLPXX_CASE(16, 256)
   MPLPXX_CASE(32, 64)
