@@ -264,10 +264,10 @@ def bench_c2(M, W, iters=30, with_cpu=True):
 def bench_rules(M, W, iters=200):
     """MPLP (M) and uniform (U) against MPLP++ (H) from the same start (phi =
     0): dual traces of `iters` iterations, each rule on the per-matching
-    engine (same kernel structure, one launch per matching), and (H) and (M)
-    also on the persistent mailbox engine (timed there; the trace of (M) comes
-    from the per-matching engine, and the two engines' final states are
-    compared bit for bit); seconds to reach D* - eps|D*|, D* the best final
+    engine (same kernel structure, one launch per matching), and every rule
+    also on the persistent mailbox engine (timed there; the traces of (M) and
+    (U) come from the per-matching engine, and the two engines' final states
+    are compared bit for bit); seconds to reach D* - eps|D*|, D* the best final
     dual of all runs, from each run's own time per iteration."""
     out = {}
     for key, model in (("pose_k200_l64", W.pose(200, 64, seed=0)),
@@ -276,7 +276,7 @@ def bench_rules(M, W, iters=200):
         same = {}
         for name, rule, engine in (("H_persistent", M.RULE_H, M.ENGINE_PERSISTENT), ("H", M.RULE_H, M.ENGINE_STEP),
                                    ("M_persistent", M.RULE_M, M.ENGINE_PERSISTENT), ("M", M.RULE_M, M.ENGINE_STEP),
-                                   ("U", M.RULE_U, M.ENGINE_STEP)):
+                                   ("U_persistent", M.RULE_U, M.ENGINE_PERSISTENT), ("U", M.RULE_U, M.ENGINE_STEP)):
             with M.Solver.from_model(model) as s:
                 s.set_option(M.OPT_ENGINE, engine)
                 s.set_option(M.OPT_RULE, rule)
@@ -289,13 +289,14 @@ def bench_rules(M, W, iters=200):
                 s.set_state(U0, phi0)
                 tr = s.iterate_trace(iters)
                 st_tr = s.get_state(comp=True)
-            if name == "M_persistent":
+            if name in ("M_persistent", "U_persistent"):
                 same[name] = all(np.array_equal(x, y) for x, y in zip(st_it, st_tr))
             runs[name] = (tr, t_it)
         d_star = float(max(tr.max() for tr, _ in runs.values()))
         eps = [1e-1, 1e-2, 1e-3, 1e-4, 1e-5]
         rec = {"m": model.m, "iterations": iters, "d_star": d_star, "eps_rel": eps,
-               "M_persistent_state_equals_per_matching": same.get("M_persistent")}
+               "M_persistent_state_equals_per_matching": same.get("M_persistent"),
+               "U_persistent_state_equals_per_matching": same.get("U_persistent")}
         for name, (tr, t_it) in runs.items():
             rec[name] = {"s_per_iter": t_it, "final_dual": float(tr[-1]), "time_to_bound_s": time_to_bound(tr, t_it, d_star, eps),
                          "iterations_to_bound": {f"{e:g}": (None if not np.any(tr >= d_star - e * abs(d_star))

@@ -329,13 +329,14 @@ int mplpxx_iterate_trace(mplpxx_solver* h, int32_t k, double* trace);
  * change of the method: MPLPXX_RULE_H (default) the MPLP++ handshake (H);
  * MPLPXX_RULE_M the MPLP update (M), both nodes get half of the row and
  * column minima of the aggregated cost; MPLPXX_RULE_U the uniform update
- * (U), both nodes get half of its overall minimum.  (U), traces under
- * (M), FP64 handles and MPLPXX_OPT_THREADS other than 0 or 256 run the
+ * (U), both nodes get half of its overall minimum.  Traces under (M) or
+ * (U), FP64 handles and MPLPXX_OPT_THREADS other than 0 or 256 run the
  * per-matching engine whatever MPLPXX_OPT_ENGINE says; mplpxx_iterate of
- * an FP32 handle under (M) runs the persistent mailbox engine (four compute
- * waves, two passes per update) unless MPLPXX_OPT_ENGINE asks for the
- * per-matching one, with the same bits; MPLPXX_INFO_ENGINE reports the
- * per-matching engine for (M) and (U).  The adjoint and the batch API take
+ * an FP32 handle under (M) or (U) runs the persistent mailbox engine (four
+ * compute waves; two passes per update for (M), one and a reduction for
+ * (U)) unless MPLPXX_OPT_ENGINE asks for the per-matching one, with the
+ * same bits; MPLPXX_INFO_ENGINE reports the per-matching engine for (M)
+ * and (U).  The adjoint and the batch API take
  * (H) only (mplpxx_adjoint_forward returns MPLPXX_EINVAL under another
  * rule). */
 #define MPLPXX_OPT_RULE 7

@@ -156,7 +156,7 @@ template <typename T> int max_blocks_per_cu(int engine, int LT, int NT);
 // to 64, 1 for 128; 1: one step, for tiles up to 64 without a trace)
 // kind: a structured cost (MPLPXX_COST_*, NT = 256, LT <= 64) whose tiles
 // are formed from the slots' parameters
-// rule: MPLPXX_RULE_H, or MPLPXX_RULE_M (dense tables, NT = 256, no trace)
+// rule: MPLPXX_RULE_H, or MPLPXX_RULE_M / _U (dense tables, NT = 256, no trace)
 hipError_t launch_persistent_mb(const HsArgs<float>& a, unsigned long long* mb, int LT, int NT, int grid, int iters,
                                 int phi_in_lds, size_t dyn_lds, hipStream_t st, int prefetch = 0, int kind = 0,
                                 int rule = 0);

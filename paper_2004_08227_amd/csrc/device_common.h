@@ -715,7 +715,7 @@ __device__ __forceinline__ bool mb_run(const MbView& v_in, int first_in, int str
     }
     // pass 1: p(s) = min_t [th(s,t) + a_v(t)], b = (a_u - p) / 2
     // ((M), Sec. 4: the column pass takes a_u itself, b = a_u)
-    static_assert(RULE == MPLPXX_RULE_H || (RULE == MPLPXX_RULE_M && !TRACE), "update rule");
+    static_assert(RULE == MPLPXX_RULE_H || ((RULE == MPLPXX_RULE_M || RULE == MPLPXX_RULE_U) && !TRACE), "update rule");
     float b[S::BR], pm[S::BR];
     {
 #pragma unroll
@@ -729,18 +729,30 @@ __device__ __forceinline__ bool mb_run(const MbView& v_in, int first_in, int str
 #pragma unroll
       for (int i = 0; i < S::BR; ++i) b[i] = RULE == MPLPXX_RULE_M ? au[i] : 0.5f * (au[i] - pm[i]);
     }
-    // pass 2: q(t) = min_s [th(s,t) + b(s)]  ((M): p'(t) = min_s [th(s,t) + a_u(s)])
+    // pass 2: q(t) = min_s [th(s,t) + b(s)]  ((M): p'(t) = min_s [th(s,t) + a_u(s)];
+    // (U): instead this wave's part of G = min over real rows of a'_u(s) + p(s))
     float qv[S::BC];
+    if constexpr (RULE == MPLPXX_RULE_U) {
+      float gm = __builtin_inff();
 #pragma unroll
-    for (int jj = 0; jj < S::BC; ++jj) {
-      float mn = xc[0][jj] + b[0];
+      for (int i = 0; i < S::BR; ++i)
+        if (FULL || rb * S::BR + i < L) gm = vmin(gm, au[i] + pm[i]);
+      gm = col4_min(gm);
+      if (lane == 0) sm.red[wave][0] = gm;
 #pragma unroll
-      for (int i = 1; i < S::BR; ++i) mn = vmin(mn, xc[i][jj] + b[i]);
-      qv[jj] = col4_min(mn);
-    }
-    if (lane < 16) {
+      for (int jj = 0; jj < S::BC; ++jj) qv[jj] = 0.0f;
+    } else {
 #pragma unroll
-      for (int jj = 0; jj < S::BC; ++jj) sm.red[wave][cb * S::BC + jj] = qv[jj];
+      for (int jj = 0; jj < S::BC; ++jj) {
+        float mn = xc[0][jj] + b[0];
+#pragma unroll
+        for (int i = 1; i < S::BR; ++i) mn = vmin(mn, xc[i][jj] + b[i]);
+        qv[jj] = col4_min(mn);
+      }
+      if (lane < 16) {
+#pragma unroll
+        for (int jj = 0; jj < S::BC; ++jj) sm.red[wave][cb * S::BC + jj] = qv[jj];
+      }
     }
 #if MPLPXX_FINE_STAMPS
     if (v.stamps && last_iter && tid == 0) v.stamps[(size_t)slot * kStampStride + 6] = wall_clock64();
@@ -769,21 +781,31 @@ __device__ __forceinline__ bool mb_run(const MbView& v_in, int first_in, int str
       qv[jj] = mn;
     }
     // the output column's message q' + delta, q' reduced the same way
-    // ((M): (p' - a'_v)/2 + delta)
+    // ((M): (p' - a'_v)/2 + delta; (U): (G/2 - a'_v) + delta)
     float omsg;
-    {
+    float ghalf = 0.0f;
+    if constexpr (RULE == MPLPXX_RULE_U) {
+      float gm = sm.red[0][0];
+#pragma unroll
+      for (int w = 1; w < S::W; ++w) gm = vmin(gm, sm.red[w][0]);
+      ghalf = 0.5f * gm;
+      omsg = (ghalf - (sm.uv[parity][out_ic] - fc.pvo)) + delta;
+    } else {
       float mn = opart[0];
 #pragma unroll
       for (int w = 1; w < S::W; ++w) mn = vmin(mn, opart[w]);
       if constexpr (RULE == MPLPXX_RULE_M) omsg = 0.5f * (mn - (sm.uv[parity][out_ic] - fc.pvo)) + delta;
       else omsg = mn + delta;
     }
-    // pass 3: r(s) = min_t [th(s,t) - q(t)]  ((M): none; the row message is
-    // (p - a'_u)/2 - delta)
+    // pass 3: r(s) = min_t [th(s,t) - q(t)]  ((M), (U): none; the row message
+    // is (p - a'_u)/2 - delta, or (G/2 - a'_u) - delta)
     float r[S::BR];
     if constexpr (RULE == MPLPXX_RULE_M) {
 #pragma unroll
       for (int i = 0; i < S::BR; ++i) r[i] = 0.5f * (pm[i] - au[i]);
+    } else if constexpr (RULE == MPLPXX_RULE_U) {
+#pragma unroll
+      for (int i = 0; i < S::BR; ++i) r[i] = ghalf - au[i];
     } else {
 #pragma unroll
       for (int i = 0; i < S::BR; ++i) {

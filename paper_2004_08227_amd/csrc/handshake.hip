@@ -372,10 +372,10 @@ static const void* mb_gen_kernel(bool phi_in_lds, bool full, bool far) {
 #undef MPLPXX_G
 }
 
-// the (M) update on the dense engine (four compute waves, no trace)
-template <int LT>
-static const void* mb_rule_m_kernel(bool phi_in_lds, bool full, bool far) {
-#define MPLPXX_G(P, F, A) (const void*)k_persistent_mb<LT, 256, P, F, false, A, (LT <= 64 ? 2 : 1), kCostDense, MPLPXX_RULE_M>
+// the (M) and (U) updates on the dense engine (four compute waves, no trace)
+template <int LT, int RULE>
+static const void* mb_rule_kernel(bool phi_in_lds, bool full, bool far) {
+#define MPLPXX_G(P, F, A) (const void*)k_persistent_mb<LT, 256, P, F, false, A, (LT <= 64 ? 2 : 1), kCostDense, RULE>
   return phi_in_lds ? (full ? (far ? MPLPXX_G(true, true, true) : MPLPXX_G(true, true, false))
                             : (far ? MPLPXX_G(true, false, true) : MPLPXX_G(true, false, false)))
                     : (full ? (far ? MPLPXX_G(false, true, true) : MPLPXX_G(false, true, false))
@@ -389,9 +389,11 @@ static hipError_t launch_mb_one(const HsArgs<float>& a, unsigned long long* mb, 
   void* args[] = {(void*)&a, (void*)&mb, (void*)&iters};
   if (rule != MPLPXX_RULE_H) {
     if constexpr (NT == 256) {
-      if (rule != MPLPXX_RULE_M || kind != kCostDense || a.trace) return hipErrorInvalidValue;
+      if ((rule != MPLPXX_RULE_M && rule != MPLPXX_RULE_U) || kind != kCostDense || a.trace)
+        return hipErrorInvalidValue;
       const bool far = (a.m / grid) >= (LT <= 64 ? 2 : 1) + 2;
-      const void* f = mb_rule_m_kernel<LT>(phi_in_lds, a.L == LT, far);
+      const void* f = rule == MPLPXX_RULE_M ? mb_rule_kernel<LT, MPLPXX_RULE_M>(phi_in_lds, a.L == LT, far)
+                                            : mb_rule_kernel<LT, MPLPXX_RULE_U>(phi_in_lds, a.L == LT, far);
       const hipError_t e = hipLaunchCooperativeKernel(f, dim3(grid), dim3(NT + 128), args, dyn_lds, st);
       if (e != hipSuccess) (void)hipGetLastError();
       return e;

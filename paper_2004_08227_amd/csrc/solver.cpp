@@ -154,11 +154,11 @@ struct mplpxx_solver {
     if (engine_opt == ENGINE_STEP || engine_opt == ENGINE_PERSISTENT) return engine_opt;
     return ENGINE_PERSISTENT;
   }
-  // (M) on FP32 dense handles also runs on the mailbox engine (four compute
-  // waves) when no trace is asked for; traces and (U) use the per-matching
+  // (M) and (U) on FP32 dense handles also run on the mailbox engine (four
+  // compute waves) when no trace is asked for; traces use the per-matching
   // engine, with the same bits
-  bool rule_m_mailbox() const {
-    return rule == MPLPXX_RULE_M && dtype == MPLPXX_F32 && !potts && max_deg < 65536 && engine_opt != ENGINE_STEP &&
+  bool rule_mailbox() const {
+    return rule != MPLPXX_RULE_H && dtype == MPLPXX_F32 && !potts && max_deg < 65536 && engine_opt != ENGINE_STEP &&
            (threads_opt == 0 || threads_opt == 256);
   }
   // FP32 mailbox engine: one workgroup per compute unit, or, when a matching
@@ -168,7 +168,7 @@ struct mplpxx_solver {
   bool mb_engine() const { return dtype == MPLPXX_F32 && engine() == ENGINE_PERSISTENT; }
   int grid() const {
     int g = grid_opt > 0 ? grid_opt : num_cus;
-    if (grid_opt == 0 && (mb_engine() || rule_m_mailbox()) && max_step > num_cus)
+    if (grid_opt == 0 && (mb_engine() || rule_mailbox()) && max_step > num_cus)
       g = std::max(num_cus, std::min(max_step, (potts && !gen_tiles() ? max_blocks_per_cu_mb_potts()
                                                                        : max_blocks_per_cu_mb(LT(), NT())) *
                                                      num_cus));
@@ -487,9 +487,9 @@ template <typename T> int iterate_t(mplpxx_solver* h, int k, double* trace_host)
     h->trace_cap = k;
   }
   int trace_w = 1;
-  const bool rule_m_mb = !trace_host && h->rule_m_mailbox();
-  const int engine = rule_m_mb ? ENGINE_PERSISTENT : h->engine();
-  const int LT = h->LT(), NT = rule_m_mb ? 256 : h->NT();
+  const bool rule_mb = !trace_host && h->rule_mailbox();
+  const int engine = rule_mb ? ENGINE_PERSISTENT : h->engine();
+  const int LT = h->LT(), NT = rule_mb ? 256 : h->NT();
   HIP_TRY(hipEventRecord(h->ev0, st));
   if (h->m > 0 && k > 0) {
     if (engine == ENGINE_STEP) {
@@ -535,7 +535,7 @@ template <typename T> int iterate_t(mplpxx_solver* h, int k, double* trace_host)
         HIP_TRY(launch_persistent_mb_potts(a, h->d_mb, G, k, in_lds, in_lds ? phi_bytes : 0, st, h->potts));
       else
         HIP_TRY(launch_persistent_mb(a, h->d_mb, LT, NT, G, k, in_lds, in_lds ? phi_bytes : 0, st, h->prefetch_opt,
-                                     h->gen_tiles() ? h->potts : 0, rule_m_mb ? MPLPXX_RULE_M : MPLPXX_RULE_H));
+                                     h->gen_tiles() ? h->potts : 0, rule_mb ? h->rule : MPLPXX_RULE_H));
       HIP_TRY(launch_mb_fini(static_cast<float*>(h->d_U), h->d_Ulo, h->d_mb, h->n, h->L,
                              trace_host ? h->d_trace_nodes + (size_t)(k - 1) * h->n : nullptr, st));
     } else if (!trace_host && h->L <= 64) {

@@ -1,5 +1,5 @@
 """GPU tests of the other BCA-updates of Sec. 4: MPLP (M) and uniform (U),
-on the per-matching engine (and (M) also on the mailbox engine, bitwise the
+on the per-matching engine (and on the mailbox engine, bitwise the
 per-matching one), against the paper's two-node example (printed
 values and the closed forms of (M) and (U) on the same inputs), the FP64
 oracle (1e-12 in FP64, 1e-5 in FP32), and the dominance of one (H)
@@ -103,16 +103,18 @@ def test_rule_fp32_matches_oracle(name, make, iters, rule):
     ("sparse_large_matchings", lambda: W.potts_er(700, 16, 0.08, seed=11), 6),
     ("pose_full_size", lambda: W.pose(200, 64, seed=0), 200)], ids=[c[0] for c in CASES[1:]] +
     ["pose_L64", "sparse_large_matchings", "pose_full_size"])
-def test_rule_m_on_the_mailbox_engine_is_bitwise_the_per_matching_engine(name, make, iters):
-    """FP32 iterate under (M) runs the persistent mailbox engine (two passes
-    per update); its state, certified dual and rounding are bitwise those of
-    the per-matching engine, whose traces the oracle pins."""
-    _announce("rule M mailbox", name)
+@pytest.mark.parametrize("rule", ["M", "U"])
+def test_rule_on_the_mailbox_engine_is_bitwise_the_per_matching_engine(name, make, iters, rule):
+    """FP32 iterate under (M) or (U) runs the persistent mailbox engine (two
+    passes per update, or one and a reduction); its state, certified dual
+    and rounding are bitwise those of the per-matching engine, whose traces
+    the oracle pins."""
+    _announce("rule mailbox", rule, name)
     model = make()
     out = []
     for engine in (M.ENGINE_PERSISTENT, M.ENGINE_STEP):
         with M.Solver.from_model(model) as s:
-            s.set_option(M.OPT_RULE, M.RULE_M)
+            s.set_option(M.OPT_RULE, M.RULE_M if rule == "M" else M.RULE_U)
             s.set_option(M.OPT_ENGINE, engine)
             s.iterate(iters)
             out.append((s.get_state(comp=True), s.dual_bound(), s.decode()))
