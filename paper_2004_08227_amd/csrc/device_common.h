@@ -41,15 +41,19 @@ template <typename T> __device__ __forceinline__ T row16_min(T x) {
 }
 
 // the same for N independent values at once (interleaved for ILP)
-template <int N, typename T> __device__ __forceinline__ void row16_min_n(T (&x)[N]) {
+// (STEPS < 4 stops early: after 3 steps each lane holds the minimum over its
+// half row)
+template <int N, int STEPS = 4, typename T> __device__ __forceinline__ void row16_min_n(T (&x)[N]) {
 #pragma unroll
   for (int k = 0; k < N; ++k) x[k] = vmin(x[k], dpp_f<0xB1>(x[k]));
 #pragma unroll
   for (int k = 0; k < N; ++k) x[k] = vmin(x[k], dpp_f<0x4E>(x[k]));
 #pragma unroll
   for (int k = 0; k < N; ++k) x[k] = vmin(x[k], dpp_f<0x141>(x[k]));
+  if constexpr (STEPS == 4) {
 #pragma unroll
-  for (int k = 0; k < N; ++k) x[k] = vmin(x[k], dpp_f<0x140>(x[k]));
+    for (int k = 0; k < N; ++k) x[k] = vmin(x[k], dpp_f<0x140>(x[k]));
+  }
 }
 
 // minimum over lanes l, l^16, l^32, l^48 (the 4 row blocks of one wave)
@@ -63,6 +67,41 @@ __device__ __forceinline__ double col4_min(double x) {
   x = vmin(x, __shfl_xor(x, 16, 64));
   x = vmin(x, __shfl_xor(x, 32, 64));
   return x;
+}
+
+// Column minima over the wave's four row blocks for BC columns per lane,
+// stored to red[cb * BC + jj].  The swaps carry two different columns each:
+// a 16-lane swap of columns a and b leaves row blocks 0..3 holding the
+// pairwise minima (rows 0-1 of a, rows 0-1 of b, rows 2-3 of a, rows 2-3 of
+// b), and a 32-lane swap of two such results joins rows 0-1 with rows 2-3,
+// so with four columns row block k ends with the minimum of column k: three
+// swaps and three minima where a swap of each column with itself needs
+// eight of each and eight copies.
+__device__ __forceinline__ float pair16_min(float a, float b) {
+  auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return vmin(__uint_as_float(r[0]), __uint_as_float(r[1]));
+}
+__device__ __forceinline__ float join32_min(float a, float b) {
+  auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return vmin(__uint_as_float(r[0]), __uint_as_float(r[1]));
+}
+template <int BC>
+__device__ __forceinline__ void col4_min_store(const float (&x)[BC], float* red, int cb, int lane) {
+  const int k = lane >> 4;
+  if constexpr (BC == 1) {
+    const float m = col4_min(x[0]);
+    if (lane < 16) red[cb] = m;
+  } else if constexpr (BC == 2) {
+    // row blocks 0..3 end with columns 0, 1, 0, 1
+    const float m = pair16_min(x[0], x[1]);
+    const float f = join32_min(m, m);
+    if (lane < 32) red[cb * 2 + k] = f;
+  } else {
+    static_assert(BC % 4 == 0, "columns per lane");
+#pragma unroll
+    for (int g = 0; g < BC; g += 4)
+      red[cb * BC + g + k] = join32_min(pair16_min(x[g], x[g + 1]), pair16_min(x[g + 2], x[g + 3]));
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -103,6 +142,20 @@ __device__ __forceinline__ float bf16_round(float x) {
 __device__ __forceinline__ void comp_update(float hi, float lo, float phi_old, float phi_new, float& nhi, float& nlo) {
   const float d = hi - phi_old;
   const float e1 = two_sum_err(hi, -phi_old, d);
+  const float s = d + phi_new;
+  const float e2 = two_sum_err(d, phi_new, s);
+  const float c = (e1 + e2) + lo;
+  nhi = s + c;
+  nlo = bf16_round(two_sum_err(s, c, nhi));
+}
+// comp_update in two parts with the same operations in the same order (so
+// the same bits): the head needs only the old value and message, the tail
+// adds the new message.
+__device__ __forceinline__ void comp_update_head(float hi, float phi_old, float& d, float& e1) {
+  d = hi - phi_old;
+  e1 = two_sum_err(hi, -phi_old, d);
+}
+__device__ __forceinline__ void comp_update_tail(float d, float e1, float lo, float phi_new, float& nhi, float& nlo) {
   const float s = d + phi_new;
   const float e2 = two_sum_err(d, phi_new, s);
   const float c = (e1 + e2) + lo;
@@ -610,6 +663,7 @@ __device__ __forceinline__ bool mb_run(const MbView& v_in, int first_in, int str
   // output lane of this thread
   constexpr int VPW = LT / S::W;
   static_assert(VPW <= 4 * (16 - S::BR), "column outputs per wave");
+  static_assert(S::BR <= 8, "row outputs in the first half of a row block");
   const bool out_u = cb < S::BR;
   const int out_s = rb * S::BR + cb;
   const int lw = (rb & 3) * (16 - S::BR) + (cb - S::BR);
@@ -680,6 +734,21 @@ __device__ __forceinline__ bool mb_run(const MbView& v_in, int first_in, int str
       else gen_tile<LT, NT, KIND>(v.tables + (size_t)(first + jq * stride) * cost_params(KIND), xp);
       if (PHI_FAR) load_phiset(fp, jq);
     }
+    // This lane's mailbox target and version need no result of the passes:
+    // formed here, before the step's barriers (the empty asm keeps them here
+    // rather than at their use, on the step's critical path).
+    const int node = out_u ? si.u : si.v;
+    const bool outk = out_uk || out_v;
+    unsigned long long* mb_dst = nullptr;
+    unsigned ver = 0;
+    if (!LDSU) {
+      mb_dst = outk ? v.mb + (size_t)node * L + out_i : v.sink + (tid & ~63);
+      ver = (out_u ? want_u : want_v) + 1;
+      asm volatile("" ::"v"(mb_dst), "v"(ver));
+    }
+    // (and the next slot's metadata is loaded here, not late in the step)
+    asm volatile("" ::"s"(si_next.u), "s"(si_next.v), "s"(si_next.pos_u), "s"(si_next.pos_v), "s"(si_next.deg_u),
+                 "s"(si_next.deg_v));
 #if MPLPXX_FINE_STAMPS
     if (v.stamps && last_iter && tid == 0) v.stamps[(size_t)slot * kStampStride + 4] = wall_clock64();
 #endif
@@ -747,13 +816,17 @@ __device__ __forceinline__ bool mb_run(const MbView& v_in, int first_in, int str
         float mn = xc[0][jj] + b[0];
 #pragma unroll
         for (int i = 1; i < S::BR; ++i) mn = vmin(mn, xc[i][jj] + b[i]);
-        qv[jj] = col4_min(mn);
+        qv[jj] = mn;
       }
-      if (lane < 16) {
-#pragma unroll
-        for (int jj = 0; jj < S::BC; ++jj) sm.red[wave][cb * S::BC + jj] = qv[jj];
-      }
+      col4_min_store<S::BC>(qv, sm.red[wave], cb, lane);
     }
+    // The head of this lane's compensated update needs only the old value
+    // and message: done before the mid-step barrier (the empty asm keeps it
+    // there; the compiler would otherwise sink it to its use after the
+    // barrier, on the step's critical path).
+    float cd, ce1;
+    comp_update_head(ohi, ophi, cd, ce1);
+    asm volatile("" : "+v"(cd), "+v"(ce1));
 #if MPLPXX_FINE_STAMPS
     if (v.stamps && last_iter && tid == 0) v.stamps[(size_t)slot * kStampStride + 6] = wall_clock64();
 #endif
@@ -814,7 +887,25 @@ __device__ __forceinline__ bool mb_run(const MbView& v_in, int first_in, int str
         for (int jj = 1; jj < S::BC; ++jj) mn = vmin(mn, xc[i][jj] - qv[jj]);
         r[i] = mn;
       }
-      row16_min_n<S::BR>(r);
+      if (TRACE) {
+        row16_min_n<S::BR>(r);  // (the trace needs every row's minimum)
+      } else {
+        // Only lane cb = i of a row block needs row i's minimum: three
+        // exchanges leave each lane the minimum over its half row, then
+        // lanes cb and 15 - cb both take row min(cb, 15 - cb) and one
+        // mirrored exchange joins the halves (BR <= 8: every output lane
+        // is in the first half).
+        row16_min_n<S::BR, 3>(r);
+        // (every lane finishes every half-row minimum first, so the choice
+        // below stays a select instead of becoming divergent branches)
+#pragma unroll
+        for (int i = 0; i < S::BR; ++i) asm volatile("" : "+v"(r[i]));
+        const int half_row = cb < 8 ? cb : 15 - cb;
+        float sel = r[0];
+#pragma unroll
+        for (int i = 1; i < S::BR; ++i) sel = half_row == i ? r[i] : sel;
+        r[0] = vmin(sel, dpp_f<0x140>(sel));
+      }
     }
     if (TRACE) {
       // edge term of Eq. (3) after this update from the stored messages
@@ -841,9 +932,11 @@ __device__ __forceinline__ bool mb_run(const MbView& v_in, int first_in, int str
     }
     if (out_u) {
       float rr = r[0];
+      if (RULE != MPLPXX_RULE_H || TRACE) {
 #pragma unroll
-      for (int i = 1; i < S::BR; ++i)
-        if (cb == i) rr = r[i];
+        for (int i = 1; i < S::BR; ++i)
+          if (cb == i) rr = r[i];
+      }
       omsg = rr - delta;
     }
     // push back: the new unary through the mailbox, the message to memory.
@@ -854,18 +947,15 @@ __device__ __forceinline__ bool mb_run(const MbView& v_in, int first_in, int str
     // operations are in flight, and it would then wait for all of them,
     // prefetches too.
     float* phi_w = phi_of(slot, j);
-    const bool outk = out_uk || out_v;
     float nhi, nlo;
-    comp_update(ohi, olo, ophi, omsg, nhi, nlo);
-    const int node = out_u ? si.u : si.v;
+    comp_update_tail(cd, ce1, olo, omsg, nhi, nlo);
     if (LDSU) {
       if (outk) {
         v.lds_hi[(size_t)node * L + out_i] = nhi;
         v.lds_lo[(size_t)node * L + out_i] = (unsigned short)(__float_as_uint(nlo) >> 16);
       }
     } else {
-      const unsigned ver = (out_u ? want_u : want_v) + 1;
-      mb_store(outk ? v.mb + (size_t)node * L + out_i : v.sink + (tid & ~63), mb_pack(nhi, nlo, ver));
+      mb_store(mb_dst, mb_pack(nhi, nlo, ver));
     }
     if (PHI_LDS) {
       if (outk) phi_w[(out_u ? 0 : L) + out_i] = omsg;
