@@ -328,36 +328,32 @@ __device__ __forceinline__ bool sync_gather(const unsigned long long* __restrict
   const int lane = threadIdx.x & 63;
   constexpr int PER = (LT + 63) / 64;
   want &= 0xFFFFu;
-  bool have[PER];
+  // Every lane reloads its words until the whole wave sees the version:
+  // no word can move past it meanwhile, since this workgroup makes the
+  // node's next update (lanes past L read word L - 1).
+  // (one exit from the loop, so that the delivery follows a hit directly)
   unsigned long long val[PER];
-#pragma unroll
-  for (int k = 0; k < PER; ++k) have[k] = (lane + 64 * k) >= L;
   long long spins = 0;
-  for (;;) {
+  bool done;
+  do {
     bool all = true;
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-      if (!have[k]) {
-        const unsigned long long w = mb_load(mb_row + lane + 64 * k);
-        if (mb_ver(w) == want) {
-          have[k] = true;
-          val[k] = w;
-        } else {
-          all = false;
-        }
-      }
+      const int s = lane + 64 * k;
+      val[k] = mb_load(mb_row + (s < L ? s : L - 1));
+      all &= mb_ver(val[k]) == want;
     }
-    if (__all(all)) break;
-    if (++spins > spin_limit || ((spins & 255) == 0 && ld_dev(err) != 0)) {
-      unsigned seen = want;
+    done = __all(all);
+  } while (!done && ++spins <= spin_limit && ((spins & 255) != 0 || ld_dev(err) == 0));
+  if (!done) {
+    unsigned seen = want;
 #pragma unroll
-      for (int k = 0; k < PER; ++k)
-        if (!have[k]) seen = mb_ver(mb_load(mb_row + lane + 64 * k));
-      // smallest version still missing in the wave
-      for (int o = 32; o >= 1; o >>= 1) seen = min(seen, (unsigned)__shfl_xor((int)seen, o, 64));
-      *seen_out = seen;
-      return false;
-    }
+    for (int k = 0; k < PER; ++k)
+      if (mb_ver(val[k]) != want) seen = mb_ver(val[k]);
+    // smallest version still missing in the wave
+    for (int o = 32; o >= 1; o >>= 1) seen = min(seen, (unsigned)__shfl_xor((int)seen, o, 64));
+    *seen_out = seen;
+    return false;
   }
   float c = __builtin_inff();
 #pragma unroll
