@@ -159,10 +159,12 @@ int mplpxx_create_potts(int32_t n, int32_t L, int64_t m, const int32_t* edges, c
  * linear, truncated quadratic); unaries as for mplpxx_create (FP32).  Runs on the persistent
  * mailbox engine with one compute wave per workgroup in label order, or on
  * its four compute waves with each tile formed from the edge's parameters
- * (MPLPXX_OPT_THREADS 64 or 256; the default: 256 for the truncated kinds,
- * for Potts costs up to 32 labels).  Formed tiles hold exactly the expanded
- * table's entries, so that engine gives the dense handle's bits for every
- * kind.  In label order:
+ * (MPLPXX_OPT_THREADS 64 or 256; the default: formed tiles for the
+ * truncated kinds and for Potts costs up to 32 labels, with one compute wave
+ * instead of four at 16 labels when a matching has more edges than the
+ * device has compute units, as for tables).  Formed tiles hold exactly the
+ * expanded table's entries, so that engine gives the dense handle's bits for
+ * every kind.  In label order:
  * Potts: as mplpxx_create_potts (bitwise the dense handle on
  * the expanded tables).
  * Truncated linear: each pass is a min-plus distance transform in O(L) work

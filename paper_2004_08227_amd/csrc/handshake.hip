@@ -362,9 +362,9 @@ static hipError_t launch_one(const HsArgs<T>& a, int engine, int slot_begin, int
 
 // structured costs on the dense mailbox engine, the tiles formed from the
 // slots' parameters (TRACE off, default prefetch)
-template <int LT, int KIND>
+template <int LT, int NT, int KIND>
 static const void* mb_gen_kernel(bool phi_in_lds, bool full, bool far) {
-#define MPLPXX_G(P, F, A) (const void*)k_persistent_mb<LT, 256, P, F, false, A, (LT <= 64 ? 2 : 1), KIND>
+#define MPLPXX_G(P, F, A) (const void*)k_persistent_mb<LT, NT, P, F, false, A, (LT <= 64 ? 2 : 1), KIND>
   return phi_in_lds ? (full ? (far ? MPLPXX_G(true, true, true) : MPLPXX_G(true, true, false))
                             : (far ? MPLPXX_G(true, false, true) : MPLPXX_G(true, false, false)))
                     : (full ? (far ? MPLPXX_G(false, true, true) : MPLPXX_G(false, true, false))
@@ -401,12 +401,13 @@ static hipError_t launch_mb_one(const HsArgs<float>& a, unsigned long long* mb, 
     return hipErrorInvalidValue;
   }
   if (kind != kCostDense) {
-    if constexpr (NT == 256 && LT <= 64) {
+    // (four compute waves up to 64 labels; one compute wave at 16 labels)
+    if constexpr ((NT == 256 && LT <= 64) || (NT == 64 && LT == 16)) {
       const bool far = (a.m / grid) >= 4;
-      const void* f = kind == MPLPXX_COST_POTTS ? mb_gen_kernel<LT, MPLPXX_COST_POTTS>(phi_in_lds, a.L == LT, far)
+      const void* f = kind == MPLPXX_COST_POTTS ? mb_gen_kernel<LT, NT, MPLPXX_COST_POTTS>(phi_in_lds, a.L == LT, far)
                       : kind == MPLPXX_COST_TRUNC_LINEAR
-                          ? mb_gen_kernel<LT, MPLPXX_COST_TRUNC_LINEAR>(phi_in_lds, a.L == LT, far)
-                          : mb_gen_kernel<LT, MPLPXX_COST_TRUNC_QUAD>(phi_in_lds, a.L == LT, far);
+                          ? mb_gen_kernel<LT, NT, MPLPXX_COST_TRUNC_LINEAR>(phi_in_lds, a.L == LT, far)
+                          : mb_gen_kernel<LT, NT, MPLPXX_COST_TRUNC_QUAD>(phi_in_lds, a.L == LT, far);
       const hipError_t e = hipLaunchCooperativeKernel(f, dim3(grid), dim3(NT + 128), args, dyn_lds, st);
       if (e != hipSuccess) (void)hipGetLastError();
       return e;

@@ -132,7 +132,13 @@ struct mplpxx_solver {
     return potts != MPLPXX_COST_POTTS || L <= 32;
   }
   int NT() const {
-    if (potts) return gen_tiles() ? 256 : 64;
+    if (potts) {
+      if (!gen_tiles()) return 64;  // label order: one compute wave
+      if (threads_opt) return 256;
+      // formed tiles: one compute wave at 16 labels when a matching has
+      // more edges than there are compute units, as for tables below
+      return LT() == 16 && max_step > num_cus ? 64 : 256;
+    }
     // default: one compute wave at 16 labels when a matching has more edges
     // than there are compute units (several workgroups then share a compute
     // unit: sparse graphs of 1,000 nodes run 3-5 % faster per iteration, a

@@ -80,6 +80,39 @@ def test_formed_tiles_are_the_default():
         assert s.info("threads") == 256
 
 
+STRUCT_16 = [
+    ("potts", M.COST_POTTS, lambda: W.potts_pure(700, 16, 0.1, seed=41)),
+    ("trunc_linear", M.COST_TRUNC_LINEAR, lambda: W.trunc_linear(700, 16, 0.1, seed=42, tau=5.0)),
+    ("trunc_quad", M.COST_TRUNC_QUAD, lambda: W.trunc_quad(700, 16, 0.1, seed=43, tau=20.0)),
+]
+
+
+@pytest.mark.parametrize("name,kind,make", STRUCT_16, ids=[c[0] for c in STRUCT_16])
+def test_formed_tiles_one_compute_wave_at_16_labels(name, kind, make):
+    # 16 labels and matchings with more edges than there are compute units:
+    # the formed tiles run one compute wave by default, like the tables, and
+    # give the dense handle's bits
+    _announce("formed tiles one wave", name)
+    params, dense = make()
+    iters = 6
+    with M.Solver.from_structured(params, kind) as s, M.Solver.from_model(dense) as sd:
+        # (the default takes one wave only when a matching outnumbers the CUs)
+        assert s.info("threads") == 64 and sd.info("threads") == 64
+        s.iterate(iters)
+        sd.iterate(iters)
+        assert s.dual_bound() == sd.dual_bound()
+        for a, b in zip(sd.get_state(comp=True), s.get_state(comp=True)):
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+        # four compute waves (threads 256) give the same bits
+        s.set_option(M.OPT_THREADS, 256)
+        assert s.info("threads") == 256
+        U0 = dense.unaries.copy()
+        s.set_state(U0, np.zeros((dense.m, 2, dense.L), np.float32))
+        s.iterate(iters)
+        for a, b in zip(sd.get_state(comp=True), s.get_state(comp=True)):
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
 def test_per_edge_truncation_and_zero_weights():
     _announce("trunc linear per-edge tau")
     rng = np.random.default_rng(11)
