@@ -33,7 +33,7 @@ METRIC = "edge-block updates/s + HBM GB/s fraction; time-to-dual-bound vs plain,
 # iteration of the pose n=200/L=64 launch, and the factors that map each
 # counter to bytes, from the same counters on a 1 GiB copy.  Valid only for
 # the kernel sources they were taken on (hash below); otherwise null.
-TRAFFIC = {"src_sha": "97893b073755f5ff", "fetch_kib_per_iter": 3760335.5625 / 20, "fetch_scale": 2.0,
+TRAFFIC = {"src_sha": "8c57154f050dfbd2", "fetch_kib_per_iter": 3768204.6875 / 20, "fetch_scale": 2.0,
            "write_kib_per_iter": 457708.0 / 20, "write_scale": 1.0}
 TRAFFIC_SRCS = ("paper_2004_08227_amd/csrc/common.h", "paper_2004_08227_amd/csrc/device_common.h",
                 "paper_2004_08227_amd/csrc/step_common.h", "paper_2004_08227_amd/csrc/potts_passes.h",
